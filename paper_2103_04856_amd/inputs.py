@@ -1,0 +1,85 @@
+"""Seeded synthetic inputs for the energy, the gradient and the descent loop.
+
+This module only makes initial fields and coefficient tables; it holds none of
+the energy's arithmetic and imports nothing else from this package, so both the
+HIP path's tests and the FP64 oracle's tests draw from it.
+
+Fields are float64 numpy arrays indexed [z, y, x] on the periodic unit cube
+[0, 1)^3 with N samples per axis at cell centres x_i = (i + 1/2) h, h = 1/N.
+Shapes use the tanh profile u = tanh(d / (sqrt(2) eps)) of eq. (tanh_profile),
+with d the minimum-image signed distance (positive inside, u ~ +1 inside).
+"""
+
+import math
+
+import numpy as np
+
+
+def cell_centres(n):
+    h = 1.0 / n
+    return (np.arange(n) + 0.5) * h
+
+
+def _min_image(x, c):
+    d = x - c
+    return d - np.round(d)
+
+
+def _mesh(n):
+    x = cell_centres(n)
+    return np.meshgrid(x, x, x, indexing="ij")    # [z, y, x] order: Z, Y, X
+
+
+def uniform_noise(n, seed, lo=-1.0, hi=1.0, batch=None):
+    """u0 ~ U(lo, hi) i.i.d. per voxel, from numpy's default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    shape = (n, n, n) if batch is None else (batch, n, n, n)
+    return rng.uniform(lo, hi, size=shape)
+
+
+def tanh_sphere(n, radius, eps, centre=(0.5, 0.5, 0.5)):
+    """Ball of the given radius: d = radius - |x - centre| (minimum image)."""
+    Z, Y, X = _mesh(n)
+    r = np.sqrt(_min_image(X, centre[0]) ** 2 + _min_image(Y, centre[1]) ** 2
+                + _min_image(Z, centre[2]) ** 2)
+    return np.tanh((radius - r) / (math.sqrt(2.0) * eps))
+
+
+def tanh_cylinder(n, radius, eps, axis="z", centre=(0.5, 0.5)):
+    """Infinite (periodic) solid cylinder along `axis` with the given radius."""
+    Z, Y, X = _mesh(n)
+    coords = {"x": X, "y": Y, "z": Z}
+    others = [k for k in "xyz" if k != axis]
+    r = np.sqrt(_min_image(coords[others[0]], centre[0]) ** 2
+                + _min_image(coords[others[1]], centre[1]) ** 2)
+    return np.tanh((radius - r) / (math.sqrt(2.0) * eps))
+
+
+def tanh_slab(n, half_width, eps, axis="x", centre=0.5):
+    """Slab |x_axis - centre| < half_width (two parallel planes)."""
+    Z, Y, X = _mesh(n)
+    c = {"x": X, "y": Y, "z": Z}[axis]
+    return np.tanh((half_width - np.abs(_min_image(c, centre))) / (math.sqrt(2.0) * eps))
+
+
+def noisy_sphere(n, radius, eps, noise_std, seed):
+    """tanh sphere plus i.i.d. N(0, noise_std^2) noise from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    return tanh_sphere(n, radius, eps) + rng.normal(0.0, noise_std, size=(n, n, n))
+
+
+def random_instance_table(batch, seed):
+    """Per-instance polynomial and mass draws for a batch of independent textures.
+
+    p = a k1^2 + b k2^2 + c k1 k2 + d (k1 + k2), a, b ~ U(0, 2), c ~ U(-1, 1),
+    d ~ U(-6, 0); returns (coeffs[batch, 6] in (a20, a11, a02, a10, a01, a00)
+    order, target means[batch] ~ U(-0.5, 0.5)).
+    """
+    rng = np.random.default_rng(seed)
+    A = rng.uniform(0.0, 2.0, batch)
+    B = rng.uniform(0.0, 2.0, batch)
+    C = rng.uniform(-1.0, 1.0, batch)
+    D = rng.uniform(-6.0, 0.0, batch)
+    coeffs = np.stack([A, C, B, D, D, np.zeros(batch)], axis=1)
+    means = rng.uniform(-0.5, 0.5, batch)
+    return coeffs, means
