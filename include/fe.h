@@ -1,0 +1,154 @@
+/*
+ * fe.h - C ABI of the MI355X (gfx950) curvature phase-field energy library.
+ *
+ * The library evaluates the discrete phase-field energy F_eps of eq. (Feps)
+ * (Sec. 3.2), its exact gradient with respect to the phase field u, and a
+ * mass-preserving descent step, on periodic 3-D voxel grids, for one or many
+ * independent instances at once.
+ *
+ * Discrete problem (Sec. 4.1, Implementation details). For each instance b
+ * with field u on an nz x ny x nx periodic grid of spacing h:
+ *
+ *   M  = -eps Hess_h u + (W'(u)/eps) g g^T / (|g|^2 + xi^2),  W'(s) = s^3 - s
+ *   F_h(u) = h^3 sum_voxels [ c1 ||M||^2 + c2 (Tr M)^2 + c3 Tr M S
+ *                             + c4 rho Tr M + c5 rho S + c6 eps |g|^2 ]
+ *
+ * with g = central-difference gradient, Hess_h = compact 19-point periodic
+ * Hessian, rho = sqrt(|g|^2 + xi^2), S = sqrt(softplus_xi(2||M||^2 - (Tr M)^2)),
+ * softplus_xi(x) = xi log(1 + exp(x/xi)), xi = 1e-6, and
+ *   c1 = (a20 + a02 - a11)/(2 eps), c2 = a11/(2 eps), c3 = (a20 - a02)/(2 eps),
+ *   c4 = (a10 + a01)/2, c5 = (a10 - a01)/2, c6 = a00
+ * for the polynomial p(k1,k2) = a20 k1^2 + a11 k1 k2 + a02 k2^2 + a10 k1
+ * + a01 k2 + a00 of eq. (F) (Sec. 2.1).
+ *
+ * Layout: every field is a dense, contiguous device array [batch][nz][ny][nx]
+ * (x fastest) of float (FE_F32) or double (FE_F64), on the device that was
+ * current when the context was created. Field pointers are owned by the
+ * caller; the library never frees or reallocates them.
+ *
+ * Errors: every int-returning call returns FE_OK (0) on success and a
+ * negative FE_E* code otherwise; fe_last_error() then describes the failure.
+ * No C++ exception crosses this interface. Calls are ordered on the
+ * context's stream; only calls that return values into host memory
+ * synchronise that stream. One context must not be used from two host
+ * threads at the same time.
+ */
+#ifndef FE_H_
+#define FE_H_
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum fe_dtype { FE_F32 = 0, FE_F64 = 1 };
+
+enum fe_status {
+  FE_OK = 0,
+  FE_EINVAL = -1,     /* invalid argument: sizes, NULL pointers, eps <= 0, non-finite values */
+  FE_EHIP = -2,       /* a HIP runtime call or kernel launch failed */
+  FE_ENOMEM = -3,     /* device or host allocation failed */
+  FE_ENONFINITE = -4  /* an energy came out NaN/Inf; outputs were still written */
+};
+
+typedef struct fe_grid {
+  int nx, ny, nz;   /* samples per axis, each >= 1 */
+  int batch;        /* number of independent instances, >= 1 */
+  double h;         /* grid spacing (same on every axis), > 0 */
+  int dtype;        /* FE_F32 or FE_F64: element type of every field */
+} fe_grid;
+
+typedef struct fe_ctx fe_ctx;   /* opaque: parameters, reduction workspace, step buffers, graphs */
+
+/*
+ * Create a context for `grid`.
+ *   eps      host [batch]: interface width eps_b > 0 of each instance (eq. (Meps)).
+ *   p_coeffs host [batch][6]: (a20, a11, a02, a10, a01, a00) of each instance,
+ *            the coefficient order of Sec. 3.2; all finite.
+ *   stream   hipStream_t to order work on, or NULL for the default stream.
+ *   out      receives the new context.
+ * Allocates only small device workspaces (O(batch x blocks) doubles); the
+ * ping-pong buffer of fe_step is allocated on its first call.
+ * Returns FE_EINVAL, FE_ENOMEM or FE_EHIP on failure (*out is then NULL).
+ */
+int fe_create(const fe_grid* grid, const double* eps, const double* p_coeffs,
+              void* stream, fe_ctx** out);
+
+/* Replace eps [batch] and p_coeffs [batch][6] (same meaning as fe_create). No allocation. */
+int fe_set_params(fe_ctx* ctx, const double* eps, const double* p_coeffs);
+
+/* Order subsequent work on `stream` (hipStream_t, NULL = default stream). */
+int fe_set_stream(fe_ctx* ctx, void* stream);
+
+/*
+ * Energy only: energy[b] = F_h(u_b) in double.
+ *   u       device field [batch][nz][ny][nx], read only.
+ *   energy  host [batch], or NULL. Non-NULL synchronises the stream.
+ * FE_ENONFINITE if an energy is NaN/Inf (energy[] is still written).
+ */
+int fe_energy(fe_ctx* ctx, const void* u, double* energy);
+
+/*
+ * Energy and gradient: g = dF_h/du, the exact derivative of the h^3-weighted
+ * finite sum (the h^3 factor is included), and energy[b] = F_h(u_b).
+ *   u       device field, read only.
+ *   g       device field, written; must not overlap u.
+ *   energy  host [batch] or NULL (non-NULL synchronises the stream).
+ */
+int fe_energy_grad(fe_ctx* ctx, const void* u, void* g, double* energy);
+
+/*
+ * As fe_energy / fe_energy_grad, but the energies go to device memory and
+ * nothing synchronises: energy_dev is a device array of `batch` doubles, or NULL.
+ * g may be NULL to compute the energy only.
+ */
+int fe_energy_grad_async(fe_ctx* ctx, const void* u, void* g, double* energy_dev);
+
+/*
+ * nsteps mass-preserving descent steps, in place on u (Sec. 4.1 keeps the mean
+ * of u fixed along the flow):
+ *   u <- v + (mass[b] - mean(v)),  v = u - tau dF_h/du,
+ * i.e. a gradient step followed by the L2 projection onto {mean(u_b) = mass[b]}.
+ * The first step also moves an initial mean that differs from mass[b] onto it.
+ *   u       device field, read and overwritten with the result.
+ *   mass    host [batch]: target mean of each instance.
+ *   tau     step size (> 0, finite).
+ *   nsteps  number of steps, >= 0 (0 is a no-op).
+ *   energy  host [batch] or NULL: F_h of the field before the last step
+ *           (synchronises the stream when non-NULL).
+ * Uses a context-owned ping-pong field of the same size as u (allocated on
+ * first use) and replays captured HIP graphs for the step loop.
+ */
+int fe_step(fe_ctx* ctx, void* u, const double* mass, double tau, int nsteps, double* energy);
+
+/*
+ * Launch-shape selection. Variants are numbered 0 .. fe_num_variants()-1;
+ * fe_variant_info describes one (x and y interior tile, threads per block,
+ * element size it supports). fe_set_launch picks a variant and a z-chunk
+ * length (planes per block, >= 1; 0 = automatic). FE_EINVAL for a variant
+ * that does not support the context's dtype.
+ */
+int fe_num_variants(void);
+int fe_variant_info(int variant, int* tile_x, int* tile_y, int* threads, int* dtype_mask);
+int fe_set_launch(fe_ctx* ctx, int variant, int z_chunk);
+int fe_get_launch(const fe_ctx* ctx, int* variant, int* z_chunk);
+
+/*
+ * Time every variant that supports the context's dtype (and a few z-chunk
+ * lengths) on fe_energy_grad_async(u, g) with `iters` launches each, pick the
+ * fastest, and keep it in the context. u and g as in fe_energy_grad; g is
+ * overwritten. best_us (host, may be NULL) receives the best time per call
+ * in microseconds. Synchronises the stream.
+ */
+int fe_autotune(fe_ctx* ctx, const void* u, void* g, int iters, double* best_us);
+
+/* Release the context and everything it allocated. NULL is a no-op. */
+void fe_destroy(fe_ctx* ctx);
+
+/* Text of the last error raised on this host thread ("" if none). */
+const char* fe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FE_H_ */

@@ -1,0 +1,632 @@
+// Host side of the C ABI declared in include/fe.h: argument validation,
+// per-instance constants, launch-shape selection, the graph-replayed step
+// loop and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "fe.h"
+#include "fe_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define FE_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return set_error(FE_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));          \
+  } while (0)
+
+constexpr double kXi = 1e-6;   // Sec. 4.1: offset of |grad u| and scale of the smoothed x^+
+
+// ---------------------------------------------------------------------------
+// Launch variants: interior tile (TX x TY) and threads per block.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+using SweepFn = void (*)(fe::SweepArgs<T>);
+
+template <typename T>
+struct Kernels {
+  SweepFn<T> grad = nullptr;
+  SweepFn<T> step = nullptr;
+  SweepFn<T> energy = nullptr;
+};
+
+struct Variant {
+  int tx, ty, nt;
+  int dtype_mask;   // bit 0: FE_F32, bit 1: FE_F64
+  Kernels<float> k32;
+  Kernels<double> k64;
+};
+
+template <typename T, int TX, int TY, int NT>
+Kernels<T> make_kernels() {
+  Kernels<T> k;
+  k.grad = fe::grad_sweep<T, TX, TY, NT, false>;
+  k.step = fe::grad_sweep<T, TX, TY, NT, true>;
+  k.energy = fe::energy_sweep<T, TX, TY, NT>;
+  return k;
+}
+
+// Static LDS of grad_sweep is (3 (TX+4)(TY+4) + 10 (TX+2)(TY+2)) sizeof(T) and
+// is kept <= 64 KiB; double-precision variants therefore use smaller tiles.
+const std::vector<Variant>& variants() {
+  static const std::vector<Variant> v = [] {
+    std::vector<Variant> r;
+    auto add32 = [&](int tx, int ty, int nt, Kernels<float> k) {
+      Variant x{tx, ty, nt, 1, k, {}};
+      r.push_back(x);
+    };
+    auto add64 = [&](int tx, int ty, int nt, Kernels<double> k) {
+      Variant x{tx, ty, nt, 2, {}, k};
+      r.push_back(x);
+    };
+    add32(64, 16, 1024, make_kernels<float, 64, 16, 1024>());
+    add32(64, 8, 512, make_kernels<float, 64, 8, 512>());
+    add32(32, 16, 512, make_kernels<float, 32, 16, 512>());
+    add32(32, 8, 256, make_kernels<float, 32, 8, 256>());
+    add32(16, 16, 256, make_kernels<float, 16, 16, 256>());
+    add32(16, 8, 128, make_kernels<float, 16, 8, 128>());
+    add32(8, 8, 64, make_kernels<float, 8, 8, 64>());
+    add64(32, 8, 256, make_kernels<double, 32, 8, 256>());
+    add64(16, 16, 256, make_kernels<double, 16, 16, 256>());
+    add64(16, 8, 128, make_kernels<double, 16, 8, 128>());
+    add64(8, 8, 64, make_kernels<double, 8, 8, 64>());
+    return r;
+  }();
+  return v;
+}
+
+template <typename T>
+const Kernels<T>& kernels_of(const Variant& v);
+template <>
+const Kernels<float>& kernels_of<float>(const Variant& v) { return v.k32; }
+template <>
+const Kernels<double>& kernels_of<double>(const Variant& v) { return v.k64; }
+
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+
+struct GraphKey {
+  void* u;
+  double tau;
+  int pairs;
+  int variant;
+  int lz;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(u, tau, pairs, variant, lz) < std::tie(o.u, o.tau, o.pairs, o.variant, o.lz);
+  }
+};
+
+struct fe_ctx {
+  fe_grid grid{};
+  int device = 0;
+  hipStream_t stream = nullptr;       // caller's stream (may be null = default)
+  hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
+  std::vector<double> eps, coeffs;    // host copies [batch], [batch][6]
+  void* d_prm = nullptr;              // InstParams<T>[batch]
+  double* d_partials = nullptr;       // [batch][max_blocks][2]
+  double* d_energy = nullptr;         // [batch]
+  double* d_mass = nullptr;           // [batch]
+  double* d_shift = nullptr;          // [2][batch]
+  void* d_pingpong = nullptr;         // one field, allocated by the first fe_step
+  size_t max_blocks = 0;              // per instance, over all variants and z chunks
+  int variant = -1;
+  int lz = 0;                         // 0 = automatic
+  std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+size_t elem_size(const fe_grid& g) { return g.dtype == FE_F64 ? 8 : 4; }
+size_t field_elems(const fe_grid& g) { return (size_t)g.nx * g.ny * g.nz * g.batch; }
+
+int check_grid(const fe_grid* g) {
+  if (!g) return set_error(FE_EINVAL, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1)
+    return set_error(FE_EINVAL, "grid sizes must be >= 1 (got %d x %d x %d)", g->nx, g->ny, g->nz);
+  if (g->batch < 1) return set_error(FE_EINVAL, "batch must be >= 1 (got %d)", g->batch);
+  if (!(g->h > 0.0) || !std::isfinite(g->h)) return set_error(FE_EINVAL, "h must be finite and > 0");
+  if (g->dtype != FE_F32 && g->dtype != FE_F64) return set_error(FE_EINVAL, "dtype must be FE_F32 or FE_F64");
+  const double n = (double)g->nx * g->ny * g->nz;
+  if (n * g->batch > 4.0e9 || (double)g->nx * g->ny > 2.0e9)
+    return set_error(FE_EINVAL, "grid too large for 32-bit plane indexing");
+  return FE_OK;
+}
+
+int check_params(int batch, const double* eps, const double* a) {
+  if (!eps || !a) return set_error(FE_EINVAL, "eps and p_coeffs must not be NULL");
+  for (int b = 0; b < batch; ++b) {
+    if (!(eps[b] > 0.0) || !std::isfinite(eps[b]))
+      return set_error(FE_EINVAL, "eps[%d] must be finite and > 0", b);
+    for (int i = 0; i < 6; ++i)
+      if (!std::isfinite(a[6 * b + i])) return set_error(FE_EINVAL, "p_coeffs[%d][%d] is not finite", b, i);
+  }
+  return FE_OK;
+}
+
+// c1..c6 of eq. (Feps) and the gather scales, per instance.
+template <typename T>
+void fill_params(const fe_ctx* c, std::vector<fe::InstParams<T>>& out) {
+  const double h = c->grid.h, h3 = h * h * h;
+  out.resize(c->grid.batch);
+  for (int b = 0; b < c->grid.batch; ++b) {
+    const double e = c->eps[b];
+    const double* a = &c->coeffs[6 * b];
+    const double a20 = a[0], a11 = a[1], a02 = a[2], a10 = a[3], a01 = a[4], a00 = a[5];
+    fe::InstParams<T>& p = out[b];
+    p.eps_d = e;
+    p.inv_eps_d = 1.0 / e;
+    p.inv_eps = T(1.0 / e);
+    p.c1 = T((a20 + a02 - a11) / (2.0 * e));
+    p.c2 = T(a11 / (2.0 * e));
+    p.c3 = T((a20 - a02) / (2.0 * e));
+    p.c4 = T((a10 + a01) / 2.0);
+    p.c5 = T((a10 - a01) / 2.0);
+    p.c6e = T(a00 * e);
+    p.sc_u = T(h3);
+    p.sc_gamma = T(h3 / (2.0 * h));
+    p.sc_tdiag = T(-e * h3 / (h * h));
+    p.sc_toff = T(-e * h3 / (4.0 * h * h));
+  }
+}
+
+template <typename T>
+fe::StencilConsts<T> stencil_consts(double h) {
+  fe::StencilConsts<T> k;
+  k.inv2h = 1.0 / (2.0 * h);
+  k.invh2 = 1.0 / (h * h);
+  k.inv4h2 = 1.0 / (4.0 * h * h);
+  k.xi2 = kXi * kXi;
+  k.xi = T(kXi);
+  k.inv_xi = T(1.0 / kXi);
+  return k;
+}
+
+int upload_params(fe_ctx* c) {
+  if (c->grid.dtype == FE_F32) {
+    std::vector<fe::InstParams<float>> p;
+    fill_params(c, p);
+    FE_HIP(hipMemcpyAsync(c->d_prm, p.data(), p.size() * sizeof(p[0]), hipMemcpyHostToDevice, c->stream));
+  } else {
+    std::vector<fe::InstParams<double>> p;
+    fill_params(c, p);
+    FE_HIP(hipMemcpyAsync(c->d_prm, p.data(), p.size() * sizeof(p[0]), hipMemcpyHostToDevice, c->stream));
+  }
+  // the host vectors die here: make sure the copies have consumed them
+  FE_HIP(hipStreamSynchronize(c->stream));
+  return FE_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+bool variant_ok(int v, int dtype) {
+  if (v < 0 || v >= (int)variants().size()) return false;
+  return variants()[v].dtype_mask & (dtype == FE_F64 ? 2 : 1);
+}
+
+// Launch geometry of the chosen variant.
+struct Geometry {
+  int ntx, nty, nzc, lz, per_inst;
+};
+
+Geometry geometry(const fe_ctx* c, int variant, int lz_req) {
+  const Variant& v = variants()[variant];
+  Geometry g;
+  g.ntx = ceil_div(c->grid.nx, v.tx);
+  g.nty = ceil_div(c->grid.ny, v.ty);
+  int lz = lz_req;
+  if (lz <= 0) {
+    // aim at >= ~1024 blocks in total (several per CU on 256 CUs), but keep
+    // chunks >= 8 planes so the two recomputed boundary planes stay cheap
+    const double cols = (double)g.ntx * g.nty * c->grid.batch;
+    lz = (int)std::ceil(cols * c->grid.nz / 1024.0);
+    lz = std::max(lz, 8);
+  }
+  lz = std::min(std::max(lz, 1), c->grid.nz);
+  g.lz = lz;
+  g.nzc = ceil_div(c->grid.nz, lz);
+  g.per_inst = g.ntx * g.nty * g.nzc;
+  return g;
+}
+
+int default_variant(const fe_grid& g) {
+  const int dt = g.dtype;
+  // the largest tile whose x and y extents do not exceed the grid by much
+  for (int v = 0; v < (int)variants().size(); ++v) {
+    if (!variant_ok(v, dt)) continue;
+    const Variant& x = variants()[v];
+    if (x.tx <= std::max(g.nx, 8) && x.ty <= std::max(g.ny, 8)) return v;
+  }
+  for (int v = (int)variants().size() - 1; v >= 0; --v)
+    if (variant_ok(v, dt)) return v;
+  return 0;
+}
+
+template <typename T>
+int launch_sweep(fe_ctx* c, hipStream_t s, int kind /*0 energy,1 grad,2 step*/, const void* src, void* dst,
+                 const double* shift_in, double tau) {
+  const Geometry geo = geometry(c, c->variant, c->lz);
+  if ((size_t)geo.per_inst > c->max_blocks) return set_error(FE_EINVAL, "internal: partials workspace too small");
+  const Variant& v = variants()[c->variant];
+  const Kernels<T>& k = kernels_of<T>(v);
+  fe::SweepArgs<T> a;
+  a.src = static_cast<const T*>(src);
+  a.dst = static_cast<T*>(dst);
+  a.prm = static_cast<const fe::InstParams<T>*>(c->d_prm);
+  a.shift_in = shift_in;
+  a.partials = c->d_partials;
+  a.k = stencil_consts<T>(c->grid.h);
+  a.tau = T(tau);
+  a.nx = c->grid.nx;
+  a.ny = c->grid.ny;
+  a.nz = c->grid.nz;
+  a.ntx = geo.ntx;
+  a.nty = geo.nty;
+  a.nzc = geo.nzc;
+  a.lz = geo.lz;
+  a.batch = c->grid.batch;
+  const dim3 grid((unsigned)(geo.per_inst * c->grid.batch));
+  const dim3 block((unsigned)v.nt);
+  SweepFn<T> fn = kind == 0 ? k.energy : (kind == 1 ? k.grad : k.step);
+  hipLaunchKernelGGL(fn, grid, block, 0, s, a);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+int sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, const double* shift_in, double tau) {
+  return c->grid.dtype == FE_F32 ? launch_sweep<float>(c, s, kind, src, dst, shift_in, tau)
+                                 : launch_sweep<double>(c, s, kind, src, dst, shift_in, tau);
+}
+
+int finalize(fe_ctx* c, hipStream_t s, bool step, double* energy_dev, double* shift_out) {
+  const Geometry geo = geometry(c, c->variant, c->lz);
+  const double h = c->grid.h;
+  const double inv_nvox = 1.0 / ((double)c->grid.nx * c->grid.ny * c->grid.nz);
+  if (step)
+    hipLaunchKernelGGL(fe::finalize_sums<true>, dim3(c->grid.batch), dim3(256), 0, s, c->d_partials,
+                       geo.per_inst, h * h * h, energy_dev, c->d_mass, inv_nvox, shift_out);
+  else
+    hipLaunchKernelGGL(fe::finalize_sums<false>, dim3(c->grid.batch), dim3(256), 0, s, c->d_partials,
+                       geo.per_inst, h * h * h, energy_dev, (const double*)nullptr, inv_nvox, (double*)nullptr);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+int copy_energy_out(fe_ctx* c, double* energy) {
+  if (!energy) return FE_OK;
+  FE_HIP(hipMemcpyAsync(energy, c->d_energy, sizeof(double) * c->grid.batch, hipMemcpyDeviceToHost, c->stream));
+  FE_HIP(hipStreamSynchronize(c->stream));
+  for (int b = 0; b < c->grid.batch; ++b)
+    if (!std::isfinite(energy[b])) return set_error(FE_ENONFINITE, "energy[%d] is not finite", b);
+  return FE_OK;
+}
+
+void drop_graphs(fe_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
+// One descent step: src (+ shift_in) -> dst, then shift_out = mass - mean(dst).
+int step_once(fe_ctx* c, hipStream_t s, const void* src, void* dst, const double* shift_in, double* shift_out,
+              double tau) {
+  int rc = sweep(c, s, 2, src, dst, shift_in, tau);
+  if (rc) return rc;
+  return finalize(c, s, true, c->d_energy, shift_out);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+int fe_create(const fe_grid* grid, const double* eps, const double* p_coeffs, void* stream, fe_ctx** out) {
+  g_last_error.clear();
+  if (!out) return set_error(FE_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  rc = check_params(grid->batch, eps, p_coeffs);
+  if (rc) return rc;
+
+  fe_ctx* c = new (std::nothrow) fe_ctx();
+  if (!c) return set_error(FE_ENOMEM, "host allocation failed");
+  c->grid = *grid;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->eps.assign(eps, eps + grid->batch);
+  c->coeffs.assign(p_coeffs, p_coeffs + 6 * grid->batch);
+  c->variant = default_variant(*grid);
+  c->lz = 0;
+
+  auto fail = [&](int code) {
+    fe_destroy(c);
+    return code;
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) return fail(set_error(FE_EHIP, "hipGetDevice failed"));
+  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return fail(set_error(FE_EHIP, "hipStreamCreateWithFlags failed"));
+
+  // partials workspace: the largest per-instance block count of any variant at z chunk 1
+  size_t mb = 0;
+  for (int v = 0; v < (int)variants().size(); ++v) {
+    if (!variant_ok(v, grid->dtype)) continue;
+    const Variant& x = variants()[v];
+    mb = std::max(mb, (size_t)ceil_div(grid->nx, x.tx) * ceil_div(grid->ny, x.ty) * grid->nz);
+  }
+  c->max_blocks = mb;
+  const size_t prm_bytes = grid->dtype == FE_F32 ? sizeof(fe::InstParams<float>) : sizeof(fe::InstParams<double>);
+  if (hipMalloc(&c->d_prm, prm_bytes * grid->batch) != hipSuccess ||
+      hipMalloc((void**)&c->d_partials, sizeof(double) * 2 * mb * grid->batch) != hipSuccess ||
+      hipMalloc((void**)&c->d_energy, sizeof(double) * grid->batch) != hipSuccess ||
+      hipMalloc((void**)&c->d_mass, sizeof(double) * grid->batch) != hipSuccess ||
+      hipMalloc((void**)&c->d_shift, sizeof(double) * 2 * grid->batch) != hipSuccess)
+    return fail(set_error(FE_ENOMEM, "device workspace allocation failed"));
+  rc = upload_params(c);
+  if (rc) return fail(rc);
+  *out = c;
+  return FE_OK;
+}
+
+int fe_set_params(fe_ctx* c, const double* eps, const double* p_coeffs) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  int rc = check_params(c->grid.batch, eps, p_coeffs);
+  if (rc) return rc;
+  DeviceGuard dg(c->device);
+  c->eps.assign(eps, eps + c->grid.batch);
+  c->coeffs.assign(p_coeffs, p_coeffs + 6 * c->grid.batch);
+  return upload_params(c);
+}
+
+int fe_set_stream(fe_ctx* c, void* stream) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  c->stream = static_cast<hipStream_t>(stream);
+  return FE_OK;
+}
+
+int fe_energy_grad_async(fe_ctx* c, const void* u, void* g, double* energy_dev) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!u) return set_error(FE_EINVAL, "u is NULL");
+  if (g == u) return set_error(FE_EINVAL, "g must not alias u");
+  DeviceGuard dg(c->device);
+  int rc = sweep(c, c->stream, g ? 1 : 0, u, g, nullptr, 0.0);
+  if (rc) return rc;
+  return finalize(c, c->stream, false, energy_dev ? energy_dev : c->d_energy, nullptr);
+}
+
+int fe_energy(fe_ctx* c, const void* u, double* energy) {
+  int rc = fe_energy_grad_async(c, u, nullptr, c ? c->d_energy : nullptr);
+  if (rc) return rc;
+  DeviceGuard dg(c->device);
+  return copy_energy_out(c, energy);
+}
+
+int fe_energy_grad(fe_ctx* c, const void* u, void* g, double* energy) {
+  if (c && !g) return set_error(FE_EINVAL, "g is NULL (use fe_energy for the energy only)");
+  int rc = fe_energy_grad_async(c, u, g, c ? c->d_energy : nullptr);
+  if (rc) return rc;
+  DeviceGuard dg(c->device);
+  return copy_energy_out(c, energy);
+}
+
+int fe_step(fe_ctx* c, void* u, const double* mass, double tau, int nsteps, double* energy) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!u) return set_error(FE_EINVAL, "u is NULL");
+  if (!mass) return set_error(FE_EINVAL, "mass is NULL");
+  if (nsteps < 0) return set_error(FE_EINVAL, "nsteps must be >= 0");
+  if (!(tau > 0.0) || !std::isfinite(tau)) return set_error(FE_EINVAL, "tau must be finite and > 0");
+  for (int b = 0; b < c->grid.batch; ++b)
+    if (!std::isfinite(mass[b])) return set_error(FE_EINVAL, "mass[%d] is not finite", b);
+  if (nsteps == 0) return FE_OK;
+  DeviceGuard dg(c->device);
+  const int B = c->grid.batch;
+  if (!c->d_pingpong) {
+    if (hipMalloc(&c->d_pingpong, field_elems(c->grid) * elem_size(c->grid)) != hipSuccess) {
+      c->d_pingpong = nullptr;
+      return set_error(FE_ENOMEM, "ping-pong field allocation failed");
+    }
+  }
+  FE_HIP(hipMemcpyAsync(c->d_mass, mass, sizeof(double) * B, hipMemcpyHostToDevice, c->stream));
+  double* s0 = c->d_shift;        // shift of the ping-pong field
+  double* s1 = c->d_shift + B;    // shift of u
+  hipLaunchKernelGGL(fe::fill_f64, dim3(ceil_div(B, 64)), dim3(64), 0, c->stream, s1, B, 0.0);
+  FE_HIP(hipGetLastError());
+  void* A = c->d_pingpong;
+
+  // pairs of steps u -> A -> u, replayed from a captured graph
+  const int npairs = nsteps / 2;
+  const int gpairs = std::min(npairs, 16);
+  if (gpairs > 0) {
+    GraphKey key{u, tau, gpairs, c->variant, c->lz};
+    auto it = c->graphs.find(key);
+    hipGraphExec_t exec = nullptr;
+    if (it == c->graphs.end()) {
+      hipGraph_t graph = nullptr;
+      FE_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      int rc = FE_OK;
+      for (int i = 0; i < gpairs && rc == FE_OK; ++i) {
+        rc = step_once(c, c->cap_stream, u, A, s1, s0, tau);
+        if (rc == FE_OK) rc = step_once(c, c->cap_stream, A, u, s0, s1, tau);
+      }
+      hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
+      if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (ec != hipSuccess) return set_error(FE_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+      hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) return set_error(FE_EHIP, "graph instantiate failed: %s", hipGetErrorString(ei));
+      if (c->graphs.size() > 16) drop_graphs(c);
+      c->graphs[key] = exec;
+    } else {
+      exec = it->second;
+    }
+    for (int r = 0; r < npairs / gpairs; ++r) FE_HIP(hipGraphLaunch(exec, c->stream));
+    for (int i = 0; i < npairs % gpairs; ++i) {
+      int rc = step_once(c, c->stream, u, A, s1, s0, tau);
+      if (rc == FE_OK) rc = step_once(c, c->stream, A, u, s0, s1, tau);
+      if (rc) return rc;
+    }
+  }
+  const size_t per_inst = (size_t)c->grid.nx * c->grid.ny * c->grid.nz;
+  const int nblk = (int)std::min<size_t>((field_elems(c->grid) + 255) / 256, 65536);
+  if (nsteps % 2) {
+    int rc = step_once(c, c->stream, u, A, s1, s0, tau);
+    if (rc) return rc;
+    if (c->grid.dtype == FE_F32)
+      hipLaunchKernelGGL(fe::add_shift<float>, dim3(nblk), dim3(256), 0, c->stream, (const float*)A, (float*)u, s0,
+                         per_inst, B);
+    else
+      hipLaunchKernelGGL(fe::add_shift<double>, dim3(nblk), dim3(256), 0, c->stream, (const double*)A, (double*)u,
+                         s0, per_inst, B);
+  } else {
+    if (c->grid.dtype == FE_F32)
+      hipLaunchKernelGGL(fe::add_shift<float>, dim3(nblk), dim3(256), 0, c->stream, (const float*)u, (float*)u, s1,
+                         per_inst, B);
+    else
+      hipLaunchKernelGGL(fe::add_shift<double>, dim3(nblk), dim3(256), 0, c->stream, (const double*)u, (double*)u,
+                         s1, per_inst, B);
+  }
+  FE_HIP(hipGetLastError());
+  return copy_energy_out(c, energy);
+}
+
+int fe_num_variants(void) { return (int)variants().size(); }
+
+int fe_variant_info(int variant, int* tile_x, int* tile_y, int* threads, int* dtype_mask) {
+  if (variant < 0 || variant >= (int)variants().size()) return set_error(FE_EINVAL, "no variant %d", variant);
+  const Variant& v = variants()[variant];
+  if (tile_x) *tile_x = v.tx;
+  if (tile_y) *tile_y = v.ty;
+  if (threads) *threads = v.nt;
+  if (dtype_mask) *dtype_mask = v.dtype_mask;
+  return FE_OK;
+}
+
+int fe_set_launch(fe_ctx* c, int variant, int z_chunk) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!variant_ok(variant, c->grid.dtype))
+    return set_error(FE_EINVAL, "variant %d does not exist or does not support this dtype", variant);
+  if (z_chunk < 0) return set_error(FE_EINVAL, "z_chunk must be >= 0");
+  c->variant = variant;
+  c->lz = z_chunk;
+  return FE_OK;
+}
+
+int fe_get_launch(const fe_ctx* c, int* variant, int* z_chunk) {
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (variant) *variant = c->variant;
+  if (z_chunk) *z_chunk = geometry(c, c->variant, c->lz).lz;
+  return FE_OK;
+}
+
+int fe_autotune(fe_ctx* c, const void* u, void* g, int iters, double* best_us) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!u || !g || u == g) return set_error(FE_EINVAL, "u and g must be distinct device fields");
+  if (iters < 1) return set_error(FE_EINVAL, "iters must be >= 1");
+  DeviceGuard dg(c->device);
+  const int keep_v = c->variant, keep_lz = c->lz;
+  hipEvent_t e0, e1;
+  FE_HIP(hipEventCreate(&e0));
+  FE_HIP(hipEventCreate(&e1));
+  double best = 1e300;
+  int best_v = keep_v, best_lz = keep_lz;
+  const int lzs[] = {4, 8, 16, 32, 64};
+  int rc = FE_OK;
+  for (int v = 0; v < (int)variants().size() && rc == FE_OK; ++v) {
+    if (!variant_ok(v, c->grid.dtype)) continue;
+    const Variant& x = variants()[v];
+    if (x.tx > 2 * c->grid.nx || x.ty > 2 * c->grid.ny) continue;
+    for (int lz : lzs) {
+      if (lz > c->grid.nz) continue;
+      c->variant = v;
+      c->lz = lz;
+      rc = fe_energy_grad_async(c, u, g, nullptr);   // warm-up
+      if (rc) break;
+      if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = set_error(FE_EHIP, "hipEventRecord failed"); break; }
+      for (int i = 0; i < iters && rc == FE_OK; ++i) rc = fe_energy_grad_async(c, u, g, nullptr);
+      if (rc) break;
+      if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = set_error(FE_EHIP, "event timing failed");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const double us = 1000.0 * ms / iters;
+      if (us < best) {
+        best = us;
+        best_v = v;
+        best_lz = lz;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->variant = best_v;
+  c->lz = best_lz;
+  if (rc) return rc;
+  if (best_us) *best_us = best;
+  return FE_OK;
+}
+
+void fe_destroy(fe_ctx* c) {
+  if (!c) return;
+  DeviceGuard dg(c->device);
+  drop_graphs(c);
+  if (c->d_prm) (void)hipFree(c->d_prm);
+  if (c->d_partials) (void)hipFree(c->d_partials);
+  if (c->d_energy) (void)hipFree(c->d_energy);
+  if (c->d_mass) (void)hipFree(c->d_mass);
+  if (c->d_shift) (void)hipFree(c->d_shift);
+  if (c->d_pingpong) (void)hipFree(c->d_pingpong);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  delete c;
+}
+
+const char* fe_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

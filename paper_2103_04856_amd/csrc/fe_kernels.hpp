@@ -1,0 +1,357 @@
+// HIP kernels for gfx950: the fused energy + gradient sweep, the energy-only
+// sweep, the deterministic per-instance finalisation and the step helpers.
+//
+// Data layout: fields are [batch][nz][ny][nx], x fastest. A block owns an
+// interior tile of TX x TY columns and a chunk of lz consecutive z planes of
+// one instance, and streams through the planes (2.5-D blocking):
+//
+//   * u is staged in LDS as a rolling window of three planes, each with a
+//     periodic halo of 2 in x and y (the gather needs the adjoint on a ring
+//     of one voxel, and the adjoint at a voxel needs the 19-point stencil);
+//   * for every plane the block computes forward + adjoint on the interior
+//     plus a one-voxel ring (the Hessian is recomputed, never stored) and
+//     parks the ten scaled adjoint values in LDS;
+//   * the transposed stencils are applied as adds: in-plane terms from LDS,
+//     terms from the planes above and below through a three-plane register
+//     pipeline, so each output voxel is written exactly once;
+//   * sums (energy, mass of the stepped field) are accumulated per thread in
+//     FP64, reduced with wavefront shuffles and one LDS pass, and written as
+//     one partial per block; a second tiny kernel adds the partials of each
+//     instance in a fixed order (deterministic, no atomics).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fe_voxel.hpp"
+
+namespace fe {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int wrap_index(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+// Block-wide sum of two doubles; result valid in thread 0. Fixed reduction
+// order, so repeated runs give identical bits.
+template <int NT>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double (*sred)[2]) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, kWave);
+    b += __shfl_xor(b, off, kWave);
+  }
+  const int lane = threadIdx.x % kWave;
+  const int wv = threadIdx.x / kWave;
+  if (lane == 0) {
+    sred[wv][0] = a;
+    sred[wv][1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / kWave; ++i) {
+      sa += sred[i][0];
+      sb += sred[i][1];
+    }
+    a = sa;
+    b = sb;
+  }
+}
+
+// Linear block id -> logical tile, so that the blocks dispatched to one XCD
+// (hardware round-robins consecutive ids over the 8 XCDs) form a contiguous
+// range of neighbouring tiles that share halo lines in that XCD's L2.
+__device__ __forceinline__ int xcd_logical_block(int linear, int total) {
+  constexpr int kXcd = 8;
+  if (total % kXcd != 0) return linear;
+  return (linear % kXcd) * (total / kXcd) + linear / kXcd;
+}
+
+template <typename T>
+struct SweepArgs {
+  const T* src;                 // [batch][nz][ny][nx]
+  T* dst;                       // gradient, or stepped field (STEP); unused by the energy sweep
+  const InstParams<T>* prm;     // [batch]
+  const double* shift_in;       // STEP: per-instance uniform shift of src (nullable)
+  double* partials;             // [batch][blocks_per_instance][2]
+  StencilConsts<T> k;
+  T tau;                        // STEP: step size
+  int nx, ny, nz;
+  int ntx, nty, nzc, lz;        // tiles in x and y, z chunks, planes per chunk
+  int batch;
+};
+
+// Fused forward + adjoint + transposed-stencil gather.
+//   STEP = false: dst = dF_h/du (h^3 included); partial[1] = sum of src.
+//   STEP = true : dst = u - tau dF_h/du with u = src + shift_in[b];
+//                 partial[1] = sum of dst.
+// partial[0] = sum of the energy density over the block's output voxels.
+template <typename T, int TX, int TY, int NT, bool STEP>
+__global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
+  constexpr int UX = TX + 4, UY = TY + 4;      // u window: interior + halo 2
+  constexpr int RX = TX + 2, RY = TY + 2;      // adjoint ring: interior + 1
+  constexpr int NU = (UX * UY + NT - 1) / NT;  // u elements loaded per thread per plane
+  constexpr int NR = (RX * RY + NT - 1) / NT;  // ring voxels per thread
+  constexpr int NO = TX * TY / NT;             // output voxels per thread
+  static_assert(TX * TY % NT == 0, "interior tile must be a multiple of the block");
+  enum { UB = 0, GX, GY, GZ, TXX, TYY, TZZ, TXY, TXZ, TYZ, NFIELD };
+
+  __shared__ T su[3][UY * UX];
+  __shared__ T sx[NFIELD][RY * RX];
+  __shared__ double sred[NT / kWave][2];
+
+  const int tid = threadIdx.x;
+  const int per_inst = a.ntx * a.nty * a.nzc;
+  const int total = per_inst * a.batch;
+  const int logical = xcd_logical_block(blockIdx.x, total);
+  const int inst = logical / per_inst;
+  int rem = logical - inst * per_inst;
+  const int tx = rem % a.ntx;
+  rem /= a.ntx;
+  const int ty = rem % a.nty;
+  const int chunk = rem / a.nty;
+  const int x0 = tx * TX, y0 = ty * TY, k0 = chunk * a.lz;
+  const int kend = min(k0 + a.lz, a.nz);       // output planes [k0, kend)
+
+  const size_t plane = (size_t)a.nx * a.ny;
+  const T* srcb = a.src + (size_t)inst * a.nz * plane;
+  T* dstb = a.dst + (size_t)inst * a.nz * plane;
+  const InstParams<T> prm = a.prm[inst];
+  const T shift = (STEP && a.shift_in) ? T(a.shift_in[inst]) : T(0);
+
+  // In-plane offsets of the u window, computed once (periodic wrap in x, y).
+  int uoff[NU];
+#pragma unroll
+  for (int j = 0; j < NU; ++j) {
+    const int e = tid + j * NT;
+    const int ex = e % UX, ey = e / UX;
+    uoff[j] = (e < UX * UY) ? wrap_index(y0 - 2 + ey, a.ny) * a.nx + wrap_index(x0 - 2 + ex, a.nx) : 0;
+  }
+  auto load_plane = [&](int p, int slot) {
+    const T* sp = srcb + (size_t)wrap_index(p, a.nz) * plane;
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      const int e = tid + j * NT;
+      if (e < UX * UY) su[slot][e] = sp[uoff[j]] + shift;
+    }
+  };
+
+  double acc_f = 0.0, acc_m = 0.0;
+  T c_prev[NO], l_prev[NO], l_pp[NO];
+#pragma unroll
+  for (int j = 0; j < NO; ++j) c_prev[j] = l_prev[j] = l_pp[j] = T(0);
+
+  // planes k0-2 and k0-1 -> slots 0 and 1; plane p lives in slot (p - k0 + 2) % 3
+  load_plane(k0 - 2, 0);
+  load_plane(k0 - 1, 1);
+
+  const int nit = (kend - k0) + 2;             // forward planes k0-1 .. kend
+  for (int it = 0; it < nit; ++it) {
+    const int p = k0 - 1 + it;
+    const int sm = it % 3, sc = (it + 1) % 3, sp = (it + 2) % 3;   // slots of p-1, p, p+1
+    load_plane(p + 1, sp);
+    __syncthreads();
+
+    // ---- forward + adjoint on the ring-extended plane p ----
+    const bool out_plane = (p >= k0) && (p < kend);
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      const int v = tid + j * NT;
+      if (v < RX * RY) {
+        const int rx = v % RX, ry = v / RX;
+        const int c = (ry + 1) * UX + rx + 1;
+        const T* pc = su[sc] + c;
+        const T* pm = su[sm] + c;
+        const T* pp = su[sp] + c;
+        Stencil19<T> s;
+        s.c = pc[0];
+        s.xm = pc[-1]; s.xp = pc[1]; s.ym = pc[-UX]; s.yp = pc[UX]; s.zm = pm[0]; s.zp = pp[0];
+        s.xpyp = pc[UX + 1]; s.xpym = pc[1 - UX]; s.xmyp = pc[UX - 1]; s.xmym = pc[-UX - 1];
+        s.xpzp = pp[1]; s.xpzm = pm[1]; s.xmzp = pp[-1]; s.xmzm = pm[-1];
+        s.ypzp = pp[UX]; s.ypzm = pm[UX]; s.ymzp = pp[-UX]; s.ymzm = pm[-UX];
+        VoxelAdjoint<T> ad;
+        const T f = voxel_density_adjoint(s, prm, a.k, ad);
+        sx[UB][v] = ad.ub;
+        sx[GX][v] = ad.gx; sx[GY][v] = ad.gy; sx[GZ][v] = ad.gz;
+        sx[TXX][v] = ad.txx; sx[TYY][v] = ad.tyy; sx[TZZ][v] = ad.tzz;
+        sx[TXY][v] = ad.txy; sx[TXZ][v] = ad.txz; sx[TYZ][v] = ad.tyz;
+        const bool interior = rx >= 1 && rx <= TX && ry >= 1 && ry <= TY &&
+                              x0 + rx - 1 < a.nx && y0 + ry - 1 < a.ny;
+        if (out_plane && interior) acc_f += double(f);
+      }
+    }
+    __syncthreads();
+
+    // ---- transposed stencils on the interior ----
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      const int w = tid + j * NT;
+      const int ix = w % TX, iy = w / TX;
+      const int v = (iy + 1) * RX + ix + 1;
+      const T d = (sx[TXZ][v + 1] - sx[TXZ][v - 1]) + (sx[TYZ][v + RX] - sx[TYZ][v - RX]);
+      const T tzz = sx[TZZ][v], gz = sx[GZ][v];
+      const T up = tzz - gz + d;     // what plane p adds to output plane p-1
+      const T lo = tzz + gz - d;     // what plane p adds to output plane p+1
+      if (it >= 2) {
+        const int po = p - 1;
+        const int gx = x0 + ix, gy = y0 + iy;
+        if (gx < a.nx && gy < a.ny) {
+          const T g = c_prev[j] + up + l_pp[j];
+          const size_t idx = (size_t)po * plane + (size_t)gy * a.nx + gx;
+          if (STEP) {
+            const T un = su[sm][(iy + 2) * UX + ix + 2] - a.tau * g;
+            dstb[idx] = un;
+            acc_m += double(un);
+          } else {
+            dstb[idx] = g;
+            acc_m += double(su[sm][(iy + 2) * UX + ix + 2]);
+          }
+        }
+      }
+      const T tc = sx[TXX][v], tyy = sx[TYY][v];
+      const T cin = (sx[UB][v] - (tzz + tzz) - (tc + tc) - (tyy + tyy))
+                    - (sx[GX][v + 1] - sx[GX][v - 1]) - (sx[GY][v + RX] - sx[GY][v - RX])
+                    + (sx[TXX][v + 1] + sx[TXX][v - 1]) + (sx[TYY][v + RX] + sx[TYY][v - RX])
+                    + ((sx[TXY][v + RX + 1] - sx[TXY][v - RX + 1]) - (sx[TXY][v + RX - 1] - sx[TXY][v - RX - 1]));
+      l_pp[j] = l_prev[j];
+      l_prev[j] = lo;
+      c_prev[j] = cin;
+    }
+    // the next iteration overwrites the slot of plane p-1 and the adjoint planes
+    __syncthreads();
+  }
+
+  block_sum2<NT>(acc_f, acc_m, sred);
+  if (tid == 0) {
+    double* out = a.partials + ((size_t)inst * per_inst + (logical - inst * per_inst)) * 2;
+    out[0] = acc_f;
+    out[1] = acc_m;
+  }
+}
+
+// Forward only: per-block sums of the energy density and of u.
+template <typename T, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void energy_sweep(SweepArgs<T> a) {
+  constexpr int UX = TX + 2, UY = TY + 2;      // halo 1 suffices for the forward stencil
+  constexpr int NU = (UX * UY + NT - 1) / NT;
+  constexpr int NO = TX * TY / NT;
+  static_assert(TX * TY % NT == 0, "interior tile must be a multiple of the block");
+
+  __shared__ T su[3][UY * UX];
+  __shared__ double sred[NT / kWave][2];
+
+  const int tid = threadIdx.x;
+  const int per_inst = a.ntx * a.nty * a.nzc;
+  const int total = per_inst * a.batch;
+  const int logical = xcd_logical_block(blockIdx.x, total);
+  const int inst = logical / per_inst;
+  int rem = logical - inst * per_inst;
+  const int tx = rem % a.ntx;
+  rem /= a.ntx;
+  const int ty = rem % a.nty;
+  const int chunk = rem / a.nty;
+  const int x0 = tx * TX, y0 = ty * TY, k0 = chunk * a.lz;
+  const int kend = min(k0 + a.lz, a.nz);
+
+  const size_t plane = (size_t)a.nx * a.ny;
+  const T* srcb = a.src + (size_t)inst * a.nz * plane;
+  const InstParams<T> prm = a.prm[inst];
+
+  int uoff[NU];
+#pragma unroll
+  for (int j = 0; j < NU; ++j) {
+    const int e = tid + j * NT;
+    const int ex = e % UX, ey = e / UX;
+    uoff[j] = (e < UX * UY) ? wrap_index(y0 - 1 + ey, a.ny) * a.nx + wrap_index(x0 - 1 + ex, a.nx) : 0;
+  }
+  auto load_plane = [&](int p, int slot) {
+    const T* sp = srcb + (size_t)wrap_index(p, a.nz) * plane;
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      const int e = tid + j * NT;
+      if (e < UX * UY) su[slot][e] = sp[uoff[j]];
+    }
+  };
+
+  double acc_f = 0.0, acc_m = 0.0;
+  load_plane(k0 - 1, 0);
+  load_plane(k0, 1);
+  for (int it = 0; it < kend - k0; ++it) {
+    const int p = k0 + it;
+    const int sm = it % 3, sc = (it + 1) % 3, sp = (it + 2) % 3;
+    load_plane(p + 1, sp);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      const int w = tid + j * NT;
+      const int ix = w % TX, iy = w / TX;
+      const int c = (iy + 1) * UX + ix + 1;
+      const T* pc = su[sc] + c;
+      const T* pm = su[sm] + c;
+      const T* pp = su[sp] + c;
+      Stencil19<T> s;
+      s.c = pc[0];
+      s.xm = pc[-1]; s.xp = pc[1]; s.ym = pc[-UX]; s.yp = pc[UX]; s.zm = pm[0]; s.zp = pp[0];
+      s.xpyp = pc[UX + 1]; s.xpym = pc[1 - UX]; s.xmyp = pc[UX - 1]; s.xmym = pc[-UX - 1];
+      s.xpzp = pp[1]; s.xpzm = pm[1]; s.xmzp = pp[-1]; s.xmzm = pm[-1];
+      s.ypzp = pp[UX]; s.ypzm = pm[UX]; s.ymzp = pp[-UX]; s.ymzm = pm[-UX];
+      const T f = voxel_density(s, prm, a.k);
+      if (x0 + ix < a.nx && y0 + iy < a.ny) {
+        acc_f += double(f);
+        acc_m += double(s.c);
+      }
+    }
+    __syncthreads();
+  }
+
+  block_sum2<NT>(acc_f, acc_m, sred);
+  if (tid == 0) {
+    double* out = a.partials + ((size_t)inst * per_inst + (logical - inst * per_inst)) * 2;
+    out[0] = acc_f;
+    out[1] = acc_m;
+  }
+}
+
+// One block per instance: add the per-block partials in a fixed order.
+//   energy[b] = h3 * sum partial[0];  STEP: shift_out[b] = mass[b] - sum partial[1] / nvox.
+template <bool STEP>
+__global__ __launch_bounds__(256) void finalize_sums(const double* __restrict__ partials, int nblk,
+                                                     double h3, double* __restrict__ energy,
+                                                     const double* __restrict__ mass, double inv_nvox,
+                                                     double* __restrict__ shift_out) {
+  __shared__ double sred[256 / kWave][2];
+  const int b = blockIdx.x;
+  const double* pp = partials + (size_t)b * nblk * 2;
+  double sf = 0.0, sm = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) {
+    sf += pp[2 * i];
+    sm += pp[2 * i + 1];
+  }
+  block_sum2<256>(sf, sm, sred);
+  if (threadIdx.x == 0) {
+    if (energy) energy[b] = h3 * sf;
+    if (STEP) shift_out[b] = mass[b] - sm * inv_nvox;
+  }
+}
+
+// dst[b][i] = src[b][i] + shift[b] (src may equal dst).
+template <typename T>
+__global__ __launch_bounds__(256) void add_shift(const T* src, T* dst, const double* __restrict__ shift,
+                                                 size_t per_inst, int batch) {
+  const size_t n = per_inst * (size_t)batch;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int b = (int)(i / per_inst);
+    dst[i] = src[i] + T(shift[b]);
+  }
+}
+
+__global__ __launch_bounds__(64) void fill_f64(double* p, int n, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace fe

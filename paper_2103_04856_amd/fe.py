@@ -1,0 +1,260 @@
+"""Python binding of the C ABI in include/fe.h (argument marshalling only).
+
+Every step of the energy, gradient and descent runs in the HIP kernels of
+libfe.so; this module only checks tensors, passes device pointers and the
+current torch stream, and wraps the entry points for autograd. There is no
+CPU path: the library must be built (python -m paper_2103_04856_amd.build) and
+fields must live on a ROCm device.
+
+Fields are torch tensors of shape [batch, nz, ny, nx] (or [nz, ny, nx] for a
+single instance), contiguous, float32 or float64, x fastest.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfe.so")
+
+FE_F32, FE_F64 = 0, 1
+FE_OK, FE_EINVAL, FE_EHIP, FE_ENOMEM, FE_ENONFINITE = 0, -1, -2, -3, -4
+_CODES = {FE_EINVAL: "FE_EINVAL", FE_EHIP: "FE_EHIP", FE_ENOMEM: "FE_ENOMEM", FE_ENONFINITE: "FE_ENONFINITE"}
+
+
+class FeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class FeGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("batch", ctypes.c_int), ("h", ctypes.c_double), ("dtype", ctypes.c_int)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int)
+
+# name -> (restype, argtypes); the full set of entry points of include/fe.h
+SIGNATURES = {
+    "fe_create": (ctypes.c_int, [ctypes.POINTER(FeGrid), _DP, _DP, _P, ctypes.POINTER(_P)]),
+    "fe_set_params": (ctypes.c_int, [_P, _DP, _DP]),
+    "fe_set_stream": (ctypes.c_int, [_P, _P]),
+    "fe_energy": (ctypes.c_int, [_P, _P, _DP]),
+    "fe_energy_grad": (ctypes.c_int, [_P, _P, _P, _DP]),
+    "fe_energy_grad_async": (ctypes.c_int, [_P, _P, _P, _P]),
+    "fe_step": (ctypes.c_int, [_P, _P, _DP, ctypes.c_double, ctypes.c_int, _DP]),
+    "fe_num_variants": (ctypes.c_int, []),
+    "fe_variant_info": (ctypes.c_int, [ctypes.c_int, _IP, _IP, _IP, _IP]),
+    "fe_set_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
+    "fe_get_launch": (ctypes.c_int, [_P, _IP, _IP]),
+    "fe_autotune": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _DP]),
+    "fe_destroy": (None, [_P]),
+    "fe_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Load libfe.so (once). Raises if the library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2103_04856_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != FE_OK:
+        raise FeError(rc, lib().fe_last_error().decode())
+
+
+def _dbl(values):
+    arr = (ctypes.c_double * len(values))(*[float(v) for v in values])
+    return arr
+
+
+def variants():
+    """[(tile_x, tile_y, threads, dtype_mask)] of every launch variant."""
+    L = lib()
+    out = []
+    for v in range(L.fe_num_variants()):
+        a, b, c, d = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(L.fe_variant_info(v, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+        out.append((a.value, b.value, c.value, d.value))
+    return out
+
+
+def _torch_dtype(fe_dtype):
+    return torch.float32 if fe_dtype == FE_F32 else torch.float64
+
+
+class FeContext:
+    """One set of B independent problems on an nz x ny x nx periodic grid.
+
+    eps: float or [B]; coeffs: (a20, a11, a02, a10, a01, a00) or [B][6]
+    (the coefficient order of Sec. 3.2). dtype: torch.float32 or torch.float64.
+    """
+
+    def __init__(self, shape, h, eps, coeffs, dtype=torch.float32, device=None):
+        if len(shape) == 3:
+            shape = (1, *shape)
+        B, nz, ny, nx = (int(s) for s in shape)
+        self.shape = (B, nz, ny, nx)
+        self.h = float(h)
+        self.dtype = dtype
+        if dtype not in (torch.float32, torch.float64):
+            raise TypeError("dtype must be torch.float32 or torch.float64")
+        self.device = (torch.device("cuda", torch.cuda.current_device()) if device is None
+                       else torch.device(device))
+        eps_l, coeff_l = self._param_lists(eps, coeffs, B)
+        grid = FeGrid(nx, ny, nz, B, self.h, FE_F32 if dtype == torch.float32 else FE_F64)
+        handle = _P()
+        with torch.cuda.device(self.device):
+            _check(lib().fe_create(ctypes.byref(grid), _dbl(eps_l), _dbl(coeff_l),
+                                   _P(torch.cuda.current_stream().cuda_stream), ctypes.byref(handle)))
+        self._h = handle
+        self.eps, self.coeffs = eps_l, [coeff_l[6 * b:6 * b + 6] for b in range(B)]
+
+    @staticmethod
+    def _param_lists(eps, coeffs, B):
+        if isinstance(eps, (int, float)):
+            eps = [float(eps)] * B
+        eps = [float(e) for e in eps]
+        flat = [float(c) for c in torch.as_tensor(coeffs, dtype=torch.float64).reshape(-1).tolist()]
+        if len(flat) == 6:
+            flat = flat * B
+        if len(eps) != B or len(flat) != 6 * B:
+            raise ValueError(f"need {B} eps values and {B} x 6 coefficients")
+        return eps, flat
+
+    # -- lifetime ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fe_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers -------------------------------------------------------------
+    def _field(self, t, name):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must be a device tensor (there is no CPU path)")
+        if t.dtype != self.dtype:
+            raise TypeError(f"{name} has dtype {t.dtype}, context expects {self.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        shp = tuple(t.shape)
+        if shp != self.shape and not (self.shape[0] == 1 and shp == self.shape[1:]):
+            raise ValueError(f"{name} has shape {shp}, context expects {self.shape}")
+        return _P(t.data_ptr())
+
+    def _sync_stream(self):
+        _check(lib().fe_set_stream(self._h, _P(torch.cuda.current_stream(self.device).cuda_stream)))
+
+    # -- API -------------------------------------------------------------------
+    def set_params(self, eps, coeffs):
+        eps_l, coeff_l = self._param_lists(eps, coeffs, self.shape[0])
+        self._sync_stream()
+        _check(lib().fe_set_params(self._h, _dbl(eps_l), _dbl(coeff_l)))
+        self.eps, self.coeffs = eps_l, [coeff_l[6 * b:6 * b + 6] for b in range(self.shape[0])]
+
+    def energy(self, u):
+        """F_h(u_b) for every instance, as a float64 CPU tensor [B] (synchronises)."""
+        out = (ctypes.c_double * self.shape[0])()
+        self._sync_stream()
+        _check(lib().fe_energy(self._h, self._field(u, "u"), out))
+        return torch.tensor(list(out), dtype=torch.float64)
+
+    def energy_grad(self, u, g=None):
+        """(F_h [B] float64 on CPU, g = dF_h/du); synchronises."""
+        g = torch.empty_like(u) if g is None else g
+        out = (ctypes.c_double * self.shape[0])()
+        self._sync_stream()
+        _check(lib().fe_energy_grad(self._h, self._field(u, "u"), self._field(g, "g"), out))
+        return torch.tensor(list(out), dtype=torch.float64), g
+
+    def energy_grad_async(self, u, g=None, energy_out=None, with_grad=True):
+        """Stream-ordered, no sync: (energies as a float64 device tensor [B], g or None)."""
+        if with_grad and g is None:
+            g = torch.empty_like(u)
+        if energy_out is None:
+            energy_out = torch.empty(self.shape[0], dtype=torch.float64, device=u.device)
+        self._sync_stream()
+        _check(lib().fe_energy_grad_async(self._h, self._field(u, "u"),
+                                          self._field(g, "g") if with_grad else _P(0),
+                                          _P(energy_out.data_ptr())))
+        return energy_out, g
+
+    def step(self, u, mass, tau, nsteps):
+        """nsteps mass-projected descent steps in place on u; returns F_h before the last step."""
+        B = self.shape[0]
+        if isinstance(mass, (int, float)):
+            mass = [float(mass)] * B
+        if len(mass) != B:
+            raise ValueError(f"need {B} mass values")
+        out = (ctypes.c_double * B)()
+        self._sync_stream()
+        _check(lib().fe_step(self._h, self._field(u, "u"), _dbl(mass), float(tau), int(nsteps), out))
+        return torch.tensor(list(out), dtype=torch.float64)
+
+    def set_launch(self, variant, z_chunk=0):
+        _check(lib().fe_set_launch(self._h, int(variant), int(z_chunk)))
+
+    def get_launch(self):
+        v, z = ctypes.c_int(), ctypes.c_int()
+        _check(lib().fe_get_launch(self._h, ctypes.byref(v), ctypes.byref(z)))
+        return v.value, z.value
+
+    def autotune(self, u, g=None, iters=10):
+        """Time every launch variant on u and keep the fastest; returns (variant, z_chunk, us)."""
+        g = torch.empty_like(u) if g is None else g
+        best = ctypes.c_double()
+        self._sync_stream()
+        _check(lib().fe_autotune(self._h, self._field(u, "u"), self._field(g, "g"), int(iters),
+                                 ctypes.byref(best)))
+        v, z = self.get_launch()
+        return v, z, best.value
+
+
+class FeEnergy(torch.autograd.Function):
+    """E = F_h(u) per instance (float64 [B]); backward recomputes the Hessian and
+    applies the hand-written adjoint kernel: dL/du = sum_b dL/dE_b dF_h/du_b."""
+
+    @staticmethod
+    def forward(ctx, u, fe):
+        E, _ = fe.energy_grad_async(u, with_grad=False)
+        ctx.fe = fe
+        ctx.save_for_backward(u)
+        return E
+
+    @staticmethod
+    def backward(ctx, gE):
+        (u,) = ctx.saved_tensors
+        _, g = ctx.fe.energy_grad_async(u.contiguous())
+        scale = gE.to(u.dtype)
+        if u.dim() == 4:
+            scale = scale.view(-1, 1, 1, 1)
+        else:
+            scale = scale.reshape(())
+        return g * scale, None
+
+
+def feps(u, fe):
+    """Differentiable F_h(u) through the HIP kernels (see FeEnergy)."""
+    return FeEnergy.apply(u, fe)

@@ -1,0 +1,210 @@
+"""Parity of the HIP energy and gradient with the FP64 oracle, through the C ABI.
+
+Sizes: the small cases span several tiles with ragged tails; the full-size
+cases use the exact launch configuration of the benchmark and check sampled
+outputs (per-voxel gradients from local periodic patches, the energy from
+slab-wise oracle densities).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fe_oracle as fo
+from paper_2103_04856_amd import fe, inputs
+
+from gpu_helpers import (ALL_TERMS, ASYM_C3, HELFRICH_SC, TOL, WILLMORE_QUARTER, check_energy_grad, log,
+                         oracle_input, rel_l2, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+def test_device_present():
+    assert torch.cuda.is_available(), "no ROCm device visible"
+    log(f"device: {torch.cuda.get_device_name(0)}")
+
+
+# --------------------------------------------------------------------------
+# Small and medium grids: the whole field against the oracle
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_noise_32cubed_willmore(dtype):
+    """32^3 periodic grid, h = 1/32, u0 ~ U(-1,1) (seed 1001), eps = 2h, p = (k1+k2)^2/4."""
+    n = 32
+    h = 1.0 / n
+    log(f"case noise32 {dtype}")
+    e, g = check_energy_grad(inputs.uniform_noise(n, 1001), h, 2 * h, WILLMORE_QUARTER, dtype)
+    log(f"  energy rel {e[0]:.2e}  grad rel L2 {g[0]:.2e}")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_noisy_sphere_64cubed(dtype):
+    """64^3, u0 = tanh sphere of radius 0.3 + N(0, 0.01^2) noise (seed 1002), eps = 1.5h."""
+    n = 64
+    h = 1.0 / n
+    log(f"case sphere64 {dtype}")
+    u = inputs.noisy_sphere(n, 0.3, 1.5 * h, 0.01, 1002)
+    e, g = check_energy_grad(u, h, 1.5 * h, WILLMORE_QUARTER, dtype)
+    log(f"  energy rel {e[0]:.2e}  grad rel L2 {g[0]:.2e}")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("a", [ASYM_C3, HELFRICH_SC, ALL_TERMS], ids=["asym", "helfrich", "allterms"])
+def test_noise_48cubed_every_term(dtype, a):
+    n = 48
+    h = 1.0 / n
+    log(f"case noise48 {a} {dtype}")
+    e, g = check_energy_grad(inputs.uniform_noise(n, 1003), h, 2 * h, a, dtype)
+    log(f"  energy rel {e[0]:.2e}  grad rel L2 {g[0]:.2e}")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_ragged_grids_every_variant(dtype):
+    """Non-cubic grids whose sizes are no multiple of any tile, in every launch variant
+    and several z-chunk lengths (partial tiles, wrap of the halo over the grid)."""
+    shapes = [(9, 13, 20), (5, 7, 3), (17, 6, 70), (2, 3, 4), (1, 1, 5)]
+    for vi, (tx, ty, nt, mask) in enumerate(fe.variants()):
+        if not mask & (2 if dtype == torch.float64 else 1):
+            continue
+        for shp in shapes:
+            for zc in (0, 1, 4):
+                rng = np.random.default_rng(sum(shp) + vi)
+                u = rng.uniform(-1, 1, size=shp)
+                log(f"case ragged variant={vi} ({tx}x{ty}/{nt}) shape={shp} zc={zc} {dtype}")
+                check_energy_grad(u, 0.1, 0.2, ALL_TERMS, dtype, variant=vi, z_chunk=zc)
+
+
+def test_batched_instances_with_own_parameters():
+    """B = 6 instances of 24^3 with different eps, coefficients and fields in one launch."""
+    n, B = 24, 6
+    h = 1.0 / n
+    coeffs, _ = inputs.random_instance_table(B, 4999)
+    U = np.stack([inputs.uniform_noise(n, 4000 + b) for b in range(B)])
+    eps = [2 * h * (1 + 0.1 * b) for b in range(B)]
+    for dtype in (torch.float64, torch.float32):
+        log(f"case batched B={B} {dtype}")
+        check_energy_grad(U, h, eps, coeffs, dtype)
+
+
+def test_batched_equals_single_bitwise():
+    """One batched launch gives the same bits as one launch per instance."""
+    n, B = 32, 4
+    h = 1.0 / n
+    coeffs, _ = inputs.random_instance_table(B, 4999)
+    U = np.stack([inputs.uniform_noise(n, 4000 + b) for b in range(B)])
+    for dtype in (torch.float64, torch.float32):
+        ctx = fe.FeContext(U.shape, h, 2 * h, coeffs, dtype=dtype)
+        ud = to_dev(U, dtype)
+        E, g = ctx.energy_grad(ud)
+        for b in range(B):
+            c1 = fe.FeContext((1, n, n, n), h, 2 * h, coeffs[b], dtype=dtype)
+            c1.set_launch(*ctx.get_launch())
+            Eb, gb = c1.energy_grad(ud[b:b + 1].contiguous())
+            assert Eb[0].item() == E[b].item()
+            assert torch.equal(gb[0], g[b])
+
+
+def test_repeated_calls_are_bitwise_deterministic():
+    n = 40
+    u = to_dev(inputs.uniform_noise(n, 7), torch.float32)
+    ctx = fe.FeContext(u.shape, 1 / n, 2 / n, ASYM_C3, dtype=torch.float32)
+    E1, g1 = ctx.energy_grad(u)
+    E2, g2 = ctx.energy_grad(u)
+    assert torch.equal(E1, E2) and torch.equal(g1, g2)
+
+
+def test_nonfinite_energy_is_reported():
+    n = 16
+    u = inputs.uniform_noise(n, 3)
+    u[3, 4, 5] = np.nan
+    ctx = fe.FeContext((1, n, n, n), 1 / n, 2 / n, WILLMORE_QUARTER, dtype=torch.float64)
+    with pytest.raises(fe.FeError) as ei:
+        ctx.energy_grad(to_dev(u, torch.float64))
+    assert ei.value.code == fe.FE_ENONFINITE
+
+
+# --------------------------------------------------------------------------
+# Full sizes, in the benchmark's launch configuration
+# --------------------------------------------------------------------------
+
+def _patch(U, z, y, x, r=4):
+    """Periodic (2r+1)^3 patch of U centred at (z, y, x)."""
+    idx = [np.arange(c - r, c + r + 1) % n for c, n in zip((z, y, x), U.shape)]
+    return U[np.ix_(*idx)]
+
+
+def _sampled_gradient_check(Un, gn, h, eps, a, tol, nsamp=48, seed=0):
+    """The gradient at a voxel depends on u within +-2 per axis: the oracle on a
+    9^3 periodic patch gives the exact value at the patch centre."""
+    rng = np.random.default_rng(seed)
+    pts = [tuple(int(rng.integers(0, s)) for s in Un.shape) for _ in range(nsamp)]
+    # always include corners and faces of the grid (periodic wrap of the halo)
+    pts += [(0, 0, 0), tuple(s - 1 for s in Un.shape), (0, Un.shape[1] - 1, 0), (Un.shape[0] - 1, 0, 5)]
+    got, ref = [], []
+    for (z, y, x) in pts:
+        P = _patch(Un, z, y, x)
+        _, gp = fo.energy_grad(P, h, eps, a)
+        ref.append(gp[4, 4, 4])
+        got.append(gn[z, y, x])
+    ref, got = np.array(ref), np.array(got)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err <= tol, err
+    return err
+
+
+def _slab_energy(Un, h, eps, a, slab=32):
+    """Oracle energy by z slabs with one ghost plane on each side (bounded memory)."""
+    nz = Un.shape[0]
+    E, Eabs = 0.0, 0.0
+    for z0 in range(0, nz, slab):
+        z1 = min(z0 + slab, nz)
+        zi = np.arange(z0 - 1, z1 + 1) % nz
+        pw = fo.pointwise(Un[zi], h, eps, a)
+        E += float(np.sum(pw["f"][1:-1]))
+        Eabs += float(sum(np.sum(np.abs(t[1:-1])) for t in pw["terms"]))
+    return h ** 3 * E, h ** 3 * Eabs
+
+
+@pytest.mark.parametrize("cfg", ["256_helfrich", "128_asym"])
+def test_full_size_sampled(cfg):
+    if cfg == "256_helfrich":
+        n, seed, eps_h, a = 256, 1005, 1.5, HELFRICH_SC
+    else:
+        n, seed, eps_h, a = 128, 1003, 2.0, ASYM_C3
+    h = 1.0 / n
+    log(f"case full {cfg}")
+    u = to_dev(inputs.uniform_noise(n, seed), torch.float32)
+    ctx = fe.FeContext(u.shape, h, eps_h * h, a, dtype=torch.float32)
+    E, g = ctx.energy_grad(u)
+    Un = oracle_input(u)
+    gn = g.cpu().double().numpy()
+    err = _sampled_gradient_check(Un, gn, h, eps_h * h, a, TOL[torch.float32]["grad"])
+    Eo, Eabs = _slab_energy(Un, h, eps_h * h, a)
+    rel = abs(E[0].item() - Eo) / max(abs(Eo), Eabs)
+    log(f"  sampled grad rel {err:.2e}  energy rel {rel:.2e}")
+    assert rel <= TOL[torch.float32]["energy"]
+
+
+def test_full_size_batched_16x128_sampled():
+    """16 x 128^3 FP32 with per-instance (eps, a): instances 0 and 15 in full, the
+    rest by sampled gradients."""
+    n, B = 128, 16
+    h = 1.0 / n
+    coeffs, _ = inputs.random_instance_table(B, 4999)
+    U = np.stack([inputs.uniform_noise(n, 4000 + b) for b in range(B)])
+    ud = to_dev(U, torch.float32)
+    del U
+    ctx = fe.FeContext(ud.shape, h, 2 * h, coeffs, dtype=torch.float32)
+    E, g = ctx.energy_grad(ud)
+    for b in range(B):
+        Un = oracle_input(ud[b])
+        gn = g[b].cpu().double().numpy()
+        if b in (0, B - 1):
+            Eo, go = fo.energy_grad(Un, h, 2 * h, coeffs[b])
+            scale = max(abs(Eo), fo.energy_abs(Un, h, 2 * h, coeffs[b]))
+            assert abs(E[b].item() - Eo) / scale <= TOL[torch.float32]["energy"]
+            assert rel_l2(gn, go) <= TOL[torch.float32]["grad"]
+        else:
+            _sampled_gradient_check(Un, gn, h, 2 * h, coeffs[b], TOL[torch.float32]["grad"], nsamp=12, seed=b)
+    log("  batched 16x128 ok")

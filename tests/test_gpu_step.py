@@ -1,0 +1,170 @@
+"""The mass-projected descent step on the GPU: trajectory parity with the oracle
+for the first steps, exact mass, graph replay equal to eager, energy decrease."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fe_oracle as fo
+from paper_2103_04856_amd import fe, inputs
+
+from gpu_helpers import ASYM_C3, WILLMORE_QUARTER, log, oracle_input, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_first_steps_match_oracle_fp64():
+    """32^3 FP64, u0 ~ U(-1,1), eps = 2h, Willmore p, mean 0, tau = 1e-3: ten steps."""
+    n = 32
+    h = 1.0 / n
+    u0 = inputs.uniform_noise(n, 1001)
+    ud = to_dev(u0, torch.float64)
+    ctx = fe.FeContext((1, n, n, n), h, 2 * h, WILLMORE_QUARTER, dtype=torch.float64)
+    uo = oracle_input(ud)
+    for k in range(10):
+        Eg = ctx.step(ud, [0.0], 1e-3, 1)
+        uo, Eo = fo.mass_projected_step(uo, h, 2 * h, WILLMORE_QUARTER, 0.0, 1e-3)
+        assert abs(Eg[0].item() - Eo) <= 1e-10 * abs(Eo)
+        err = rel_l2(ud.cpu().numpy(), uo)
+        assert err <= 1e-11, (k, err)
+    log(f"  10-step trajectory rel {err:.2e}")
+
+
+def test_nsteps_call_equals_single_steps_and_oracle():
+    """fe_step(n = 37) replays captured graphs; it must equal 37 calls of n = 1 (bitwise).
+    Against the oracle: 37 steps with p = (k1+k2)^2/4, and 5 steps with an asymmetric p
+    (with a20 != a02 the flow amplifies rounding differences ~1e13-fold over 37 steps,
+    through dS/dX = 1/(2S) near umbilic voxels, so only a short prefix is unique)."""
+    n = 16
+    h = 1.0 / n
+    u0 = inputs.uniform_noise(n, 21)
+    for dtype in (torch.float64, torch.float32):
+        for a, nref in ((ASYM_C3, 5), (WILLMORE_QUARTER, 37)):
+            ctx = fe.FeContext((1, n, n, n), h, 2 * h, a, dtype=dtype)
+            u1 = to_dev(u0, dtype)
+            u2 = u1.clone()
+            uo = oracle_input(u1)
+            E1 = ctx.step(u1, [-0.3], 1e-3, 37)
+            for _ in range(37):
+                E2 = ctx.step(u2, [-0.3], 1e-3, 1)
+            assert torch.equal(u1, u2) and E1[0].item() == E2[0].item()
+            if dtype == torch.float64:
+                u3 = to_dev(u0, dtype)
+                Eg = ctx.step(u3, [-0.3], 1e-3, nref)
+                uo, Es = fo.descend(uo, h, 2 * h, a, -0.3, 1e-3, nref)
+                assert rel_l2(u3.cpu().numpy(), uo) <= 1e-10, a
+                assert abs(Eg[0].item() - Es[-1]) <= 1e-9 * abs(Es[-1])
+
+
+def test_mass_is_exact_every_step():
+    n = 32
+    h = 1.0 / n
+    for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 2e-6)):
+        u = to_dev(inputs.uniform_noise(n, 5), dtype)
+        ctx = fe.FeContext((1, n, n, n), h, 2 * h, ASYM_C3, dtype=dtype)
+        for k in range(5):
+            ctx.step(u, [-0.3], 1e-3, 1 + k)
+            s = u.double().sum().item()
+            assert abs(s - (-0.3) * n ** 3) <= tol * u.double().abs().sum().item(), (dtype, k, s)
+
+
+def test_energy_decreases_after_first_step():
+    """Config-1 flow (32^3 FP64, tau = 1e-3): monotone decrease after step 1 and the
+    energy after 200 steps within 1% of the oracle run."""
+    n = 32
+    h = 1.0 / n
+    u0 = inputs.uniform_noise(n, 1001)
+    ud = to_dev(u0, torch.float64)
+    ctx = fe.FeContext((1, n, n, n), h, 2 * h, WILLMORE_QUARTER, dtype=torch.float64)
+    Es = []
+    for k in range(20):
+        Es.append(ctx.step(ud, [0.0], 1e-3, 10)[0].item())
+    assert all(Es[i + 1] < Es[i] for i in range(len(Es) - 1)), Es
+    Efinal = ctx.energy(ud)[0].item()
+    uo, _ = fo.descend(u0, h, 2 * h, WILLMORE_QUARTER, 0.0, 1e-3, 200)
+    Eo = fo.energy(uo, h, 2 * h, WILLMORE_QUARTER)
+    log(f"  200 steps: gpu {Efinal:.6g} oracle {Eo:.6g}")
+    assert abs(Efinal - Eo) <= 1e-2 * abs(Eo)
+
+
+def test_batched_step_per_instance_mass():
+    n, B = 24, 5
+    h = 1.0 / n
+    coeffs, means = inputs.random_instance_table(B, 4999)
+    U = np.stack([inputs.uniform_noise(n, 4000 + b) for b in range(B)])
+    ud = to_dev(U, torch.float64)
+    ctx = fe.FeContext(ud.shape, h, 2 * h, coeffs, dtype=torch.float64)
+    uo = [oracle_input(ud[b]) for b in range(B)]
+    ctx.step(ud, list(means), 1e-3, 4)
+    for b in range(B):
+        ref, _ = fo.descend(uo[b], h, 2 * h, coeffs[b], means[b], 1e-3, 4)
+        assert rel_l2(ud[b].cpu().numpy(), ref) <= 1e-10
+        assert abs(ud[b].mean().item() - means[b]) <= 1e-12
+
+
+def test_batched_16x128_flow_stays_finite():
+    """The batched workload (16 x 128^3 FP32, per-instance coefficients and means) with
+    tau = 2.5e-4 for 200 graph-replayed steps: finite, mass kept, energy decreasing."""
+    n, B = 128, 16
+    h = 1.0 / n
+    coeffs, means = inputs.random_instance_table(B, 4999)
+    ud = torch.stack([to_dev(inputs.uniform_noise(n, 4000 + b), torch.float32) for b in range(B)])
+    ctx = fe.FeContext(ud.shape, h, 2 * h, coeffs, dtype=torch.float32)
+    E0 = ctx.energy(ud)
+    E1 = ctx.step(ud, list(means), 2.5e-4, 100)
+    E2 = ctx.step(ud, list(means), 2.5e-4, 100)
+    assert torch.isfinite(E2).all()
+    assert (E2 < E1).all() and (E1 < E0).all(), (E0, E1, E2)
+    m = ud.double().mean(dim=(1, 2, 3)).cpu().numpy()
+    assert np.abs(m - means).max() < 1e-6
+    log(f"  batched flow E0 {E0.sum().item():.4g} -> {E2.sum().item():.4g}")
+
+
+def test_fp32_first_steps_close_to_oracle():
+    n = 64
+    h = 1.0 / n
+    u0 = inputs.noisy_sphere(n, 0.3, 1.5 * h, 0.01, 1002)
+    ud = to_dev(u0, torch.float32)
+    m = float(ud.double().mean().item())
+    uo = oracle_input(ud)
+    ctx = fe.FeContext((1, n, n, n), h, 1.5 * h, WILLMORE_QUARTER, dtype=torch.float32)
+    ctx.step(ud, [m], 1e-3, 3)
+    uo, _ = fo.descend(uo, h, 1.5 * h, WILLMORE_QUARTER, m, 1e-3, 3)
+    # the change of u over three steps is what is compared
+    err = rel_l2(ud.cpu().double().numpy() - u0, uo - u0)
+    log(f"  fp32 3-step update rel {err:.2e}")
+    assert err <= 1e-3
+
+
+def test_autograd_function_matches_kernel_gradient():
+    n = 24
+    h = 1.0 / n
+    for dtype in (torch.float64, torch.float32):
+        u = to_dev(inputs.uniform_noise(n, 9), dtype).requires_grad_(True)
+        ctx = fe.FeContext((1, n, n, n), h, 2 * h, ASYM_C3, dtype=dtype)
+        E = fe.feps(u, ctx)
+        (3.0 * E.sum()).backward()
+        _, g = ctx.energy_grad(u.detach())
+        assert torch.allclose(u.grad, 3.0 * g, rtol=1e-6 if dtype == torch.float32 else 1e-14)
+        Eo, go = fo.energy_grad(oracle_input(u), h, 2 * h, ASYM_C3)
+        assert rel_l2(u.grad.cpu().double().numpy() / 3.0, go) <= (1e-3 if dtype == torch.float32 else 1e-9)
+
+
+def test_autograd_descent_loop_keeps_mass():
+    """Descent driven by autograd: u <- u - tau dE/du, then the mean is projected back."""
+    n = 32
+    h = 1.0 / n
+    u = to_dev(inputs.uniform_noise(n, 1003), torch.float32)
+    ctx = fe.FeContext((1, n, n, n), h, 2 * h, ASYM_C3, dtype=torch.float32)
+    m = -0.3
+    Es = []
+    for _ in range(30):
+        x = u.clone().requires_grad_(True)
+        E = fe.feps(x, ctx)
+        E.sum().backward()
+        with torch.no_grad():
+            v = x - 1e-3 * x.grad
+            u = v + (m - v.double().mean()).to(v.dtype)
+        Es.append(E.item())
+    assert abs(u.double().mean().item() - m) < 1e-6
+    assert Es[-1] < Es[1]
