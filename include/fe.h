@@ -121,6 +121,28 @@ int fe_energy_grad_async(fe_ctx* ctx, const void* u, void* g, double* energy_dev
 int fe_step(fe_ctx* ctx, void* u, const double* mass, double tau, int nsteps, double* energy);
 
 /*
+ * nsteps mass-preserving steps with the optimiser the paper runs its flows
+ * with (Adam, Sec. 4.1: learning rate 1e-3, betas (0.9, 0.999), no weight
+ * decay), in place on u:
+ *   g = dF_h/du,  m1 <- beta1 m1 + (1 - beta1) g,  m2 <- beta2 m2 + (1 - beta2) g^2,
+ *   v = u - lr (m1 / (1 - beta1^t)) / (sqrt(m2 / (1 - beta2^t)) + adam_eps),
+ *   u <- v + (mass[b] - mean(v)),  t <- t + 1,
+ * per voxel, with the moments m1, m2 and the step number t (starting at 1)
+ * kept in the context from one call to the next (fe_adam_reset clears them).
+ * The per-voxel normalisation bounds every move by about lr, which keeps the
+ * descent stable where dF_h/du spikes near umbilic voxels (it grows like
+ * 1/sqrt(2||M||^2 - (Tr M)^2) there when a20 != a02 or a10 != a01).
+ *   u, mass, nsteps, energy  as for fe_step.
+ *   lr > 0, 0 <= beta1, beta2 < 1, adam_eps > 0, all finite, else FE_EINVAL.
+ * Allocates the two moment fields (each the size of u) on first use.
+ */
+int fe_step_adam(fe_ctx* ctx, void* u, const double* mass, double lr, double beta1, double beta2,
+                 double adam_eps, int nsteps, double* energy);
+
+/* Zero the Adam moments and reset the step number to 1. Stream-ordered, no allocation. */
+int fe_adam_reset(fe_ctx* ctx);
+
+/*
  * Launch-shape selection. Variants are numbered 0 .. fe_num_variants()-1;
  * fe_variant_info describes one (x and y interior tile, threads per block,
  * element size it supports). fe_set_launch picks a variant and a z-chunk

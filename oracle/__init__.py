@@ -18,9 +18,9 @@ Modules:
 from .fe_oracle import (XI, double_well, double_well_prime, fd_gradient, fd_hessian,
                         fd_laplacian, feps_coefficients, softplus, logistic, pointwise,
                         energy, energy_abs, adjoint_fields, energy_grad, mass_projected_step,
-                        descend, energy_grad_batch)
+                        descend, adam_projected_step, descend_adam, energy_grad_batch)
 
 __all__ = ["XI", "double_well", "double_well_prime", "fd_gradient", "fd_hessian",
            "fd_laplacian", "feps_coefficients", "softplus", "logistic", "pointwise", "energy",
            "energy_abs", "adjoint_fields", "energy_grad", "mass_projected_step", "descend",
-           "energy_grad_batch"]
+           "adam_projected_step", "descend_adam", "energy_grad_batch"]

@@ -296,6 +296,38 @@ def descend(u, h, eps, a, m, tau, nsteps, xi=XI, mode="smooth"):
     return u, energies
 
 
+def adam_projected_step(u, m1, m2, t, h, eps, a, m, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8,
+                        xi=XI, mode="smooth"):
+    """One mass-preserving step with Adam, the optimiser of Sec. 4.1 (learning rate,
+    betas and no weight decay as stated there; adam_eps is not stated, 1e-8 is read).
+
+    Adam (Kingma & Ba) on the voxel values with step number t >= 1:
+    m1 <- beta1 m1 + (1-beta1) g, m2 <- beta2 m2 + (1-beta2) g^2,
+    v = u - lr (m1/(1-beta1^t)) / (sqrt(m2/(1-beta2^t)) + adam_eps), then the L2
+    projection onto {mean = m}. Returns (u_new, m1, m2, F_h(u)).
+    """
+    E, grad = energy_grad(u, h, eps, a, xi, mode)
+    m1 = beta1 * m1 + (1.0 - beta1) * grad
+    m2 = beta2 * m2 + (1.0 - beta2) * grad * grad
+    mhat = m1 / (1.0 - beta1 ** t)
+    vhat = m2 / (1.0 - beta2 ** t)
+    v = np.asarray(u, dtype=np.float64) - lr * mhat / (np.sqrt(vhat) + adam_eps)
+    return v + (m - np.mean(v)), m1, m2, E
+
+
+def descend_adam(u, h, eps, a, m, nsteps, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, xi=XI,
+                 mode="smooth"):
+    """nsteps Adam steps from zero moments; returns (u_final, [F_h before each step])."""
+    u = np.asarray(u, dtype=np.float64)
+    m1 = np.zeros_like(u)
+    m2 = np.zeros_like(u)
+    energies = []
+    for t in range(1, nsteps + 1):
+        u, m1, m2, E = adam_projected_step(u, m1, m2, t, h, eps, a, m, lr, beta1, beta2, adam_eps, xi, mode)
+        energies.append(E)
+    return u, energies
+
+
 # --------------------------------------------------------------------------
 # Batched helpers (independent instances, each with its own eps, a, m)
 # --------------------------------------------------------------------------

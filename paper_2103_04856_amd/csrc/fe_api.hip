@@ -50,6 +50,7 @@ template <typename T>
 struct Kernels {
   SweepFn<T> grad = nullptr;
   SweepFn<T> step = nullptr;
+  SweepFn<T> adam = nullptr;
   SweepFn<T> energy = nullptr;
 };
 
@@ -63,8 +64,9 @@ struct Variant {
 template <typename T, int TX, int TY, int NT>
 Kernels<T> make_kernels() {
   Kernels<T> k;
-  k.grad = fe::grad_sweep<T, TX, TY, NT, false>;
-  k.step = fe::grad_sweep<T, TX, TY, NT, true>;
+  k.grad = fe::grad_sweep<T, TX, TY, NT, fe::kGrad>;
+  k.step = fe::grad_sweep<T, TX, TY, NT, fe::kStepGD>;
+  k.adam = fe::grad_sweep<T, TX, TY, NT, fe::kStepAdam>;
   k.energy = fe::energy_sweep<T, TX, TY, NT>;
   return k;
 }
@@ -113,14 +115,23 @@ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 // Context
 // ---------------------------------------------------------------------------
 
+// Step-rule hyper-parameters (baked into captured graphs).
+struct StepRule {
+  int mode;        // fe::kStepGD or fe::kStepAdam
+  double tau;      // GD step size or Adam learning rate
+  double beta1, beta2, adam_eps;
+};
+
 struct GraphKey {
   void* u;
-  double tau;
+  int mode;
+  double tau, beta1, beta2, adam_eps;
   int pairs;
   int variant;
   int lz;
   bool operator<(const GraphKey& o) const {
-    return std::tie(u, tau, pairs, variant, lz) < std::tie(o.u, o.tau, o.pairs, o.variant, o.lz);
+    return std::tie(u, mode, tau, beta1, beta2, adam_eps, pairs, variant, lz) <
+           std::tie(o.u, o.mode, o.tau, o.beta1, o.beta2, o.adam_eps, o.pairs, o.variant, o.lz);
   }
 };
 
@@ -136,6 +147,9 @@ struct fe_ctx {
   double* d_mass = nullptr;           // [batch]
   double* d_shift = nullptr;          // [2][batch]
   void* d_pingpong = nullptr;         // one field, allocated by the first fe_step
+  void* d_m1 = nullptr;               // Adam moments, allocated by the first fe_step_adam
+  void* d_m2 = nullptr;
+  int* d_adam_t = nullptr;            // Adam step number (device)
   size_t max_blocks = 0;              // per instance, over all variants and z chunks
   int variant = -1;
   int lz = 0;                         // 0 = automatic
@@ -278,9 +292,10 @@ int default_variant(const fe_grid& g) {
   return 0;
 }
 
+// kind: -1 energy only, else a fe::SweepMode
 template <typename T>
-int launch_sweep(fe_ctx* c, hipStream_t s, int kind /*0 energy,1 grad,2 step*/, const void* src, void* dst,
-                 const double* shift_in, double tau) {
+int launch_sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, const double* shift_in,
+                 const StepRule& rule) {
   const Geometry geo = geometry(c, c->variant, c->lz);
   if ((size_t)geo.per_inst > c->max_blocks) return set_error(FE_EINVAL, "internal: partials workspace too small");
   const Variant& v = variants()[c->variant];
@@ -292,7 +307,13 @@ int launch_sweep(fe_ctx* c, hipStream_t s, int kind /*0 energy,1 grad,2 step*/, 
   a.shift_in = shift_in;
   a.partials = c->d_partials;
   a.k = stencil_consts<T>(c->grid.h);
-  a.tau = T(tau);
+  a.m1 = static_cast<T*>(c->d_m1);
+  a.m2 = static_cast<T*>(c->d_m2);
+  a.adam_t = c->d_adam_t;
+  a.tau = T(rule.tau);
+  a.beta1 = T(rule.beta1);
+  a.beta2 = T(rule.beta2);
+  a.adam_eps = T(rule.adam_eps);
   a.nx = c->grid.nx;
   a.ny = c->grid.ny;
   a.nz = c->grid.nz;
@@ -303,27 +324,31 @@ int launch_sweep(fe_ctx* c, hipStream_t s, int kind /*0 energy,1 grad,2 step*/, 
   a.batch = c->grid.batch;
   const dim3 grid((unsigned)(geo.per_inst * c->grid.batch));
   const dim3 block((unsigned)v.nt);
-  SweepFn<T> fn = kind == 0 ? k.energy : (kind == 1 ? k.grad : k.step);
+  SweepFn<T> fn = kind < 0 ? k.energy
+                 : kind == fe::kGrad ? k.grad
+                 : kind == fe::kStepGD ? k.step : k.adam;
   hipLaunchKernelGGL(fn, grid, block, 0, s, a);
   FE_HIP(hipGetLastError());
   return FE_OK;
 }
 
-int sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, const double* shift_in, double tau) {
-  return c->grid.dtype == FE_F32 ? launch_sweep<float>(c, s, kind, src, dst, shift_in, tau)
-                                 : launch_sweep<double>(c, s, kind, src, dst, shift_in, tau);
+int sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, const double* shift_in,
+          const StepRule& rule) {
+  return c->grid.dtype == FE_F32 ? launch_sweep<float>(c, s, kind, src, dst, shift_in, rule)
+                                 : launch_sweep<double>(c, s, kind, src, dst, shift_in, rule);
 }
 
-int finalize(fe_ctx* c, hipStream_t s, bool step, double* energy_dev, double* shift_out) {
+int finalize(fe_ctx* c, hipStream_t s, bool step, double* energy_dev, double* shift_out, int* adam_t) {
   const Geometry geo = geometry(c, c->variant, c->lz);
   const double h = c->grid.h;
   const double inv_nvox = 1.0 / ((double)c->grid.nx * c->grid.ny * c->grid.nz);
   if (step)
     hipLaunchKernelGGL(fe::finalize_sums<true>, dim3(c->grid.batch), dim3(256), 0, s, c->d_partials,
-                       geo.per_inst, h * h * h, energy_dev, c->d_mass, inv_nvox, shift_out);
+                       geo.per_inst, h * h * h, energy_dev, c->d_mass, inv_nvox, shift_out, adam_t);
   else
     hipLaunchKernelGGL(fe::finalize_sums<false>, dim3(c->grid.batch), dim3(256), 0, s, c->d_partials,
-                       geo.per_inst, h * h * h, energy_dev, (const double*)nullptr, inv_nvox, (double*)nullptr);
+                       geo.per_inst, h * h * h, energy_dev, (const double*)nullptr, inv_nvox, (double*)nullptr,
+                       (int*)nullptr);
   FE_HIP(hipGetLastError());
   return FE_OK;
 }
@@ -344,10 +369,103 @@ void drop_graphs(fe_ctx* c) {
 
 // One descent step: src (+ shift_in) -> dst, then shift_out = mass - mean(dst).
 int step_once(fe_ctx* c, hipStream_t s, const void* src, void* dst, const double* shift_in, double* shift_out,
-              double tau) {
-  int rc = sweep(c, s, 2, src, dst, shift_in, tau);
+              const StepRule& rule) {
+  int rc = sweep(c, s, rule.mode, src, dst, shift_in, rule);
   if (rc) return rc;
-  return finalize(c, s, true, c->d_energy, shift_out);
+  return finalize(c, s, true, c->d_energy, shift_out, rule.mode == fe::kStepAdam ? c->d_adam_t : nullptr);
+}
+
+int adam_reset_launch(fe_ctx* c) {
+  const size_t n = field_elems(c->grid);
+  const int nblk = (int)std::min<size_t>((n + 255) / 256, 65536);
+  if (c->grid.dtype == FE_F32)
+    hipLaunchKernelGGL(fe::adam_reset<float>, dim3(nblk), dim3(256), 0, c->stream, (float*)c->d_m1,
+                       (float*)c->d_m2, n, c->d_adam_t);
+  else
+    hipLaunchKernelGGL(fe::adam_reset<double>, dim3(nblk), dim3(256), 0, c->stream, (double*)c->d_m1,
+                       (double*)c->d_m2, n, c->d_adam_t);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int nsteps, double* energy);
+
+int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int nsteps, double* energy) {
+  if (!u) return set_error(FE_EINVAL, "u is NULL");
+  if (!mass) return set_error(FE_EINVAL, "mass is NULL");
+  if (nsteps < 0) return set_error(FE_EINVAL, "nsteps must be >= 0");
+  for (int b = 0; b < c->grid.batch; ++b)
+    if (!std::isfinite(mass[b])) return set_error(FE_EINVAL, "mass[%d] is not finite", b);
+  if (nsteps == 0) return FE_OK;
+  DeviceGuard dg(c->device);
+  const int B = c->grid.batch;
+  if (!c->d_pingpong) {
+    if (hipMalloc(&c->d_pingpong, field_elems(c->grid) * elem_size(c->grid)) != hipSuccess) {
+      c->d_pingpong = nullptr;
+      return set_error(FE_ENOMEM, "ping-pong field allocation failed");
+    }
+  }
+  FE_HIP(hipMemcpyAsync(c->d_mass, mass, sizeof(double) * B, hipMemcpyHostToDevice, c->stream));
+  double* s0 = c->d_shift;        // shift of the ping-pong field
+  double* s1 = c->d_shift + B;    // shift of u
+  hipLaunchKernelGGL(fe::fill_f64, dim3(ceil_div(B, 64)), dim3(64), 0, c->stream, s1, B, 0.0);
+  FE_HIP(hipGetLastError());
+  void* A = c->d_pingpong;
+
+  // pairs of steps u -> A -> u, replayed from a captured graph
+  const int npairs = nsteps / 2;
+  const int gpairs = std::min(npairs, 16);
+  if (gpairs > 0) {
+    GraphKey key{u, rule.mode, rule.tau, rule.beta1, rule.beta2, rule.adam_eps, gpairs, c->variant, c->lz};
+    auto it = c->graphs.find(key);
+    hipGraphExec_t exec = nullptr;
+    if (it == c->graphs.end()) {
+      hipGraph_t graph = nullptr;
+      FE_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      int rc = FE_OK;
+      for (int i = 0; i < gpairs && rc == FE_OK; ++i) {
+        rc = step_once(c, c->cap_stream, u, A, s1, s0, rule);
+        if (rc == FE_OK) rc = step_once(c, c->cap_stream, A, u, s0, s1, rule);
+      }
+      hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
+      if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (ec != hipSuccess) return set_error(FE_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+      hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) return set_error(FE_EHIP, "graph instantiate failed: %s", hipGetErrorString(ei));
+      if (c->graphs.size() > 16) drop_graphs(c);
+      c->graphs[key] = exec;
+    } else {
+      exec = it->second;
+    }
+    for (int r = 0; r < npairs / gpairs; ++r) FE_HIP(hipGraphLaunch(exec, c->stream));
+    for (int i = 0; i < npairs % gpairs; ++i) {
+      int rc = step_once(c, c->stream, u, A, s1, s0, rule);
+      if (rc == FE_OK) rc = step_once(c, c->stream, A, u, s0, s1, rule);
+      if (rc) return rc;
+    }
+  }
+  const size_t per_inst = (size_t)c->grid.nx * c->grid.ny * c->grid.nz;
+  const int nblk = (int)std::min<size_t>((field_elems(c->grid) + 255) / 256, 65536);
+  const void* last = u;
+  const double* shift = s1;
+  if (nsteps % 2) {
+    int rc = step_once(c, c->stream, u, A, s1, s0, rule);
+    if (rc) return rc;
+    last = A;
+    shift = s0;
+  }
+  if (c->grid.dtype == FE_F32)
+    hipLaunchKernelGGL(fe::add_shift<float>, dim3(nblk), dim3(256), 0, c->stream, (const float*)last, (float*)u,
+                       shift, per_inst, B);
+  else
+    hipLaunchKernelGGL(fe::add_shift<double>, dim3(nblk), dim3(256), 0, c->stream, (const double*)last,
+                       (double*)u, shift, per_inst, B);
+  FE_HIP(hipGetLastError());
+  return copy_energy_out(c, energy);
 }
 
 }  // namespace
@@ -429,9 +547,10 @@ int fe_energy_grad_async(fe_ctx* c, const void* u, void* g, double* energy_dev) 
   if (!u) return set_error(FE_EINVAL, "u is NULL");
   if (g == u) return set_error(FE_EINVAL, "g must not alias u");
   DeviceGuard dg(c->device);
-  int rc = sweep(c, c->stream, g ? 1 : 0, u, g, nullptr, 0.0);
+  const StepRule none{fe::kGrad, 0.0, 0.0, 0.0, 0.0};
+  int rc = sweep(c, c->stream, g ? fe::kGrad : -1, u, g, nullptr, none);
   if (rc) return rc;
-  return finalize(c, c->stream, false, energy_dev ? energy_dev : c->d_energy, nullptr);
+  return finalize(c, c->stream, false, energy_dev ? energy_dev : c->d_energy, nullptr, nullptr);
 }
 
 int fe_energy(fe_ctx* c, const void* u, double* energy) {
@@ -452,85 +571,44 @@ int fe_energy_grad(fe_ctx* c, const void* u, void* g, double* energy) {
 int fe_step(fe_ctx* c, void* u, const double* mass, double tau, int nsteps, double* energy) {
   g_last_error.clear();
   if (!c) return set_error(FE_EINVAL, "ctx is NULL");
-  if (!u) return set_error(FE_EINVAL, "u is NULL");
-  if (!mass) return set_error(FE_EINVAL, "mass is NULL");
-  if (nsteps < 0) return set_error(FE_EINVAL, "nsteps must be >= 0");
   if (!(tau > 0.0) || !std::isfinite(tau)) return set_error(FE_EINVAL, "tau must be finite and > 0");
-  for (int b = 0; b < c->grid.batch; ++b)
-    if (!std::isfinite(mass[b])) return set_error(FE_EINVAL, "mass[%d] is not finite", b);
-  if (nsteps == 0) return FE_OK;
-  DeviceGuard dg(c->device);
-  const int B = c->grid.batch;
-  if (!c->d_pingpong) {
-    if (hipMalloc(&c->d_pingpong, field_elems(c->grid) * elem_size(c->grid)) != hipSuccess) {
-      c->d_pingpong = nullptr;
-      return set_error(FE_ENOMEM, "ping-pong field allocation failed");
-    }
-  }
-  FE_HIP(hipMemcpyAsync(c->d_mass, mass, sizeof(double) * B, hipMemcpyHostToDevice, c->stream));
-  double* s0 = c->d_shift;        // shift of the ping-pong field
-  double* s1 = c->d_shift + B;    // shift of u
-  hipLaunchKernelGGL(fe::fill_f64, dim3(ceil_div(B, 64)), dim3(64), 0, c->stream, s1, B, 0.0);
-  FE_HIP(hipGetLastError());
-  void* A = c->d_pingpong;
+  const StepRule rule{fe::kStepGD, tau, 0.0, 0.0, 0.0};
+  return run_steps(c, u, mass, rule, nsteps, energy);
+}
 
-  // pairs of steps u -> A -> u, replayed from a captured graph
-  const int npairs = nsteps / 2;
-  const int gpairs = std::min(npairs, 16);
-  if (gpairs > 0) {
-    GraphKey key{u, tau, gpairs, c->variant, c->lz};
-    auto it = c->graphs.find(key);
-    hipGraphExec_t exec = nullptr;
-    if (it == c->graphs.end()) {
-      hipGraph_t graph = nullptr;
-      FE_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-      int rc = FE_OK;
-      for (int i = 0; i < gpairs && rc == FE_OK; ++i) {
-        rc = step_once(c, c->cap_stream, u, A, s1, s0, tau);
-        if (rc == FE_OK) rc = step_once(c, c->cap_stream, A, u, s0, s1, tau);
-      }
-      hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
-      if (rc) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return rc;
-      }
-      if (ec != hipSuccess) return set_error(FE_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
-      hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (ei != hipSuccess) return set_error(FE_EHIP, "graph instantiate failed: %s", hipGetErrorString(ei));
-      if (c->graphs.size() > 16) drop_graphs(c);
-      c->graphs[key] = exec;
-    } else {
-      exec = it->second;
+int fe_step_adam(fe_ctx* c, void* u, const double* mass, double lr, double beta1, double beta2, double adam_eps,
+                 int nsteps, double* energy) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!(lr > 0.0) || !std::isfinite(lr)) return set_error(FE_EINVAL, "lr must be finite and > 0");
+  if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+    return set_error(FE_EINVAL, "beta1 and beta2 must lie in [0, 1)");
+  if (!(adam_eps > 0.0) || !std::isfinite(adam_eps)) return set_error(FE_EINVAL, "adam_eps must be finite and > 0");
+  if (!c->d_m1) {
+    DeviceGuard dg(c->device);
+    const size_t bytes = field_elems(c->grid) * elem_size(c->grid);
+    if (hipMalloc(&c->d_m1, bytes) != hipSuccess || hipMalloc(&c->d_m2, bytes) != hipSuccess ||
+        hipMalloc((void**)&c->d_adam_t, sizeof(int)) != hipSuccess) {
+      if (c->d_m1) (void)hipFree(c->d_m1);
+      if (c->d_m2) (void)hipFree(c->d_m2);
+      if (c->d_adam_t) (void)hipFree(c->d_adam_t);
+      c->d_m1 = c->d_m2 = nullptr;
+      c->d_adam_t = nullptr;
+      return set_error(FE_ENOMEM, "Adam moment allocation failed");
     }
-    for (int r = 0; r < npairs / gpairs; ++r) FE_HIP(hipGraphLaunch(exec, c->stream));
-    for (int i = 0; i < npairs % gpairs; ++i) {
-      int rc = step_once(c, c->stream, u, A, s1, s0, tau);
-      if (rc == FE_OK) rc = step_once(c, c->stream, A, u, s0, s1, tau);
-      if (rc) return rc;
-    }
-  }
-  const size_t per_inst = (size_t)c->grid.nx * c->grid.ny * c->grid.nz;
-  const int nblk = (int)std::min<size_t>((field_elems(c->grid) + 255) / 256, 65536);
-  if (nsteps % 2) {
-    int rc = step_once(c, c->stream, u, A, s1, s0, tau);
+    int rc = adam_reset_launch(c);
     if (rc) return rc;
-    if (c->grid.dtype == FE_F32)
-      hipLaunchKernelGGL(fe::add_shift<float>, dim3(nblk), dim3(256), 0, c->stream, (const float*)A, (float*)u, s0,
-                         per_inst, B);
-    else
-      hipLaunchKernelGGL(fe::add_shift<double>, dim3(nblk), dim3(256), 0, c->stream, (const double*)A, (double*)u,
-                         s0, per_inst, B);
-  } else {
-    if (c->grid.dtype == FE_F32)
-      hipLaunchKernelGGL(fe::add_shift<float>, dim3(nblk), dim3(256), 0, c->stream, (const float*)u, (float*)u, s1,
-                         per_inst, B);
-    else
-      hipLaunchKernelGGL(fe::add_shift<double>, dim3(nblk), dim3(256), 0, c->stream, (const double*)u, (double*)u,
-                         s1, per_inst, B);
   }
-  FE_HIP(hipGetLastError());
-  return copy_energy_out(c, energy);
+  const StepRule rule{fe::kStepAdam, lr, beta1, beta2, adam_eps};
+  return run_steps(c, u, mass, rule, nsteps, energy);
+}
+
+int fe_adam_reset(fe_ctx* c) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!c->d_m1) return FE_OK;   // nothing allocated yet: the first fe_step_adam starts from zero
+  DeviceGuard dg(c->device);
+  return adam_reset_launch(c);
 }
 
 int fe_num_variants(void) { return (int)variants().size(); }
@@ -623,6 +701,9 @@ void fe_destroy(fe_ctx* c) {
   if (c->d_mass) (void)hipFree(c->d_mass);
   if (c->d_shift) (void)hipFree(c->d_shift);
   if (c->d_pingpong) (void)hipFree(c->d_pingpong);
+  if (c->d_m1) (void)hipFree(c->d_m1);
+  if (c->d_m2) (void)hipFree(c->d_m2);
+  if (c->d_adam_t) (void)hipFree(c->d_adam_t);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }

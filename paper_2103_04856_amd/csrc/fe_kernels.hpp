@@ -71,26 +71,34 @@ __device__ __forceinline__ int xcd_logical_block(int linear, int total) {
   return (linear % kXcd) * (total / kXcd) + linear / kXcd;
 }
 
+// What the fused sweep writes.
+enum SweepMode {
+  kGrad = 0,      // dst = dF_h/du (h^3 included); partial[1] = sum of src
+  kStepGD = 1,    // dst = u - tau dF_h/du, u = src + shift_in[b]; partial[1] = sum of dst
+  kStepAdam = 2,  // dst = u - lr mhat / (sqrt(vhat) + adam_eps), moments updated in place
+};
+
 template <typename T>
 struct SweepArgs {
   const T* src;                 // [batch][nz][ny][nx]
-  T* dst;                       // gradient, or stepped field (STEP); unused by the energy sweep
+  T* dst;                       // gradient or stepped field; unused by the energy sweep
   const InstParams<T>* prm;     // [batch]
-  const double* shift_in;       // STEP: per-instance uniform shift of src (nullable)
+  const double* shift_in;       // steps: per-instance uniform shift of src (nullable)
   double* partials;             // [batch][blocks_per_instance][2]
+  T* m1;                        // Adam: first moment, same layout as src
+  T* m2;                        // Adam: second moment
+  const int* adam_t;            // Adam: step number t >= 1 (device, advanced by the finalisation)
   StencilConsts<T> k;
-  T tau;                        // STEP: step size
+  T tau;                        // GD step size, or Adam learning rate
+  T beta1, beta2, adam_eps;     // Adam
   int nx, ny, nz;
   int ntx, nty, nzc, lz;        // tiles in x and y, z chunks, planes per chunk
   int batch;
 };
 
-// Fused forward + adjoint + transposed-stencil gather.
-//   STEP = false: dst = dF_h/du (h^3 included); partial[1] = sum of src.
-//   STEP = true : dst = u - tau dF_h/du with u = src + shift_in[b];
-//                 partial[1] = sum of dst.
+// Fused forward + adjoint + transposed-stencil gather, then the write of MODE.
 // partial[0] = sum of the energy density over the block's output voxels.
-template <typename T, int TX, int TY, int NT, bool STEP>
+template <typename T, int TX, int TY, int NT, int MODE>
 __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   constexpr int UX = TX + 4, UY = TY + 4;      // u window: interior + halo 2
   constexpr int RX = TX + 2, RY = TY + 2;      // adjoint ring: interior + 1
@@ -121,7 +129,15 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   const T* srcb = a.src + (size_t)inst * a.nz * plane;
   T* dstb = a.dst + (size_t)inst * a.nz * plane;
   const InstParams<T> prm = a.prm[inst];
+  constexpr bool STEP = MODE != kGrad;
   const T shift = (STEP && a.shift_in) ? T(a.shift_in[inst]) : T(0);
+  // Adam bias corrections 1/(1 - beta^t)
+  T bc1 = T(1), bc2 = T(1);
+  if (MODE == kStepAdam) {
+    const int t = *a.adam_t;
+    bc1 = T(1) / (T(1) - T(::pow(double(a.beta1), double(t))));
+    bc2 = T(1) / (T(1) - T(::pow(double(a.beta2), double(t))));
+  }
 
   // In-plane offsets of the u window, computed once (periodic wrap in x, y).
   int uoff[NU];
@@ -202,8 +218,18 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
         if (gx < a.nx && gy < a.ny) {
           const T g = c_prev[j] + up + l_pp[j];
           const size_t idx = (size_t)po * plane + (size_t)gy * a.nx + gx;
-          if (STEP) {
+          if (MODE == kStepGD) {
             const T un = su[sm][(iy + 2) * UX + ix + 2] - a.tau * g;
+            dstb[idx] = un;
+            acc_m += double(un);
+          } else if (MODE == kStepAdam) {
+            const size_t gi = (size_t)inst * a.nz * plane + idx;
+            const T mo = a.beta1 * a.m1[gi] + (T(1) - a.beta1) * g;
+            const T vo = a.beta2 * a.m2[gi] + (T(1) - a.beta2) * g * g;
+            a.m1[gi] = mo;
+            a.m2[gi] = vo;
+            const T den = sqrt(vo * bc2) + a.adam_eps;
+            const T un = su[sm][(iy + 2) * UX + ix + 2] - a.tau * (mo * bc1) / den;
             dstb[idx] = un;
             acc_m += double(un);
           } else {
@@ -322,7 +348,7 @@ template <bool STEP>
 __global__ __launch_bounds__(256) void finalize_sums(const double* __restrict__ partials, int nblk,
                                                      double h3, double* __restrict__ energy,
                                                      const double* __restrict__ mass, double inv_nvox,
-                                                     double* __restrict__ shift_out) {
+                                                     double* __restrict__ shift_out, int* adam_t) {
   __shared__ double sred[256 / kWave][2];
   const int b = blockIdx.x;
   const double* pp = partials + (size_t)b * nblk * 2;
@@ -335,6 +361,7 @@ __global__ __launch_bounds__(256) void finalize_sums(const double* __restrict__ 
   if (threadIdx.x == 0) {
     if (energy) energy[b] = h3 * sf;
     if (STEP) shift_out[b] = mass[b] - sm * inv_nvox;
+    if (STEP && adam_t && b == 0) *adam_t += 1;
   }
 }
 
@@ -352,6 +379,16 @@ __global__ __launch_bounds__(256) void add_shift(const T* src, T* dst, const dou
 __global__ __launch_bounds__(64) void fill_f64(double* p, int n, double v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+// Zero both Adam moments and set the step number to 1.
+template <typename T>
+__global__ __launch_bounds__(256) void adam_reset(T* m1, T* m2, size_t n, int* t) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    m1[i] = T(0);
+    m2[i] = T(0);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *t = 1;
 }
 
 }  // namespace fe

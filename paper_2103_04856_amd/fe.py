@@ -48,6 +48,9 @@ SIGNATURES = {
     "fe_energy_grad": (ctypes.c_int, [_P, _P, _P, _DP]),
     "fe_energy_grad_async": (ctypes.c_int, [_P, _P, _P, _P]),
     "fe_step": (ctypes.c_int, [_P, _P, _DP, ctypes.c_double, ctypes.c_int, _DP]),
+    "fe_step_adam": (ctypes.c_int, [_P, _P, _DP, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int, _DP]),
+    "fe_adam_reset": (ctypes.c_int, [_P]),
     "fe_num_variants": (ctypes.c_int, []),
     "fe_variant_info": (ctypes.c_int, [ctypes.c_int, _IP, _IP, _IP, _IP]),
     "fe_set_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
@@ -212,6 +215,24 @@ class FeContext:
         self._sync_stream()
         _check(lib().fe_step(self._h, self._field(u, "u"), _dbl(mass), float(tau), int(nsteps), out))
         return torch.tensor(list(out), dtype=torch.float64)
+
+    def step_adam(self, u, mass, nsteps, lr=1e-3, betas=(0.9, 0.999), adam_eps=1e-8):
+        """nsteps mass-projected Adam steps in place on u (moments kept in the context);
+        returns F_h before the last step."""
+        B = self.shape[0]
+        if isinstance(mass, (int, float)):
+            mass = [float(mass)] * B
+        if len(mass) != B:
+            raise ValueError(f"need {B} mass values")
+        out = (ctypes.c_double * B)()
+        self._sync_stream()
+        _check(lib().fe_step_adam(self._h, self._field(u, "u"), _dbl(mass), float(lr), float(betas[0]),
+                                  float(betas[1]), float(adam_eps), int(nsteps), out))
+        return torch.tensor(list(out), dtype=torch.float64)
+
+    def adam_reset(self):
+        self._sync_stream()
+        _check(lib().fe_adam_reset(self._h))
 
     def set_launch(self, variant, z_chunk=0):
         _check(lib().fe_set_launch(self._h, int(variant), int(z_chunk)))

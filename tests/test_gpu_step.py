@@ -102,22 +102,60 @@ def test_batched_step_per_instance_mass():
         assert abs(ud[b].mean().item() - means[b]) <= 1e-12
 
 
-def test_batched_16x128_flow_stays_finite():
-    """The batched workload (16 x 128^3 FP32, per-instance coefficients and means) with
-    tau = 2.5e-4 for 200 graph-replayed steps: finite, mass kept, energy decreasing."""
+def test_adam_first_steps_match_oracle():
+    """Mass-projected Adam steps (lr 1e-3, betas (0.9, 0.999)): FP64 trajectory and
+    energies against the oracle for five steps, across two calls (moments persist)."""
+    n = 20
+    h = 1.0 / n
+    u0 = inputs.uniform_noise(n, 1003)
+    for a in (ASYM_C3, WILLMORE_QUARTER):
+        ud = to_dev(u0, torch.float64)
+        ctx = fe.FeContext((1, n, n, n), h, 2 * h, a, dtype=torch.float64)
+        ctx.step_adam(ud, [-0.3], 3)
+        E = ctx.step_adam(ud, [-0.3], 2)
+        uo, Es = fo.descend_adam(oracle_input(to_dev(u0, torch.float64)), h, 2 * h, a, -0.3, 5)
+        assert rel_l2(ud.cpu().numpy(), uo) <= 1e-10, a
+        assert abs(E[0].item() - Es[-1]) <= 1e-10 * abs(Es[-1])
+        # reset: the same five steps again from u0
+        ctx.adam_reset()
+        ud2 = to_dev(u0, torch.float64)
+        ctx.step_adam(ud2, [-0.3], 5)
+        assert torch.equal(ud2, ud)
+
+
+def test_adam_graph_replay_equals_single_steps():
+    n = 16
+    h = 1.0 / n
+    u0 = inputs.uniform_noise(n, 44)
+    for dtype in (torch.float64, torch.float32):
+        c1 = fe.FeContext((1, n, n, n), h, 2 * h, ASYM_C3, dtype=dtype)
+        c2 = fe.FeContext((1, n, n, n), h, 2 * h, ASYM_C3, dtype=dtype)
+        u1, u2 = to_dev(u0, dtype), to_dev(u0, dtype)
+        c1.step_adam(u1, [0.1], 41)
+        for _ in range(41):
+            c2.step_adam(u2, [0.1], 1)
+        assert torch.equal(u1, u2)
+        assert abs(u1.double().mean().item() - 0.1) < (1e-13 if dtype == torch.float64 else 1e-6)
+
+
+def test_batched_16x128_adam_flow_stays_finite():
+    """The batched workload (16 x 128^3 FP32, per-instance coefficients and target
+    means) with mass-projected Adam, lr 1e-3, for 300 graph-replayed steps: finite,
+    mass kept, energy decreasing. (The plain gradient step diverges here within a
+    few steps at any useful tau: dF_h/du spikes near umbilic voxels.)"""
     n, B = 128, 16
     h = 1.0 / n
     coeffs, means = inputs.random_instance_table(B, 4999)
     ud = torch.stack([to_dev(inputs.uniform_noise(n, 4000 + b), torch.float32) for b in range(B)])
     ctx = fe.FeContext(ud.shape, h, 2 * h, coeffs, dtype=torch.float32)
     E0 = ctx.energy(ud)
-    E1 = ctx.step(ud, list(means), 2.5e-4, 100)
-    E2 = ctx.step(ud, list(means), 2.5e-4, 100)
+    E1 = ctx.step_adam(ud, list(means), 100)
+    E2 = ctx.step_adam(ud, list(means), 200)
     assert torch.isfinite(E2).all()
     assert (E2 < E1).all() and (E1 < E0).all(), (E0, E1, E2)
     m = ud.double().mean(dim=(1, 2, 3)).cpu().numpy()
     assert np.abs(m - means).max() < 1e-6
-    log(f"  batched flow E0 {E0.sum().item():.4g} -> {E2.sum().item():.4g}")
+    log(f"  batched Adam flow E0 {E0.sum().item():.4g} -> {E2.sum().item():.4g}")
 
 
 def test_fp32_first_steps_close_to_oracle():

@@ -301,3 +301,41 @@ def test_descent_decreases_energy_at_small_step():
     u = inputs.uniform_noise(n, 1001)
     _, Es = fo.descend(u, h, 2 * h, WILLMORE_QUARTER, 0.0, 1e-3, 8)
     assert all(Es[i + 1] < Es[i] for i in range(1, len(Es) - 1)), Es
+
+
+# --------------------------------------------------------------------------
+# The Adam step (Sec. 4.1 runs the flows with Adam)
+# --------------------------------------------------------------------------
+
+def test_adam_first_step_is_normalised_sign_step():
+    """At t = 1 with zero moments, mhat = g and vhat = g^2, so every voxel moves by
+    -lr g/(|g| + eps_adam) before the uniform mass shift."""
+    u = inputs.uniform_noise(8, 31)
+    h, eps, a = 1 / 8, 0.25, (1.0, 0.0, 0.2, -4.0, -4.0, 0.0)
+    _, g = fo.energy_grad(u, h, eps, a)
+    un, m1, m2, _ = fo.adam_projected_step(u, np.zeros_like(u), np.zeros_like(u), 1, h, eps, a, float(u.mean()))
+    move = -1e-3 * g / (np.abs(g) + 1e-8)
+    np.testing.assert_allclose(un - u, move - move.mean(), atol=1e-15)
+    np.testing.assert_allclose(m1, 0.1 * g, rtol=1e-15)
+    np.testing.assert_allclose(m2, 0.001 * g * g, rtol=4e-15)
+
+
+def test_adam_matches_torch_optimizer():
+    """The Adam update of the oracle equals torch.optim.Adam (the optimiser the paper
+    uses, Sec. 4.1, lr 1e-3, betas (0.9, 0.999), no weight decay) fed the same
+    gradients, with the mass projection applied after each optimiser step."""
+    import torch
+    n = 6
+    h, eps, a, m = 1 / 6, 2 / 6, (1.0, 0.3, 2.0, -3.0, 5.0, 0.7), -0.2
+    u0 = inputs.uniform_noise(n, 17)
+    uo, _ = fo.descend_adam(u0, h, eps, a, m, 6)
+    x = torch.tensor(u0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([x], lr=1e-3, betas=(0.9, 0.999), eps=1e-8, weight_decay=0)
+    for _ in range(6):
+        _, g = fo.energy_grad(x.detach().numpy(), h, eps, a)
+        opt.zero_grad()
+        x.grad = torch.from_numpy(g)
+        opt.step()
+        with torch.no_grad():
+            x += m - x.mean()
+    np.testing.assert_allclose(x.detach().numpy(), uo, rtol=0, atol=1e-13)
