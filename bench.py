@@ -100,11 +100,20 @@ def bench_batched(n, B, steps, warmup, tune):
         del g
     ctx.step_adam(U, list(means), warmup, lr=ADAM_LR)
     ms_b = time_region(lambda: ctx.step_adam(U, list(means), steps, lr=ADAM_LR)) / steps
-    # the same 16 textures, one single-instance context each, called one after the other
+    # the same 16 textures, one single-instance context each, called one after the other,
+    # each with the launch shape that is best for a single 128^3 grid
     singles = []
+    single_launch = None
     for b in range(B):
         c1 = fe.FeContext((1, n, n, n), h, 2 * h, coeffs[b], dtype=torch.float32)
-        c1.set_launch(*ctx.get_launch())
+        if single_launch is None and tune:
+            g1 = torch.empty_like(U[0:1])
+            v1, z1, us1 = c1.autotune(U[0:1], g1, iters=5)
+            log(f"autotune single 128: variant {v1} {fe.variants()[v1][:3]} z_chunk {z1}: {us1:.1f} us")
+            single_launch = (v1, z1)
+            del g1
+        if single_launch is not None:
+            c1.set_launch(*single_launch)
         singles.append(c1)
     views = [U[b:b + 1] for b in range(B)]
     for b in range(B):

@@ -71,8 +71,8 @@ Kernels<T> make_kernels() {
   return k;
 }
 
-// Static LDS of grad_sweep is (3 (TX+4)(TY+4) + 10 (TX+2)(TY+2)) sizeof(T) and
-// is kept <= 64 KiB; double-precision variants therefore use smaller tiles.
+// Static LDS of grad_sweep is (4 (TX+4)(TY+4) + 10 (TX+2)(TY+2)) sizeof(T) plus
+// 16 bytes per wave; gfx950 allows up to 160 KiB per workgroup.
 const std::vector<Variant>& variants() {
   static const std::vector<Variant> v = [] {
     std::vector<Variant> r;
@@ -84,13 +84,16 @@ const std::vector<Variant>& variants() {
       Variant x{tx, ty, nt, 2, {}, k};
       r.push_back(x);
     };
+    add32(64, 32, 1024, make_kernels<float, 64, 32, 1024>());
     add32(64, 16, 1024, make_kernels<float, 64, 16, 1024>());
+    add32(64, 16, 512, make_kernels<float, 64, 16, 512>());
     add32(64, 8, 512, make_kernels<float, 64, 8, 512>());
     add32(32, 16, 512, make_kernels<float, 32, 16, 512>());
     add32(32, 8, 256, make_kernels<float, 32, 8, 256>());
     add32(16, 16, 256, make_kernels<float, 16, 16, 256>());
     add32(16, 8, 128, make_kernels<float, 16, 8, 128>());
     add32(8, 8, 64, make_kernels<float, 8, 8, 64>());
+    add64(32, 16, 512, make_kernels<double, 32, 16, 512>());
     add64(32, 8, 256, make_kernels<double, 32, 8, 256>());
     add64(16, 16, 256, make_kernels<double, 16, 16, 256>());
     add64(16, 8, 128, make_kernels<double, 16, 8, 128>());
@@ -197,6 +200,7 @@ void fill_params(const fe_ctx* c, std::vector<fe::InstParams<T>>& out) {
     fe::InstParams<T>& p = out[b];
     p.eps_d = e;
     p.inv_eps_d = 1.0 / e;
+    p.eps = T(e);
     p.inv_eps = T(1.0 / e);
     p.c1 = T((a20 + a02 - a11) / (2.0 * e));
     p.c2 = T(a11 / (2.0 * e));
@@ -218,6 +222,10 @@ fe::StencilConsts<T> stencil_consts(double h) {
   k.invh2 = 1.0 / (h * h);
   k.inv4h2 = 1.0 / (4.0 * h * h);
   k.xi2 = kXi * kXi;
+  k.inv2h_t = T(k.inv2h);
+  k.invh2_t = T(k.invh2);
+  k.inv4h2_t = T(k.inv4h2);
+  k.xi2_t = T(k.xi2);
   k.xi = T(kXi);
   k.inv_xi = T(1.0 / kXi);
   return k;

@@ -96,47 +96,79 @@ struct SweepArgs {
   int batch;
 };
 
-// Fused forward + adjoint + transposed-stencil gather, then the write of MODE.
-// partial[0] = sum of the energy density over the block's output voxels.
-template <typename T, int TX, int TY, int NT, int MODE>
-__global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
-  constexpr int UX = TX + 4, UY = TY + 4;      // u window: interior + halo 2
-  constexpr int RX = TX + 2, RY = TY + 2;      // adjoint ring: interior + 1
-  constexpr int NU = (UX * UY + NT - 1) / NT;  // u elements loaded per thread per plane
-  constexpr int NR = (RX * RY + NT - 1) / NT;  // ring voxels per thread
-  constexpr int NO = TX * TY / NT;             // output voxels per thread
-  static_assert(TX * TY % NT == 0, "interior tile must be a multiple of the block");
-  enum { UB = 0, GX, GY, GZ, TXX, TYY, TZZ, TXY, TXZ, TYZ, NFIELD };
+// The 19 stencil samples around the LDS position pc (plane p), pm (p-1), pp (p+1).
+template <typename T, int UX>
+__device__ __forceinline__ Stencil19<T> load_stencil(const T* pc, const T* pm, const T* pp) {
+  Stencil19<T> s;
+  s.c = pc[0];
+  s.xm = pc[-1]; s.xp = pc[1]; s.ym = pc[-UX]; s.yp = pc[UX]; s.zm = pm[0]; s.zp = pp[0];
+  s.xpyp = pc[UX + 1]; s.xpym = pc[1 - UX]; s.xmyp = pc[UX - 1]; s.xmym = pc[-UX - 1];
+  s.xpzp = pp[1]; s.xpzm = pm[1]; s.xmzp = pp[-1]; s.xmzm = pm[-1];
+  s.ypzp = pp[UX]; s.ypzm = pm[UX]; s.ymzp = pp[-UX]; s.ymzm = pm[-UX];
+  return s;
+}
 
-  __shared__ T su[3][UY * UX];
-  __shared__ T sx[NFIELD][RY * RX];
-  __shared__ double sred[NT / kWave][2];
+// Block -> (instance, tile x, tile y, z chunk).
+struct BlockTile {
+  int inst, logical, per_inst, x0, y0, k0, kend;
+};
 
-  const int tid = threadIdx.x;
-  const int per_inst = a.ntx * a.nty * a.nzc;
-  const int total = per_inst * a.batch;
-  const int logical = xcd_logical_block(blockIdx.x, total);
-  const int inst = logical / per_inst;
-  int rem = logical - inst * per_inst;
+template <typename T, int TX, int TY>
+__device__ __forceinline__ BlockTile block_tile(const SweepArgs<T>& a) {
+  BlockTile b;
+  b.per_inst = a.ntx * a.nty * a.nzc;
+  b.logical = xcd_logical_block(blockIdx.x, b.per_inst * a.batch);
+  b.inst = b.logical / b.per_inst;
+  int rem = b.logical - b.inst * b.per_inst;
   const int tx = rem % a.ntx;
   rem /= a.ntx;
   const int ty = rem % a.nty;
   const int chunk = rem / a.nty;
-  const int x0 = tx * TX, y0 = ty * TY, k0 = chunk * a.lz;
-  const int kend = min(k0 + a.lz, a.nz);       // output planes [k0, kend)
+  b.x0 = tx * TX;
+  b.y0 = ty * TY;
+  b.k0 = chunk * a.lz;
+  b.kend = min(b.k0 + a.lz, a.nz);
+  return b;
+}
 
-  const size_t plane = (size_t)a.nx * a.ny;
-  const T* srcb = a.src + (size_t)inst * a.nz * plane;
-  T* dstb = a.dst + (size_t)inst * a.nz * plane;
-  const InstParams<T> prm = a.prm[inst];
+// Fused forward + adjoint + transposed-stencil gather, then the write of MODE.
+// partial[0] = sum of the energy density over the block's output voxels.
+//
+// Per plane p of the chunk (p = k0-1 .. kend): the u plane p+1, prefetched into
+// registers one plane earlier, goes to LDS; barrier; forward + adjoint on the
+// (TX+2) x (TY+2) ring-extended plane p into LDS; barrier; the gather finishes
+// output plane p-1. Four u slots keep plane p-1 readable by the gather while
+// the next plane is staged, so two barriers per plane suffice.
+template <typename T, int TX, int TY, int NT, int MODE>
+__global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
+  constexpr int UX = TX + 4, UY = TY + 4;      // u window: interior + halo 2
+  constexpr int RX = TX + 2, RY = TY + 2;      // adjoint ring: interior + 1
+  constexpr int NU = (UX * UY + NT - 1) / NT;  // u elements staged per thread per plane
+  constexpr int NR = (RX * RY + NT - 1) / NT;  // ring voxels per thread
+  constexpr int NO = TX * TY / NT;             // output voxels per thread
+  static_assert(TX * TY % NT == 0, "interior tile must be a multiple of the block");
+  enum { UB = 0, GX, GY, GZ, TXX, TYY, TZZ, TXY, TXZ, TYZ, NFIELD };
   constexpr bool STEP = MODE != kGrad;
-  const T shift = (STEP && a.shift_in) ? T(a.shift_in[inst]) : T(0);
+
+  __shared__ T su[4][UY * UX];
+  __shared__ T sx[NFIELD][RY * RX];
+  __shared__ double sred[NT / kWave][2];
+
+  const int tid = threadIdx.x;
+  const BlockTile bt = block_tile<T, TX, TY>(a);
+  const int x0 = bt.x0, y0 = bt.y0, k0 = bt.k0, kend = bt.kend;
+  const size_t plane = (size_t)a.nx * a.ny;
+  const size_t inst_off = (size_t)bt.inst * a.nz * plane;
+  const T* srcb = a.src + inst_off;
+  T* dstb = a.dst + inst_off;
+  const InstParams<T> prm = a.prm[bt.inst];
+  const T shift = (STEP && a.shift_in) ? T(a.shift_in[bt.inst]) : T(0);
   // Adam bias corrections 1/(1 - beta^t)
   T bc1 = T(1), bc2 = T(1);
   if (MODE == kStepAdam) {
     const int t = *a.adam_t;
-    bc1 = T(1) / (T(1) - T(::pow(double(a.beta1), double(t))));
-    bc2 = T(1) / (T(1) - T(::pow(double(a.beta2), double(t))));
+    bc1 = T(1.0 / (1.0 - ::pow(double(a.beta1), double(t))));
+    bc2 = T(1.0 / (1.0 - ::pow(double(a.beta2), double(t))));
   }
 
   // In-plane offsets of the u window, computed once (periodic wrap in x, y).
@@ -147,12 +179,18 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
     const int ex = e % UX, ey = e / UX;
     uoff[j] = (e < UX * UY) ? wrap_index(y0 - 2 + ey, a.ny) * a.nx + wrap_index(x0 - 2 + ex, a.nx) : 0;
   }
-  auto load_plane = [&](int p, int slot) {
+  T pre[NU];
+  auto fetch = [&](int p) {
     const T* sp = srcb + (size_t)wrap_index(p, a.nz) * plane;
+#pragma unroll
+    for (int j = 0; j < NU; ++j)
+      if (tid + j * NT < UX * UY) pre[j] = sp[uoff[j]];
+  };
+  auto stage = [&](int slot) {
 #pragma unroll
     for (int j = 0; j < NU; ++j) {
       const int e = tid + j * NT;
-      if (e < UX * UY) su[slot][e] = sp[uoff[j]] + shift;
+      if (e < UX * UY) su[slot][e] = pre[j] + shift;
     }
   };
 
@@ -161,15 +199,32 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
 #pragma unroll
   for (int j = 0; j < NO; ++j) c_prev[j] = l_prev[j] = l_pp[j] = T(0);
 
-  // planes k0-2 and k0-1 -> slots 0 and 1; plane p lives in slot (p - k0 + 2) % 3
-  load_plane(k0 - 2, 0);
-  load_plane(k0 - 1, 1);
+  // plane q lives in slot (q - k0 + 2) & 3
+  fetch(k0 - 2);
+  stage(0);
+  fetch(k0 - 1);
+  stage(1);
+  fetch(k0);
 
   const int nit = (kend - k0) + 2;             // forward planes k0-1 .. kend
   for (int it = 0; it < nit; ++it) {
     const int p = k0 - 1 + it;
-    const int sm = it % 3, sc = (it + 1) % 3, sp = (it + 2) % 3;   // slots of p-1, p, p+1
-    load_plane(p + 1, sp);
+    const int sm = it & 3, sc = (it + 1) & 3, sp = (it + 2) & 3;   // slots of p-1, p, p+1
+    stage(sp);
+    if (it + 1 < nit) fetch(p + 2);            // in flight during this plane's compute
+    // Adam moments of this iteration's output plane p-1, also in flight
+    T m1v[NO], m2v[NO];
+    if (MODE == kStepAdam && it >= 2) {
+#pragma unroll
+      for (int j = 0; j < NO; ++j) {
+        const int w = tid + j * NT;
+        const int gx = x0 + w % TX, gy = y0 + w / TX;
+        const size_t gi = inst_off + (size_t)(p - 1) * plane + (size_t)gy * a.nx + gx;
+        const bool ok = gx < a.nx && gy < a.ny;
+        m1v[j] = ok ? a.m1[gi] : T(0);
+        m2v[j] = ok ? a.m2[gi] : T(0);
+      }
+    }
     __syncthreads();
 
     // ---- forward + adjoint on the ring-extended plane p ----
@@ -183,14 +238,9 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
         const T* pc = su[sc] + c;
         const T* pm = su[sm] + c;
         const T* pp = su[sp] + c;
-        Stencil19<T> s;
-        s.c = pc[0];
-        s.xm = pc[-1]; s.xp = pc[1]; s.ym = pc[-UX]; s.yp = pc[UX]; s.zm = pm[0]; s.zp = pp[0];
-        s.xpyp = pc[UX + 1]; s.xpym = pc[1 - UX]; s.xmyp = pc[UX - 1]; s.xmym = pc[-UX - 1];
-        s.xpzp = pp[1]; s.xpzm = pm[1]; s.xmzp = pp[-1]; s.xmzm = pm[-1];
-        s.ypzp = pp[UX]; s.ypzm = pm[UX]; s.ymzp = pp[-UX]; s.ymzm = pm[-UX];
         VoxelAdjoint<T> ad;
-        const T f = voxel_density_adjoint(s, prm, a.k, ad);
+        const T f = voxel_density_adjoint(load_stencil<T, UX>(pc, pm, pp),
+                                          [&]() { return load_stencil<T, UX>(pc, pm, pp); }, prm, a.k, ad);
         sx[UB][v] = ad.ub;
         sx[GX][v] = ad.gx; sx[GY][v] = ad.gy; sx[GZ][v] = ad.gz;
         sx[TXX][v] = ad.txx; sx[TYY][v] = ad.tyy; sx[TZZ][v] = ad.tzz;
@@ -213,28 +263,26 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
       const T up = tzz - gz + d;     // what plane p adds to output plane p-1
       const T lo = tzz + gz - d;     // what plane p adds to output plane p+1
       if (it >= 2) {
-        const int po = p - 1;
         const int gx = x0 + ix, gy = y0 + iy;
         if (gx < a.nx && gy < a.ny) {
           const T g = c_prev[j] + up + l_pp[j];
-          const size_t idx = (size_t)po * plane + (size_t)gy * a.nx + gx;
+          const size_t idx = (size_t)(p - 1) * plane + (size_t)gy * a.nx + gx;
+          const T uc = su[sm][(iy + 2) * UX + ix + 2];
           if (MODE == kStepGD) {
-            const T un = su[sm][(iy + 2) * UX + ix + 2] - a.tau * g;
+            const T un = uc - a.tau * g;
             dstb[idx] = un;
             acc_m += double(un);
           } else if (MODE == kStepAdam) {
-            const size_t gi = (size_t)inst * a.nz * plane + idx;
-            const T mo = a.beta1 * a.m1[gi] + (T(1) - a.beta1) * g;
-            const T vo = a.beta2 * a.m2[gi] + (T(1) - a.beta2) * g * g;
-            a.m1[gi] = mo;
-            a.m2[gi] = vo;
-            const T den = sqrt(vo * bc2) + a.adam_eps;
-            const T un = su[sm][(iy + 2) * UX + ix + 2] - a.tau * (mo * bc1) / den;
+            const T mo = a.beta1 * m1v[j] + (T(1) - a.beta1) * g;
+            const T vo = a.beta2 * m2v[j] + (T(1) - a.beta2) * g * g;
+            a.m1[inst_off + idx] = mo;
+            a.m2[inst_off + idx] = vo;
+            const T un = uc - a.tau * (mo * bc1) / (sqrt(vo * bc2) + a.adam_eps);
             dstb[idx] = un;
             acc_m += double(un);
           } else {
             dstb[idx] = g;
-            acc_m += double(su[sm][(iy + 2) * UX + ix + 2]);
+            acc_m += double(uc);
           }
         }
       }
@@ -247,13 +295,11 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
       l_prev[j] = lo;
       c_prev[j] = cin;
     }
-    // the next iteration overwrites the slot of plane p-1 and the adjoint planes
-    __syncthreads();
   }
 
   block_sum2<NT>(acc_f, acc_m, sred);
   if (tid == 0) {
-    double* out = a.partials + ((size_t)inst * per_inst + (logical - inst * per_inst)) * 2;
+    double* out = a.partials + (size_t)bt.logical * 2;
     out[0] = acc_f;
     out[1] = acc_m;
   }
@@ -271,21 +317,11 @@ __global__ __launch_bounds__(NT) void energy_sweep(SweepArgs<T> a) {
   __shared__ double sred[NT / kWave][2];
 
   const int tid = threadIdx.x;
-  const int per_inst = a.ntx * a.nty * a.nzc;
-  const int total = per_inst * a.batch;
-  const int logical = xcd_logical_block(blockIdx.x, total);
-  const int inst = logical / per_inst;
-  int rem = logical - inst * per_inst;
-  const int tx = rem % a.ntx;
-  rem /= a.ntx;
-  const int ty = rem % a.nty;
-  const int chunk = rem / a.nty;
-  const int x0 = tx * TX, y0 = ty * TY, k0 = chunk * a.lz;
-  const int kend = min(k0 + a.lz, a.nz);
-
+  const BlockTile bt = block_tile<T, TX, TY>(a);
+  const int x0 = bt.x0, y0 = bt.y0, k0 = bt.k0, kend = bt.kend;
   const size_t plane = (size_t)a.nx * a.ny;
-  const T* srcb = a.src + (size_t)inst * a.nz * plane;
-  const InstParams<T> prm = a.prm[inst];
+  const T* srcb = a.src + (size_t)bt.inst * a.nz * plane;
+  const InstParams<T> prm = a.prm[bt.inst];
 
   int uoff[NU];
 #pragma unroll
@@ -319,16 +355,11 @@ __global__ __launch_bounds__(NT) void energy_sweep(SweepArgs<T> a) {
       const T* pc = su[sc] + c;
       const T* pm = su[sm] + c;
       const T* pp = su[sp] + c;
-      Stencil19<T> s;
-      s.c = pc[0];
-      s.xm = pc[-1]; s.xp = pc[1]; s.ym = pc[-UX]; s.yp = pc[UX]; s.zm = pm[0]; s.zp = pp[0];
-      s.xpyp = pc[UX + 1]; s.xpym = pc[1 - UX]; s.xmyp = pc[UX - 1]; s.xmym = pc[-UX - 1];
-      s.xpzp = pp[1]; s.xpzm = pm[1]; s.xmzp = pp[-1]; s.xmzm = pm[-1];
-      s.ypzp = pp[UX]; s.ypzm = pm[UX]; s.ymzp = pp[-UX]; s.ymzm = pm[-UX];
-      const T f = voxel_density(s, prm, a.k);
+      const T f = voxel_density(load_stencil<T, UX>(pc, pm, pp),
+                                [&]() { return load_stencil<T, UX>(pc, pm, pp); }, prm, a.k);
       if (x0 + ix < a.nx && y0 + iy < a.ny) {
         acc_f += double(f);
-        acc_m += double(s.c);
+        acc_m += double(pc[0]);
       }
     }
     __syncthreads();
@@ -336,7 +367,7 @@ __global__ __launch_bounds__(NT) void energy_sweep(SweepArgs<T> a) {
 
   block_sum2<NT>(acc_f, acc_m, sred);
   if (tid == 0) {
-    double* out = a.partials + ((size_t)inst * per_inst + (logical - inst * per_inst)) * 2;
+    double* out = a.partials + (size_t)bt.logical * 2;
     out[0] = acc_f;
     out[1] = acc_m;
   }

@@ -6,12 +6,16 @@
 // xi log(1 + exp(x / xi)). The adjoint is the reverse-mode derivative of that
 // chain with respect to the stencil values (u, g_a, H_ab) of one voxel.
 //
-// Precision: the chain from the stencil differences to X = 2||M||^2 - (Tr M)^2
-// always runs in FP64. X is a difference of two nearly equal terms wherever two
-// eigenvalues of M nearly coincide (umbilic points, e.g. every point of a
-// sphere), and dS/dX = 1/(2S) there, so an FP32 X would leave the gradient at
-// such voxels undetermined. Everything after X (the positive part, the density,
-// the adjoint and the gather) runs in the storage precision T.
+// Precision: X = 2||M||^2 - (Tr M)^2 is a difference of two nearly equal terms
+// wherever two eigenvalues of M nearly coincide (umbilic points, e.g. every
+// point of a sphere), and dS/dX = 1/(2S) there, so an X with an FP32 rounding
+// error of ~1e-7 ||M||^2 would leave the gradient at such voxels undetermined.
+// The FP32 path therefore evaluates the chain from the stencil differences to
+// X in FP32 and, where |X| < 2^-12 (2||M||^2 + (Tr M)^2) and that scale is not
+// negligible next to xi, evaluates it again in FP64 (differences of FP32
+// samples are exact in FP64). In noise fields this re-evaluation touches
+// under 0.1% of the voxels. Everything after X (the positive part, the
+// density, the adjoint and the gather) runs in the storage precision T.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,8 +29,8 @@ namespace fe {
 // with theta = -eps Mbar folded into the scale.
 template <typename T>
 struct InstParams {
-  double eps_d, inv_eps_d;     // forward chain (FP64)
-  T inv_eps;
+  double eps_d, inv_eps_d;     // FP64 forward chain
+  T eps, inv_eps;
   T c1, c2, c3, c4, c5, c6e;   // c6e = c6 * eps
   T sc_u;                      // h^3
   T sc_gamma;                  // h^3 / (2h)
@@ -41,6 +45,7 @@ struct StencilConsts {
   double invh2;    // 1 / h^2
   double inv4h2;   // 1 / (4 h^2)
   double xi2;      // xi^2
+  T inv2h_t, invh2_t, inv4h2_t, xi2_t;   // the same in the storage precision
   T xi;            // 1e-6
   T inv_xi;        // 1 / xi
 };
@@ -81,7 +86,7 @@ struct Forward {
   T c;                          // u(i)
   T gx, gy, gz;                 // central differences
   T mxx, myy, mzz, mxy, mxz, myz;
-  T dxx, dyy, dzz;              // 2 M_aa - Tr M (formed in FP64: cancels near umbilics)
+  T dxx, dyy, dzz;              // 2 M_aa - Tr M
   T tr, n2, X;                  // Tr M, ||M||^2, 2||M||^2 - (Tr M)^2
   T q;                          // |g|^2
   T sw;                         // W'(u) / (eps (q + xi^2))
@@ -100,8 +105,8 @@ struct VoxelAdjoint {
 
 // Stencils, M and its invariants in FP64.
 template <typename T>
-__device__ __forceinline__ Forward<T> forward_chain(const Stencil19<T>& s, const InstParams<T>& p,
-                                                    const StencilConsts<T>& k) {
+__device__ __forceinline__ Forward<T> forward_fp64(const Stencil19<T>& s, const InstParams<T>& p,
+                                                   const StencilConsts<T>& k) {
   const double c = s.c;
   const double gx = (double(s.xp) - double(s.xm)) * k.inv2h;
   const double gy = (double(s.yp) - double(s.ym)) * k.inv2h;
@@ -150,6 +155,78 @@ __device__ __forceinline__ Forward<T> forward_chain(const Stencil19<T>& s, const
   return o;
 }
 
+// Stencils, M and its invariants in FP32, and whether X is too ill-conditioned
+// for that precision (see the header comment).
+__device__ __forceinline__ Forward<float> forward_fp32(const Stencil19<float>& s, const InstParams<float>& p,
+                                                       const StencilConsts<float>& k, bool& redo) {
+  const float c = s.c;
+  const float gx = (s.xp - s.xm) * k.inv2h_t;
+  const float gy = (s.yp - s.ym) * k.inv2h_t;
+  const float gz = (s.zp - s.zm) * k.inv2h_t;
+  const float c2u = c + c;
+  const float hxx = (s.xp + s.xm - c2u) * k.invh2_t;
+  const float hyy = (s.yp + s.ym - c2u) * k.invh2_t;
+  const float hzz = (s.zp + s.zm - c2u) * k.invh2_t;
+  const float hxy = ((s.xpyp - s.xpym) - (s.xmyp - s.xmym)) * k.inv4h2_t;
+  const float hxz = ((s.xpzp - s.xpzm) - (s.xmzp - s.xmzm)) * k.inv4h2_t;
+  const float hyz = ((s.ypzp - s.ypzm) - (s.ymzp - s.ymzm)) * k.inv4h2_t;
+
+  const float gxx = gx * gx, gyy = gy * gy, gzz = gz * gz;
+  const float q = gxx + gyy + gzz;
+  const float r = q + k.xi2_t;
+  const float rinv = rcp_t(r);
+  const float w = c * (c * c - 1.0f);
+  const float sw = w * p.inv_eps * rinv;
+  const float e = p.eps;
+
+  Forward<float> o;
+  o.mxx = sw * gxx - e * hxx;
+  o.myy = sw * gyy - e * hyy;
+  o.mzz = sw * gzz - e * hzz;
+  o.mxy = sw * (gx * gy) - e * hxy;
+  o.mxz = sw * (gx * gz) - e * hxz;
+  o.myz = sw * (gy * gz) - e * hyz;
+  const float tr = o.mxx + o.myy + o.mzz;
+  const float d = o.mxx * o.mxx + o.myy * o.myy + o.mzz * o.mzz;
+  const float od = o.mxy * o.mxy + o.mxz * o.mxz + o.myz * o.myz;
+  const float n2 = d + 2.0f * od;
+  const float tr2 = tr * tr;
+  o.X = 2.0f * n2 - tr2;
+  const float scale = 2.0f * n2 + tr2;
+  redo = (scale > 4096.0f * k.xi) && (fabsf(o.X) < scale * (1.0f / 4096.0f));
+  o.c = c;
+  o.gx = gx; o.gy = gy; o.gz = gz;
+  o.dxx = o.mxx + o.mxx - tr;
+  o.dyy = o.myy + o.myy - tr;
+  o.dzz = o.mzz + o.mzz - tr;
+  o.tr = tr;
+  o.n2 = n2;
+  o.q = q;
+  o.sw = sw;
+  o.r = r;
+  o.rinv = rinv;
+  return o;
+}
+
+// The forward chain in the storage precision; reload() returns the stencil
+// again for the (rare) FP64 re-evaluation.
+template <typename Reload>
+__device__ __forceinline__ Forward<double> forward_chain(const Stencil19<double>& s, Reload,
+                                                         const InstParams<double>& p,
+                                                         const StencilConsts<double>& k) {
+  return forward_fp64(s, p, k);
+}
+
+template <typename Reload>
+__device__ __forceinline__ Forward<float> forward_chain(const Stencil19<float>& s, Reload reload,
+                                                        const InstParams<float>& p,
+                                                        const StencilConsts<float>& k) {
+  bool redo;
+  Forward<float> o = forward_fp32(s, p, k, redo);
+  if (redo) o = forward_fp64(reload(), p, k);
+  return o;
+}
+
 // Smoothed positive part P = xi log(1 + exp(X/xi)) and its derivative
 // sig = logistic(X/xi). Beyond |X| = 40 xi, exp(-|X|/xi) < 5e-18 is below the
 // rounding unit of either precision, so P = max(X, 0) and sig = [X > 0] exactly.
@@ -169,10 +246,10 @@ __device__ __forceinline__ void softplus_xi(T X, const StencilConsts<T>& k, T& P
 }
 
 // Forward only: the energy density f at one voxel.
-template <typename T>
-__device__ __forceinline__ T voxel_density(const Stencil19<T>& s, const InstParams<T>& p,
+template <typename T, typename Reload>
+__device__ __forceinline__ T voxel_density(const Stencil19<T>& s, Reload reload, const InstParams<T>& p,
                                            const StencilConsts<T>& k) {
-  const Forward<T> fw = forward_chain(s, p, k);
+  const Forward<T> fw = forward_chain(s, reload, p, k);
   T P, sig;
   softplus_xi(fw.X, k, P, sig);
   const T S = P > T(0) ? P * rsqrt_t(P) : T(0);
@@ -182,10 +259,10 @@ __device__ __forceinline__ T voxel_density(const Stencil19<T>& s, const InstPara
 
 // Forward and adjoint at one voxel. Returns the density f; writes the scaled
 // partial derivatives of f with respect to u(i), g_a(i) and H_ab(i).
-template <typename T>
-__device__ __forceinline__ T voxel_density_adjoint(const Stencil19<T>& s, const InstParams<T>& p,
+template <typename T, typename Reload>
+__device__ __forceinline__ T voxel_density_adjoint(const Stencil19<T>& s, Reload reload, const InstParams<T>& p,
                                                    const StencilConsts<T>& k, VoxelAdjoint<T>& a) {
-  const Forward<T> fw = forward_chain(s, p, k);
+  const Forward<T> fw = forward_chain(s, reload, p, k);
   const T tr = fw.tr;
   T P, sig;
   softplus_xi(fw.X, k, P, sig);
@@ -202,8 +279,8 @@ __device__ __forceinline__ T voxel_density_adjoint(const Stencil19<T>& s, const 
   const T rhob = p.c4 * tr + p.c5 * S;               // df/drho
   const T kap = Sb * sig * (T(0.5) * rsP);           // df/dX  (dS/dX = sig / (2S); 0 where S = 0)
   // df/dM through N2 (c1 + 2 kap), Tr M (trb0 - 2 Tr M kap) and X; the X part
-  // of the diagonal, 2 kap (2 M_aa - Tr M), uses the FP64-formed differences so
-  // that no two kap-sized terms cancel in the storage precision.
+  // of the diagonal is written 2 kap (2 M_aa - Tr M), with the difference formed
+  // by the forward chain, so that no two kap-sized terms cancel.
   const T trb0 = T(2) * p.c2 * tr + p.c3 * S + p.c4 * rho;
   const T c1x2 = p.c1 + p.c1;
   const T kap2 = kap + kap;
