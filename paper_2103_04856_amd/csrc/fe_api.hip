@@ -38,6 +38,7 @@ int set_error(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr double kXi = 1e-6;   // Sec. 4.1: offset of |grad u| and scale of the smoothed x^+
+constexpr int kGraphPairs = 8;  // descent steps per captured graph: 2 x kGraphPairs
 
 // ---------------------------------------------------------------------------
 // Launch variants: interior tile (TX x TY) and threads per block.
@@ -71,8 +72,9 @@ Kernels<T> make_kernels() {
   return k;
 }
 
-// Static LDS of grad_sweep is (4 (TX+4)(TY+4) + 10 (TX+2)(TY+2)) sizeof(T) plus
-// 16 bytes per wave; gfx950 allows up to 160 KiB per workgroup.
+// Static LDS of grad_sweep is (4 (TX+4)(TY+4) + 7 (TX+2)(TY+2)) sizeof(T) plus
+// 16 bytes per wave; gfx950 allows up to 160 KiB per workgroup. The block size
+// need not divide the tile (the last round of a thread may be idle).
 const std::vector<Variant>& variants() {
   static const std::vector<Variant> v = [] {
     std::vector<Variant> r;
@@ -84,9 +86,13 @@ const std::vector<Variant>& variants() {
       Variant x{tx, ty, nt, 2, {}, k};
       r.push_back(x);
     };
+    add32(64, 32, 768, make_kernels<float, 64, 32, 768>());
+    add32(64, 16, 512, make_kernels<float, 64, 16, 512>());
     add32(64, 32, 1024, make_kernels<float, 64, 32, 1024>());
     add32(64, 16, 1024, make_kernels<float, 64, 16, 1024>());
-    add32(64, 16, 512, make_kernels<float, 64, 16, 512>());
+    add32(64, 16, 384, make_kernels<float, 64, 16, 384>());
+    add32(32, 32, 512, make_kernels<float, 32, 32, 512>());
+    add32(32, 16, 320, make_kernels<float, 32, 16, 320>());
     add32(64, 8, 512, make_kernels<float, 64, 8, 512>());
     add32(32, 16, 512, make_kernels<float, 32, 16, 512>());
     add32(32, 8, 256, make_kernels<float, 32, 8, 256>());
@@ -146,6 +152,7 @@ struct fe_ctx {
   std::vector<double> eps, coeffs;    // host copies [batch], [batch][6]
   void* d_prm = nullptr;              // InstParams<T>[batch]
   double* d_partials = nullptr;       // [batch][max_blocks][2]
+  int* d_counters = nullptr;          // [batch + 1] finished-block counters (zero between launches)
   double* d_energy = nullptr;         // [batch]
   double* d_mass = nullptr;           // [batch]
   double* d_shift = nullptr;          // [2][batch]
@@ -156,6 +163,7 @@ struct fe_ctx {
   size_t max_blocks = 0;              // per instance, over all variants and z chunks
   int variant = -1;
   int lz = 0;                         // 0 = automatic
+  int num_cu = 256;                   // compute units of the device
   std::map<GraphKey, hipGraphExec_t> graphs;
 };
 
@@ -188,7 +196,8 @@ int check_params(int batch, const double* eps, const double* a) {
   return FE_OK;
 }
 
-// c1..c6 of eq. (Feps) and the gather scales, per instance.
+// Per-instance constants: c1..c6 of eq. (Feps) folded with the unit scales of
+// the raw-difference formulation (s = eps/h^2, 1/(2h), h^3, eps/(4h^2)).
 template <typename T>
 void fill_params(const fe_ctx* c, std::vector<fe::InstParams<T>>& out) {
   const double h = c->grid.h, h3 = h * h * h;
@@ -197,37 +206,28 @@ void fill_params(const fe_ctx* c, std::vector<fe::InstParams<T>>& out) {
     const double e = c->eps[b];
     const double* a = &c->coeffs[6 * b];
     const double a20 = a[0], a11 = a[1], a02 = a[2], a10 = a[3], a01 = a[4], a00 = a[5];
+    const double c1 = (a20 + a02 - a11) / (2.0 * e), c2 = a11 / (2.0 * e), c3 = (a20 - a02) / (2.0 * e);
+    const double c4 = (a10 + a01) / 2.0, c5 = (a10 - a01) / 2.0, c6 = a00;
+    const double sc = e / (h * h);
     fe::InstParams<T>& p = out[b];
-    p.eps_d = e;
-    p.inv_eps_d = 1.0 / e;
-    p.eps = T(e);
-    p.inv_eps = T(1.0 / e);
-    p.c1 = T((a20 + a02 - a11) / (2.0 * e));
-    p.c2 = T(a11 / (2.0 * e));
-    p.c3 = T((a20 - a02) / (2.0 * e));
-    p.c4 = T((a10 + a01) / 2.0);
-    p.c5 = T((a10 - a01) / 2.0);
-    p.c6e = T(a00 * e);
-    p.sc_u = T(h3);
-    p.sc_gamma = T(h3 / (2.0 * h));
-    p.sc_tdiag = T(-e * h3 / (h * h));
-    p.sc_toff = T(-e * h3 / (4.0 * h * h));
+    p.lam_d = 1.0 / (e * sc);
+    p.lam = T(p.lam_d);
+    p.C1 = T(h3 * c1 * sc * sc);
+    p.C2 = T(h3 * c2 * sc * sc);
+    p.C3 = T(h3 * c3 * sc * sc);
+    p.C4 = T(h3 * c4 * sc / (2.0 * h));
+    p.C5 = T(h3 * c5 * sc / (2.0 * h));
+    p.C6 = T(h3 * c6 * e / (4.0 * h * h));
+    p.xi = T(kXi / (sc * sc));
+    p.inv_xi = T(sc * sc / kXi);
   }
 }
 
 template <typename T>
-fe::StencilConsts<T> stencil_consts(double h) {
-  fe::StencilConsts<T> k;
-  k.inv2h = 1.0 / (2.0 * h);
-  k.invh2 = 1.0 / (h * h);
-  k.inv4h2 = 1.0 / (4.0 * h * h);
-  k.xi2 = kXi * kXi;
-  k.inv2h_t = T(k.inv2h);
-  k.invh2_t = T(k.invh2);
-  k.inv4h2_t = T(k.inv4h2);
-  k.xi2_t = T(k.xi2);
-  k.xi = T(kXi);
-  k.inv_xi = T(1.0 / kXi);
+fe::GridConsts<T> grid_consts(double h) {
+  fe::GridConsts<T> k;
+  k.reg_d = 4.0 * h * h * kXi * kXi;
+  k.reg = T(k.reg_d);
   return k;
 }
 
@@ -274,11 +274,11 @@ Geometry geometry(const fe_ctx* c, int variant, int lz_req) {
   g.nty = ceil_div(c->grid.ny, v.ty);
   int lz = lz_req;
   if (lz <= 0) {
-    // aim at >= ~1024 blocks in total (several per CU on 256 CUs), but keep
-    // chunks >= 8 planes so the two recomputed boundary planes stay cheap
+    // the longest power-of-two chunk (fewest recomputed boundary planes) that
+    // still gives every compute unit a block, and at least 4 planes
     const double cols = (double)g.ntx * g.nty * c->grid.batch;
-    lz = (int)std::ceil(cols * c->grid.nz / 1024.0);
-    lz = std::max(lz, 8);
+    lz = 4;
+    while (2 * lz <= c->grid.nz && cols * ceil_div(c->grid.nz, 2 * lz) >= c->num_cu) lz *= 2;
   }
   lz = std::min(std::max(lz, 1), c->grid.nz);
   g.lz = lz;
@@ -289,7 +289,8 @@ Geometry geometry(const fe_ctx* c, int variant, int lz_req) {
 
 int default_variant(const fe_grid& g) {
   const int dt = g.dtype;
-  // the largest tile whose x and y extents do not exceed the grid by much
+  // variants are listed best-first for large grids: take the first whose tile
+  // the grid fills
   for (int v = 0; v < (int)variants().size(); ++v) {
     if (!variant_ok(v, dt)) continue;
     const Variant& x = variants()[v];
@@ -300,10 +301,11 @@ int default_variant(const fe_grid& g) {
   return 0;
 }
 
-// kind: -1 energy only, else a fe::SweepMode
+// kind: -1 energy only, else a fe::SweepMode. One launch computes the sweep and
+// its per-instance sums: energy_dev[b] and, for steps, shift_out[b].
 template <typename T>
 int launch_sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, const double* shift_in,
-                 const StepRule& rule) {
+                 double* shift_out, double* energy_dev, const StepRule& rule) {
   const Geometry geo = geometry(c, c->variant, c->lz);
   if ((size_t)geo.per_inst > c->max_blocks) return set_error(FE_EINVAL, "internal: partials workspace too small");
   const Variant& v = variants()[c->variant];
@@ -314,7 +316,12 @@ int launch_sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst,
   a.prm = static_cast<const fe::InstParams<T>*>(c->d_prm);
   a.shift_in = shift_in;
   a.partials = c->d_partials;
-  a.k = stencil_consts<T>(c->grid.h);
+  a.counters = c->d_counters;
+  a.energy = energy_dev;
+  a.mass = c->d_mass;
+  a.shift_out = shift_out;
+  a.inv_nvox = 1.0 / ((double)c->grid.nx * c->grid.ny * c->grid.nz);
+  a.k = grid_consts<T>(c->grid.h);
   a.m1 = static_cast<T*>(c->d_m1);
   a.m2 = static_cast<T*>(c->d_m2);
   a.adam_t = c->d_adam_t;
@@ -341,24 +348,10 @@ int launch_sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst,
 }
 
 int sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, const double* shift_in,
-          const StepRule& rule) {
-  return c->grid.dtype == FE_F32 ? launch_sweep<float>(c, s, kind, src, dst, shift_in, rule)
-                                 : launch_sweep<double>(c, s, kind, src, dst, shift_in, rule);
-}
-
-int finalize(fe_ctx* c, hipStream_t s, bool step, double* energy_dev, double* shift_out, int* adam_t) {
-  const Geometry geo = geometry(c, c->variant, c->lz);
-  const double h = c->grid.h;
-  const double inv_nvox = 1.0 / ((double)c->grid.nx * c->grid.ny * c->grid.nz);
-  if (step)
-    hipLaunchKernelGGL(fe::finalize_sums<true>, dim3(c->grid.batch), dim3(256), 0, s, c->d_partials,
-                       geo.per_inst, h * h * h, energy_dev, c->d_mass, inv_nvox, shift_out, adam_t);
-  else
-    hipLaunchKernelGGL(fe::finalize_sums<false>, dim3(c->grid.batch), dim3(256), 0, s, c->d_partials,
-                       geo.per_inst, h * h * h, energy_dev, (const double*)nullptr, inv_nvox, (double*)nullptr,
-                       (int*)nullptr);
-  FE_HIP(hipGetLastError());
-  return FE_OK;
+          double* shift_out, double* energy_dev, const StepRule& rule) {
+  return c->grid.dtype == FE_F32
+             ? launch_sweep<float>(c, s, kind, src, dst, shift_in, shift_out, energy_dev, rule)
+             : launch_sweep<double>(c, s, kind, src, dst, shift_in, shift_out, energy_dev, rule);
 }
 
 int copy_energy_out(fe_ctx* c, double* energy) {
@@ -378,9 +371,7 @@ void drop_graphs(fe_ctx* c) {
 // One descent step: src (+ shift_in) -> dst, then shift_out = mass - mean(dst).
 int step_once(fe_ctx* c, hipStream_t s, const void* src, void* dst, const double* shift_in, double* shift_out,
               const StepRule& rule) {
-  int rc = sweep(c, s, rule.mode, src, dst, shift_in, rule);
-  if (rc) return rc;
-  return finalize(c, s, true, c->d_energy, shift_out, rule.mode == fe::kStepAdam ? c->d_adam_t : nullptr);
+  return sweep(c, s, rule.mode, src, dst, shift_in, shift_out, c->d_energy, rule);
 }
 
 int adam_reset_launch(fe_ctx* c) {
@@ -420,9 +411,16 @@ int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int 
   FE_HIP(hipGetLastError());
   void* A = c->d_pingpong;
 
-  // pairs of steps u -> A -> u, replayed from a captured graph
+  // pairs of steps u -> A -> u: whole blocks of kGraphPairs pairs are replayed
+  // from one captured graph (the same graph for any nsteps), the rest launch
+  // directly
   const int npairs = nsteps / 2;
-  const int gpairs = std::min(npairs, 16);
+  const int gpairs = npairs >= kGraphPairs ? kGraphPairs : 0;
+  for (int i = 0; i < (gpairs ? npairs % gpairs : npairs); ++i) {
+    int rc = step_once(c, c->stream, u, A, s1, s0, rule);
+    if (rc == FE_OK) rc = step_once(c, c->stream, A, u, s0, s1, rule);
+    if (rc) return rc;
+  }
   if (gpairs > 0) {
     GraphKey key{u, rule.mode, rule.tau, rule.beta1, rule.beta2, rule.adam_eps, gpairs, c->variant, c->lz};
     auto it = c->graphs.find(key);
@@ -450,11 +448,6 @@ int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int 
       exec = it->second;
     }
     for (int r = 0; r < npairs / gpairs; ++r) FE_HIP(hipGraphLaunch(exec, c->stream));
-    for (int i = 0; i < npairs % gpairs; ++i) {
-      int rc = step_once(c, c->stream, u, A, s1, s0, rule);
-      if (rc == FE_OK) rc = step_once(c, c->stream, A, u, s0, s1, rule);
-      if (rc) return rc;
-    }
   }
   const size_t per_inst = (size_t)c->grid.nx * c->grid.ny * c->grid.nz;
   const int nblk = (int)std::min<size_t>((field_elems(c->grid) + 255) / 256, 65536);
@@ -507,6 +500,11 @@ int fe_create(const fe_grid* grid, const double* eps, const double* p_coeffs, vo
     return code;
   };
   if (hipGetDevice(&c->device) != hipSuccess) return fail(set_error(FE_EHIP, "hipGetDevice failed"));
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && ncu > 0)
+      c->num_cu = ncu;
+  }
   if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return fail(set_error(FE_EHIP, "hipStreamCreateWithFlags failed"));
 
@@ -523,8 +521,12 @@ int fe_create(const fe_grid* grid, const double* eps, const double* p_coeffs, vo
       hipMalloc((void**)&c->d_partials, sizeof(double) * 2 * mb * grid->batch) != hipSuccess ||
       hipMalloc((void**)&c->d_energy, sizeof(double) * grid->batch) != hipSuccess ||
       hipMalloc((void**)&c->d_mass, sizeof(double) * grid->batch) != hipSuccess ||
-      hipMalloc((void**)&c->d_shift, sizeof(double) * 2 * grid->batch) != hipSuccess)
+      hipMalloc((void**)&c->d_shift, sizeof(double) * 2 * grid->batch) != hipSuccess ||
+      hipMalloc((void**)&c->d_counters, sizeof(int) * (grid->batch + 1)) != hipSuccess)
     return fail(set_error(FE_ENOMEM, "device workspace allocation failed"));
+  hipLaunchKernelGGL(fe::fill_i32, dim3(ceil_div(grid->batch + 1, 64)), dim3(64), 0, c->stream, c->d_counters,
+                     grid->batch + 1, 0);
+  if (hipGetLastError() != hipSuccess) return fail(set_error(FE_EHIP, "counter initialisation failed"));
   rc = upload_params(c);
   if (rc) return fail(rc);
   *out = c;
@@ -556,9 +558,8 @@ int fe_energy_grad_async(fe_ctx* c, const void* u, void* g, double* energy_dev) 
   if (g == u) return set_error(FE_EINVAL, "g must not alias u");
   DeviceGuard dg(c->device);
   const StepRule none{fe::kGrad, 0.0, 0.0, 0.0, 0.0};
-  int rc = sweep(c, c->stream, g ? fe::kGrad : -1, u, g, nullptr, none);
-  if (rc) return rc;
-  return finalize(c, c->stream, false, energy_dev ? energy_dev : c->d_energy, nullptr, nullptr);
+  return sweep(c, c->stream, g ? fe::kGrad : -1, u, g, nullptr, nullptr, energy_dev ? energy_dev : c->d_energy,
+               none);
 }
 
 int fe_energy(fe_ctx* c, const void* u, double* energy) {
@@ -661,7 +662,7 @@ int fe_autotune(fe_ctx* c, const void* u, void* g, int iters, double* best_us) {
   FE_HIP(hipEventCreate(&e1));
   double best = 1e300;
   int best_v = keep_v, best_lz = keep_lz;
-  const int lzs[] = {4, 8, 16, 32, 64};
+  const int lzs[] = {4, 8, 16, 32, 64, 128};
   int rc = FE_OK;
   for (int v = 0; v < (int)variants().size() && rc == FE_OK; ++v) {
     if (!variant_ok(v, c->grid.dtype)) continue;
@@ -708,6 +709,7 @@ void fe_destroy(fe_ctx* c) {
   if (c->d_energy) (void)hipFree(c->d_energy);
   if (c->d_mass) (void)hipFree(c->d_mass);
   if (c->d_shift) (void)hipFree(c->d_shift);
+  if (c->d_counters) (void)hipFree(c->d_counters);
   if (c->d_pingpong) (void)hipFree(c->d_pingpong);
   if (c->d_m1) (void)hipFree(c->d_m1);
   if (c->d_m2) (void)hipFree(c->d_m2);

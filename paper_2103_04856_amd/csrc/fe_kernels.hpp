@@ -16,8 +16,9 @@
 //     pipeline, so each output voxel is written exactly once;
 //   * sums (energy, mass of the stepped field) are accumulated per thread in
 //     FP64, reduced with wavefront shuffles and one LDS pass, and written as
-//     one partial per block; a second tiny kernel adds the partials of each
-//     instance in a fixed order (deterministic, no atomics).
+//     one partial per block; the last block of each instance adds that
+//     instance's partials in a fixed order (deterministic) and writes the
+//     energy and the mass shift, so one launch is one whole step.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -85,16 +86,64 @@ struct SweepArgs {
   const InstParams<T>* prm;     // [batch]
   const double* shift_in;       // steps: per-instance uniform shift of src (nullable)
   double* partials;             // [batch][blocks_per_instance][2]
+  int* counters;                // [batch + 1] finished-block counters, zero between launches
+  double* energy;               // [batch] out: h^3 sum f
+  const double* mass;           // steps: [batch] target means
+  double* shift_out;            // steps: [batch] out: mass - mean(dst)
+  double inv_nvox;
   T* m1;                        // Adam: first moment, same layout as src
   T* m2;                        // Adam: second moment
   const int* adam_t;            // Adam: step number t >= 1 (device, advanced by the finalisation)
-  StencilConsts<T> k;
+  GridConsts<T> k;
   T tau;                        // GD step size, or Adam learning rate
   T beta1, beta2, adam_eps;     // Adam
   int nx, ny, nz;
   int ntx, nty, nzc, lz;        // tiles in x and y, z chunks, planes per chunk
   int batch;
 };
+
+// End of a sweep block: reduce the block's sums into its partial; the last block
+// of an instance to finish adds that instance's partials in a fixed order and
+// writes the energy (and, for steps, the shift that projects the stepped field
+// back onto its target mean). The last of those advances the Adam step number.
+// Counters are reset by the blocks that observe them full, so every launch (and
+// every graph replay) starts from zero without a memset.
+template <int NT, int MODE, typename T>
+__device__ __forceinline__ void finish_block(const SweepArgs<T>& a, int inst, int logical, int per_inst,
+                                             double acc_f, double acc_m, double (*sred)[2]) {
+  __shared__ int s_last;
+  block_sum2<NT>(acc_f, acc_m, sred);
+  if (threadIdx.x == 0) {
+    double* out = a.partials + (size_t)logical * 2;
+    out[0] = acc_f;
+    out[1] = acc_m;
+    __threadfence();
+    s_last = atomicAdd(&a.counters[inst], 1) == per_inst - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  const double* pp = a.partials + (size_t)inst * per_inst * 2;
+  double sf = 0.0, sm = 0.0;
+  for (int i = threadIdx.x; i < per_inst; i += NT) {
+    sf += pp[2 * i];
+    sm += pp[2 * i + 1];
+  }
+  __syncthreads();   // sred is reused
+  block_sum2<NT>(sf, sm, sred);
+  if (threadIdx.x == 0) {
+    a.energy[inst] = sf;
+    if (MODE == kStepGD || MODE == kStepAdam) a.shift_out[inst] = a.mass[inst] - sm * a.inv_nvox;
+    atomicExch(&a.counters[inst], 0);
+    if (MODE == kStepAdam) {
+      __threadfence();
+      if (atomicAdd(&a.counters[a.batch], 1) == a.batch - 1) {
+        atomicAdd(const_cast<int*>(a.adam_t), 1);
+        atomicExch(&a.counters[a.batch], 0);
+      }
+    }
+  }
+}
 
 // The 19 stencil samples around the LDS position pc (plane p), pm (p-1), pp (p+1).
 template <typename T, int UX>
@@ -136,18 +185,21 @@ __device__ __forceinline__ BlockTile block_tile(const SweepArgs<T>& a) {
 //
 // Per plane p of the chunk (p = k0-1 .. kend): the u plane p+1, prefetched into
 // registers one plane earlier, goes to LDS; barrier; forward + adjoint on the
-// (TX+2) x (TY+2) ring-extended plane p into LDS; barrier; the gather finishes
-// output plane p-1. Four u slots keep plane p-1 readable by the gather while
-// the next plane is staged, so two barriers per plane suffice.
+// (TX+2) x (TY+2) ring-extended plane p; barrier; the gather finishes output
+// plane p-1. Each thread evaluates the interior voxels it later gathers, so
+// their centre-only adjoints (du, da_z, db_aa) stay in registers and only the
+// seven values the neighbours read go through LDS; the one-voxel border of
+// the ring is shared out afterwards. Four u slots keep plane p-1 readable by
+// the gather while the next plane is staged, so two barriers per plane suffice.
 template <typename T, int TX, int TY, int NT, int MODE>
 __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   constexpr int UX = TX + 4, UY = TY + 4;      // u window: interior + halo 2
   constexpr int RX = TX + 2, RY = TY + 2;      // adjoint ring: interior + 1
   constexpr int NU = (UX * UY + NT - 1) / NT;  // u elements staged per thread per plane
-  constexpr int NR = (RX * RY + NT - 1) / NT;  // ring voxels per thread
-  constexpr int NO = TX * TY / NT;             // output voxels per thread
-  static_assert(TX * TY % NT == 0, "interior tile must be a multiple of the block");
-  enum { UB = 0, GX, GY, GZ, TXX, TYY, TZZ, TXY, TXZ, TYZ, NFIELD };
+  constexpr int NO = (TX * TY + NT - 1) / NT;  // interior (output) voxels per thread
+  constexpr int NB = 2 * RX + 2 * TY;          // border voxels of the ring
+  constexpr int NBR = (NB + NT - 1) / NT;      // border voxels per thread
+  enum { GX = 0, GY, BXX, BYY, BXY, BXZ, BYZ, NFIELD };
   constexpr bool STEP = MODE != kGrad;
 
   __shared__ T su[4][UY * UX];
@@ -193,6 +245,13 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
       if (e < UX * UY) su[slot][e] = pre[j] + shift;
     }
   };
+  // ring position of border voxel b (top row, bottom row, then the two side columns)
+  auto border_pos = [](int b) {
+    if (b < RX) return b;
+    if (b < 2 * RX) return (RY - 1) * RX + (b - RX);
+    const int k = b - 2 * RX;
+    return (1 + (k >> 1)) * RX + ((k & 1) ? RX - 1 : 0);
+  };
 
   double acc_f = 0.0, acc_m = 0.0;
   T c_prev[NO], l_prev[NO], l_pp[NO];
@@ -220,7 +279,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
         const int w = tid + j * NT;
         const int gx = x0 + w % TX, gy = y0 + w / TX;
         const size_t gi = inst_off + (size_t)(p - 1) * plane + (size_t)gy * a.nx + gx;
-        const bool ok = gx < a.nx && gy < a.ny;
+        const bool ok = w < TX * TY && gx < a.nx && gy < a.ny;
         m1v[j] = ok ? a.m1[gi] : T(0);
         m2v[j] = ok ? a.m2[gi] : T(0);
       }
@@ -229,80 +288,92 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
 
     // ---- forward + adjoint on the ring-extended plane p ----
     const bool out_plane = (p >= k0) && (p < kend);
+    auto eval = [&](int v, VoxelAdjoint<T>& ad) {
+      const int c = (v / RX + 1) * UX + v % RX + 1;
+      const T* pc = su[sc] + c;
+      const T* pm = su[sm] + c;
+      const T* pp = su[sp] + c;
+      const T f = voxel_density_adjoint(load_stencil<T, UX>(pc, pm, pp),
+                                        [&]() { return load_stencil<T, UX>(pc, pm, pp); }, prm, a.k, ad);
+      sx[GX][v] = ad.gx; sx[GY][v] = ad.gy;
+      sx[BXX][v] = ad.nbxx; sx[BYY][v] = ad.nbyy;
+      sx[BXY][v] = ad.nbxy; sx[BXZ][v] = ad.nbxz; sx[BYZ][v] = ad.nbyz;
+      return f;
+    };
+    T own_ub[NO], own_gz[NO], own_bxx[NO], own_byy[NO], own_bzz[NO];
 #pragma unroll
-    for (int j = 0; j < NR; ++j) {
-      const int v = tid + j * NT;
-      if (v < RX * RY) {
-        const int rx = v % RX, ry = v / RX;
-        const int c = (ry + 1) * UX + rx + 1;
-        const T* pc = su[sc] + c;
-        const T* pm = su[sm] + c;
-        const T* pp = su[sp] + c;
+    for (int j = 0; j < NO; ++j) {
+      const int w = tid + j * NT;
+      if (w < TX * TY) {
+        const int ix = w % TX, iy = w / TX;
         VoxelAdjoint<T> ad;
-        const T f = voxel_density_adjoint(load_stencil<T, UX>(pc, pm, pp),
-                                          [&]() { return load_stencil<T, UX>(pc, pm, pp); }, prm, a.k, ad);
-        sx[UB][v] = ad.ub;
-        sx[GX][v] = ad.gx; sx[GY][v] = ad.gy; sx[GZ][v] = ad.gz;
-        sx[TXX][v] = ad.txx; sx[TYY][v] = ad.tyy; sx[TZZ][v] = ad.tzz;
-        sx[TXY][v] = ad.txy; sx[TXZ][v] = ad.txz; sx[TYZ][v] = ad.tyz;
-        const bool interior = rx >= 1 && rx <= TX && ry >= 1 && ry <= TY &&
-                              x0 + rx - 1 < a.nx && y0 + ry - 1 < a.ny;
-        if (out_plane && interior) acc_f += double(f);
+        const T f = eval((iy + 1) * RX + ix + 1, ad);
+        own_ub[j] = ad.ub;
+        own_gz[j] = ad.gz;
+        own_bxx[j] = ad.nbxx;
+        own_byy[j] = ad.nbyy;
+        own_bzz[j] = ad.nbzz;
+        if (out_plane && x0 + ix < a.nx && y0 + iy < a.ny) acc_f += double(f);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NBR; ++j) {
+      const int b = tid + j * NT;
+      if (b < NB) {
+        VoxelAdjoint<T> ad;
+        (void)eval(border_pos(b), ad);
       }
     }
     __syncthreads();
 
     // ---- transposed stencils on the interior ----
+    // The b adjoints are held negated (nb = -df/db), which flips their signs here.
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
       const int w = tid + j * NT;
-      const int ix = w % TX, iy = w / TX;
-      const int v = (iy + 1) * RX + ix + 1;
-      const T d = (sx[TXZ][v + 1] - sx[TXZ][v - 1]) + (sx[TYZ][v + RX] - sx[TYZ][v - RX]);
-      const T tzz = sx[TZZ][v], gz = sx[GZ][v];
-      const T up = tzz - gz + d;     // what plane p adds to output plane p-1
-      const T lo = tzz + gz - d;     // what plane p adds to output plane p+1
-      if (it >= 2) {
-        const int gx = x0 + ix, gy = y0 + iy;
-        if (gx < a.nx && gy < a.ny) {
-          const T g = c_prev[j] + up + l_pp[j];
-          const size_t idx = (size_t)(p - 1) * plane + (size_t)gy * a.nx + gx;
-          const T uc = su[sm][(iy + 2) * UX + ix + 2];
-          if (MODE == kStepGD) {
-            const T un = uc - a.tau * g;
-            dstb[idx] = un;
-            acc_m += double(un);
-          } else if (MODE == kStepAdam) {
-            const T mo = a.beta1 * m1v[j] + (T(1) - a.beta1) * g;
-            const T vo = a.beta2 * m2v[j] + (T(1) - a.beta2) * g * g;
-            a.m1[inst_off + idx] = mo;
-            a.m2[inst_off + idx] = vo;
-            const T un = uc - a.tau * (mo * bc1) / (sqrt(vo * bc2) + a.adam_eps);
-            dstb[idx] = un;
-            acc_m += double(un);
-          } else {
-            dstb[idx] = g;
-            acc_m += double(uc);
+      if (w < TX * TY) {
+        const int ix = w % TX, iy = w / TX;
+        const int v = (iy + 1) * RX + ix + 1;
+        const T d = (sx[BXZ][v + 1] - sx[BXZ][v - 1]) + (sx[BYZ][v + RX] - sx[BYZ][v - RX]);
+        const T bzz = own_bzz[j], gz = own_gz[j];
+        const T upn = bzz + gz + d;    // minus what plane p adds to output plane p-1
+        const T lo = gz + d - bzz;     // what plane p adds to output plane p+1
+        if (it >= 2) {
+          const int gx = x0 + ix, gy = y0 + iy;
+          if (gx < a.nx && gy < a.ny) {
+            const T g = (c_prev[j] - upn) + l_pp[j];
+            const size_t idx = (size_t)(p - 1) * plane + (size_t)gy * a.nx + gx;
+            const T uc = su[sm][(iy + 2) * UX + ix + 2];
+            if (MODE == kStepGD) {
+              const T un = uc - a.tau * g;
+              dstb[idx] = un;
+              acc_m += double(un);
+            } else if (MODE == kStepAdam) {
+              const T mo = a.beta1 * m1v[j] + (T(1) - a.beta1) * g;
+              const T vo = a.beta2 * m2v[j] + (T(1) - a.beta2) * g * g;
+              a.m1[inst_off + idx] = mo;
+              a.m2[inst_off + idx] = vo;
+              const T un = uc - a.tau * (mo * bc1) / (sqrt(vo * bc2) + a.adam_eps);
+              dstb[idx] = un;
+              acc_m += double(un);
+            } else {
+              dstb[idx] = g;
+              acc_m += double(uc);
+            }
           }
         }
+        const T cin = (own_ub[j] + T(2) * ((bzz + own_bxx[j]) + own_byy[j]))
+                      - ((sx[GX][v + 1] - sx[GX][v - 1]) + (sx[GY][v + RX] - sx[GY][v - RX]))
+                      - ((sx[BXX][v + 1] + sx[BXX][v - 1]) + (sx[BYY][v + RX] + sx[BYY][v - RX]))
+                      - ((sx[BXY][v + RX + 1] - sx[BXY][v - RX + 1]) - (sx[BXY][v + RX - 1] - sx[BXY][v - RX - 1]));
+        l_pp[j] = l_prev[j];
+        l_prev[j] = lo;
+        c_prev[j] = cin;
       }
-      const T tc = sx[TXX][v], tyy = sx[TYY][v];
-      const T cin = (sx[UB][v] - (tzz + tzz) - (tc + tc) - (tyy + tyy))
-                    - (sx[GX][v + 1] - sx[GX][v - 1]) - (sx[GY][v + RX] - sx[GY][v - RX])
-                    + (sx[TXX][v + 1] + sx[TXX][v - 1]) + (sx[TYY][v + RX] + sx[TYY][v - RX])
-                    + ((sx[TXY][v + RX + 1] - sx[TXY][v - RX + 1]) - (sx[TXY][v + RX - 1] - sx[TXY][v - RX - 1]));
-      l_pp[j] = l_prev[j];
-      l_prev[j] = lo;
-      c_prev[j] = cin;
     }
   }
 
-  block_sum2<NT>(acc_f, acc_m, sred);
-  if (tid == 0) {
-    double* out = a.partials + (size_t)bt.logical * 2;
-    out[0] = acc_f;
-    out[1] = acc_m;
-  }
+  finish_block<NT, MODE>(a, bt.inst, bt.logical, bt.per_inst, acc_f, acc_m, sred);
 }
 
 // Forward only: per-block sums of the energy density and of u.
@@ -310,8 +381,7 @@ template <typename T, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void energy_sweep(SweepArgs<T> a) {
   constexpr int UX = TX + 2, UY = TY + 2;      // halo 1 suffices for the forward stencil
   constexpr int NU = (UX * UY + NT - 1) / NT;
-  constexpr int NO = TX * TY / NT;
-  static_assert(TX * TY % NT == 0, "interior tile must be a multiple of the block");
+  constexpr int NO = (TX * TY + NT - 1) / NT;
 
   __shared__ T su[3][UY * UX];
   __shared__ double sred[NT / kWave][2];
@@ -350,6 +420,7 @@ __global__ __launch_bounds__(NT) void energy_sweep(SweepArgs<T> a) {
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
       const int w = tid + j * NT;
+      if (w >= TX * TY) continue;
       const int ix = w % TX, iy = w / TX;
       const int c = (iy + 1) * UX + ix + 1;
       const T* pc = su[sc] + c;
@@ -365,35 +436,7 @@ __global__ __launch_bounds__(NT) void energy_sweep(SweepArgs<T> a) {
     __syncthreads();
   }
 
-  block_sum2<NT>(acc_f, acc_m, sred);
-  if (tid == 0) {
-    double* out = a.partials + (size_t)bt.logical * 2;
-    out[0] = acc_f;
-    out[1] = acc_m;
-  }
-}
-
-// One block per instance: add the per-block partials in a fixed order.
-//   energy[b] = h3 * sum partial[0];  STEP: shift_out[b] = mass[b] - sum partial[1] / nvox.
-template <bool STEP>
-__global__ __launch_bounds__(256) void finalize_sums(const double* __restrict__ partials, int nblk,
-                                                     double h3, double* __restrict__ energy,
-                                                     const double* __restrict__ mass, double inv_nvox,
-                                                     double* __restrict__ shift_out, int* adam_t) {
-  __shared__ double sred[256 / kWave][2];
-  const int b = blockIdx.x;
-  const double* pp = partials + (size_t)b * nblk * 2;
-  double sf = 0.0, sm = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += 256) {
-    sf += pp[2 * i];
-    sm += pp[2 * i + 1];
-  }
-  block_sum2<256>(sf, sm, sred);
-  if (threadIdx.x == 0) {
-    if (energy) energy[b] = h3 * sf;
-    if (STEP) shift_out[b] = mass[b] - sm * inv_nvox;
-    if (STEP && adam_t && b == 0) *adam_t += 1;
-  }
+  finish_block<NT, kGrad>(a, bt.inst, bt.logical, bt.per_inst, acc_f, acc_m, sred);
 }
 
 // dst[b][i] = src[b][i] + shift[b] (src may equal dst).
@@ -408,6 +451,11 @@ __global__ __launch_bounds__(256) void add_shift(const T* src, T* dst, const dou
 }
 
 __global__ __launch_bounds__(64) void fill_f64(double* p, int n, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(64) void fill_i32(int* p, int n, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }

@@ -4,50 +4,54 @@
 // regularisations of Sec. 4.1: rho = sqrt(|g|^2 + xi^2) replaces |grad u|,
 // n (x) n = g g^T / (|g|^2 + xi^2), and the positive part is the softplus
 // xi log(1 + exp(x / xi)). The adjoint is the reverse-mode derivative of that
-// chain with respect to the stencil values (u, g_a, H_ab) of one voxel.
+// chain with respect to the stencil values of one voxel.
 //
-// Precision: X = 2||M||^2 - (Tr M)^2 is a difference of two nearly equal terms
-// wherever two eigenvalues of M nearly coincide (umbilic points, e.g. every
-// point of a sphere), and dS/dX = 1/(2S) there, so an X with an FP32 rounding
-// error of ~1e-7 ||M||^2 would leave the gradient at such voxels undetermined.
-// The FP32 path therefore evaluates the chain from the stencil differences to
-// X in FP32 and, where |X| < 2^-12 (2||M||^2 + (Tr M)^2) and that scale is not
-// negligible next to xi, evaluates it again in FP64 (differences of FP32
-// samples are exact in FP64). In noise fields this re-evaluation touches
-// under 0.1% of the voxels. Everything after X (the positive part, the
-// density, the adjoint and the gather) runs in the storage precision T.
+// Units. Everything is written in raw stencil differences of u, which are O(1)
+// for any field with |u| <~ 1:
+//   a_a  = u(i+e_a) - u(i-e_a)                       = 2h g_a
+//   b_aa = u(i+e_a) + u(i-e_a) - 2u(i)               = h^2 H_aa
+//   b_ab = u(++) - u(+-) - u(-+) + u(--)             = 4h^2 H_ab
+// With s = eps/h^2, lam = h^2/eps^2, Q = |a|^2, R = Q + 4h^2 xi^2:
+//   M_aa = s (lam W'(u) a_a^2 / R - b_aa) = s m_aa
+//   M_ab = s (4 lam W'(u) a_a a_b / R - b_ab) / 4 = s o_ab / 4
+//   Tr M = s T~, ||M||^2 = s^2 N~ with N~ = sum m_aa^2 + sum o_ab^2 / 8,
+//   2||M||^2 - (Tr M)^2 = s^2 X~, S = s S~ with S~ = sqrt(softplus_{xi/s^2}(X~)),
+//   rho = sqrt(R) / (2h), eps |g|^2 = eps Q / (4h^2).
+// The factors s, 1/(2h), h^3 and eps/(4h^2) are folded into six per-instance
+// coefficients C1..C6, so that the per-voxel density f~ = h^3 f and F_h is the
+// plain sum of f~; its derivatives with respect to a, b and u are then the
+// values the transposed stencils spread, with no further scaling.
+//
+// Precision: X~ is a difference of two nearly equal terms wherever two
+// eigenvalues of M nearly coincide (umbilic points, e.g. every point of a
+// sphere), and dS/dX = 1/(2S) there, so an X~ with an FP32 rounding error of
+// ~1e-7 N~ would leave the gradient at such voxels undetermined. The FP32 path
+// therefore evaluates the chain up to X~ in FP32 and, where
+// |X~| < 2^-12 (2N~ + T~^2) and that scale is not negligible next to the
+// softplus width, evaluates it again in FP64 (differences of FP32 samples are
+// exact in FP64). In noise fields this re-evaluation touches under 0.1% of the
+// voxels. Everything after X~ (the positive part, the density, the adjoint)
+// runs in the storage precision T.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace fe {
 
-// Per-instance constants. The adjoint outputs are pre-multiplied by the
-// factors the transposed stencils need, so that the gather is adds only:
-//   ubar' = h^3 ubar,  gamma' = h^3/(2h) gamma,
-//   theta'_aa = h^3/h^2 theta_aa,  theta'_ab = h^3/(4h^2) theta_ab,
-// with theta = -eps Mbar folded into the scale.
+// Per-instance constants (see the unit conventions above).
 template <typename T>
 struct InstParams {
-  double eps_d, inv_eps_d;     // FP64 forward chain
-  T eps, inv_eps;
-  T c1, c2, c3, c4, c5, c6e;   // c6e = c6 * eps
-  T sc_u;                      // h^3
-  T sc_gamma;                  // h^3 / (2h)
-  T sc_tdiag;                  // -eps h^3 / h^2
-  T sc_toff;                   // -eps h^3 / (4 h^2)
+  double lam_d;                // h^2 / eps^2, for the FP64 chain
+  T lam;                       // h^2 / eps^2
+  T C1, C2, C3, C4, C5, C6;    // h^3 c1 s^2, h^3 c2 s^2, h^3 c3 s^2, h^3 c4 s/(2h), h^3 c5 s/(2h), h^3 c6 eps/(4h^2)
+  T xi, inv_xi;                // softplus width in X~ units: xi h^4 / eps^2, and its inverse
 };
 
 // Grid constants shared by all instances.
 template <typename T>
-struct StencilConsts {
-  double inv2h;    // 1 / (2h)
-  double invh2;    // 1 / h^2
-  double inv4h2;   // 1 / (4 h^2)
-  double xi2;      // xi^2
-  T inv2h_t, invh2_t, inv4h2_t, xi2_t;   // the same in the storage precision
-  T xi;            // 1e-6
-  T inv_xi;        // 1 / xi
+struct GridConsts {
+  double reg_d;                // 4 h^2 xi^2 (the xi offset in R), FP64
+  T reg;                       // same in T
 };
 
 // ---- precision-specific helpers -----------------------------------------
@@ -58,8 +62,14 @@ __device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x
 __device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
 __device__ __forceinline__ float exp_t(float x) { return __expf(x); }
 __device__ __forceinline__ double exp_t(double x) { return ::exp(x); }
-__device__ __forceinline__ float log1p_t(float x) { return ::log1pf(x); }
-__device__ __forceinline__ double log1p_t(double x) { return ::log1p(x); }
+// log(1 + e) for 0 <= e <= 1: log of the rounded sum, corrected by the
+// rounding error of that sum to first order (a few ulp, also when 1 + e
+// rounds to 1).
+__device__ __forceinline__ float log1p_t(float e) {
+  const float s = 1.0f + e;
+  return __logf(s) - ((s - 1.0f) - e) * __builtin_amdgcn_rcpf(s);
+}
+__device__ __forceinline__ double log1p_t(double e) { return ::log1p(e); }
 
 // 1/x in FP64 to full precision: hardware estimate and two Newton steps.
 __device__ __forceinline__ double rcp_f64(double x) {
@@ -84,127 +94,114 @@ struct Stencil19 {
 template <typename T>
 struct Forward {
   T c;                          // u(i)
-  T gx, gy, gz;                 // central differences
-  T mxx, myy, mzz, mxy, mxz, myz;
-  T dxx, dyy, dzz;              // 2 M_aa - Tr M
-  T tr, n2, X;                  // Tr M, ||M||^2, 2||M||^2 - (Tr M)^2
-  T q;                          // |g|^2
-  T sw;                         // W'(u) / (eps (q + xi^2))
-  T r;                          // q + xi^2
-  T rinv;                       // 1 / r
+  T ax, ay, az;                 // raw central differences
+  T mxx, myy, mzz;              // m_aa
+  T oxy, oxz, oyz;              // o_ab
+  T dxx, dyy, dzz;              // 2 m_aa - T~
+  T tr, n2, X;                  // T~, N~, X~
+  T Q, sw, R, Rinv;             // |a|^2, lam W'(u) / R, R, 1/R
 };
 
-// Adjoint of one voxel, already scaled for the transposed-stencil gather.
+// Adjoint of one voxel: derivatives of f~ with respect to the raw stencil
+// values, which the transposed stencils spread to the neighbours. The b
+// entries are returned negated (nb = -df~/db), which the gather absorbs.
 template <typename T>
 struct VoxelAdjoint {
-  T ub;                 // h^3 df/du (through W')
-  T gx, gy, gz;         // h^3/(2h) df/dg_a
-  T txx, tyy, tzz;      // h^3/h^2 df/dH_aa
-  T txy, txz, tyz;      // h^3/(4h^2) df/dH_ab
+  T ub;                 // df~/du(i) through W'
+  T gx, gy, gz;         // df~/da_a
+  T nbxx, nbyy, nbzz;   // -df~/db_aa
+  T nbxy, nbxz, nbyz;   // -df~/db_ab
 };
 
-// Stencils, M and its invariants in FP64.
+// The chain up to X~ in FP64 (see the header comment).
 template <typename T>
 __device__ __forceinline__ Forward<T> forward_fp64(const Stencil19<T>& s, const InstParams<T>& p,
-                                                   const StencilConsts<T>& k) {
+                                                   const GridConsts<T>& k) {
   const double c = s.c;
-  const double gx = (double(s.xp) - double(s.xm)) * k.inv2h;
-  const double gy = (double(s.yp) - double(s.ym)) * k.inv2h;
-  const double gz = (double(s.zp) - double(s.zm)) * k.inv2h;
+  const double ax = double(s.xp) - double(s.xm);
+  const double ay = double(s.yp) - double(s.ym);
+  const double az = double(s.zp) - double(s.zm);
   const double c2u = c + c;
-  const double hxx = (double(s.xp) + double(s.xm) - c2u) * k.invh2;
-  const double hyy = (double(s.yp) + double(s.ym) - c2u) * k.invh2;
-  const double hzz = (double(s.zp) + double(s.zm) - c2u) * k.invh2;
-  const double hxy = ((double(s.xpyp) - double(s.xpym)) - (double(s.xmyp) - double(s.xmym))) * k.inv4h2;
-  const double hxz = ((double(s.xpzp) - double(s.xpzm)) - (double(s.xmzp) - double(s.xmzm))) * k.inv4h2;
-  const double hyz = ((double(s.ypzp) - double(s.ypzm)) - (double(s.ymzp) - double(s.ymzm))) * k.inv4h2;
+  const double bxx = double(s.xp) + double(s.xm) - c2u;
+  const double byy = double(s.yp) + double(s.ym) - c2u;
+  const double bzz = double(s.zp) + double(s.zm) - c2u;
+  const double bxy = (double(s.xpyp) - double(s.xpym)) - (double(s.xmyp) - double(s.xmym));
+  const double bxz = (double(s.xpzp) - double(s.xpzm)) - (double(s.xmzp) - double(s.xmzm));
+  const double byz = (double(s.ypzp) - double(s.ypzm)) - (double(s.ymzp) - double(s.ymzm));
 
-  const double gxx = gx * gx, gyy = gy * gy, gzz = gz * gz;
-  const double q = gxx + gyy + gzz;
-  const double r = q + k.xi2;
-  const double rinv = rcp_f64(r);
-  const double w = c * (c * c - 1.0);                 // W'(u)
-  const double sw = w * p.inv_eps_d * rinv;           // W'(u) / (eps (q + xi^2))
-  const double e = p.eps_d;
-
-  const double mxx = sw * gxx - e * hxx;
-  const double myy = sw * gyy - e * hyy;
-  const double mzz = sw * gzz - e * hzz;
-  const double mxy = sw * (gx * gy) - e * hxy;
-  const double mxz = sw * (gx * gz) - e * hxz;
-  const double myz = sw * (gy * gz) - e * hyz;
-
+  const double axx = ax * ax, ayy = ay * ay, azz = az * az;
+  const double Q = axx + ayy + azz;
+  const double R = Q + k.reg_d;
+  const double Rinv = rcp_f64(R);
+  const double sw = p.lam_d * c * (c * c - 1.0) * Rinv;
+  const double sw4 = 4.0 * sw;
+  const double mxx = sw * axx - bxx;
+  const double myy = sw * ayy - byy;
+  const double mzz = sw * azz - bzz;
+  const double oxy = sw4 * (ax * ay) - bxy;
+  const double oxz = sw4 * (ax * az) - bxz;
+  const double oyz = sw4 * (ay * az) - byz;
   const double tr = mxx + myy + mzz;
-  const double n2 = mxx * mxx + myy * myy + mzz * mzz + 2.0 * (mxy * mxy + mxz * mxz + myz * myz);
+  const double n2 = (mxx * mxx + myy * myy + mzz * mzz) + 0.125 * (oxy * oxy + oxz * oxz + oyz * oyz);
 
   Forward<T> o;
   o.c = s.c;
-  o.gx = T(gx); o.gy = T(gy); o.gz = T(gz);
+  o.ax = T(ax); o.ay = T(ay); o.az = T(az);
   o.mxx = T(mxx); o.myy = T(myy); o.mzz = T(mzz);
-  o.mxy = T(mxy); o.mxz = T(mxz); o.myz = T(myz);
+  o.oxy = T(oxy); o.oxz = T(oxz); o.oyz = T(oyz);
   o.dxx = T(2.0 * mxx - tr);
   o.dyy = T(2.0 * myy - tr);
   o.dzz = T(2.0 * mzz - tr);
   o.tr = T(tr);
   o.n2 = T(n2);
   o.X = T(2.0 * n2 - tr * tr);
-  o.q = T(q);
+  o.Q = T(Q);
   o.sw = T(sw);
-  o.r = T(r);
-  o.rinv = T(rinv);
+  o.R = T(R);
+  o.Rinv = T(Rinv);
   return o;
 }
 
-// Stencils, M and its invariants in FP32, and whether X is too ill-conditioned
-// for that precision (see the header comment).
+// The chain up to X~ in FP32, and whether X~ is too ill-conditioned for it.
 __device__ __forceinline__ Forward<float> forward_fp32(const Stencil19<float>& s, const InstParams<float>& p,
-                                                       const StencilConsts<float>& k, bool& redo) {
-  const float c = s.c;
-  const float gx = (s.xp - s.xm) * k.inv2h_t;
-  const float gy = (s.yp - s.ym) * k.inv2h_t;
-  const float gz = (s.zp - s.zm) * k.inv2h_t;
-  const float c2u = c + c;
-  const float hxx = (s.xp + s.xm - c2u) * k.invh2_t;
-  const float hyy = (s.yp + s.ym - c2u) * k.invh2_t;
-  const float hzz = (s.zp + s.zm - c2u) * k.invh2_t;
-  const float hxy = ((s.xpyp - s.xpym) - (s.xmyp - s.xmym)) * k.inv4h2_t;
-  const float hxz = ((s.xpzp - s.xpzm) - (s.xmzp - s.xmzm)) * k.inv4h2_t;
-  const float hyz = ((s.ypzp - s.ypzm) - (s.ymzp - s.ymzm)) * k.inv4h2_t;
-
-  const float gxx = gx * gx, gyy = gy * gy, gzz = gz * gz;
-  const float q = gxx + gyy + gzz;
-  const float r = q + k.xi2_t;
-  const float rinv = rcp_t(r);
-  const float w = c * (c * c - 1.0f);
-  const float sw = w * p.inv_eps * rinv;
-  const float e = p.eps;
-
+                                                       const GridConsts<float>& k, bool& redo) {
   Forward<float> o;
-  o.mxx = sw * gxx - e * hxx;
-  o.myy = sw * gyy - e * hyy;
-  o.mzz = sw * gzz - e * hzz;
-  o.mxy = sw * (gx * gy) - e * hxy;
-  o.mxz = sw * (gx * gz) - e * hxz;
-  o.myz = sw * (gy * gz) - e * hyz;
-  const float tr = o.mxx + o.myy + o.mzz;
-  const float d = o.mxx * o.mxx + o.myy * o.myy + o.mzz * o.mzz;
-  const float od = o.mxy * o.mxy + o.mxz * o.mxz + o.myz * o.myz;
-  const float n2 = d + 2.0f * od;
-  const float tr2 = tr * tr;
-  o.X = 2.0f * n2 - tr2;
-  const float scale = 2.0f * n2 + tr2;
-  redo = (scale > 4096.0f * k.xi) && (fabsf(o.X) < scale * (1.0f / 4096.0f));
+  const float c = s.c;
   o.c = c;
-  o.gx = gx; o.gy = gy; o.gz = gz;
-  o.dxx = o.mxx + o.mxx - tr;
-  o.dyy = o.myy + o.myy - tr;
-  o.dzz = o.mzz + o.mzz - tr;
-  o.tr = tr;
-  o.n2 = n2;
-  o.q = q;
-  o.sw = sw;
-  o.r = r;
-  o.rinv = rinv;
+  o.ax = s.xp - s.xm;
+  o.ay = s.yp - s.ym;
+  o.az = s.zp - s.zm;
+  const float c2u = c + c;
+  const float bxx = (s.xp + s.xm) - c2u;
+  const float byy = (s.yp + s.ym) - c2u;
+  const float bzz = (s.zp + s.zm) - c2u;
+  const float bxy = (s.xpyp - s.xpym) - (s.xmyp - s.xmym);
+  const float bxz = (s.xpzp - s.xpzm) - (s.xmzp - s.xmzm);
+  const float byz = (s.ypzp - s.ypzm) - (s.ymzp - s.ymzm);
+
+  const float axx = o.ax * o.ax, ayy = o.ay * o.ay, azz = o.az * o.az;
+  o.Q = axx + ayy + azz;
+  o.R = o.Q + k.reg;
+  o.Rinv = rcp_t(o.R);
+  o.sw = c * (p.lam * (c * c) - p.lam) * o.Rinv;
+  const float sw4 = 4.0f * o.sw;
+  o.mxx = o.sw * axx - bxx;
+  o.myy = o.sw * ayy - byy;
+  o.mzz = o.sw * azz - bzz;
+  o.oxy = sw4 * (o.ax * o.ay) - bxy;
+  o.oxz = sw4 * (o.ax * o.az) - bxz;
+  o.oyz = sw4 * (o.ay * o.az) - byz;
+  o.tr = o.mxx + o.myy + o.mzz;
+  const float d = o.mxx * o.mxx + o.myy * o.myy + o.mzz * o.mzz;
+  const float od = o.oxy * o.oxy + o.oxz * o.oxz + o.oyz * o.oyz;
+  o.n2 = od * 0.125f + d;
+  const float n2x2 = o.n2 + o.n2;
+  o.X = n2x2 - o.tr * o.tr;
+  const float scale = n2x2 + o.tr * o.tr;
+  redo = (scale > 4096.0f * p.xi) && (fabsf(o.X) < scale * (1.0f / 4096.0f));
+  o.dxx = 2.0f * o.mxx - o.tr;
+  o.dyy = 2.0f * o.myy - o.tr;
+  o.dzz = 2.0f * o.mzz - o.tr;
   return o;
 }
 
@@ -213,14 +210,14 @@ __device__ __forceinline__ Forward<float> forward_fp32(const Stencil19<float>& s
 template <typename Reload>
 __device__ __forceinline__ Forward<double> forward_chain(const Stencil19<double>& s, Reload,
                                                          const InstParams<double>& p,
-                                                         const StencilConsts<double>& k) {
+                                                         const GridConsts<double>& k) {
   return forward_fp64(s, p, k);
 }
 
 template <typename Reload>
 __device__ __forceinline__ Forward<float> forward_chain(const Stencil19<float>& s, Reload reload,
                                                         const InstParams<float>& p,
-                                                        const StencilConsts<float>& k) {
+                                                        const GridConsts<float>& k) {
   bool redo;
   Forward<float> o = forward_fp32(s, p, k, redo);
   if (redo) o = forward_fp64(reload(), p, k);
@@ -228,89 +225,88 @@ __device__ __forceinline__ Forward<float> forward_chain(const Stencil19<float>& 
 }
 
 // Smoothed positive part P = xi log(1 + exp(X/xi)) and its derivative
-// sig = logistic(X/xi). Beyond |X| = 40 xi, exp(-|X|/xi) < 5e-18 is below the
-// rounding unit of either precision, so P = max(X, 0) and sig = [X > 0] exactly.
+// sig = logistic(X/xi), in X~ units. Beyond |X| = 40 xi, exp(-|X|/xi) < 5e-18
+// is below the rounding unit of either precision, so P = max(X, 0) and
+// sig = [X > 0] exactly.
 template <typename T>
-__device__ __forceinline__ void softplus_xi(T X, const StencilConsts<T>& k, T& P, T& sig) {
+__device__ __forceinline__ void softplus_xi(T X, const InstParams<T>& p, T& P, T& sig) {
   const T ax = X < T(0) ? -X : X;
-  if (ax < T(40) * k.xi) {
-    const T e = exp_t(-ax * k.inv_xi);
-    const T mx = X > T(0) ? X : T(0);
-    P = mx + k.xi * log1p_t(e);
+  const T mx = X > T(0) ? X : T(0);
+  if (ax < T(40) * p.xi) {
+    const T e = exp_t(-ax * p.inv_xi);
+    P = mx + p.xi * log1p_t(e);
     const T inv = rcp_t(T(1) + e);
     sig = X >= T(0) ? inv : e * inv;
   } else {
-    P = X > T(0) ? X : T(0);
+    P = mx;
     sig = X > T(0) ? T(1) : T(0);
   }
 }
 
-// Forward only: the energy density f at one voxel.
+// Forward only: the scaled energy density f~ = h^3 f at one voxel.
 template <typename T, typename Reload>
 __device__ __forceinline__ T voxel_density(const Stencil19<T>& s, Reload reload, const InstParams<T>& p,
-                                           const StencilConsts<T>& k) {
+                                           const GridConsts<T>& k) {
   const Forward<T> fw = forward_chain(s, reload, p, k);
   T P, sig;
-  softplus_xi(fw.X, k, P, sig);
+  softplus_xi(fw.X, p, P, sig);
   const T S = P > T(0) ? P * rsqrt_t(P) : T(0);
-  const T rho = fw.r * rsqrt_t(fw.r);
-  return p.c1 * fw.n2 + fw.tr * (p.c2 * fw.tr + p.c3 * S + p.c4 * rho) + p.c5 * rho * S + p.c6e * fw.q;
+  const T rho = fw.R * rsqrt_t(fw.R);
+  return p.C1 * fw.n2 + fw.tr * (p.C2 * fw.tr + p.C3 * S + p.C4 * rho) + p.C5 * rho * S + p.C6 * fw.Q;
 }
 
-// Forward and adjoint at one voxel. Returns the density f; writes the scaled
-// partial derivatives of f with respect to u(i), g_a(i) and H_ab(i).
+// Forward and adjoint at one voxel. Returns f~ and writes its derivatives with
+// respect to u(i), a_a and (negated) b_ab.
 template <typename T, typename Reload>
 __device__ __forceinline__ T voxel_density_adjoint(const Stencil19<T>& s, Reload reload, const InstParams<T>& p,
-                                                   const StencilConsts<T>& k, VoxelAdjoint<T>& a) {
+                                                   const GridConsts<T>& k, VoxelAdjoint<T>& a) {
   const Forward<T> fw = forward_chain(s, reload, p, k);
   const T tr = fw.tr;
   T P, sig;
-  softplus_xi(fw.X, k, P, sig);
-  const bool pos = P > T(0);
-  const T rsP = pos ? rsqrt_t(P) : T(0);
+  softplus_xi(fw.X, p, P, sig);
+  const T rsP = P > T(0) ? rsqrt_t(P) : T(0);
   const T S = P * rsP;
-  const T rs = rsqrt_t(fw.r);
-  const T rho = fw.r * rs;
+  const T rs = rsqrt_t(fw.R);
+  const T rho = fw.R * rs;                         // 2h rho
 
-  const T f = p.c1 * fw.n2 + tr * (p.c2 * tr + p.c3 * S + p.c4 * rho) + p.c5 * rho * S + p.c6e * fw.q;
+  const T f = p.C1 * fw.n2 + tr * (p.C2 * tr + p.C3 * S + p.C4 * rho) + p.C5 * rho * S + p.C6 * fw.Q;
 
   // ---- reverse sweep ----
-  const T Sb = p.c3 * tr + p.c5 * rho;               // df/dS
-  const T rhob = p.c4 * tr + p.c5 * S;               // df/drho
-  const T kap = Sb * sig * (T(0.5) * rsP);           // df/dX  (dS/dX = sig / (2S); 0 where S = 0)
-  // df/dM through N2 (c1 + 2 kap), Tr M (trb0 - 2 Tr M kap) and X; the X part
-  // of the diagonal is written 2 kap (2 M_aa - Tr M), with the difference formed
-  // by the forward chain, so that no two kap-sized terms cancel.
-  const T trb0 = T(2) * p.c2 * tr + p.c3 * S + p.c4 * rho;
-  const T c1x2 = p.c1 + p.c1;
+  const T Sb = p.C3 * tr + p.C5 * rho;             // df/dS~
+  const T rhob = p.C4 * tr + p.C5 * S;             // df/drho~
+  const T kap = Sb * sig * (T(0.5) * rsP);         // df/dX~  (dS~/dX~ = sig / (2S~); 0 where S~ = 0)
   const T kap2 = kap + kap;
-  const T bxx = c1x2 * fw.mxx + trb0 + kap2 * fw.dxx;   // df/dM_aa
+  // df/dm_aa = 2 C1 m_aa + df/dT~ + 2 kap (2 m_aa - T~): the X~ part is written
+  // with the difference formed in the forward chain, so no two kap-sized
+  // terms cancel.
+  const T trb0 = T(2) * p.C2 * tr + p.C3 * S + p.C4 * rho;
+  const T c1x2 = p.C1 + p.C1;
+  const T bxx = c1x2 * fw.mxx + trb0 + kap2 * fw.dxx;
   const T byy = c1x2 * fw.myy + trb0 + kap2 * fw.dyy;
   const T bzz = c1x2 * fw.mzz + trb0 + kap2 * fw.dzz;
-  const T n2b4 = T(4) * (p.c1 + kap2);
-  const T bxy = n2b4 * fw.mxy;                       // df/dM_ab (both symmetric entries)
-  const T bxz = n2b4 * fw.mxz;
-  const T byz = n2b4 * fw.myz;
+  // q_ab = 4 df/do_ab = (C1 + 2 kap) o_ab
+  const T cq = p.C1 + kap2;
+  const T qxy = cq * fw.oxy, qxz = cq * fw.oxz, qyz = cq * fw.oyz;
+  // m_aa = sw a_a^2 - b_aa,  o_ab = 4 sw a_a a_b - b_ab
+  a.nbxx = bxx;
+  a.nbyy = byy;
+  a.nbzz = bzz;
+  a.nbxy = T(0.25) * qxy;
+  a.nbxz = T(0.25) * qxz;
+  a.nbyz = T(0.25) * qyz;
 
-  // M_ab = -eps H_ab + sw g_a g_b
-  a.txx = p.sc_tdiag * bxx;
-  a.tyy = p.sc_tdiag * byy;
-  a.tzz = p.sc_tdiag * bzz;
-  a.txy = p.sc_toff * bxy;
-  a.txz = p.sc_toff * bxz;
-  a.tyz = p.sc_toff * byz;
-
-  const T gx = fw.gx, gy = fw.gy, gz = fw.gz, sw = fw.sw;
-  const T swb = bxx * gx * gx + byy * gy * gy + bzz * gz * gz + bxy * gx * gy + bxz * gx * gz + byz * gy * gz;
-  // sw = W'(u) / (eps r), r = q + xi^2, rho = sqrt(r)
-  const T qb = p.c6e + T(0.5) * rhob * rs - swb * sw * fw.rinv;                       // df/dq
+  const T ax = fw.ax, ay = fw.ay, az = fw.az, sw = fw.sw;
+  const T swb = bxx * (ax * ax) + byy * (ay * ay) + bzz * (az * az) +
+                (qxy * (ax * ay) + qxz * (ax * az) + qyz * (ay * az));      // df/dsw
+  // sw = lam W'(u) / R, R = Q + reg, rho~ = sqrt(R)
+  const T Qb = p.C6 + T(0.5) * rhob * rs - swb * sw * fw.Rinv;            // df/dQ
   const T c = fw.c;
-  a.ub = p.sc_u * swb * (T(3) * c * c - T(1)) * p.inv_eps * fw.rinv;
-  const T qb2 = qb + qb;
+  a.ub = swb * (p.lam * (T(3) * c * c - T(1))) * fw.Rinv;
+  const T Qb2 = Qb + Qb;
   const T bxx2 = bxx + bxx, byy2 = byy + byy, bzz2 = bzz + bzz;
-  a.gx = p.sc_gamma * (sw * (bxx2 * gx + bxy * gy + bxz * gz) + qb2 * gx);
-  a.gy = p.sc_gamma * (sw * (byy2 * gy + bxy * gx + byz * gz) + qb2 * gy);
-  a.gz = p.sc_gamma * (sw * (bzz2 * gz + bxz * gx + byz * gy) + qb2 * gz);
+  a.gx = sw * (bxx2 * ax + qxy * ay + qxz * az) + Qb2 * ax;
+  a.gy = sw * (byy2 * ay + qxy * ax + qyz * az) + Qb2 * ay;
+  a.gz = sw * (bzz2 * az + qxz * ax + qyz * ay) + Qb2 * az;
   return f;
 }
 
