@@ -86,9 +86,9 @@ const std::vector<Variant>& variants() {
       Variant x{tx, ty, nt, 2, {}, k};
       r.push_back(x);
     };
+    add32(64, 32, 1024, make_kernels<float, 64, 32, 1024>());
     add32(64, 32, 768, make_kernels<float, 64, 32, 768>());
     add32(64, 16, 512, make_kernels<float, 64, 16, 512>());
-    add32(64, 32, 1024, make_kernels<float, 64, 32, 1024>());
     add32(64, 16, 1024, make_kernels<float, 64, 16, 1024>());
     add32(64, 16, 384, make_kernels<float, 64, 16, 384>());
     add32(32, 32, 512, make_kernels<float, 32, 32, 512>());

@@ -255,8 +255,9 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
 
   double acc_f = 0.0, acc_m = 0.0;
   T c_prev[NO], l_prev[NO], l_pp[NO];
+  T m1c[NO], m2c[NO], m1n[NO], m2n[NO];        // Adam moments: current and next output plane
 #pragma unroll
-  for (int j = 0; j < NO; ++j) c_prev[j] = l_prev[j] = l_pp[j] = T(0);
+  for (int j = 0; j < NO; ++j) c_prev[j] = l_prev[j] = l_pp[j] = m1n[j] = m2n[j] = T(0);
 
   // plane q lives in slot (q - k0 + 2) & 3
   fetch(k0 - 2);
@@ -271,17 +272,25 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
     const int sm = it & 3, sc = (it + 1) & 3, sp = (it + 2) & 3;   // slots of p-1, p, p+1
     stage(sp);
     if (it + 1 < nit) fetch(p + 2);            // in flight during this plane's compute
-    // Adam moments of this iteration's output plane p-1, also in flight
-    T m1v[NO], m2v[NO];
-    if (MODE == kStepAdam && it >= 2) {
+    // Adam moments of output plane p (written in the next iteration), loaded a
+    // whole plane ahead: the wait for them then leaves this plane's stores in
+    // flight (loads and stores share one in-order counter)
+    if (MODE == kStepAdam) {
 #pragma unroll
       for (int j = 0; j < NO; ++j) {
-        const int w = tid + j * NT;
-        const int gx = x0 + w % TX, gy = y0 + w / TX;
-        const size_t gi = inst_off + (size_t)(p - 1) * plane + (size_t)gy * a.nx + gx;
-        const bool ok = w < TX * TY && gx < a.nx && gy < a.ny;
-        m1v[j] = ok ? a.m1[gi] : T(0);
-        m2v[j] = ok ? a.m2[gi] : T(0);
+        m1c[j] = m1n[j];
+        m2c[j] = m2n[j];
+      }
+      if (it + 1 < nit && p >= k0) {
+#pragma unroll
+        for (int j = 0; j < NO; ++j) {
+          const int w = tid + j * NT;
+          const int gx = x0 + w % TX, gy = y0 + w / TX;
+          const size_t gi = inst_off + (size_t)p * plane + (size_t)gy * a.nx + gx;
+          const bool ok = w < TX * TY && gx < a.nx && gy < a.ny;
+          m1n[j] = ok ? a.m1[gi] : T(0);
+          m2n[j] = ok ? a.m2[gi] : T(0);
+        }
       }
     }
     __syncthreads();
@@ -349,11 +358,11 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
               dstb[idx] = un;
               acc_m += double(un);
             } else if (MODE == kStepAdam) {
-              const T mo = a.beta1 * m1v[j] + (T(1) - a.beta1) * g;
-              const T vo = a.beta2 * m2v[j] + (T(1) - a.beta2) * g * g;
+              const T mo = a.beta1 * m1c[j] + (T(1) - a.beta1) * g;
+              const T vo = a.beta2 * m2c[j] + (T(1) - a.beta2) * g * g;
               a.m1[inst_off + idx] = mo;
               a.m2[inst_off + idx] = vo;
-              const T un = uc - a.tau * (mo * bc1) / (sqrt(vo * bc2) + a.adam_eps);
+              const T un = uc - a.tau * (mo * bc1) * rcp_t(sqrt_t(vo * bc2) + a.adam_eps);
               dstb[idx] = un;
               acc_m += double(un);
             } else {
