@@ -86,13 +86,11 @@ const std::vector<Variant>& variants() {
       Variant x{tx, ty, nt, 2, {}, k};
       r.push_back(x);
     };
-    add32(64, 32, 1024, make_kernels<float, 64, 32, 1024>());
-    add32(64, 32, 768, make_kernels<float, 64, 32, 768>());
     add32(64, 16, 512, make_kernels<float, 64, 16, 512>());
-    add32(64, 16, 1024, make_kernels<float, 64, 16, 1024>());
-    add32(64, 16, 384, make_kernels<float, 64, 16, 384>());
+    add32(64, 32, 1024, make_kernels<float, 64, 32, 1024>());
     add32(32, 32, 512, make_kernels<float, 32, 32, 512>());
-    add32(32, 16, 320, make_kernels<float, 32, 16, 320>());
+    add32(64, 32, 768, make_kernels<float, 64, 32, 768>());
+    add32(64, 16, 1024, make_kernels<float, 64, 16, 1024>());
     add32(64, 8, 512, make_kernels<float, 64, 8, 512>());
     add32(32, 16, 512, make_kernels<float, 32, 16, 512>());
     add32(32, 8, 256, make_kernels<float, 32, 8, 256>());
@@ -267,6 +265,15 @@ struct Geometry {
   int ntx, nty, nzc, lz, per_inst;
 };
 
+// Blocks of the step sweep of `variant` that one compute unit holds at once.
+int block_slots(const fe_ctx* c, int variant) {
+  const Variant& v = variants()[variant];
+  const void* fn = c->grid.dtype == FE_F32 ? (const void*)v.k32.step : (const void*)v.k64.step;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, v.nt, 0) != hipSuccess || n < 1) n = 1;
+  return n;
+}
+
 Geometry geometry(const fe_ctx* c, int variant, int lz_req) {
   const Variant& v = variants()[variant];
   Geometry g;
@@ -275,10 +282,11 @@ Geometry geometry(const fe_ctx* c, int variant, int lz_req) {
   int lz = lz_req;
   if (lz <= 0) {
     // the longest power-of-two chunk (fewest recomputed boundary planes) that
-    // still gives every compute unit a block, and at least 4 planes
+    // still fills every resident block slot of the device, and at least 4 planes
     const double cols = (double)g.ntx * g.nty * c->grid.batch;
+    const double slots = (double)c->num_cu * block_slots(c, variant);
     lz = 4;
-    while (2 * lz <= c->grid.nz && cols * ceil_div(c->grid.nz, 2 * lz) >= c->num_cu) lz *= 2;
+    while (2 * lz <= c->grid.nz && cols * ceil_div(c->grid.nz, 2 * lz) >= slots) lz *= 2;
   }
   lz = std::min(std::max(lz, 1), c->grid.nz);
   g.lz = lz;

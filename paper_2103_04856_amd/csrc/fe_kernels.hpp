@@ -196,9 +196,10 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   constexpr int UX = TX + 4, UY = TY + 4;      // u window: interior + halo 2
   constexpr int RX = TX + 2, RY = TY + 2;      // adjoint ring: interior + 1
   constexpr int NU = (UX * UY + NT - 1) / NT;  // u elements staged per thread per plane
-  constexpr int NO = (TX * TY + NT - 1) / NT;  // interior (output) voxels per thread
+  constexpr int NI = TX * TY;                  // interior (output) voxels
+  constexpr int NO = (NI + NT - 1) / NT;       // interior voxels per thread
   constexpr int NB = 2 * RX + 2 * TY;          // border voxels of the ring
-  constexpr int NBR = (NB + NT - 1) / NT;      // border voxels per thread
+  constexpr int NW = (NI + NB + NT - 1) / NT;  // ring voxels per thread (interior first)
   enum { GX = 0, GY, BXX, BYY, BXY, BXZ, BYZ, NFIELD };
   constexpr bool STEP = MODE != kGrad;
 
@@ -309,28 +310,27 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
       sx[BXY][v] = ad.nbxy; sx[BXZ][v] = ad.nbxz; sx[BYZ][v] = ad.nbyz;
       return f;
     };
+    // Interior and border voxels are dealt out from one index space, so the
+    // per-thread counts differ by at most one (the border goes to the threads
+    // whose interior share is shorter).
     T own_ub[NO], own_gz[NO], own_bxx[NO], own_byy[NO], own_bzz[NO];
 #pragma unroll
-    for (int j = 0; j < NO; ++j) {
-      const int w = tid + j * NT;
-      if (w < TX * TY) {
-        const int ix = w % TX, iy = w / TX;
+    for (int j = 0; j < NW; ++j) {
+      const int item = tid + j * NT;
+      if (item < NI + NB) {
+        const bool inner = item < NI;
+        const int ix = item % TX, iy = item / TX;
+        const int v = inner ? (iy + 1) * RX + ix + 1 : border_pos(item - NI);
         VoxelAdjoint<T> ad;
-        const T f = eval((iy + 1) * RX + ix + 1, ad);
-        own_ub[j] = ad.ub;
-        own_gz[j] = ad.gz;
-        own_bxx[j] = ad.nbxx;
-        own_byy[j] = ad.nbyy;
-        own_bzz[j] = ad.nbzz;
-        if (out_plane && x0 + ix < a.nx && y0 + iy < a.ny) acc_f += double(f);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NBR; ++j) {
-      const int b = tid + j * NT;
-      if (b < NB) {
-        VoxelAdjoint<T> ad;
-        (void)eval(border_pos(b), ad);
+        const T f = eval(v, ad);
+        if (j < NO && inner) {
+          own_ub[j] = ad.ub;
+          own_gz[j] = ad.gz;
+          own_bxx[j] = ad.nbxx;
+          own_byy[j] = ad.nbyy;
+          own_bzz[j] = ad.nbzz;
+          if (out_plane && x0 + ix < a.nx && y0 + iy < a.ny) acc_f += double(f);
+        }
       }
     }
     __syncthreads();
