@@ -6,8 +6,9 @@ import it. It imports nothing from the product package, and the product
 package imports nothing from it.
 
 Modules:
-  fe_oracle     the discrete energy, its hand-derived adjoint gradient and the
-                mass-projected descent step (eqs. (Meps), (Feps); Sec. 4.1)
+  fe_oracle     the discrete energy, its hand-derived adjoint gradient, the
+                mass-projected descent step (eqs. (Meps), (Feps); Sec. 4.1), and
+                the H^-1 flow of Algorithm 1 (div A + m0, blur, Adam on A)
   classical     Cahn-Hilliard, Willmore and Helfrich phase fields and the diffuse
                 curvatures, each from its own equation (Secs. 2.3, 3.1)
   closed_forms  continuum values on tanh-profile spheres, cylinders and planes by
@@ -18,9 +19,13 @@ Modules:
 from .fe_oracle import (XI, double_well, double_well_prime, fd_gradient, fd_hessian,
                         fd_laplacian, feps_coefficients, softplus, logistic, pointwise,
                         energy, energy_abs, adjoint_fields, energy_grad, mass_projected_step,
-                        descend, adam_projected_step, descend_adam, energy_grad_batch)
+                        descend, adam_projected_step, descend_adam, energy_grad_batch,
+                        fd_divergence, gaussian_weights, gaussian_blur, hminus_energy,
+                        hminus_energy_grad, hminus_adam_step, hminus_descend)
 
 __all__ = ["XI", "double_well", "double_well_prime", "fd_gradient", "fd_hessian",
            "fd_laplacian", "feps_coefficients", "softplus", "logistic", "pointwise", "energy",
            "energy_abs", "adjoint_fields", "energy_grad", "mass_projected_step", "descend",
-           "adam_projected_step", "descend_adam", "energy_grad_batch"]
+           "adam_projected_step", "descend_adam", "energy_grad_batch", "fd_divergence",
+           "gaussian_weights", "gaussian_blur", "hminus_energy", "hminus_energy_grad",
+           "hminus_adam_step", "hminus_descend"]

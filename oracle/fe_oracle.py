@@ -340,3 +340,86 @@ def energy_grad_batch(U, h, eps_list, a_list, xi=XI, mode="smooth"):
         Es.append(E)
         Gs.append(G)
     return np.array(Es), np.stack(Gs)
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1 (Sec. 4.1): the H^-1 flow through u = div A + m0, a small
+# Gaussian blur, and Adam on the vector field A
+# --------------------------------------------------------------------------
+
+def fd_divergence(A, h):
+    """div A = sum_a (A_a(i + e_a) - A_a(i - e_a)) / (2h), periodic; A is [3, nz, ny, nx]
+    with components (x, y, z) (the same central differences as the gradient)."""
+    return sum((_at(A[a_], _unit(a_)) - _at(A[a_], _unit(a_, -1))) / (2.0 * h) for a_ in range(3))
+
+
+def gaussian_weights(sigma_k):
+    """Normalised taps w_j, |j| <= ceil(4 sigma_k), of the sampled Gaussian exp(-j^2 / (2 sigma_k^2));
+    sigma_k = 0 gives the identity [1]."""
+    if sigma_k <= 0:
+        return np.array([1.0])
+    r = int(np.ceil(4.0 * sigma_k))
+    j = np.arange(-r, r + 1, dtype=np.float64)
+    w = np.exp(-j * j / (2.0 * sigma_k * sigma_k))
+    return w / w.sum()
+
+
+def gaussian_blur(u, sigma_k):
+    """Separable periodic convolution of u [nz, ny, nx] with the sampled Gaussian along
+    x, then y, then z. The kernel is even, so the blur is its own adjoint."""
+    w = gaussian_weights(sigma_k)
+    r = (len(w) - 1) // 2
+    out = np.asarray(u, dtype=np.float64)
+    for a_ in range(3):
+        acc = np.zeros_like(out)
+        for k, wk in enumerate(w):
+            acc += wk * _at(out, _unit(a_, k - r))
+        out = acc
+    return out
+
+
+def hminus_energy(A, h, eps, a, m0, sigma_k, xi=XI, mode="smooth"):
+    """G_eps(A) = F_h(k * (div A + m0)) (Algorithm 1, with the blur before the energy)."""
+    return energy(gaussian_blur(fd_divergence(A, h) + m0, sigma_k), h, eps, a, xi, mode)
+
+
+def hminus_energy_grad(A, h, eps, a, m0, sigma_k, xi=XI, mode="smooth"):
+    """(G_eps(A), dG/dA, u) with u = k * (div A + m0): the chain rule of Algorithm 1.
+
+    dG/du_b = dF_h/du (at the blurred field), dG/du = k * dG/du_b (even kernel),
+    dG/dA_a = -(dG/du(i + e_a) - dG/du(i - e_a)) / (2h) (the central difference is
+    anti-self-adjoint on a periodic grid), i.e. dG/dA = -grad dF/du of Sec. 4.1.
+    """
+    u = gaussian_blur(fd_divergence(A, h) + m0, sigma_k)
+    E, gb = energy_grad(u, h, eps, a, xi, mode)
+    gu = gaussian_blur(gb, sigma_k)
+    gA = np.stack([-(_at(gu, _unit(a_)) - _at(gu, _unit(a_, -1))) / (2.0 * h) for a_ in range(3)])
+    return E, gA, u
+
+
+def hminus_adam_step(A, m1, m2, t, h, eps, a, m0, sigma_k, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8,
+                     xi=XI, mode="smooth"):
+    """One iteration of Algorithm 1: G and dG/dA at A, then Adam on A (step number t >= 1).
+    Returns (A_new, m1, m2, G(A), u) with u the blurred phase field at A."""
+    E, gA, u = hminus_energy_grad(A, h, eps, a, m0, sigma_k, xi, mode)
+    m1 = beta1 * m1 + (1.0 - beta1) * gA
+    m2 = beta2 * m2 + (1.0 - beta2) * gA * gA
+    mhat = m1 / (1.0 - beta1 ** t)
+    vhat = m2 / (1.0 - beta2 ** t)
+    A_new = np.asarray(A, dtype=np.float64) - lr * mhat / (np.sqrt(vhat) + adam_eps)
+    return A_new, m1, m2, E, u
+
+
+def hminus_descend(A, h, eps, a, m0, sigma_k, nsteps, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8,
+                   xi=XI, mode="smooth"):
+    """nsteps iterations of Algorithm 1 from zero moments. Returns (A, [G before each step], u_final)
+    with u_final = k * (div A + m0) at the final A."""
+    A = np.asarray(A, dtype=np.float64)
+    m1 = np.zeros_like(A)
+    m2 = np.zeros_like(A)
+    energies = []
+    for t in range(1, nsteps + 1):
+        A, m1, m2, E, _ = hminus_adam_step(A, m1, m2, t, h, eps, a, m0, sigma_k, lr, beta1, beta2, adam_eps,
+                                           xi, mode)
+        energies.append(E)
+    return A, energies, gaussian_blur(fd_divergence(A, h) + m0, sigma_k)

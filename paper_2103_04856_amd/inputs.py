@@ -83,3 +83,11 @@ def random_instance_table(batch, seed):
     coeffs = np.stack([A, C, B, D, D, np.zeros(batch)], axis=1)
     means = rng.uniform(-0.5, 0.5, batch)
     return coeffs, means
+
+
+def white_noise_vector_field(n, seed, std, batch=None):
+    """A0 ~ N(0, std^2) i.i.d. per voxel and component: the random initial vector field
+    of Algorithm 1. Shape [3, n, n, n] (components x, y, z) or [batch, 3, n, n, n]."""
+    rng = np.random.default_rng(seed)
+    shape = (3, n, n, n) if batch is None else (batch, 3, n, n, n)
+    return rng.normal(0.0, std, size=shape)
