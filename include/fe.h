@@ -143,6 +143,34 @@ int fe_step_adam(fe_ctx* ctx, void* u, const double* mass, double lr, double bet
 int fe_adam_reset(fe_ctx* ctx);
 
 /*
+ * nsteps iterations of the paper's generation algorithm (Algorithm 1, Sec. 4.1):
+ * the mass-preserving H^-1 flow written as an L2 flow on a periodic vector
+ * field A through u = div A + m0, with a small Gaussian blur before the energy
+ * and Adam on A:
+ *   u = k * (div A + m0),  G(A) = F_h(u),
+ *   dG/dA = -grad (k * dF_h/du)   (div and grad are the periodic central
+ *                                   differences; the kernel k is even),
+ *   A <- A - lr mhat / (sqrt(vhat) + adam_eps)   (Adam, moments kept in the
+ *                                                  context; fe_hminus_reset clears them).
+ * mean(u) = m0 holds exactly, since div A has zero mean and k sums to 1.
+ *   A        device [batch][3][nz][ny][nx] (components x, y, z), updated in place.
+ *   m0       host [batch]: the mass (target mean) of each instance.
+ *   sigma_k  blur standard deviation in voxels, 0 <= sigma_k <= 4 (0: no blur);
+ *            taps exp(-j^2 / (2 sigma_k^2)), |j| <= ceil(4 sigma_k), normalised.
+ *   lr, beta1, beta2, adam_eps  Adam settings (the paper: 1e-3, 0.9, 0.999).
+ *   u_out    device field [batch][nz][ny][nx] or NULL: receives k * (div A + m0)
+ *            at the final A (the field whose zero level set is the texture).
+ *   energy   host [batch] or NULL: G before the last update (synchronises).
+ * Requires nz * batch and ny * batch <= 65535. Allocates two work fields and
+ * the six moment fields of A on first use; replays captured graphs.
+ */
+int fe_hminus_step(fe_ctx* ctx, void* A, const double* m0, double sigma_k, double lr, double beta1,
+                   double beta2, double adam_eps, int nsteps, void* u_out, double* energy);
+
+/* Zero the Adam moments of A and reset their step number to 1. No allocation. */
+int fe_hminus_reset(fe_ctx* ctx);
+
+/*
  * Launch-shape selection. Variants are numbered 0 .. fe_num_variants()-1;
  * fe_variant_info describes one (x and y interior tile, threads per block,
  * element size it supports). fe_set_launch picks a variant and a z-chunk

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "fe.h"
+#include "fe_flow.hpp"
 #include "fe_kernels.hpp"
 
 namespace {
@@ -130,17 +131,18 @@ struct StepRule {
 };
 
 struct GraphKey {
-  void* u;
-  int mode;
-  double tau, beta1, beta2, adam_eps;
-  int pairs;
+  void* u;                      // the field (or vector field) the graph updates in place
+  int mode;                     // fe::SweepMode of a step loop, or kFlowMode
+  double tau, beta1, beta2, adam_eps, sigma;
+  int pairs;                    // step pairs (or flow iterations) per graph
   int variant;
   int lz;
   bool operator<(const GraphKey& o) const {
-    return std::tie(u, mode, tau, beta1, beta2, adam_eps, pairs, variant, lz) <
-           std::tie(o.u, o.mode, o.tau, o.beta1, o.beta2, o.adam_eps, o.pairs, o.variant, o.lz);
+    return std::tie(u, mode, tau, beta1, beta2, adam_eps, sigma, pairs, variant, lz) <
+           std::tie(o.u, o.mode, o.tau, o.beta1, o.beta2, o.adam_eps, o.sigma, o.pairs, o.variant, o.lz);
   }
 };
+constexpr int kFlowMode = 100;
 
 struct fe_ctx {
   fe_grid grid{};
@@ -158,6 +160,11 @@ struct fe_ctx {
   void* d_m1 = nullptr;               // Adam moments, allocated by the first fe_step_adam
   void* d_m2 = nullptr;
   int* d_adam_t = nullptr;            // Adam step number (device)
+  void* d_w0 = nullptr;               // H^-1 flow: two scalar work fields
+  void* d_w1 = nullptr;
+  void* d_am1 = nullptr;              // H^-1 flow: Adam moments of A ([batch][3] fields each)
+  void* d_am2 = nullptr;
+  int* d_flow_t = nullptr;            // H^-1 flow: Adam step number (device)
   size_t max_blocks = 0;              // per instance, over all variants and z chunks
   int variant = -1;
   int lz = 0;                         // 0 = automatic
@@ -397,6 +404,117 @@ int adam_reset_launch(fe_ctx* c) {
 
 int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int nsteps, double* energy);
 
+// ---- H^-1 flow (Algorithm 1) ---------------------------------------------
+
+template <typename T>
+fe::BlurTaps<T> blur_taps(double sigma_k) {
+  fe::BlurTaps<T> k{};
+  k.r = sigma_k > 0.0 ? (int)std::ceil(4.0 * sigma_k) : 0;
+  double w[2 * fe::kBlurMaxR + 1];
+  double sum = 0.0;
+  for (int j = -k.r; j <= k.r; ++j) {
+    w[j + k.r] = k.r ? std::exp(-(double)j * j / (2.0 * sigma_k * sigma_k)) : 1.0;
+    sum += w[j + k.r];
+  }
+  for (int j = 0; j <= 2 * k.r; ++j) k.w[j] = T(w[j] / sum);
+  return k;
+}
+
+struct FlowRule {
+  double sigma_k, lr, beta1, beta2, adam_eps;
+};
+
+// u = k * (div A + m0) into `out`, using the two work fields (out may be one of them).
+template <typename T>
+int flow_field(fe_ctx* c, hipStream_t s, const void* A, void* out, double sigma_k) {
+  const fe::FieldDims d{c->grid.nx, c->grid.ny, c->grid.nz, c->grid.batch};
+  const dim3 blk(64, 4);
+  const dim3 g3(ceil_div(d.nx, 64), ceil_div(d.ny, 4), d.nz * d.batch);
+  const T inv2h = T(1.0 / (2.0 * c->grid.h));
+  if (sigma_k <= 0.0) {
+    hipLaunchKernelGGL(fe::div_field<T>, g3, blk, 0, s, (const T*)A, (T*)out, c->d_mass, d, inv2h);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+  }
+  T* w0 = static_cast<T*>(c->d_w0);
+  T* w1 = static_cast<T*>(c->d_w1);
+  T* mid = out == c->d_w0 ? w1 : w0;            // never the output
+  T* other = mid == w0 ? w1 : w0;               // may be the output
+  const fe::BlurTaps<T> k = blur_taps<T>(sigma_k);
+  hipLaunchKernelGGL(fe::div_field<T>, g3, blk, 0, s, (const T*)A, mid, c->d_mass, d, inv2h);
+  hipLaunchKernelGGL(fe::blur_x<T>, dim3(ceil_div(d.nx, 256), d.ny, d.nz * d.batch), dim3(256), 0, s,
+                     (const T*)mid, other, d, k);
+  hipLaunchKernelGGL((fe::blur_yz<T, 1>), dim3(ceil_div(d.nx, 64), ceil_div(d.ny, 64), d.nz * d.batch), blk, 0,
+                     s, (const T*)other, mid, d, k);
+  hipLaunchKernelGGL((fe::blur_yz<T, 2>), dim3(ceil_div(d.nx, 64), ceil_div(d.nz, 64), d.ny * d.batch), blk, 0,
+                     s, (const T*)mid, (T*)out, d, k);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+// tmp <- k * f (three passes; f is overwritten by the middle pass).
+template <typename T>
+int blur_into(fe_ctx* c, hipStream_t s, T* f, T* tmp, double sigma_k) {
+  if (sigma_k <= 0.0) return FE_OK;
+  const fe::FieldDims d{c->grid.nx, c->grid.ny, c->grid.nz, c->grid.batch};
+  const fe::BlurTaps<T> k = blur_taps<T>(sigma_k);
+  const dim3 blk(64, 4);
+  hipLaunchKernelGGL(fe::blur_x<T>, dim3(ceil_div(d.nx, 256), d.ny, d.nz * d.batch), dim3(256), 0, s,
+                     (const T*)f, tmp, d, k);
+  hipLaunchKernelGGL((fe::blur_yz<T, 1>), dim3(ceil_div(d.nx, 64), ceil_div(d.ny, 64), d.nz * d.batch), blk, 0,
+                     s, (const T*)tmp, f, d, k);
+  hipLaunchKernelGGL((fe::blur_yz<T, 2>), dim3(ceil_div(d.nx, 64), ceil_div(d.nz, 64), d.ny * d.batch), blk, 0,
+                     s, (const T*)f, tmp, d, k);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+// One iteration of Algorithm 1 on A (in place), energies into d_energy.
+template <typename T>
+int flow_iteration(fe_ctx* c, hipStream_t s, void* A, const FlowRule& fr) {
+  T* w0 = static_cast<T*>(c->d_w0);
+  T* w1 = static_cast<T*>(c->d_w1);
+  // ub = k * (div A + m0) in w1
+  int rc = flow_field<T>(c, s, A, w1, fr.sigma_k);
+  if (rc) return rc;
+  // gb = dF/du at ub, in w0 (energy of ub into d_energy)
+  const StepRule none{fe::kGrad, 0.0, 0.0, 0.0, 0.0};
+  rc = sweep(c, s, fe::kGrad, w1, w0, nullptr, nullptr, c->d_energy, none);
+  if (rc) return rc;
+  // gu = k * gb: blur w0 through w1, the result lands in w1
+  T* gu = w0;
+  if (fr.sigma_k > 0.0) {
+    rc = blur_into<T>(c, s, w0, w1, fr.sigma_k);
+    if (rc) return rc;
+    gu = w1;
+  }
+  const fe::FieldDims d{c->grid.nx, c->grid.ny, c->grid.nz, c->grid.batch};
+  hipLaunchKernelGGL(fe::adam_vector_field<T>, dim3(ceil_div(d.nx, 64), ceil_div(d.ny, 4), d.nz * d.batch),
+                     dim3(64, 4), 0, s, (const T*)gu, (T*)A, (T*)c->d_am1, (T*)c->d_am2, d,
+                     T(1.0 / (2.0 * c->grid.h)), T(fr.lr), T(fr.beta1), T(fr.beta2), T(fr.adam_eps),
+                     (const int*)c->d_flow_t);
+  hipLaunchKernelGGL(fe::bump_counter, dim3(1), dim3(64), 0, s, c->d_flow_t);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+int flow_iteration_any(fe_ctx* c, hipStream_t s, void* A, const FlowRule& fr) {
+  return c->grid.dtype == FE_F32 ? flow_iteration<float>(c, s, A, fr) : flow_iteration<double>(c, s, A, fr);
+}
+
+int flow_reset_launch(fe_ctx* c) {
+  const size_t n = 3 * field_elems(c->grid);
+  const int nblk = (int)std::min<size_t>((n + 255) / 256, 65536);
+  if (c->grid.dtype == FE_F32)
+    hipLaunchKernelGGL(fe::adam_reset<float>, dim3(nblk), dim3(256), 0, c->stream, (float*)c->d_am1,
+                       (float*)c->d_am2, n, c->d_flow_t);
+  else
+    hipLaunchKernelGGL(fe::adam_reset<double>, dim3(nblk), dim3(256), 0, c->stream, (double*)c->d_am1,
+                       (double*)c->d_am2, n, c->d_flow_t);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
 int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int nsteps, double* energy) {
   if (!u) return set_error(FE_EINVAL, "u is NULL");
   if (!mass) return set_error(FE_EINVAL, "mass is NULL");
@@ -430,7 +548,7 @@ int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int 
     if (rc) return rc;
   }
   if (gpairs > 0) {
-    GraphKey key{u, rule.mode, rule.tau, rule.beta1, rule.beta2, rule.adam_eps, gpairs, c->variant, c->lz};
+    GraphKey key{u, rule.mode, rule.tau, rule.beta1, rule.beta2, rule.adam_eps, 0.0, gpairs, c->variant, c->lz};
     auto it = c->graphs.find(key);
     hipGraphExec_t exec = nullptr;
     if (it == c->graphs.end()) {
@@ -628,6 +746,92 @@ int fe_adam_reset(fe_ctx* c) {
   return adam_reset_launch(c);
 }
 
+int fe_hminus_step(fe_ctx* c, void* A, const double* m0, double sigma_k, double lr, double beta1, double beta2,
+                   double adam_eps, int nsteps, void* u_out, double* energy) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!A) return set_error(FE_EINVAL, "A is NULL");
+  if (!m0) return set_error(FE_EINVAL, "m0 is NULL");
+  if (nsteps < 0) return set_error(FE_EINVAL, "nsteps must be >= 0");
+  if (!(sigma_k >= 0.0) || std::ceil(4.0 * sigma_k) > fe::kBlurMaxR)
+    return set_error(FE_EINVAL, "sigma_k must lie in [0, %g]", fe::kBlurMaxR / 4.0);
+  if (!(lr > 0.0) || !std::isfinite(lr)) return set_error(FE_EINVAL, "lr must be finite and > 0");
+  if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+    return set_error(FE_EINVAL, "beta1 and beta2 must lie in [0, 1)");
+  if (!(adam_eps > 0.0) || !std::isfinite(adam_eps)) return set_error(FE_EINVAL, "adam_eps must be finite and > 0");
+  if ((long)c->grid.nz * c->grid.batch > 65535 || (long)c->grid.ny * c->grid.batch > 65535)
+    return set_error(FE_EINVAL, "nz * batch and ny * batch must be <= 65535 for the flow kernels");
+  if (u_out == A) return set_error(FE_EINVAL, "u_out must not alias A");
+  for (int b = 0; b < c->grid.batch; ++b)
+    if (!std::isfinite(m0[b])) return set_error(FE_EINVAL, "m0[%d] is not finite", b);
+  DeviceGuard dg(c->device);
+  const size_t bytes = field_elems(c->grid) * elem_size(c->grid);
+  if (!c->d_w0) {
+    if (hipMalloc(&c->d_w0, bytes) != hipSuccess || hipMalloc(&c->d_w1, bytes) != hipSuccess ||
+        hipMalloc(&c->d_am1, 3 * bytes) != hipSuccess || hipMalloc(&c->d_am2, 3 * bytes) != hipSuccess ||
+        hipMalloc((void**)&c->d_flow_t, sizeof(int)) != hipSuccess) {
+      for (void** p : {&c->d_w0, &c->d_w1, &c->d_am1, &c->d_am2, (void**)&c->d_flow_t}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+      }
+      return set_error(FE_ENOMEM, "H^-1 flow workspace allocation failed");
+    }
+    int rc = flow_reset_launch(c);
+    if (rc) return rc;
+  }
+  FE_HIP(hipMemcpyAsync(c->d_mass, m0, sizeof(double) * c->grid.batch, hipMemcpyHostToDevice, c->stream));
+  const FlowRule fr{sigma_k, lr, beta1, beta2, adam_eps};
+  constexpr int kGraphIters = 8;
+  const int gi = nsteps >= kGraphIters ? kGraphIters : 0;
+  for (int i = 0; i < (gi ? nsteps % gi : nsteps); ++i) {
+    int rc = flow_iteration_any(c, c->stream, A, fr);
+    if (rc) return rc;
+  }
+  if (gi > 0) {
+    GraphKey key{A, kFlowMode, lr, beta1, beta2, adam_eps, sigma_k, gi, c->variant, c->lz};
+    auto it = c->graphs.find(key);
+    hipGraphExec_t exec = nullptr;
+    if (it == c->graphs.end()) {
+      hipGraph_t graph = nullptr;
+      FE_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      int rc = FE_OK;
+      for (int i = 0; i < gi && rc == FE_OK; ++i) rc = flow_iteration_any(c, c->cap_stream, A, fr);
+      hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
+      if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (ec != hipSuccess) return set_error(FE_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+      hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) return set_error(FE_EHIP, "graph instantiate failed: %s", hipGetErrorString(ei));
+      if (c->graphs.size() > 16) drop_graphs(c);
+      c->graphs[key] = exec;
+    } else {
+      exec = it->second;
+    }
+    for (int r = 0; r < nsteps / gi; ++r) FE_HIP(hipGraphLaunch(exec, c->stream));
+  }
+  if (u_out) {
+    int rc = c->grid.dtype == FE_F32 ? flow_field<float>(c, c->stream, A, u_out, sigma_k)
+                                     : flow_field<double>(c, c->stream, A, u_out, sigma_k);
+    if (rc) return rc;
+  }
+  if (nsteps == 0) {
+    if (energy) for (int b = 0; b < c->grid.batch; ++b) energy[b] = 0.0;
+    return FE_OK;
+  }
+  return copy_energy_out(c, energy);
+}
+
+int fe_hminus_reset(fe_ctx* c) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!c->d_am1) return FE_OK;
+  DeviceGuard dg(c->device);
+  return flow_reset_launch(c);
+}
+
 int fe_num_variants(void) { return (int)variants().size(); }
 
 int fe_variant_info(int variant, int* tile_x, int* tile_y, int* threads, int* dtype_mask) {
@@ -722,6 +926,8 @@ void fe_destroy(fe_ctx* c) {
   if (c->d_m1) (void)hipFree(c->d_m1);
   if (c->d_m2) (void)hipFree(c->d_m2);
   if (c->d_adam_t) (void)hipFree(c->d_adam_t);
+  for (void* p : {c->d_w0, c->d_w1, c->d_am1, c->d_am2, (void*)c->d_flow_t})
+    if (p) (void)hipFree(p);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }

@@ -51,6 +51,9 @@ SIGNATURES = {
     "fe_step_adam": (ctypes.c_int, [_P, _P, _DP, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_int, _DP]),
     "fe_adam_reset": (ctypes.c_int, [_P]),
+    "fe_hminus_step": (ctypes.c_int, [_P, _P, _DP, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, _DP]),
+    "fe_hminus_reset": (ctypes.c_int, [_P]),
     "fe_num_variants": (ctypes.c_int, []),
     "fe_variant_info": (ctypes.c_int, [ctypes.c_int, _IP, _IP, _IP, _IP]),
     "fe_set_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
@@ -233,6 +236,29 @@ class FeContext:
     def adam_reset(self):
         self._sync_stream()
         _check(lib().fe_adam_reset(self._h))
+
+    def hminus_step(self, A, m0, nsteps, sigma_k=2.0, lr=1e-3, betas=(0.9, 0.999), adam_eps=1e-8, u_out=None):
+        """nsteps iterations of Algorithm 1 on the vector field A [B, 3, nz, ny, nx] (in place);
+        u_out, if given, receives k * (div A + m0). Returns G before the last update."""
+        B = self.shape[0]
+        if isinstance(m0, (int, float)):
+            m0 = [float(m0)] * B
+        if len(m0) != B:
+            raise ValueError(f"need {B} m0 values")
+        exp = (B, 3) + self.shape[1:]
+        if not isinstance(A, torch.Tensor) or A.device.type != "cuda" or A.dtype != self.dtype \
+                or not A.is_contiguous() or tuple(A.shape) not in (exp, exp[1:] if B == 1 else exp):
+            raise ValueError(f"A must be a contiguous {self.dtype} device tensor of shape {exp}")
+        out = (ctypes.c_double * B)()
+        self._sync_stream()
+        _check(lib().fe_hminus_step(self._h, _P(A.data_ptr()), _dbl(m0), float(sigma_k), float(lr),
+                                    float(betas[0]), float(betas[1]), float(adam_eps), int(nsteps),
+                                    self._field(u_out, "u_out") if u_out is not None else _P(0), out))
+        return torch.tensor(list(out), dtype=torch.float64)
+
+    def hminus_reset(self):
+        self._sync_stream()
+        _check(lib().fe_hminus_reset(self._h))
 
     def set_launch(self, variant, z_chunk=0):
         _check(lib().fe_set_launch(self._h, int(variant), int(z_chunk)))

@@ -1,0 +1,156 @@
+"""Algorithm 1 (the H^-1 flow on a vector field A, u = k * (div A + m0), Adam on A)
+on the GPU against the oracle: per-iteration parity, exact mass, graph replay equal
+to eager iterations, batched equal to single instances, energy decrease."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fe_oracle as fo
+from paper_2103_04856_amd import fe, inputs
+
+from gpu_helpers import ASYM_C3, WILLMORE_QUARTER, log, oracle_input, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _a0(n, seed, batch=None):
+    """A0 ~ N(0, (0.4 h)^2): div A0 then has a standard deviation of about 0.5."""
+    return inputs.white_noise_vector_field(n, seed, 0.4 / n, batch)
+
+
+@pytest.mark.parametrize("sigma_k", [0.0, 1.0, 2.0])
+@pytest.mark.parametrize("n,a", [(20, ASYM_C3), (24, WILLMORE_QUARTER)])
+def test_iterations_match_oracle_fp64(n, a, sigma_k):
+    """Five single iterations, each from the A the GPU holds (with an asymmetric p the flow
+    amplifies a 1e-14 perturbation of A0 to 1e-9 in five iterations, so trajectories are only
+    compared for the stable p = (k1 + k2)^2 / 4 below): G before each update, A after it, and
+    u = k * (div A + m0). The oracle carries its own Adam moments throughout."""
+    h = 1.0 / n
+    eps, m0 = 2 * h, -0.2
+    ctx = fe.FeContext((1, n, n, n), h, eps, a, dtype=torch.float64)
+    Ad = to_dev(_a0(n, 7)[None], torch.float64)
+    ud = torch.empty((1, n, n, n), dtype=torch.float64, device="cuda")
+    m1 = np.zeros((3, n, n, n))
+    m2 = np.zeros((3, n, n, n))
+    for t in range(1, 6):
+        Ao = oracle_input(Ad)[0]
+        Eg = ctx.hminus_step(Ad, [m0], 1, sigma_k=sigma_k, u_out=ud)
+        Ao, m1, m2, Eo, _ = fo.hminus_adam_step(Ao, m1, m2, t, h, eps, a, m0, sigma_k)
+        assert abs(Eg[0].item() - Eo) <= 1e-10 * abs(Eo), (t, Eg[0].item(), Eo)
+        errA = rel_l2(Ad.cpu().numpy()[0], Ao)
+        assert errA <= 1e-11, (t, errA)
+    uo = fo.gaussian_blur(fo.fd_divergence(Ao, h) + m0, sigma_k)
+    erru = rel_l2(ud.cpu().numpy()[0], uo)
+    assert erru <= 1e-11, erru
+    log(f"  n={n} sigma_k={sigma_k}: A rel {errA:.1e}, u rel {erru:.1e}")
+
+
+def test_many_iterations_match_oracle_fp64():
+    """One call of 21 iterations (two graph replays of 8 and 5 eager) against the oracle's loop."""
+    n, sigma_k = 16, 2.0
+    h = 1.0 / n
+    eps, m0 = 2 * h, 0.1
+    ctx = fe.FeContext((1, n, n, n), h, eps, WILLMORE_QUARTER, dtype=torch.float64)
+    Ad = to_dev(_a0(n, 3)[None], torch.float64)
+    ud = torch.empty((1, n, n, n), dtype=torch.float64, device="cuda")
+    Eg = ctx.hminus_step(Ad, [m0], 21, sigma_k=sigma_k, u_out=ud)
+    Ao, Es, uo = fo.hminus_descend(_a0(n, 3), h, eps, WILLMORE_QUARTER, m0, sigma_k, 21)
+    assert abs(Eg[0].item() - Es[-1]) <= 1e-9 * abs(Es[-1])
+    assert rel_l2(Ad.cpu().numpy()[0], Ao) <= 1e-9
+    assert rel_l2(ud.cpu().numpy()[0], uo) <= 1e-9
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_graph_replay_equals_eager(dtype):
+    """nsteps = 19 in one call (graphs of 8 iterations plus 3 eager) equals 19 calls of one
+    iteration, bitwise, and fe_hminus_reset restarts the moments."""
+    n = 24
+    h = 1.0 / n
+    ctx = fe.FeContext((1, n, n, n), h, 2 * h, ASYM_C3, dtype=dtype)
+    A0 = to_dev(_a0(n, 11)[None], dtype)
+    A1 = A0.clone()
+    E1 = ctx.hminus_step(A1, [0.0], 19, sigma_k=1.5)
+    ctx.hminus_reset()
+    A2 = A0.clone()
+    for _ in range(19):
+        E2 = ctx.hminus_step(A2, [0.0], 1, sigma_k=1.5)
+    assert torch.equal(A1, A2) and E1[0].item() == E2[0].item()
+    ctx.hminus_reset()
+    A3 = A0.clone()
+    E3 = ctx.hminus_step(A3, [0.0], 19, sigma_k=1.5)
+    assert torch.equal(A1, A3) and E1[0].item() == E3[0].item()
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-13), (torch.float32, 2e-6)])
+def test_mass_is_exact(dtype, tol):
+    """mean(u) = m0 per instance at any A: div A has zero mean and the blur sums to one."""
+    n, B = 32, 3
+    h = 1.0 / n
+    m0 = [-0.35, 0.0, 0.42]
+    ctx = fe.FeContext((B, n, n, n), h, 2 * h, WILLMORE_QUARTER, dtype=dtype)
+    Ad = to_dev(_a0(n, 5, B), dtype)
+    ud = torch.empty((B, n, n, n), dtype=dtype, device="cuda")
+    for k in range(3):
+        ctx.hminus_step(Ad, m0, 4 + k, sigma_k=2.0, u_out=ud)
+        mean = ud.double().mean(dim=(1, 2, 3)).cpu().numpy()
+        scale = ud.double().abs().mean(dim=(1, 2, 3)).cpu().numpy()
+        assert np.all(np.abs(mean - np.array(m0)) <= tol * scale), (k, mean)
+
+
+def test_batched_equals_single_instances():
+    """Three instances with their own eps, p and m0 in one context equal three separate contexts (bitwise)."""
+    n, B = 20, 3
+    h = 1.0 / n
+    eps = [2 * h, 2.5 * h, 1.5 * h]
+    coeffs = [ASYM_C3, WILLMORE_QUARTER, (0.5, 0.1, 1.5, -2.0, -3.0, 0.0)]
+    m0 = [-0.3, 0.1, 0.25]
+    for dtype in (torch.float64, torch.float32):
+        A0 = to_dev(_a0(n, 17, B), dtype)
+        Ab = A0.clone()
+        ub = torch.empty((B, n, n, n), dtype=dtype, device="cuda")
+        ctx = fe.FeContext((B, n, n, n), h, eps, coeffs, dtype=dtype)
+        Eb = ctx.hminus_step(Ab, m0, 10, sigma_k=2.0, u_out=ub)
+        for b in range(B):
+            cs = fe.FeContext((1, n, n, n), h, eps[b], coeffs[b], dtype=dtype)
+            As = A0[b:b + 1].clone()
+            us = torch.empty((1, n, n, n), dtype=dtype, device="cuda")
+            Es = cs.hminus_step(As, [m0[b]], 10, sigma_k=2.0, u_out=us)
+            assert torch.equal(As[0], Ab[b]) and torch.equal(us[0], ub[b]), (dtype, b)
+            assert Es[0].item() == Eb[b].item()
+
+
+def test_fp32_tracks_fp64_and_energy_decreases():
+    """48^3, eps = 2h, sigma_k = 2, Adam lr 1e-3 (the paper's settings at a smaller grid): G decreases
+    over 40 iterations and the FP32 run stays within 2% of the FP64 one (Adam's first steps are
+    close to lr * sign(dG/dA), so a 1e-7 perturbation of A0 moves G by ~2e-3 within 40 iterations:
+    the runs are compared as flows, not voxel by voxel)."""
+    n = 48
+    h = 1.0 / n
+    A0 = _a0(n, 23)[None]
+    Es = {}
+    for dtype in (torch.float64, torch.float32):
+        ctx = fe.FeContext((1, n, n, n), h, 2 * h, ASYM_C3, dtype=dtype)
+        Ad = to_dev(A0, dtype)
+        Es[dtype] = [ctx.hminus_step(Ad, [-0.1], 1 if k == 0 else 13, sigma_k=2.0)[0].item() for k in range(4)]
+    e64, e32 = np.array(Es[torch.float64]), np.array(Es[torch.float32])
+    assert abs(e32[0] - e64[0]) <= 1e-4 * abs(e64[0]), (e32[0], e64[0])
+    assert np.all(np.abs(e32 - e64) <= 2e-2 * np.abs(e64)), (e32, e64)
+    assert e64[-1] < 0.8 * e64[0], e64
+    log(f"  G at iterations 1, 14, 27, 40: {e64}")
+
+
+def test_rejects_bad_arguments():
+    n = 16
+    h = 1.0 / n
+    ctx = fe.FeContext((1, n, n, n), h, 2 * h, WILLMORE_QUARTER, dtype=torch.float32)
+    A = torch.zeros((1, 3, n, n, n), dtype=torch.float32, device="cuda")
+    with pytest.raises(fe.FeError, match="sigma_k"):
+        ctx.hminus_step(A, [0.0], 1, sigma_k=4.5)
+    with pytest.raises(fe.FeError, match="lr"):
+        ctx.hminus_step(A, [0.0], 1, lr=0.0)
+    with pytest.raises(fe.FeError, match="m0"):
+        ctx.hminus_step(A, [float("nan")], 1)
+    with pytest.raises(ValueError):
+        ctx.hminus_step(A[:, :2].contiguous(), [0.0], 1)
+    assert torch.count_nonzero(A).item() == 0
