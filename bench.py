@@ -11,8 +11,9 @@ eps = 1.5h, p = (k1 + k2 - 2)^2 + 0.5 k1 k2, target mean 0, tau = 1e-3.
 Also reported: the batched form (16 independent 128^3 textures with their own
 coefficients and target means, eps = 2h, mass-projected Adam with lr 1e-3,
 one launch per step)
-against 16 sequential single-instance calls, and the energy+gradient sweep
-without the update.
+against 16 sequential single-instance calls, the energy+gradient sweep
+without the update, and Algorithm 1 (the H^-1 flow on a vector field with
+the Gaussian blur and Adam) at the paper's 100^3 simulation size.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu] [--gpus 1]
 """
@@ -151,6 +152,31 @@ def bench_batched(n, B, steps, warmup, tune):
     return ms_b, ms_s
 
 
+# Algorithm 1 at the paper's simulation size (Sec. 5): 100^3 pixels with dx = 0.01,
+# eps = 0.02, Adam lr 1e-3, betas (0.9, 0.999), blur sigma_k = 2 pixels; the
+# coefficients and mass of its convergence figure, a = (1, 2.4, 9, 30, 170, -195)
+# in the (a20, a11, a02, a10, a01, a00) order, m0 = -0.66. The paper runs 8000
+# iterations per shape in up to 150 s on its own GPU.
+HMINUS_A = (1.0, 2.4, 9.0, 30.0, 170.0, -195.0)
+HMINUS_M0 = -0.66
+PAPER_HMINUS_ITERS, PAPER_HMINUS_SECONDS = 8000, 150.0
+
+
+def bench_hminus(n, iters, batch=1, dtype=torch.float32):
+    """Algorithm 1 on `batch` shapes of n^3 at once (each from its own A0 seed, the
+    same coefficients and mass). Returns (ms per iteration, G after 16, G at the end,
+    iterations done) with G of the first shape."""
+    h = 1.0 / n
+    A = torch.from_numpy(inputs.white_noise_vector_field(n, 2021, 0.4 * h, batch=batch)).to(dtype).cuda()
+    ctx = fe.FeContext((batch, n, n, n), h, [0.02] * batch, [HMINUS_A] * batch, dtype=dtype)
+    m0 = [HMINUS_M0] * batch
+    G0 = ctx.hminus_step(A, m0, 16, sigma_k=2.0, lr=1e-3)[0].item()   # also captures the graph
+    iters = 8 * max(1, iters // 8)
+    ms = time_region(lambda: ctx.hminus_step(A, m0, iters, sigma_k=2.0, lr=1e-3)) / iters
+    G1 = ctx.hminus_step(A, m0, 8, sigma_k=2.0, lr=1e-3)[0].item()
+    return ms, G0, G1, iters + 24
+
+
 def cpu_baseline(n=256, budget_s=10.0, max_evals=3):
     """The FP64 NumPy oracle on a bounded sample of the same workload: whole 256^3
     energy + gradient evaluations, repeated until about budget_s seconds (at most
@@ -214,6 +240,25 @@ def main():
             "sequential_singles_value": vb / (ms_s * 1e-3), "sequential_singles_ms_per_step": ms_s,
             "unit": "voxel energy+gradient evals/s", "step_rule": "mass-projected Adam, lr 1e-3"}
         log(f"  batched {ms_b * 1e3:.1f} us/step, singles {ms_s * 1e3:.1f} us/step")
+
+    log("Algorithm 1 (H^-1 flow) at 100^3 ...")
+    ms_h, G0, G1, done = bench_hminus(100, max(args.steps, 64))
+    extra["hminus_flow_100"] = {
+        "iterations_per_s": 1e3 / ms_h, "ms_per_iteration": ms_h,
+        "voxel_iterations_per_s": 100 ** 3 / (ms_h * 1e-3),
+        "seconds_for_8000_iterations": PAPER_HMINUS_ITERS * ms_h * 1e-3,
+        "energy_after_16": G0, f"energy_after_{done}": G1,
+        "config": "100^3, dx=0.01, eps=0.02, a=(1,2.4,9,30,170,-195), m0=-0.66, sigma_k=2, Adam lr 1e-3, "
+                  "A0 ~ N(0,(0.4dx)^2) seed 2021, FP32, graph-replayed",
+        "paper_context": f"{PAPER_HMINUS_ITERS} iterations in up to {PAPER_HMINUS_SECONDS:.0f} s per shape "
+                         f"(>= {PAPER_HMINUS_ITERS / PAPER_HMINUS_SECONDS:.0f} it/s) on the paper's GPU"}
+    log(f"  {ms_h * 1e3:.1f} us/iteration ({1e3 / ms_h:.0f} it/s); G {G0:.4g} -> {G1:.4g}")
+    if not args.no_batched:
+        ms_h16, _, _, _ = bench_hminus(100, max(args.steps // 2, 32), batch=16)
+        extra["hminus_flow_100"]["batched_16"] = {
+            "shape_iterations_per_s": 16e3 / ms_h16, "ms_per_iteration": ms_h16,
+            "seconds_for_8000_iterations_of_16_shapes": PAPER_HMINUS_ITERS * ms_h16 * 1e-3}
+        log(f"  16 shapes at once: {ms_h16 * 1e3:.1f} us/iteration ({16e3 / ms_h16:.0f} shape-it/s)")
 
     step_us = ms_step * 1e3
     bytes_step = BYTES_PER_VOXEL_STEP * vox

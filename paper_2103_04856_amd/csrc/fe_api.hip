@@ -164,7 +164,7 @@ struct fe_ctx {
   void* d_w1 = nullptr;
   void* d_am1 = nullptr;              // H^-1 flow: Adam moments of A ([batch][3] fields each)
   void* d_am2 = nullptr;
-  int* d_flow_t = nullptr;            // H^-1 flow: Adam step number (device)
+  fe::FlowClock* d_flow_clk = nullptr; // H^-1 flow: Adam step number and bias corrections (device)
   size_t max_blocks = 0;              // per instance, over all variants and z chunks
   int variant = -1;
   int lz = 0;                         // 0 = automatic
@@ -424,47 +424,39 @@ struct FlowRule {
   double sigma_k, lr, beta1, beta2, adam_eps;
 };
 
-// u = k * (div A + m0) into `out`, using the two work fields (out may be one of them).
-template <typename T>
-int flow_field(fe_ctx* c, hipStream_t s, const void* A, void* out, double sigma_k) {
-  const fe::FieldDims d{c->grid.nx, c->grid.ny, c->grid.nz, c->grid.batch};
-  const dim3 blk(64, 4);
-  const dim3 g3(ceil_div(d.nx, 64), ceil_div(d.ny, 4), d.nz * d.batch);
-  const T inv2h = T(1.0 / (2.0 * c->grid.h));
-  if (sigma_k <= 0.0) {
-    hipLaunchKernelGGL(fe::div_field<T>, g3, blk, 0, s, (const T*)A, (T*)out, c->d_mass, d, inv2h);
-    FE_HIP(hipGetLastError());
-    return FE_OK;
-  }
-  T* w0 = static_cast<T*>(c->d_w0);
-  T* w1 = static_cast<T*>(c->d_w1);
-  T* mid = out == c->d_w0 ? w1 : w0;            // never the output
-  T* other = mid == w0 ? w1 : w0;               // may be the output
-  const fe::BlurTaps<T> k = blur_taps<T>(sigma_k);
-  hipLaunchKernelGGL(fe::div_field<T>, g3, blk, 0, s, (const T*)A, mid, c->d_mass, d, inv2h);
-  hipLaunchKernelGGL(fe::blur_x<T>, dim3(ceil_div(d.nx, 256), d.ny, d.nz * d.batch), dim3(256), 0, s,
-                     (const T*)mid, other, d, k);
-  hipLaunchKernelGGL((fe::blur_yz<T, 1>), dim3(ceil_div(d.nx, 64), ceil_div(d.ny, 64), d.nz * d.batch), blk, 0,
-                     s, (const T*)other, mid, d, k);
-  hipLaunchKernelGGL((fe::blur_yz<T, 2>), dim3(ceil_div(d.nx, 64), ceil_div(d.nz, 64), d.ny * d.batch), blk, 0,
-                     s, (const T*)mid, (T*)out, d, k);
-  FE_HIP(hipGetLastError());
-  return FE_OK;
+// Launch shapes of the flow kernels.
+dim3 row_grid(const fe::FieldDims& d) { return dim3(ceil_div(d.nx, 64), ceil_div(d.ny, 4), d.nz * d.batch); }
+dim3 x_grid(const fe::FieldDims& d) { return dim3(ceil_div(d.nx, 64), ceil_div(d.ny, fe::kBlurRows), d.nz * d.batch); }
+dim3 axis_grid(const fe::FieldDims& d, int axis) {
+  return axis == 1 ? dim3(ceil_div(d.nx, 64), ceil_div(d.ny, fe::kBlurChunk), d.nz * d.batch)
+                   : dim3(ceil_div(d.nx, 64), ceil_div(d.nz, fe::kBlurChunk), d.ny * d.batch);
 }
 
-// tmp <- k * f (three passes; f is overwritten by the middle pass).
+// out = k * f along y then z, through `tmp` (f is left as it was; out may be f).
 template <typename T>
-int blur_into(fe_ctx* c, hipStream_t s, T* f, T* tmp, double sigma_k) {
-  if (sigma_k <= 0.0) return FE_OK;
+void blur_yz(hipStream_t s, const fe::FieldDims& d, const fe::BlurTaps<T>& k, const T* f, T* tmp, T* out) {
+  hipLaunchKernelGGL((fe::blur_axis<T, 1>), axis_grid(d, 1), dim3(64, 4), 0, s, f, tmp, d, k);
+  hipLaunchKernelGGL((fe::blur_axis<T, 2>), axis_grid(d, 2), dim3(64, 4), 0, s, (const T*)tmp, out, d, k);
+}
+
+// u = k * (div A + m0) into `out` (a user field or the work field w0, never
+// w1): x pass into w0, y pass into w1, z pass into out. `clk` advances the
+// flow clock (iterations only).
+template <typename T>
+int flow_field(fe_ctx* c, hipStream_t s, const void* A, T* out, double sigma_k, fe::FlowClock* clk,
+               double beta1, double beta2) {
   const fe::FieldDims d{c->grid.nx, c->grid.ny, c->grid.nz, c->grid.batch};
   const fe::BlurTaps<T> k = blur_taps<T>(sigma_k);
-  const dim3 blk(64, 4);
-  hipLaunchKernelGGL(fe::blur_x<T>, dim3(ceil_div(d.nx, 256), d.ny, d.nz * d.batch), dim3(256), 0, s,
-                     (const T*)f, tmp, d, k);
-  hipLaunchKernelGGL((fe::blur_yz<T, 1>), dim3(ceil_div(d.nx, 64), ceil_div(d.ny, 64), d.nz * d.batch), blk, 0,
-                     s, (const T*)tmp, f, d, k);
-  hipLaunchKernelGGL((fe::blur_yz<T, 2>), dim3(ceil_div(d.nx, 64), ceil_div(d.nz, 64), d.ny * d.batch), blk, 0,
-                     s, (const T*)f, tmp, d, k);
+  const T inv2h = T(1.0 / (2.0 * c->grid.h));
+  T* w0 = static_cast<T*>(c->d_w0);
+  if (k.r == 0) {
+    hipLaunchKernelGGL((fe::blur_x<T, true>), x_grid(d), dim3(64, 4), 0, s, (const T*)A, out, c->d_mass, d,
+                       inv2h, k, clk, beta1, beta2);
+  } else {
+    hipLaunchKernelGGL((fe::blur_x<T, true>), x_grid(d), dim3(64, 4), 0, s, (const T*)A, w0, c->d_mass, d,
+                       inv2h, k, clk, beta1, beta2);
+    blur_yz<T>(s, d, k, w0, static_cast<T*>(c->d_w1), out);
+  }
   FE_HIP(hipGetLastError());
   return FE_OK;
 }
@@ -474,26 +466,26 @@ template <typename T>
 int flow_iteration(fe_ctx* c, hipStream_t s, void* A, const FlowRule& fr) {
   T* w0 = static_cast<T*>(c->d_w0);
   T* w1 = static_cast<T*>(c->d_w1);
-  // ub = k * (div A + m0) in w1
-  int rc = flow_field<T>(c, s, A, w1, fr.sigma_k);
-  if (rc) return rc;
-  // gb = dF/du at ub, in w0 (energy of ub into d_energy)
-  const StepRule none{fe::kGrad, 0.0, 0.0, 0.0, 0.0};
-  rc = sweep(c, s, fe::kGrad, w1, w0, nullptr, nullptr, c->d_energy, none);
-  if (rc) return rc;
-  // gu = k * gb: blur w0 through w1, the result lands in w1
-  T* gu = w0;
-  if (fr.sigma_k > 0.0) {
-    rc = blur_into<T>(c, s, w0, w1, fr.sigma_k);
-    if (rc) return rc;
-    gu = w1;
-  }
   const fe::FieldDims d{c->grid.nx, c->grid.ny, c->grid.nz, c->grid.batch};
-  hipLaunchKernelGGL(fe::adam_vector_field<T>, dim3(ceil_div(d.nx, 64), ceil_div(d.ny, 4), d.nz * d.batch),
-                     dim3(64, 4), 0, s, (const T*)gu, (T*)A, (T*)c->d_am1, (T*)c->d_am2, d,
-                     T(1.0 / (2.0 * c->grid.h)), T(fr.lr), T(fr.beta1), T(fr.beta2), T(fr.adam_eps),
-                     (const int*)c->d_flow_t);
-  hipLaunchKernelGGL(fe::bump_counter, dim3(1), dim3(64), 0, s, c->d_flow_t);
+  const fe::BlurTaps<T> k = blur_taps<T>(fr.sigma_k);
+  // ub = k * (div A + m0) in w0
+  int rc = flow_field<T>(c, s, A, w0, fr.sigma_k, c->d_flow_clk, fr.beta1, fr.beta2);
+  if (rc) return rc;
+  // gb = dF/du at ub, in w1 (energy of ub into d_energy)
+  const StepRule none{fe::kGrad, 0.0, 0.0, 0.0, 0.0};
+  rc = sweep(c, s, fe::kGrad, w0, w1, nullptr, nullptr, c->d_energy, none);
+  if (rc) return rc;
+  // gu = k * gb: x pass into w0, y pass into w1, z pass into w0
+  T* gu = w1;
+  if (k.r > 0) {
+    hipLaunchKernelGGL((fe::blur_x<T, false>), x_grid(d), dim3(64, 4), 0, s, (const T*)w1, w0, nullptr, d, T(0),
+                       k, nullptr, 0.0, 0.0);
+    blur_yz<T>(s, d, k, w0, w1, w0);
+    gu = w0;
+  }
+  hipLaunchKernelGGL(fe::adam_vector_field<T>, row_grid(d), dim3(64, 4), 0, s, (const T*)gu, (T*)A,
+                     (T*)c->d_am1, (T*)c->d_am2, d, T(1.0 / (2.0 * c->grid.h)), T(fr.lr), T(fr.beta1),
+                     T(fr.beta2), T(fr.adam_eps), (const fe::FlowClock*)c->d_flow_clk);
   FE_HIP(hipGetLastError());
   return FE_OK;
 }
@@ -506,11 +498,11 @@ int flow_reset_launch(fe_ctx* c) {
   const size_t n = 3 * field_elems(c->grid);
   const int nblk = (int)std::min<size_t>((n + 255) / 256, 65536);
   if (c->grid.dtype == FE_F32)
-    hipLaunchKernelGGL(fe::adam_reset<float>, dim3(nblk), dim3(256), 0, c->stream, (float*)c->d_am1,
-                       (float*)c->d_am2, n, c->d_flow_t);
+    hipLaunchKernelGGL(fe::flow_reset<float>, dim3(nblk), dim3(256), 0, c->stream, (float*)c->d_am1,
+                       (float*)c->d_am2, n, c->d_flow_clk);
   else
-    hipLaunchKernelGGL(fe::adam_reset<double>, dim3(nblk), dim3(256), 0, c->stream, (double*)c->d_am1,
-                       (double*)c->d_am2, n, c->d_flow_t);
+    hipLaunchKernelGGL(fe::flow_reset<double>, dim3(nblk), dim3(256), 0, c->stream, (double*)c->d_am1,
+                       (double*)c->d_am2, n, c->d_flow_clk);
   FE_HIP(hipGetLastError());
   return FE_OK;
 }
@@ -769,8 +761,8 @@ int fe_hminus_step(fe_ctx* c, void* A, const double* m0, double sigma_k, double 
   if (!c->d_w0) {
     if (hipMalloc(&c->d_w0, bytes) != hipSuccess || hipMalloc(&c->d_w1, bytes) != hipSuccess ||
         hipMalloc(&c->d_am1, 3 * bytes) != hipSuccess || hipMalloc(&c->d_am2, 3 * bytes) != hipSuccess ||
-        hipMalloc((void**)&c->d_flow_t, sizeof(int)) != hipSuccess) {
-      for (void** p : {&c->d_w0, &c->d_w1, &c->d_am1, &c->d_am2, (void**)&c->d_flow_t}) {
+        hipMalloc((void**)&c->d_flow_clk, sizeof(fe::FlowClock)) != hipSuccess) {
+      for (void** p : {&c->d_w0, &c->d_w1, &c->d_am1, &c->d_am2, (void**)&c->d_flow_clk}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
       }
@@ -813,8 +805,9 @@ int fe_hminus_step(fe_ctx* c, void* A, const double* m0, double sigma_k, double 
     for (int r = 0; r < nsteps / gi; ++r) FE_HIP(hipGraphLaunch(exec, c->stream));
   }
   if (u_out) {
-    int rc = c->grid.dtype == FE_F32 ? flow_field<float>(c, c->stream, A, u_out, sigma_k)
-                                     : flow_field<double>(c, c->stream, A, u_out, sigma_k);
+    int rc = c->grid.dtype == FE_F32
+                 ? flow_field<float>(c, c->stream, A, (float*)u_out, sigma_k, nullptr, 0.0, 0.0)
+                 : flow_field<double>(c, c->stream, A, (double*)u_out, sigma_k, nullptr, 0.0, 0.0);
     if (rc) return rc;
   }
   if (nsteps == 0) {
@@ -926,7 +919,7 @@ void fe_destroy(fe_ctx* c) {
   if (c->d_m1) (void)hipFree(c->d_m1);
   if (c->d_m2) (void)hipFree(c->d_m2);
   if (c->d_adam_t) (void)hipFree(c->d_adam_t);
-  for (void* p : {c->d_w0, c->d_w1, c->d_am1, c->d_am2, (void*)c->d_flow_t})
+  for (void* p : {c->d_w0, c->d_w1, c->d_am1, c->d_am2, (void*)c->d_flow_clk})
     if (p) (void)hipFree(p);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;

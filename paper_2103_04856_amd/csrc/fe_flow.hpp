@@ -6,6 +6,12 @@
 // moments [batch][3][nz][ny][nx] (components x, y, z), x fastest. Central
 // differences are the ones of the energy's stencils; their periodic transpose
 // is minus themselves, which is where the minus sign of dG/dA comes from.
+//
+// One iteration is: blur_x<DIV> (div A + m0, blurred along x), blur_axis<1>,
+// blur_axis<2>, the sweep, blur_x of dF/du, blur_axis<1>, blur_axis<2>,
+// adam_vector_field. Without blur (r = 0) only the first kernel, the sweep and
+// the Adam kernel run. Every kernel is a 64-wide row of x per wave, so loads
+// and stores are coalesced; the blur halos are staged in LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,6 +21,7 @@
 namespace fe {
 
 constexpr int kBlurMaxR = 16;   // at most 33 taps: blur widths up to 4 voxels
+constexpr int kBlurChunk = 32;  // outputs per column segment of the y and z passes
 
 template <typename T>
 struct BlurTaps {
@@ -26,62 +33,124 @@ struct FieldDims {
   int nx, ny, nz, batch;
 };
 
-__device__ __forceinline__ int wrap_up(int v, int n) { return v >= n ? v - n : v; }
-__device__ __forceinline__ int wrap_down(int v, int n) { return v < 0 ? v + n : v; }
+// Adam step number of the flow and its bias corrections 1 / (1 - beta^t),
+// advanced once per iteration by the iteration's first kernel.
+struct FlowClock {
+  int t;
+  int pad;
+  double bc1, bc2;
+};
+
 __device__ __forceinline__ int wrap_any(int v, int n) {
   int r = v % n;
   return r < 0 ? r + n : r;
 }
+__device__ __forceinline__ int wrap_up(int v, int n) { return v >= n ? v - n : v; }
+__device__ __forceinline__ int wrap_down(int v, int n) { return v < 0 ? v + n : v; }
 
-// u[b] = m0[b] + sum_a (A_a(i + e_a) - A_a(i - e_a)) / (2h).
-// Grid: (ceil(nx/64), ceil(ny/4), nz * batch), block (64, 4).
+// sum_j w_j v[j * step], j = 0..2r. The loop runs to the largest r with a
+// uniform guard, so the taps are read at fixed offsets (kernel arguments in
+// scalar registers) rather than indexed at run time.
 template <typename T>
-__global__ __launch_bounds__(256) void div_field(const T* __restrict__ A, T* __restrict__ u,
-                                                 const double* __restrict__ m0, FieldDims d, T inv2h) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
-  const int z = blockIdx.z % d.nz, b = blockIdx.z / d.nz;
-  if (x >= d.nx || y >= d.ny) return;
-  const size_t plane = (size_t)d.nx * d.ny, vol = plane * d.nz;
-  const T* Ax = A + (size_t)b * 3 * vol;
-  const T* Ay = Ax + vol;
-  const T* Az = Ay + vol;
-  const size_t row = (size_t)z * plane + (size_t)y * d.nx;
-  const int xp = wrap_up(x + 1, d.nx), xm = wrap_down(x - 1, d.nx);
-  const size_t yp = (size_t)z * plane + (size_t)wrap_up(y + 1, d.ny) * d.nx;
-  const size_t ym = (size_t)z * plane + (size_t)wrap_down(y - 1, d.ny) * d.nx;
-  const size_t zp = (size_t)wrap_up(z + 1, d.nz) * plane + (size_t)y * d.nx;
-  const size_t zm = (size_t)wrap_down(z - 1, d.nz) * plane + (size_t)y * d.nx;
-  const T s = (Ax[row + xp] - Ax[row + xm]) + (Ay[yp + x] - Ay[ym + x]) + (Az[zp + x] - Az[zm + x]);
-  u[(size_t)b * vol + row + x] = T(m0[b]) + s * inv2h;
+__device__ __forceinline__ T taps_dot(const BlurTaps<T>& k, const T* v, int step) {
+  T acc = T(0);
+#pragma unroll
+  for (int j = 0; j <= 2 * kBlurMaxR; ++j)
+    if (j <= 2 * k.r) acc += k.w[j] * v[j * step];
+  return acc;
 }
 
-// Blur along x: one block per (row, 256-wide chunk); the row segment and its
-// periodic halo of r are staged in LDS. Grid: (ceil(nx/256), ny, nz * batch).
-template <typename T>
-__global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __restrict__ out, FieldDims d,
-                                              BlurTaps<T> k) {
-  __shared__ T s[256 + 2 * kBlurMaxR];
-  const int x0 = blockIdx.x * 256;
-  const size_t row = ((size_t)blockIdx.z * d.ny + blockIdx.y) * d.nx;   // blockIdx.z = b * nz + z
-  const T* src = in + row;
-  for (int e = threadIdx.x; e < 256 + 2 * k.r; e += 256) s[e] = src[wrap_any(x0 - k.r + e, d.nx)];
+// Blur along x of row segments: a block is kBlurRows rows x 64 x-values
+// (block (64, 4), each thread on kBlurRows / 4 rows; grid (ceil(nx/64),
+// ceil(ny/kBlurRows), nz * batch)); each row's segment and its periodic halo
+// of r go through LDS. With DIV the loaded value is div A + m0 (the field of
+// Algorithm 1) and block (0,0,0) advances the clock (when given); without, it
+// is in[]. r = 0 is a plain copy (or div). All loads of a thread are issued
+// before the first LDS write, so a block keeps many in flight.
+constexpr int kBlurRows = 16;
+
+template <typename T, bool DIV>
+__global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __restrict__ out,
+                                              const double* __restrict__ m0, FieldDims d, T inv2h,
+                                              BlurTaps<T> k, FlowClock* __restrict__ clk, double beta1,
+                                              double beta2) {
+  constexpr int kW = 64 + 2 * kBlurMaxR;
+  constexpr int kPer = (kW + 63) / 64;          // segment elements per thread and row
+  constexpr int kR = kBlurRows / 4;             // rows per thread
+  __shared__ T s[kBlurRows][kW];
+  if (DIV && clk && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0 &&
+      threadIdx.y == 0) {
+    const int t = clk->t + 1;
+    clk->t = t;
+    clk->bc1 = 1.0 / (1.0 - ::pow(beta1, (double)t));
+    clk->bc2 = 1.0 / (1.0 - ::pow(beta2, (double)t));
+  }
+  const int z = blockIdx.z % d.nz, b = blockIdx.z / d.nz;
+  const int x0 = blockIdx.x * 64;
+  const size_t plane = (size_t)d.nx * d.ny, vol = plane * d.nz;
+  const T* base = in + (size_t)b * (DIV ? 3 : 1) * vol;
+  const int nseg = 64 + 2 * k.r;
+  T v[kR][kPer][6];          // the non-DIV form uses [0] only
+#pragma unroll
+  for (int i = 0; i < kR; ++i) {
+    const int y = blockIdx.y * kBlurRows + threadIdx.y + 4 * i;
+    if (y >= d.ny) continue;
+    const size_t row = (size_t)z * plane + (size_t)y * d.nx;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int e = threadIdx.x + 64 * j;
+      if (e >= nseg) continue;
+      const int x = wrap_any(x0 - k.r + e, d.nx);
+      if (DIV) {
+        v[i][j][0] = base[row + wrap_up(x + 1, d.nx)];
+        v[i][j][1] = base[row + wrap_down(x - 1, d.nx)];
+        const T* Ay = base + vol;
+        const T* Az = base + 2 * vol;
+        v[i][j][2] = Ay[(size_t)z * plane + (size_t)wrap_up(y + 1, d.ny) * d.nx + x];
+        v[i][j][3] = Ay[(size_t)z * plane + (size_t)wrap_down(y - 1, d.ny) * d.nx + x];
+        v[i][j][4] = Az[(size_t)wrap_up(z + 1, d.nz) * plane + (size_t)y * d.nx + x];
+        v[i][j][5] = Az[(size_t)wrap_down(z - 1, d.nz) * plane + (size_t)y * d.nx + x];
+      } else {
+        v[i][j][0] = base[row + x];
+      }
+    }
+  }
+  const T mass = DIV ? T(m0[b]) : T(0);
+#pragma unroll
+  for (int i = 0; i < kR; ++i) {
+    const int y = blockIdx.y * kBlurRows + threadIdx.y + 4 * i;
+    if (y >= d.ny) continue;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int e = threadIdx.x + 64 * j;
+      if (e >= nseg) continue;
+      if (DIV)
+        s[threadIdx.y + 4 * i][e] =
+            mass + ((v[i][j][0] - v[i][j][1]) + (v[i][j][2] - v[i][j][3]) + (v[i][j][4] - v[i][j][5])) * inv2h;
+      else
+        s[threadIdx.y + 4 * i][e] = v[i][j][0];
+    }
+  }
   __syncthreads();
   const int x = x0 + threadIdx.x;
   if (x >= d.nx) return;
-  T acc = T(0);
-  for (int j = 0; j <= 2 * k.r; ++j) acc += k.w[j] * s[threadIdx.x + j];
-  out[row + x] = acc;
+#pragma unroll
+  for (int i = 0; i < kR; ++i) {
+    const int y = blockIdx.y * kBlurRows + threadIdx.y + 4 * i;
+    if (y >= d.ny) continue;
+    out[(size_t)b * vol + (size_t)z * plane + (size_t)y * d.nx + x] =
+        taps_dot(k, &s[threadIdx.y + 4 * i][threadIdx.x], 1);
+  }
 }
 
-// Blur along y (AXIS = 1) or z (AXIS = 2): a block covers 64 x-values and 64
-// positions along the axis, with the halo of r staged in LDS.
-// Grid: (ceil(nx/64), ceil(n_axis/64), n_other * batch), block (64, 4);
-// the other axis is z for AXIS = 1 and y for AXIS = 2.
+// Blur along y (AXIS = 1) or z (AXIS = 2): a block covers 64 x-values and
+// kBlurChunk positions along the axis, whose column segments and halo of r are
+// staged in LDS. Block (64, 4); grid (ceil(nx/64), ceil(n_axis/kBlurChunk),
+// n_other * batch), the other axis being z for AXIS = 1 and y for AXIS = 2.
 template <typename T, int AXIS>
-__global__ __launch_bounds__(256) void blur_yz(const T* __restrict__ in, T* __restrict__ out, FieldDims d,
-                                               BlurTaps<T> k) {
-  __shared__ T s[64 + 2 * kBlurMaxR][64];
+__global__ __launch_bounds__(256) void blur_axis(const T* __restrict__ in, T* __restrict__ out, FieldDims d,
+                                                 BlurTaps<T> k) {
+  __shared__ T s[kBlurChunk + 2 * kBlurMaxR][64];
   const int n_axis = AXIS == 1 ? d.ny : d.nz;
   const int n_other = AXIS == 1 ? d.nz : d.ny;
   const size_t stride = AXIS == 1 ? (size_t)d.nx : (size_t)d.nx * d.ny;
@@ -89,58 +158,86 @@ __global__ __launch_bounds__(256) void blur_yz(const T* __restrict__ in, T* __re
   const size_t base = (size_t)b * d.nz * d.ny * d.nx +
                       (AXIS == 1 ? (size_t)other * d.nx * d.ny : (size_t)other * d.nx);
   const int x = blockIdx.x * 64 + threadIdx.x;
-  const int p0 = blockIdx.y * 64;
+  const int p0 = blockIdx.y * kBlurChunk;
   const bool xin = x < d.nx;
-  for (int q = threadIdx.y; q < 64 + 2 * k.r; q += 4)
-    s[q][threadIdx.x] = xin ? in[base + (size_t)wrap_any(p0 - k.r + q, n_axis) * stride + x] : T(0);
+  // up to kRows rows per thread, all loads issued before the LDS writes
+  constexpr int kRows = (kBlurChunk + 2 * kBlurMaxR + 3) / 4;
+  T v[kRows];
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const int q = threadIdx.y + 4 * i;
+    if (xin && q < kBlurChunk + 2 * k.r) v[i] = in[base + (size_t)wrap_any(p0 - k.r + q, n_axis) * stride + x];
+  }
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const int q = threadIdx.y + 4 * i;
+    if (q < kBlurChunk + 2 * k.r) s[q][threadIdx.x] = xin ? v[i] : T(0);
+  }
   __syncthreads();
   if (!xin) return;
-  for (int q = threadIdx.y; q < 64; q += 4) {
+  for (int q = threadIdx.y; q < kBlurChunk; q += 4) {
     const int p = p0 + q;
     if (p >= n_axis) break;
-    T acc = T(0);
-    for (int j = 0; j <= 2 * k.r; ++j) acc += k.w[j] * s[q + j][threadIdx.x];
-    out[base + (size_t)p * stride + x] = acc;
+    out[base + (size_t)p * stride + x] = taps_dot(k, &s[q][threadIdx.x], 64);
   }
 }
 
 // Adam on A with dG/dA_a = -(g(i + e_a) - g(i - e_a)) / (2h), g = k * dF/du.
-// Moments and A are updated in place; t >= 1 is read from device memory.
-// Grid and block as div_field.
+// Moments and A are updated in place; the bias corrections come from the
+// clock, which this iteration's first kernel advanced.
+// Block (64, 4); grid (ceil(nx/64), ceil(ny/4), nz * batch).
 template <typename T>
 __global__ __launch_bounds__(256) void adam_vector_field(const T* __restrict__ g, T* __restrict__ A,
                                                          T* __restrict__ m1, T* __restrict__ m2, FieldDims d,
                                                          T inv2h, T lr, T beta1, T beta2, T adam_eps,
-                                                         const int* __restrict__ adam_t) {
+                                                         const FlowClock* __restrict__ clk) {
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y = blockIdx.y * 4 + threadIdx.y;
   const int z = blockIdx.z % d.nz, b = blockIdx.z / d.nz;
   if (x >= d.nx || y >= d.ny) return;
-  const int t = *adam_t;
-  const T bc1 = T(1.0 / (1.0 - ::pow(double(beta1), double(t))));
-  const T bc2 = T(1.0 / (1.0 - ::pow(double(beta2), double(t))));
   const size_t plane = (size_t)d.nx * d.ny, vol = plane * d.nz;
   const T* gb = g + (size_t)b * vol;
   const size_t row = (size_t)z * plane + (size_t)y * d.nx;
-  T grad[3];
-  grad[0] = -(gb[row + wrap_up(x + 1, d.nx)] - gb[row + wrap_down(x - 1, d.nx)]) * inv2h;
-  grad[1] = -(gb[(size_t)z * plane + (size_t)wrap_up(y + 1, d.ny) * d.nx + x] -
-              gb[(size_t)z * plane + (size_t)wrap_down(y - 1, d.ny) * d.nx + x]) * inv2h;
-  grad[2] = -(gb[(size_t)wrap_up(z + 1, d.nz) * plane + (size_t)y * d.nx + x] -
-              gb[(size_t)wrap_down(z - 1, d.nz) * plane + (size_t)y * d.nx + x]) * inv2h;
+  // every load of the voxel is issued before the first use, so one memory
+  // round trip covers them
+  const T gxp = gb[row + wrap_up(x + 1, d.nx)], gxm = gb[row + wrap_down(x - 1, d.nx)];
+  const T gyp = gb[(size_t)z * plane + (size_t)wrap_up(y + 1, d.ny) * d.nx + x];
+  const T gym = gb[(size_t)z * plane + (size_t)wrap_down(y - 1, d.ny) * d.nx + x];
+  const T gzp = gb[(size_t)wrap_up(z + 1, d.nz) * plane + (size_t)y * d.nx + x];
+  const T gzm = gb[(size_t)wrap_down(z - 1, d.nz) * plane + (size_t)y * d.nx + x];
+  const size_t i0 = (size_t)b * 3 * vol + row + x;
+  T av[3], m1v[3], m2v[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const size_t i = ((size_t)b * 3 + a) * vol + row + x;
-    const T mo = beta1 * m1[i] + (T(1) - beta1) * grad[a];
-    const T vo = beta2 * m2[i] + (T(1) - beta2) * grad[a] * grad[a];
-    m1[i] = mo;
-    m2[i] = vo;
-    A[i] -= lr * (mo * bc1) * rcp_t(sqrt_t(vo * bc2) + adam_eps);
+    av[a] = A[i0 + a * vol];
+    m1v[a] = m1[i0 + a * vol];
+    m2v[a] = m2[i0 + a * vol];
+  }
+  const T bc1 = T(clk->bc1), bc2 = T(clk->bc2);
+  const T grad[3] = {-(gxp - gxm) * inv2h, -(gyp - gym) * inv2h, -(gzp - gzm) * inv2h};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T mo = beta1 * m1v[a] + (T(1) - beta1) * grad[a];
+    const T vo = beta2 * m2v[a] + (T(1) - beta2) * grad[a] * grad[a];
+    m1[i0 + a * vol] = mo;
+    m2[i0 + a * vol] = vo;
+    A[i0 + a * vol] = av[a] - lr * (mo * bc1) * rcp_t(sqrt_t(vo * bc2) + adam_eps);
   }
 }
 
-__global__ __launch_bounds__(64) void bump_counter(int* t) {
-  if (threadIdx.x == 0) atomicAdd(t, 1);
+// Zero the moments (n elements each) and restart the clock at t = 0.
+template <typename T>
+__global__ __launch_bounds__(256) void flow_reset(T* m1, T* m2, size_t n, FlowClock* clk) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    m1[i] = T(0);
+    m2[i] = T(0);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    clk->t = 0;
+    clk->pad = 0;
+    clk->bc1 = 1.0;
+    clk->bc2 = 1.0;
+  }
 }
 
 }  // namespace fe
