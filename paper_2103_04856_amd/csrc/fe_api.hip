@@ -428,8 +428,8 @@ struct FlowRule {
 dim3 row_grid(const fe::FieldDims& d) { return dim3(ceil_div(d.nx, 64), ceil_div(d.ny, 4), d.nz * d.batch); }
 dim3 x_grid(const fe::FieldDims& d) { return dim3(ceil_div(d.nx, 64), ceil_div(d.ny, fe::kBlurRows), d.nz * d.batch); }
 dim3 axis_grid(const fe::FieldDims& d, int axis) {
-  return axis == 1 ? dim3(ceil_div(d.nx, 64), ceil_div(d.ny, fe::kBlurChunk), d.nz * d.batch)
-                   : dim3(ceil_div(d.nx, 64), ceil_div(d.nz, fe::kBlurChunk), d.ny * d.batch);
+  return axis == 1 ? dim3(ceil_div(d.nx, 64), ceil_div(d.ny, fe::kAxisChunk), ceil_div(d.nz, 4) * d.batch)
+                   : dim3(ceil_div(d.nx, 64), ceil_div(d.nz, fe::kAxisChunk), ceil_div(d.ny, 4) * d.batch);
 }
 
 // out = k * f along y then z, through `tmp` (f is left as it was; out may be f).

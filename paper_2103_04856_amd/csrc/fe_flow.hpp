@@ -21,7 +21,6 @@
 namespace fe {
 
 constexpr int kBlurMaxR = 16;   // at most 33 taps: blur widths up to 4 voxels
-constexpr int kBlurChunk = 32;  // outputs per column segment of the y and z passes
 
 template <typename T>
 struct BlurTaps {
@@ -143,42 +142,41 @@ __global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __res
   }
 }
 
-// Blur along y (AXIS = 1) or z (AXIS = 2): a block covers 64 x-values and
-// kBlurChunk positions along the axis, whose column segments and halo of r are
-// staged in LDS. Block (64, 4); grid (ceil(nx/64), ceil(n_axis/kBlurChunk),
-// n_other * batch), the other axis being z for AXIS = 1 and y for AXIS = 2.
+// Blur along y (AXIS = 1) or z (AXIS = 2) with a register window: each thread
+// owns kAxisChunk consecutive outputs of one column, loads that segment and
+// its periodic halo of r once (coalesced across the 64 x-lanes of a wave) and
+// forms every output from registers, so the pass needs no LDS. Block (64, 4),
+// one column per thread; grid (ceil(nx/64), ceil(n_axis/kAxisChunk),
+// ceil(n_other/4) * batch), the other axis being z for AXIS = 1 and y for
+// AXIS = 2.
+constexpr int kAxisChunk = 16;
+
 template <typename T, int AXIS>
 __global__ __launch_bounds__(256) void blur_axis(const T* __restrict__ in, T* __restrict__ out, FieldDims d,
                                                  BlurTaps<T> k) {
-  __shared__ T s[kBlurChunk + 2 * kBlurMaxR][64];
+  constexpr int kWin = kAxisChunk + 2 * kBlurMaxR;
   const int n_axis = AXIS == 1 ? d.ny : d.nz;
   const int n_other = AXIS == 1 ? d.nz : d.ny;
-  const size_t stride = AXIS == 1 ? (size_t)d.nx : (size_t)d.nx * d.ny;
-  const int other = blockIdx.z % n_other, b = blockIdx.z / n_other;
-  const size_t base = (size_t)b * d.nz * d.ny * d.nx +
-                      (AXIS == 1 ? (size_t)other * d.nx * d.ny : (size_t)other * d.nx);
+  const int og = (n_other + 3) / 4;
+  const int other = (blockIdx.z % og) * 4 + threadIdx.y, b = blockIdx.z / og;
   const int x = blockIdx.x * 64 + threadIdx.x;
-  const int p0 = blockIdx.y * kBlurChunk;
-  const bool xin = x < d.nx;
-  // up to kRows rows per thread, all loads issued before the LDS writes
-  constexpr int kRows = (kBlurChunk + 2 * kBlurMaxR + 3) / 4;
-  T v[kRows];
+  if (x >= d.nx || other >= n_other) return;
+  const size_t stride = AXIS == 1 ? (size_t)d.nx : (size_t)d.nx * d.ny;
+  const size_t base = (size_t)b * d.nz * d.ny * d.nx +
+                      (AXIS == 1 ? (size_t)other * d.nx * d.ny : (size_t)other * d.nx) + x;
+  const int p0 = blockIdx.y * kAxisChunk;
+  T v[kWin];
 #pragma unroll
-  for (int i = 0; i < kRows; ++i) {
-    const int q = threadIdx.y + 4 * i;
-    if (xin && q < kBlurChunk + 2 * k.r) v[i] = in[base + (size_t)wrap_any(p0 - k.r + q, n_axis) * stride + x];
-  }
+  for (int i = 0; i < kWin; ++i)
+    if (i < kAxisChunk + 2 * k.r) v[i] = in[base + (size_t)wrap_any(p0 - k.r + i, n_axis) * stride];
 #pragma unroll
-  for (int i = 0; i < kRows; ++i) {
-    const int q = threadIdx.y + 4 * i;
-    if (q < kBlurChunk + 2 * k.r) s[q][threadIdx.x] = xin ? v[i] : T(0);
-  }
-  __syncthreads();
-  if (!xin) return;
-  for (int q = threadIdx.y; q < kBlurChunk; q += 4) {
-    const int p = p0 + q;
-    if (p >= n_axis) break;
-    out[base + (size_t)p * stride + x] = taps_dot(k, &s[q][threadIdx.x], 64);
+  for (int o = 0; o < kAxisChunk; ++o) {
+    if (p0 + o >= n_axis) break;
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j <= 2 * kBlurMaxR; ++j)
+      if (j <= 2 * k.r) acc += k.w[j] * v[o + j];
+    out[base + (size_t)(p0 + o) * stride] = acc;
   }
 }
 
