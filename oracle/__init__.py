@@ -9,8 +9,9 @@ Modules:
   fe_oracle     the discrete energy, its hand-derived adjoint gradient, the
                 mass-projected descent step (eqs. (Meps), (Feps); Sec. 4.1), and
                 the H^-1 flow of Algorithm 1 (div A + m0, blur, Adam on A)
-  classical     Cahn-Hilliard, Willmore and Helfrich phase fields and the diffuse
-                curvatures, each from its own equation (Secs. 2.3, 3.1)
+  classical     Cahn-Hilliard, Willmore and Helfrich phase fields, the diffuse
+                curvatures, each from its own equation (Secs. 2.3, 3.1), and the
+                diagnostics built on them (curvature histogram, discrepancy)
   closed_forms  continuum values on tanh-profile spheres, cylinders and planes by
                 co-area quadrature (Sec. 3.2)
   params        coefficient vectors: eq. (redundant), Helfrich, inside-out swap

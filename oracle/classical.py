@@ -9,7 +9,9 @@ density:
 * W_eps, the Bellettini-Paolini Willmore phase field, eq. (Willmore_eps);
 * H_eps, the Bellettini-Mugnai Helfrich phase field, eq. (Helfrich_eps);
 * the diffuse curvatures of eqs. (Beps)-(kepsb), Sec. 3.1;
-* the normalised discrepancy used as a viability test in Sec. 4.5 (Experiment 4).
+* the normalised discrepancy used as a viability test in Sec. 4.5 (Experiment 4);
+* a co-area weighted histogram of (kappa1, kappa2), standing in for the
+  curvature diagram of Sec. 4.1, and the per-field viability summary.
 
 The same discretisation readings as the F_eps oracle apply: periodic central
 differences, the 7-point Laplacian, and |grad u| regularised by xi wherever it
@@ -98,3 +100,41 @@ def discrepancy(u, h, eps):
     a = 0.5 * eps * _grad_sq(u, h)
     b = double_well(u) / eps
     return float(np.sum(np.abs(a - b)) / np.sum(a + b))
+
+
+def curvature_histogram(u, h, eps, nbins, kmax, xi=XI):
+    """Co-area weighted histogram of the diffuse principal curvatures: a mesh-free
+    stand-in for the curvature diagram of Sec. 4.1 (the area-weighted law of
+    (kappa1, kappa2) on the surface).
+
+    Each voxel contributes the weight h^3 eps |grad u|^2, the density that
+    concentrates on the diffuse interface (for a tanh profile it equals
+    sqrt(2 W(u)) |grad u|, so by co-area the weights add up to the
+    sigma-weighted areas of the level sets). Its (kappa1, kappa2) from
+    eqs. (kepsa), (kepsb) are clamped to [-kmax, kmax] (values are truncated
+    there, as in the paper's diagrams) and binned uniformly:
+    index = floor((kappa + kmax) * nbins / (2 kmax)), at most nbins - 1.
+    Returns hist[nbins, nbins], indexed [bin of kappa1, bin of kappa2].
+    """
+    u = np.asarray(u, dtype=np.float64)
+    _, _, k1, k2 = diffuse_curvatures(u, h, eps, xi)
+    w = h ** 3 * eps * _grad_sq(u, h)
+    scale = nbins / (2.0 * kmax)
+
+    def index(k):
+        kc = np.clip(k, -kmax, kmax)
+        return np.minimum(np.floor((kc + kmax) * scale).astype(np.int64), nbins - 1)
+
+    hist = np.zeros((nbins, nbins))
+    np.add.at(hist, (index(k1).ravel(), index(k2).ravel()), w.ravel())
+    return hist
+
+
+def diagnostic_stats(u, h, eps, a, xi=XI):
+    """Per-field summary used to judge a generated texture (Sec. 4.5, Experiment 4):
+    (F_h, A_eps, normalised discrepancy, min u, max u). The paper deems a shape
+    viable when the discrepancy is under 0.75, max u > 0.1 and min u < -0.1."""
+    from .fe_oracle import energy
+    u = np.asarray(u, dtype=np.float64)
+    return (energy(u, h, eps, a, xi), cahn_hilliard(u, h, eps), discrepancy(u, h, eps),
+            float(u.min()), float(u.max()))
