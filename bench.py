@@ -110,7 +110,17 @@ def bench_single(n, steps, warmup, tune):
     for _ in range(3):
         ctx.energy_grad_async(u, g, E)
     ms_grad = time_region(lambda: ctx.energy_grad_async(u, g, E), reps=steps)
-    return ctx, u, ms / steps, ms_grad
+    # the diagnostics sweep: curvature fields, a 64 x 64 histogram and the summary
+    curv = torch.empty((1, 4) + u.shape, dtype=u.dtype, device=u.device)
+    hist = torch.empty((1, 64, 64), dtype=torch.float64, device=u.device)
+
+    def diag():
+        ctx.diagnostics_async(u, curv, hist, kmax=100.0)
+
+    diag()
+    ms_diag = time_region(diag, reps=max(steps // 10, 5))
+    del curv, hist
+    return ctx, u, ms / steps, ms_grad, ms_diag
 
 
 def bench_batched(n, B, steps, warmup, tune):
@@ -225,9 +235,9 @@ def main():
     n = 256
     vox = n ** 3
     log(f"device {torch.cuda.get_device_name(0)}; 256^3 FP32 step loop ...")
-    ctx, u, ms_step, ms_grad = bench_single(n, args.steps, args.warmup, args.tune)
+    ctx, u, ms_step, ms_grad, ms_diag = bench_single(n, args.steps, args.warmup, args.tune)
     variant, zc = ctx.get_launch()
-    log(f"  {ms_step * 1e3:.1f} us/step, energy+grad sweep {ms_grad * 1e3:.1f} us")
+    log(f"  {ms_step * 1e3:.1f} us/step, energy+grad sweep {ms_grad * 1e3:.1f} us, diagnostics {ms_diag * 1e3:.1f} us")
     value = vox / (ms_step * 1e-3)
 
     extra = {}
@@ -296,6 +306,9 @@ def main():
         "energy_grad_sweep": {"value": vox / (ms_grad * 1e-3), "us": ms_grad * 1e3,
                               "hbm_frac": BYTES_PER_VOXEL_GRAD * vox / (ms_grad * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "steps_per_s": 1e3 / ms_step,
+        "diagnostics_sweep": {"us": ms_diag * 1e3, "voxels_per_s": vox / (ms_diag * 1e-3),
+                              "outputs": "H, K, kappa1, kappa2 fields, 64x64 curvature histogram, "
+                                         "F_h, A_eps, discrepancy, min/max u"},
     }
     out.update(extra)
     if not args.no_cpu:

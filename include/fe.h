@@ -171,6 +171,27 @@ int fe_hminus_step(fe_ctx* ctx, void* A, const double* m0, double sigma_k, doubl
 int fe_hminus_reset(fe_ctx* ctx);
 
 /*
+ * Texture diagnostics of u in one sweep over the energy's stencils.
+ *   curv   device [batch][4][nz][ny][nx] in the context's precision, or NULL:
+ *          the diffuse mean curvature H, Gaussian curvature K and principal
+ *          curvatures kappa1 >= kappa2 of eqs. (Heps), (Keps), (kepsa),
+ *          (kepsb) (Sec. 3.1), with |grad u| regularised as sqrt(|g|^2 + xi^2).
+ *   hist   device double [batch][nbins][nbins], or NULL: histogram of
+ *          (kappa1, kappa2), indexed [bin of kappa1][bin of kappa2], each voxel
+ *          weighted by h^3 eps |grad u|^2 (the density that concentrates on
+ *          the diffuse interface); curvatures are clamped to [-kmax, kmax] and
+ *          binned uniformly, bin = min(floor((k + kmax) nbins / (2 kmax)),
+ *          nbins - 1), in the context's precision. A mesh-free stand-in for the
+ *          curvature diagram of Sec. 4.1. The call zeroes it first. Bins are
+ *          summed with floating-point atomics, so their last bits may vary
+ *          between calls. 1 <= nbins <= 64, kmax > 0.
+ *   stats  host double [batch][5], or NULL: F_h, the Cahn-Hilliard area
+ *          A_eps of eq. (CH_eps), the discrepancy of Sec. 4.5 normalised by
+ *          A_eps, min u and max u (bitwise deterministic; synchronises).
+ */
+int fe_diagnostics(fe_ctx* ctx, const void* u, void* curv, double* hist, int nbins, double kmax, double* stats);
+
+/*
  * Launch-shape selection. Variants are numbered 0 .. fe_num_variants()-1;
  * fe_variant_info describes one (x and y interior tile, threads per block,
  * element size it supports). fe_set_launch picks a variant and a z-chunk

@@ -15,6 +15,7 @@
 
 #include "fe.h"
 #include "fe_flow.hpp"
+#include "fe_diag.hpp"
 #include "fe_kernels.hpp"
 
 namespace {
@@ -165,6 +166,8 @@ struct fe_ctx {
   void* d_am1 = nullptr;              // H^-1 flow: Adam moments of A ([batch][3] fields each)
   void* d_am2 = nullptr;
   fe::FlowClock* d_flow_clk = nullptr; // H^-1 flow: Adam step number and bias corrections (device)
+  double* d_diag = nullptr;           // diagnostics: per-instance constants, stats, block partials
+  size_t diag_bytes = 0;
   size_t max_blocks = 0;              // per instance, over all variants and z chunks
   int variant = -1;
   int lz = 0;                         // 0 = automatic
@@ -507,6 +510,80 @@ int flow_reset_launch(fe_ctx* c) {
   return FE_OK;
 }
 
+// The diagnostics sweep: one tile shape for both precisions, z chunks of up to 32.
+constexpr int kDiagTX = 64, kDiagTY = 8, kDiagNT = 512, kDiagLZ = 32;
+
+template <typename T>
+int diagnostics(fe_ctx* c, const void* u, void* curv, double* hist, int nbins, double kmax, double* stats) {
+  const int B = c->grid.batch;
+  const int ntx = ceil_div(c->grid.nx, kDiagTX), nty = ceil_div(c->grid.ny, kDiagTY);
+  // the longest z chunk (fewest recomputed halo planes) that still gives every
+  // compute unit two blocks
+  int lz = kDiagLZ;
+  while (lz > 4 && (double)ntx * nty * ceil_div(c->grid.nz, lz) * B < 2.0 * c->num_cu) lz /= 2;
+  lz = std::min(lz, c->grid.nz);
+  const int nzc = ceil_div(c->grid.nz, lz);
+  const size_t per_inst = (size_t)ntx * nty * nzc;
+  // layout of d_diag: DiagInst[B] | stats[B][5] | partials[B][per_inst][5]
+  const size_t need = sizeof(fe::DiagInst) * B + sizeof(double) * fe::kDiagStats * B * (1 + per_inst);
+  if (c->diag_bytes < need) {
+    if (c->d_diag) (void)hipFree(c->d_diag);
+    c->d_diag = nullptr;
+    c->diag_bytes = 0;
+    if (hipMalloc((void**)&c->d_diag, need) != hipSuccess) {
+      c->d_diag = nullptr;
+      return set_error(FE_ENOMEM, "diagnostics workspace allocation failed");
+    }
+    c->diag_bytes = need;
+  }
+  const double h = c->grid.h;
+  std::vector<fe::DiagInst> di(B);
+  for (int b = 0; b < B; ++b) {
+    const double eps = c->eps[b];
+    di[b] = fe::DiagInst{eps * h / 8.0, h * h * h / (4.0 * eps), eps * h / 4.0};
+  }
+  fe::DiagInst* d_inst = reinterpret_cast<fe::DiagInst*>(c->d_diag);
+  double* d_stats = reinterpret_cast<double*>(d_inst + B);
+  double* d_part = d_stats + (size_t)fe::kDiagStats * B;
+  FE_HIP(hipMemcpyAsync(d_inst, di.data(), sizeof(fe::DiagInst) * B, hipMemcpyHostToDevice, c->stream));
+  if (hist) {
+    const int n = B * nbins * nbins;
+    hipLaunchKernelGGL(fe::fill_f64, dim3(ceil_div(n, 64)), dim3(64), 0, c->stream, hist, n, 0.0);
+  }
+  fe::SweepArgs<T> a{};
+  a.src = static_cast<const T*>(u);
+  a.prm = static_cast<const fe::InstParams<T>*>(c->d_prm);
+  a.k = grid_consts<T>(h);
+  a.nx = c->grid.nx;
+  a.ny = c->grid.ny;
+  a.nz = c->grid.nz;
+  a.ntx = ntx;
+  a.nty = nty;
+  a.nzc = nzc;
+  a.lz = lz;
+  a.batch = B;
+  fe::DiagArgs<T> d{};
+  d.inst = d_inst;
+  d.curv = static_cast<T*>(curv);
+  d.hist = hist;
+  d.partials = d_part;
+  d.nbins = hist ? nbins : 0;
+  d.kmax = T(kmax);
+  d.bin_scale = T(hist ? nbins / (2.0 * kmax) : 0.0);
+  d.inv_h = T(1.0 / h);
+  d.inv_h2 = T(1.0 / (h * h));
+  hipLaunchKernelGGL((fe::diag_sweep<T, kDiagTX, kDiagTY, kDiagNT>), dim3((unsigned)(per_inst * B)),
+                     dim3(kDiagNT), 0, c->stream, a, d);
+  hipLaunchKernelGGL(fe::diag_finish, dim3(B), dim3(256), 0, c->stream, (const double*)d_part, (int)per_inst,
+                     d_stats);
+  FE_HIP(hipGetLastError());
+  if (stats) {
+    FE_HIP(hipMemcpyAsync(stats, d_stats, sizeof(double) * fe::kDiagStats * B, hipMemcpyDeviceToHost, c->stream));
+    FE_HIP(hipStreamSynchronize(c->stream));
+  }
+  return FE_OK;
+}
+
 int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int nsteps, double* energy) {
   if (!u) return set_error(FE_EINVAL, "u is NULL");
   if (!mass) return set_error(FE_EINVAL, "mass is NULL");
@@ -817,6 +894,21 @@ int fe_hminus_step(fe_ctx* c, void* A, const double* m0, double sigma_k, double 
   return copy_energy_out(c, energy);
 }
 
+int fe_diagnostics(fe_ctx* c, const void* u, void* curv, double* hist, int nbins, double kmax, double* stats) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!u) return set_error(FE_EINVAL, "u is NULL");
+  if (curv == u) return set_error(FE_EINVAL, "curv must not alias u");
+  if (hist) {
+    if (nbins < 1 || nbins > fe::kDiagMaxBins)
+      return set_error(FE_EINVAL, "nbins must lie in [1, %d] (got %d)", fe::kDiagMaxBins, nbins);
+    if (!(kmax > 0.0) || !std::isfinite(kmax)) return set_error(FE_EINVAL, "kmax must be finite and > 0");
+  }
+  DeviceGuard dg(c->device);
+  return c->grid.dtype == FE_F32 ? diagnostics<float>(c, u, curv, hist, nbins, kmax, stats)
+                                 : diagnostics<double>(c, u, curv, hist, nbins, kmax, stats);
+}
+
 int fe_hminus_reset(fe_ctx* c) {
   g_last_error.clear();
   if (!c) return set_error(FE_EINVAL, "ctx is NULL");
@@ -919,7 +1011,7 @@ void fe_destroy(fe_ctx* c) {
   if (c->d_m1) (void)hipFree(c->d_m1);
   if (c->d_m2) (void)hipFree(c->d_m2);
   if (c->d_adam_t) (void)hipFree(c->d_adam_t);
-  for (void* p : {c->d_w0, c->d_w1, c->d_am1, c->d_am2, (void*)c->d_flow_clk})
+  for (void* p : {c->d_w0, c->d_w1, c->d_am1, c->d_am2, (void*)c->d_flow_clk, (void*)c->d_diag})
     if (p) (void)hipFree(p);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;

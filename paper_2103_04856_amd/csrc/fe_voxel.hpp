@@ -246,15 +246,20 @@ __device__ __forceinline__ void softplus_xi(T X, const InstParams<T>& p, T& P, T
 }
 
 // Forward only: the scaled energy density f~ = h^3 f at one voxel.
-template <typename T, typename Reload>
-__device__ __forceinline__ T voxel_density(const Stencil19<T>& s, Reload reload, const InstParams<T>& p,
-                                           const GridConsts<T>& k) {
-  const Forward<T> fw = forward_chain(s, reload, p, k);
+// f~ from the forward chain's values.
+template <typename T>
+__device__ __forceinline__ T density_of(const Forward<T>& fw, const InstParams<T>& p) {
   T P, sig;
   softplus_xi(fw.X, p, P, sig);
   const T S = P > T(0) ? P * rsqrt_t(P) : T(0);
   const T rho = fw.R * rsqrt_t(fw.R);
   return p.C1 * fw.n2 + fw.tr * (p.C2 * fw.tr + p.C3 * S + p.C4 * rho) + p.C5 * rho * S + p.C6 * fw.Q;
+}
+
+template <typename T, typename Reload>
+__device__ __forceinline__ T voxel_density(const Stencil19<T>& s, Reload reload, const InstParams<T>& p,
+                                           const GridConsts<T>& k) {
+  return density_of(forward_chain(s, reload, p, k), p);
 }
 
 // Forward and adjoint at one voxel. Returns f~ and writes its derivatives with

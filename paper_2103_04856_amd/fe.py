@@ -54,6 +54,7 @@ SIGNATURES = {
     "fe_hminus_step": (ctypes.c_int, [_P, _P, _DP, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, _DP]),
     "fe_hminus_reset": (ctypes.c_int, [_P]),
+    "fe_diagnostics": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_double, _DP]),
     "fe_num_variants": (ctypes.c_int, []),
     "fe_variant_info": (ctypes.c_int, [ctypes.c_int, _IP, _IP, _IP, _IP]),
     "fe_set_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
@@ -259,6 +260,42 @@ class FeContext:
     def hminus_reset(self):
         self._sync_stream()
         _check(lib().fe_hminus_reset(self._h))
+
+    def diagnostics(self, u, curvatures=False, nbins=0, kmax=100.0):
+        """Diffuse curvatures, the curvature histogram and the viability summary of u.
+        Returns (stats [B, 5] float64: F_h, A_eps, discrepancy, min u, max u;
+        curvatures [B, 4, nz, ny, nx] (H, K, kappa1, kappa2) or None;
+        histogram [B, nbins, nbins] float64 on the device, or None)."""
+        B = self.shape[0]
+        up = self._field(u, "u")
+        curv = None
+        if curvatures:
+            curv = torch.empty((B, 4) + self.shape[1:], dtype=self.dtype, device=u.device)
+        hist = torch.empty((B, nbins, nbins), dtype=torch.float64, device=u.device) if nbins else None
+        out = (ctypes.c_double * (5 * B))()
+        self._sync_stream()
+        _check(lib().fe_diagnostics(self._h, up, _P(curv.data_ptr()) if curv is not None else _P(0),
+                                    _P(hist.data_ptr()) if hist is not None else _P(0), int(nbins),
+                                    float(kmax), out))
+        stats = torch.tensor(list(out), dtype=torch.float64).reshape(B, 5)
+        return stats, curv, hist
+
+    def diagnostics_async(self, u, curv=None, hist=None, kmax=100.0):
+        """Stream-ordered diagnostics into preallocated outputs (curv [B, 4, nz, ny, nx] in
+        the context dtype, hist [B, nbins, nbins] float64); no summary, no synchronisation."""
+        up = self._field(u, "u")
+        nb = 0
+        if hist is not None:
+            if hist.dtype != torch.float64 or hist.dim() != 3 or hist.shape[1] != hist.shape[2] \
+                    or hist.shape[0] != self.shape[0] or not hist.is_contiguous():
+                raise ValueError("hist must be a contiguous float64 tensor [B, nbins, nbins]")
+            nb = hist.shape[1]
+        if curv is not None and (curv.dtype != self.dtype or tuple(curv.shape) != (self.shape[0], 4) + self.shape[1:]
+                                 or not curv.is_contiguous()):
+            raise ValueError("curv must be a contiguous tensor [B, 4, nz, ny, nx] of the context dtype")
+        self._sync_stream()
+        _check(lib().fe_diagnostics(self._h, up, _P(curv.data_ptr()) if curv is not None else _P(0),
+                                    _P(hist.data_ptr()) if hist is not None else _P(0), nb, float(kmax), None))
 
     def set_launch(self, variant, z_chunk=0):
         _check(lib().fe_set_launch(self._h, int(variant), int(z_chunk)))

@@ -100,4 +100,5 @@ def test_calls_on_null_context_fail_cleanly(L):
     assert L.fe_set_launch(None, 0, 0) == fe.FE_EINVAL
     assert L.fe_hminus_step(None, None, None, 2.0, 1e-3, 0.9, 0.999, 1e-8, 1, None, None) == fe.FE_EINVAL
     assert L.fe_hminus_reset(None) == fe.FE_EINVAL
+    assert L.fe_diagnostics(None, None, None, None, 8, 10.0, None) == fe.FE_EINVAL
     L.fe_destroy(None)   # no-op
