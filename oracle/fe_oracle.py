@@ -20,7 +20,9 @@ What it computes, in the order the paper defines it:
   obtained by a hand-derived reverse-mode (adjoint) sweep;
 * a mass-preserving descent step: a plain gradient step followed by the L2
   projection back onto the set {mean(u) = m}; the mass (mean) constraint is the
-  one Sec. 4.1 imposes on the flow.
+  one Sec. 4.1 imposes on the flow;
+* the extensions of Sec. 5.2: the orientation term eps mu (theta . grad u)^2
+  and space-dependent coefficients a(x) and mass m(x).
 
 Readings where the paper leaves a choice open (all listed in the design notes):
 
@@ -123,8 +125,10 @@ def feps_coefficients(a, eps):
     a = (a20, a11, a02, a10, a01, a00) in the order of Sec. 3.2.  The integrand
     is c1 ||M||^2 + c2 (Tr M)^2 + c3 Tr M S + c4 |grad u| Tr M
     + c5 |grad u| S + c6 eps |grad u|^2, with S = sqrt((2||M||^2 - (Tr M)^2)^+).
+    Each a_k may be a number or a field of the grid's shape (the spatialised
+    parameters a(x) of Sec. 5.2); the c_k are then fields too.
     """
-    a20, a11, a02, a10, a01, a00 = (float(v) for v in a)
+    a20, a11, a02, a10, a01, a00 = (np.asarray(v, dtype=np.float64) for v in a)
     return ((a20 + a02 - a11) / (2.0 * eps),
             a11 / (2.0 * eps),
             (a20 - a02) / (2.0 * eps),
@@ -161,12 +165,15 @@ def positive_part(x, xi=XI, mode="smooth"):
 # Forward: pointwise fields and the energy
 # --------------------------------------------------------------------------
 
-def pointwise(u, h, eps, a, xi=XI, mode="smooth"):
+def pointwise(u, h, eps, a, xi=XI, mode="smooth", orient=None):
     """All per-voxel quantities of eq. (Meps) and eq. (Feps) on the grid.
 
     Returns a dict with the stencil values g (3), H (6), the matrix M (6, same
     order as H), T = Tr M, N2 = ||M||_F^2, X = 2 N2 - T^2, S = sqrt(X^+ smoothed),
-    rho = sqrt(q + xi^2), q = |g|^2, the six term fields and the density f.
+    rho = sqrt(q + xi^2), q = |g|^2, the term fields and the density f.
+
+    orient = (mu, theta) adds the orientation term of Sec. 5.2,
+    eps mu (theta . grad u)^2, as a seventh term (theta as given, (x, y, z)).
     """
     u = np.asarray(u, dtype=np.float64)
     c1, c2, c3, c4, c5, c6 = feps_coefficients(a, eps)
@@ -187,18 +194,24 @@ def pointwise(u, h, eps, a, xi=XI, mode="smooth"):
     S = np.sqrt(P)
     terms = (c1 * N2, c2 * T * T, c3 * T * S, c4 * rho * T, c5 * rho * S, c6 * eps * q)
     f = terms[0] + terms[1] + terms[2] + terms[3] + terms[4] + terms[5]
+    tg = None
+    if orient is not None:
+        mu, th = orient
+        tg = th[0] * g[0] + th[1] * g[1] + th[2] * g[2]          # theta . grad u
+        terms = terms + (eps * mu * tg * tg,)
+        f = f + terms[6]
     return dict(g=g, H=H, M=M, T=T, N2=N2, X=X, P=P, dP=dP, S=S, q=q, r=r, rho=rho,
-                s=s, terms=terms, f=f, coeffs=(c1, c2, c3, c4, c5, c6))
+                s=s, terms=terms, f=f, coeffs=(c1, c2, c3, c4, c5, c6), tg=tg)
 
 
-def energy(u, h, eps, a, xi=XI, mode="smooth"):
+def energy(u, h, eps, a, xi=XI, mode="smooth", orient=None):
     """F_h(u) = h^3 sum_i f_i: eq. (Feps) with the integral as a finite sum (Sec. 4.1)."""
-    return float(h ** 3 * np.sum(pointwise(u, h, eps, a, xi, mode)["f"]))
+    return float(h ** 3 * np.sum(pointwise(u, h, eps, a, xi, mode, orient)["f"]))
 
 
-def energy_abs(u, h, eps, a, xi=XI, mode="smooth"):
+def energy_abs(u, h, eps, a, xi=XI, mode="smooth", orient=None):
     """h^3 sum_i sum_k |term_k|: the scale used for relative energy errors when F ~ 0."""
-    t = pointwise(u, h, eps, a, xi, mode)["terms"]
+    t = pointwise(u, h, eps, a, xi, mode, orient)["terms"]
     return float(h ** 3 * sum(np.sum(np.abs(x)) for x in t))
 
 
@@ -206,7 +219,7 @@ def energy_abs(u, h, eps, a, xi=XI, mode="smooth"):
 # Adjoint: exact gradient of F_h with respect to every voxel value
 # --------------------------------------------------------------------------
 
-def adjoint_fields(u, h, eps, a, xi=XI, mode="smooth"):
+def adjoint_fields(u, h, eps, a, xi=XI, mode="smooth", orient=None):
     """Per-voxel partial derivatives of f with respect to its stencil inputs.
 
     Returns (ubar, gamma[3], theta[6], fwd): ubar = df/du at the voxel itself
@@ -214,7 +227,7 @@ def adjoint_fields(u, h, eps, a, xi=XI, mode="smooth"):
     xz, yz), computed by reverse-mode differentiation of the forward chain in
     `pointwise`.
     """
-    fw = pointwise(u, h, eps, a, xi, mode)
+    fw = pointwise(u, h, eps, a, xi, mode, orient)
     c1, c2, c3, c4, c5, c6 = fw["coeffs"]
     g, M, T, S, rho, r, s = fw["g"], fw["M"], fw["T"], fw["S"], fw["rho"], fw["r"], fw["s"]
     u = np.asarray(u, dtype=np.float64)
@@ -245,17 +258,21 @@ def adjoint_fields(u, h, eps, a, xi=XI, mode="smooth"):
         s * (2.0 * M_bar[1] * g[1] + M_bar[3] * g[0] + M_bar[5] * g[2]) + 2.0 * g[1] * q_bar,
         s * (2.0 * M_bar[2] * g[2] + M_bar[4] * g[0] + M_bar[5] * g[1]) + 2.0 * g[2] * q_bar,
     ]
+    if orient is not None:
+        # d/dg_a of eps mu (theta . g)^2
+        mu, th = orient
+        gamma = [gamma[a_] + 2.0 * eps * mu * fw["tg"] * th[a_] for a_ in range(3)]
     return ubar, gamma, theta, fw
 
 
-def energy_grad(u, h, eps, a, xi=XI, mode="smooth"):
+def energy_grad(u, h, eps, a, xi=XI, mode="smooth", orient=None):
     """(F_h, dF_h/du): energy and its exact gradient, h^3 included.
 
     The gradient applies the transposes of the stencils to the per-voxel adjoint
     fields: the central difference is anti-self-adjoint on a periodic grid and
     the second and mixed differences are self-adjoint.
     """
-    ubar, gamma, theta, fw = adjoint_fields(u, h, eps, a, xi, mode)
+    ubar, gamma, theta, fw = adjoint_fields(u, h, eps, a, xi, mode, orient)
     grad = ubar.copy()
     for a_ in range(3):
         # transpose of the central difference
@@ -378,12 +395,13 @@ def gaussian_blur(u, sigma_k):
     return out
 
 
-def hminus_energy(A, h, eps, a, m0, sigma_k, xi=XI, mode="smooth"):
-    """G_eps(A) = F_h(k * (div A + m0)) (Algorithm 1, with the blur before the energy)."""
-    return energy(gaussian_blur(fd_divergence(A, h) + m0, sigma_k), h, eps, a, xi, mode)
+def hminus_energy(A, h, eps, a, m0, sigma_k, xi=XI, mode="smooth", orient=None):
+    """G_eps(A) = F_h(k * (div A + m0)) (Algorithm 1, with the blur before the energy).
+    m0 may be a field m(x) (Sec. 5.2), a may hold fields a(x)."""
+    return energy(gaussian_blur(fd_divergence(A, h) + m0, sigma_k), h, eps, a, xi, mode, orient)
 
 
-def hminus_energy_grad(A, h, eps, a, m0, sigma_k, xi=XI, mode="smooth"):
+def hminus_energy_grad(A, h, eps, a, m0, sigma_k, xi=XI, mode="smooth", orient=None):
     """(G_eps(A), dG/dA, u) with u = k * (div A + m0): the chain rule of Algorithm 1.
 
     dG/du_b = dF_h/du (at the blurred field), dG/du = k * dG/du_b (even kernel),
@@ -391,17 +409,17 @@ def hminus_energy_grad(A, h, eps, a, m0, sigma_k, xi=XI, mode="smooth"):
     anti-self-adjoint on a periodic grid), i.e. dG/dA = -grad dF/du of Sec. 4.1.
     """
     u = gaussian_blur(fd_divergence(A, h) + m0, sigma_k)
-    E, gb = energy_grad(u, h, eps, a, xi, mode)
+    E, gb = energy_grad(u, h, eps, a, xi, mode, orient)
     gu = gaussian_blur(gb, sigma_k)
     gA = np.stack([-(_at(gu, _unit(a_)) - _at(gu, _unit(a_, -1))) / (2.0 * h) for a_ in range(3)])
     return E, gA, u
 
 
 def hminus_adam_step(A, m1, m2, t, h, eps, a, m0, sigma_k, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8,
-                     xi=XI, mode="smooth"):
+                     xi=XI, mode="smooth", orient=None):
     """One iteration of Algorithm 1: G and dG/dA at A, then Adam on A (step number t >= 1).
     Returns (A_new, m1, m2, G(A), u) with u the blurred phase field at A."""
-    E, gA, u = hminus_energy_grad(A, h, eps, a, m0, sigma_k, xi, mode)
+    E, gA, u = hminus_energy_grad(A, h, eps, a, m0, sigma_k, xi, mode, orient)
     m1 = beta1 * m1 + (1.0 - beta1) * gA
     m2 = beta2 * m2 + (1.0 - beta2) * gA * gA
     mhat = m1 / (1.0 - beta1 ** t)
@@ -411,7 +429,7 @@ def hminus_adam_step(A, m1, m2, t, h, eps, a, m0, sigma_k, lr=1e-3, beta1=0.9, b
 
 
 def hminus_descend(A, h, eps, a, m0, sigma_k, nsteps, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8,
-                   xi=XI, mode="smooth"):
+                   xi=XI, mode="smooth", orient=None):
     """nsteps iterations of Algorithm 1 from zero moments. Returns (A, [G before each step], u_final)
     with u_final = k * (div A + m0) at the final A."""
     A = np.asarray(A, dtype=np.float64)
@@ -420,6 +438,6 @@ def hminus_descend(A, h, eps, a, m0, sigma_k, nsteps, lr=1e-3, beta1=0.9, beta2=
     energies = []
     for t in range(1, nsteps + 1):
         A, m1, m2, E, _ = hminus_adam_step(A, m1, m2, t, h, eps, a, m0, sigma_k, lr, beta1, beta2, adam_eps,
-                                           xi, mode)
+                                           xi, mode, orient)
         energies.append(E)
     return A, energies, gaussian_blur(fd_divergence(A, h) + m0, sigma_k)
