@@ -143,6 +143,16 @@ int fe_step_adam(fe_ctx* ctx, void* u, const double* mass, double lr, double bet
 int fe_adam_reset(fe_ctx* ctx);
 
 /*
+ * The orientation term of Sec. 5.2: every later energy, gradient, step, flow
+ * and diagnostics call adds eps mu (theta . grad u)^2 to the density (with
+ * grad u the central differences), i.e. h^3 eps mu sum_i (theta . g_i)^2 to F_h.
+ *   mu     host [batch]; 0 switches the term off for that instance (the default).
+ *   theta  host [batch][3] (x, y, z), used as given (the paper takes a unit vector).
+ * All values must be finite. Does not reallocate; synchronises the stream.
+ */
+int fe_set_orientation(fe_ctx* ctx, const double* mu, const double* theta);
+
+/*
  * nsteps iterations of the paper's generation algorithm (Algorithm 1, Sec. 4.1):
  * the mass-preserving H^-1 flow written as an L2 flow on a periodic vector
  * field A through u = div A + m0, with a small Gaussian blur before the energy

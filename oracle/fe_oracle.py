@@ -292,23 +292,23 @@ def energy_grad(u, h, eps, a, xi=XI, mode="smooth", orient=None):
 # Mass-preserving descent (Sec. 4.1: the flow keeps the mean of u fixed)
 # --------------------------------------------------------------------------
 
-def mass_projected_step(u, h, eps, a, m, tau, xi=XI, mode="smooth"):
+def mass_projected_step(u, h, eps, a, m, tau, xi=XI, mode="smooth", orient=None):
     """One step u <- P_m(u - tau dF_h/du), P_m(v) = v + (m - mean(v)).
 
     P_m is the L2-orthogonal projection onto {mean(u) = m}. Returns
     (u_new, F_h(u)), the energy being that of the field before the step.
     """
-    E, grad = energy_grad(u, h, eps, a, xi, mode)
+    E, grad = energy_grad(u, h, eps, a, xi, mode, orient)
     v = np.asarray(u, dtype=np.float64) - tau * grad
     return v + (m - np.mean(v)), E
 
 
-def descend(u, h, eps, a, m, tau, nsteps, xi=XI, mode="smooth"):
+def descend(u, h, eps, a, m, tau, nsteps, xi=XI, mode="smooth", orient=None):
     """nsteps mass-projected steps; returns (u_final, [F_h before each step])."""
     energies = []
     u = np.asarray(u, dtype=np.float64)
     for _ in range(nsteps):
-        u, E = mass_projected_step(u, h, eps, a, m, tau, xi, mode)
+        u, E = mass_projected_step(u, h, eps, a, m, tau, xi, mode, orient)
         energies.append(E)
     return u, energies
 

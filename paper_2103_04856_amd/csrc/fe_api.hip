@@ -151,6 +151,7 @@ struct fe_ctx {
   hipStream_t stream = nullptr;       // caller's stream (may be null = default)
   hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
   std::vector<double> eps, coeffs;    // host copies [batch], [batch][6]
+  std::vector<double> mu, theta;      // orientation term [batch], [batch][3] (mu = 0: off)
   void* d_prm = nullptr;              // InstParams<T>[batch]
   double* d_partials = nullptr;       // [batch][max_blocks][2]
   int* d_counters = nullptr;          // [batch + 1] finished-block counters (zero between launches)
@@ -228,6 +229,10 @@ void fill_params(const fe_ctx* c, std::vector<fe::InstParams<T>>& out) {
     p.C6 = T(h3 * c6 * e / (4.0 * h * h));
     p.xi = T(kXi / (sc * sc));
     p.inv_xi = T(sc * sc / kXi);
+    p.Co = T(h3 * e * c->mu[b] / (4.0 * h * h));
+    p.thx = T(c->theta[3 * b]);
+    p.thy = T(c->theta[3 * b + 1]);
+    p.thz = T(c->theta[3 * b + 2]);
   }
 }
 
@@ -687,6 +692,8 @@ int fe_create(const fe_grid* grid, const double* eps, const double* p_coeffs, vo
   c->stream = static_cast<hipStream_t>(stream);
   c->eps.assign(eps, eps + grid->batch);
   c->coeffs.assign(p_coeffs, p_coeffs + 6 * grid->batch);
+  c->mu.assign(grid->batch, 0.0);
+  c->theta.assign(3 * grid->batch, 0.0);
   c->variant = default_variant(*grid);
   c->lz = 0;
 
@@ -736,6 +743,21 @@ int fe_set_params(fe_ctx* c, const double* eps, const double* p_coeffs) {
   DeviceGuard dg(c->device);
   c->eps.assign(eps, eps + c->grid.batch);
   c->coeffs.assign(p_coeffs, p_coeffs + 6 * c->grid.batch);
+  return upload_params(c);
+}
+
+int fe_set_orientation(fe_ctx* c, const double* mu, const double* theta) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!mu || !theta) return set_error(FE_EINVAL, "mu and theta must not be NULL");
+  for (int b = 0; b < c->grid.batch; ++b) {
+    if (!std::isfinite(mu[b])) return set_error(FE_EINVAL, "mu[%d] is not finite", b);
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(theta[3 * b + k])) return set_error(FE_EINVAL, "theta[%d] is not finite", b);
+  }
+  DeviceGuard dg(c->device);
+  c->mu.assign(mu, mu + c->grid.batch);
+  c->theta.assign(theta, theta + 3 * c->grid.batch);
   return upload_params(c);
 }
 

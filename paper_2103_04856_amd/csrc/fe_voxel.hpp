@@ -45,6 +45,8 @@ struct InstParams {
   T lam;                       // h^2 / eps^2
   T C1, C2, C3, C4, C5, C6;    // h^3 c1 s^2, h^3 c2 s^2, h^3 c3 s^2, h^3 c4 s/(2h), h^3 c5 s/(2h), h^3 c6 eps/(4h^2)
   T xi, inv_xi;                // softplus width in X~ units: xi h^4 / eps^2, and its inverse
+  T Co;                        // orientation term of Sec. 5.2: h^3 eps mu / (4h^2) (0: off)
+  T thx, thy, thz;             // its direction theta
 };
 
 // Grid constants shared by all instances.
@@ -253,7 +255,12 @@ __device__ __forceinline__ T density_of(const Forward<T>& fw, const InstParams<T
   softplus_xi(fw.X, p, P, sig);
   const T S = P > T(0) ? P * rsqrt_t(P) : T(0);
   const T rho = fw.R * rsqrt_t(fw.R);
-  return p.C1 * fw.n2 + fw.tr * (p.C2 * fw.tr + p.C3 * S + p.C4 * rho) + p.C5 * rho * S + p.C6 * fw.Q;
+  T f = p.C1 * fw.n2 + fw.tr * (p.C2 * fw.tr + p.C3 * S + p.C4 * rho) + p.C5 * rho * S + p.C6 * fw.Q;
+  if (p.Co != T(0)) {                              // eps mu (theta . g)^2 = Co (theta . a)^2 / h^3
+    const T ta = p.thx * fw.ax + p.thy * fw.ay + p.thz * fw.az;
+    f += p.Co * ta * ta;
+  }
+  return f;
 }
 
 template <typename T, typename Reload>
@@ -276,7 +283,7 @@ __device__ __forceinline__ T voxel_density_adjoint(const Stencil19<T>& s, Reload
   const T rs = rsqrt_t(fw.R);
   const T rho = fw.R * rs;                         // 2h rho
 
-  const T f = p.C1 * fw.n2 + tr * (p.C2 * tr + p.C3 * S + p.C4 * rho) + p.C5 * rho * S + p.C6 * fw.Q;
+  T f = p.C1 * fw.n2 + tr * (p.C2 * tr + p.C3 * S + p.C4 * rho) + p.C5 * rho * S + p.C6 * fw.Q;
 
   // ---- reverse sweep ----
   const T Sb = p.C3 * tr + p.C5 * rho;             // df/dS~
@@ -314,6 +321,14 @@ __device__ __forceinline__ T voxel_density_adjoint(const Stencil19<T>& s, Reload
   a.gx = sw * (bxx2 * ax + qxy * ay + qxz * az) + Qb2 * ax;
   a.gy = sw * (byy2 * ay + qxy * ax + qyz * az) + Qb2 * ay;
   a.gz = sw * (bzz2 * az + qxz * ax + qyz * ay) + Qb2 * az;
+  if (p.Co != T(0)) {                              // orientation term and its derivative in a
+    const T ta = p.thx * ax + p.thy * ay + p.thz * az;
+    f += p.Co * ta * ta;
+    const T t2 = T(2) * p.Co * ta;
+    a.gx += t2 * p.thx;
+    a.gy += t2 * p.thy;
+    a.gz += t2 * p.thz;
+  }
   return f;
 }
 

@@ -13,6 +13,7 @@ single instance), contiguous, float32 or float64, x fastest.
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -55,6 +56,7 @@ SIGNATURES = {
                                       ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, _DP]),
     "fe_hminus_reset": (ctypes.c_int, [_P]),
     "fe_diagnostics": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_double, _DP]),
+    "fe_set_orientation": (ctypes.c_int, [_P, _DP, _DP]),
     "fe_num_variants": (ctypes.c_int, []),
     "fe_variant_info": (ctypes.c_int, [ctypes.c_int, _IP, _IP, _IP, _IP]),
     "fe_set_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
@@ -180,6 +182,18 @@ class FeContext:
         self._sync_stream()
         _check(lib().fe_set_params(self._h, _dbl(eps_l), _dbl(coeff_l)))
         self.eps, self.coeffs = eps_l, [coeff_l[6 * b:6 * b + 6] for b in range(self.shape[0])]
+
+    def set_orientation(self, mu, theta):
+        """Orientation term eps mu (theta . grad u)^2 of Sec. 5.2, per instance (mu = 0: off)."""
+        B = self.shape[0]
+        mu_l = [float(mu)] * B if isinstance(mu, (int, float)) else [float(v) for v in mu]
+        th = np.asarray(theta, dtype=np.float64).reshape(-1, 3)
+        if th.shape[0] == 1:
+            th = np.repeat(th, B, axis=0)
+        if len(mu_l) != B or th.shape[0] != B:
+            raise ValueError(f"need {B} mu values and {B} theta vectors")
+        self._sync_stream()
+        _check(lib().fe_set_orientation(self._h, _dbl(mu_l), _dbl(th.reshape(-1).tolist())))
 
     def energy(self, u):
         """F_h(u_b) for every instance, as a float64 CPU tensor [B] (synchronises)."""
