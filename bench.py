@@ -187,6 +187,47 @@ def bench_hminus(n, iters, batch=1, dtype=torch.float32):
     return ms, G0, G1, iters + 24
 
 
+# The paper's spatialised example (Sec. 5.2): four parameter sets, interpolated
+# along x over six cells (the first and last repeated), with their masses; here
+# six 100^3 cells at dx = 0.01, eps = 0.02, sigma_k = 2, Adam lr 1e-3.
+SPATIAL_SETS = [(2, 2, 2, 0, 0, 0), (1, 2, 6, -40, -40, 400), (2, 2, 2, -75, -75, 937.5),
+                (2, 2, 11, -180, -90, 4050)]
+SPATIAL_MASSES = [-0.4, -0.6, -0.7, -0.7]
+
+
+def bench_spatial_flow(iters):
+    nz, ny, nx = 100, 100, 600
+    h = 0.01
+    a_np, m_np = inputs.interpolated_parameters((nz, ny, nx), SPATIAL_SETS, SPATIAL_MASSES)
+    ctx = fe.FeContext((1, nz, ny, nx), h, 0.02, SPATIAL_SETS[0], dtype=torch.float32)
+    ctx.set_coeff_field(torch.from_numpy(a_np[None]).float().cuda())
+    ctx.set_mass_field(torch.from_numpy(m_np[None]).float().cuda())
+    del a_np, m_np
+    rng = np.random.default_rng(2022)
+    A = torch.from_numpy(rng.normal(0.0, 0.4 * h, size=(1, 3, nz, ny, nx))).float().cuda()
+    ctx.hminus_step(A, None, 16, sigma_k=2.0)
+    iters = 8 * max(1, iters // 8)
+    return time_region(lambda: ctx.hminus_step(A, None, iters, sigma_k=2.0)) / iters
+
+
+def bench_field_sweep(n, reps):
+    """The energy+gradient sweep at n^3 with a coefficient field (random around the
+    Helfrich-type vector of the main workload)."""
+    h = 1.0 / n
+    u = torch.from_numpy(inputs.uniform_noise(n, 1005)).float().cuda()[None].contiguous()
+    ctx = fe.FeContext(u.shape, h, 1.5 * h, HELFRICH_SC, dtype=torch.float32)
+    rng = np.random.default_rng(77)
+    af = torch.tensor(HELFRICH_SC, dtype=torch.float32).reshape(1, 6, 1, 1, 1).cuda() * \
+        (1 + 0.1 * torch.from_numpy(rng.uniform(-1, 1, size=(1, 6, n, n, n))).float().cuda())
+    ctx.set_coeff_field(af)
+    del af
+    g = torch.empty_like(u)
+    E = torch.empty(1, dtype=torch.float64, device=u.device)
+    for _ in range(3):
+        ctx.energy_grad_async(u, g, E)
+    return time_region(lambda: ctx.energy_grad_async(u, g, E), reps=reps)
+
+
 def cpu_baseline(n=256, budget_s=10.0, max_evals=3):
     """The FP64 NumPy oracle on a bounded sample of the same workload: whole 256^3
     energy + gradient evaluations, repeated until about budget_s seconds (at most
@@ -269,6 +310,17 @@ def main():
             "shape_iterations_per_s": 16e3 / ms_h16, "ms_per_iteration": ms_h16,
             "seconds_for_8000_iterations_of_16_shapes": PAPER_HMINUS_ITERS * ms_h16 * 1e-3}
         log(f"  16 shapes at once: {ms_h16 * 1e3:.1f} us/iteration ({16e3 / ms_h16:.0f} shape-it/s)")
+
+    log("coefficient field a(x): 256^3 sweep and the spatialised 600x100x100 flow ...")
+    ms_field = bench_field_sweep(n, max(args.steps // 2, 10))
+    ms_sflow = bench_spatial_flow(max(args.steps // 4, 16))
+    extra["coefficient_field"] = {
+        "energy_grad_sweep_256_us": ms_field * 1e3, "voxels_per_s": vox / (ms_field * 1e-3),
+        "spatial_flow_600x100x100": {"ms_per_iteration": ms_sflow, "iterations_per_s": 1e3 / ms_sflow,
+                                     "config": "a(x), m(x) interpolated along x from the four parameter sets "
+                                               "of the paper's spatialised example, dx=0.01, eps=0.02, "
+                                               "sigma_k=2, Adam lr 1e-3, FP32"}}
+    log(f"  field sweep {ms_field * 1e3:.1f} us; spatialised flow {ms_sflow * 1e3:.1f} us/iteration")
 
     step_us = ms_step * 1e3
     bytes_step = BYTES_PER_VOXEL_STEP * vox

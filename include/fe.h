@@ -143,6 +143,30 @@ int fe_step_adam(fe_ctx* ctx, void* u, const double* mass, double lr, double bet
 int fe_adam_reset(fe_ctx* ctx);
 
 /*
+ * Space-dependent coefficients a(x) of Sec. 5.2. Every later energy, gradient,
+ * step, flow and diagnostics call evaluates the density at voxel i with the
+ * coefficients a(x_i) instead of the instance's p_coeffs (eps stays per
+ * instance).
+ *   a_field  device [batch][6][nz][ny][nx] in the context's precision, the six
+ *            coefficients in the order (a20, a11, a02, a10, a01, a00); the
+ *            library keeps its own scaled copy (six fields, allocated on first
+ *            use). NULL returns to the per-instance coefficients.
+ * fe_set_params drops an installed field (its scaling depends on eps); set it
+ * again afterwards. Synchronises the stream.
+ */
+int fe_set_coeff_field(fe_ctx* ctx, const void* a_field);
+
+/*
+ * Space-dependent mass m(x) of Sec. 5.2 for fe_hminus_step: u = div A + m(x)
+ * replaces u = div A + m0, and m0 may then be NULL (it is ignored).
+ *   m_field  device [batch][nz][ny][nx] in the context's precision (copied);
+ *            NULL returns to the per-instance m0.
+ * The mean of u is then the mean of m(x). The step entry points are not
+ * affected (their constraint is the mean).
+ */
+int fe_set_mass_field(fe_ctx* ctx, const void* m_field);
+
+/*
  * The orientation term of Sec. 5.2: every later energy, gradient, step, flow
  * and diagnostics call adds eps mu (theta . grad u)^2 to the density (with
  * grad u the central differences), i.e. h^3 eps mu sum_i (theta . g_i)^2 to F_h.
@@ -164,7 +188,8 @@ int fe_set_orientation(fe_ctx* ctx, const double* mu, const double* theta);
  *                                                  context; fe_hminus_reset clears them).
  * mean(u) = m0 holds exactly, since div A has zero mean and k sums to 1.
  *   A        device [batch][3][nz][ny][nx] (components x, y, z), updated in place.
- *   m0       host [batch]: the mass (target mean) of each instance.
+ *   m0       host [batch]: the mass (target mean) of each instance; ignored,
+ *            and may be NULL, while a mass field is set (fe_set_mass_field).
  *   sigma_k  blur standard deviation in voxels, 0 <= sigma_k <= 4 (0: no blur);
  *            taps exp(-j^2 / (2 sigma_k^2)), |j| <= ceil(4 sigma_k), normalised.
  *   lr, beta1, beta2, adam_eps  Adam settings (the paper: 1e-3, 0.9, 0.999).

@@ -62,15 +62,17 @@ struct Variant {
   int dtype_mask;   // bit 0: FE_F32, bit 1: FE_F64
   Kernels<float> k32;
   Kernels<double> k64;
+  Kernels<float> k32sp;    // with a coefficient field (only some variants have them)
+  Kernels<double> k64sp;
 };
 
-template <typename T, int TX, int TY, int NT>
+template <typename T, int TX, int TY, int NT, bool SP = false>
 Kernels<T> make_kernels() {
   Kernels<T> k;
-  k.grad = fe::grad_sweep<T, TX, TY, NT, fe::kGrad>;
-  k.step = fe::grad_sweep<T, TX, TY, NT, fe::kStepGD>;
-  k.adam = fe::grad_sweep<T, TX, TY, NT, fe::kStepAdam>;
-  k.energy = fe::energy_sweep<T, TX, TY, NT>;
+  k.grad = fe::grad_sweep<T, TX, TY, NT, fe::kGrad, SP>;
+  k.step = fe::grad_sweep<T, TX, TY, NT, fe::kStepGD, SP>;
+  k.adam = fe::grad_sweep<T, TX, TY, NT, fe::kStepAdam, SP>;
+  k.energy = fe::energy_sweep<T, TX, TY, NT, SP>;
   return k;
 }
 
@@ -80,41 +82,43 @@ Kernels<T> make_kernels() {
 const std::vector<Variant>& variants() {
   static const std::vector<Variant> v = [] {
     std::vector<Variant> r;
-    auto add32 = [&](int tx, int ty, int nt, Kernels<float> k) {
-      Variant x{tx, ty, nt, 1, k, {}};
+    auto add32 = [&](int tx, int ty, int nt, Kernels<float> k, Kernels<float> ksp = {}) {
+      Variant x{tx, ty, nt, 1, k, {}, ksp, {}};
       r.push_back(x);
     };
-    auto add64 = [&](int tx, int ty, int nt, Kernels<double> k) {
-      Variant x{tx, ty, nt, 2, {}, k};
+    auto add64 = [&](int tx, int ty, int nt, Kernels<double> k, Kernels<double> ksp = {}) {
+      Variant x{tx, ty, nt, 2, {}, k, {}, ksp};
       r.push_back(x);
     };
-    add32(64, 16, 512, make_kernels<float, 64, 16, 512>());
+    // the coefficient-field kernels exist for one large, one small and the
+    // smallest tile of each precision
+    add32(64, 16, 512, make_kernels<float, 64, 16, 512>(), make_kernels<float, 64, 16, 512, true>());
     add32(64, 32, 1024, make_kernels<float, 64, 32, 1024>());
     add32(32, 32, 512, make_kernels<float, 32, 32, 512>());
     add32(64, 32, 768, make_kernels<float, 64, 32, 768>());
     add32(64, 16, 1024, make_kernels<float, 64, 16, 1024>());
     add32(64, 8, 512, make_kernels<float, 64, 8, 512>());
     add32(32, 16, 512, make_kernels<float, 32, 16, 512>());
-    add32(32, 8, 256, make_kernels<float, 32, 8, 256>());
+    add32(32, 8, 256, make_kernels<float, 32, 8, 256>(), make_kernels<float, 32, 8, 256, true>());
     add32(16, 16, 256, make_kernels<float, 16, 16, 256>());
     add32(16, 8, 128, make_kernels<float, 16, 8, 128>());
-    add32(8, 8, 64, make_kernels<float, 8, 8, 64>());
-    add64(32, 16, 512, make_kernels<double, 32, 16, 512>());
+    add32(8, 8, 64, make_kernels<float, 8, 8, 64>(), make_kernels<float, 8, 8, 64, true>());
+    add64(32, 16, 512, make_kernels<double, 32, 16, 512>(), make_kernels<double, 32, 16, 512, true>());
     add64(32, 8, 256, make_kernels<double, 32, 8, 256>());
     add64(16, 16, 256, make_kernels<double, 16, 16, 256>());
-    add64(16, 8, 128, make_kernels<double, 16, 8, 128>());
-    add64(8, 8, 64, make_kernels<double, 8, 8, 64>());
+    add64(16, 8, 128, make_kernels<double, 16, 8, 128>(), make_kernels<double, 16, 8, 128, true>());
+    add64(8, 8, 64, make_kernels<double, 8, 8, 64>(), make_kernels<double, 8, 8, 64, true>());
     return r;
   }();
   return v;
 }
 
 template <typename T>
-const Kernels<T>& kernels_of(const Variant& v);
+const Kernels<T>& kernels_of(const Variant& v, bool sp = false);
 template <>
-const Kernels<float>& kernels_of<float>(const Variant& v) { return v.k32; }
+const Kernels<float>& kernels_of<float>(const Variant& v, bool sp) { return sp ? v.k32sp : v.k32; }
 template <>
-const Kernels<double>& kernels_of<double>(const Variant& v) { return v.k64; }
+const Kernels<double>& kernels_of<double>(const Variant& v, bool sp) { return sp ? v.k64sp : v.k64; }
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
@@ -138,9 +142,11 @@ struct GraphKey {
   int pairs;                    // step pairs (or flow iterations) per graph
   int variant;
   int lz;
+  int fields;                   // bit 0: coefficient field in use, bit 1: mass field in use
   bool operator<(const GraphKey& o) const {
-    return std::tie(u, mode, tau, beta1, beta2, adam_eps, sigma, pairs, variant, lz) <
-           std::tie(o.u, o.mode, o.tau, o.beta1, o.beta2, o.adam_eps, o.sigma, o.pairs, o.variant, o.lz);
+    return std::tie(u, mode, tau, beta1, beta2, adam_eps, sigma, pairs, variant, lz, fields) <
+           std::tie(o.u, o.mode, o.tau, o.beta1, o.beta2, o.adam_eps, o.sigma, o.pairs, o.variant, o.lz,
+                    o.fields);
   }
 };
 constexpr int kFlowMode = 100;
@@ -169,6 +175,10 @@ struct fe_ctx {
   fe::FlowClock* d_flow_clk = nullptr; // H^-1 flow: Adam step number and bias corrections (device)
   double* d_diag = nullptr;           // diagnostics: per-instance constants, stats, block partials
   size_t diag_bytes = 0;
+  void* d_cfield = nullptr;           // scaled coefficient field [batch][6][nz][ny][nx] (Sec. 5.2)
+  bool use_cfield = false;
+  void* d_mfield = nullptr;           // mass field m(x) [batch][nz][ny][nx] of the flow (Sec. 5.2)
+  bool use_mfield = false;
   size_t max_blocks = 0;              // per instance, over all variants and z chunks
   int variant = -1;
   int lz = 0;                         // 0 = automatic
@@ -310,6 +320,28 @@ Geometry geometry(const fe_ctx* c, int variant, int lz_req) {
   return g;
 }
 
+bool has_sp(int v, int dtype) {
+  const Variant& x = variants()[v];
+  return dtype == FE_F32 ? x.k32sp.grad != nullptr : x.k64sp.grad != nullptr;
+}
+
+// The variant a sweep launches: the chosen one, unless a coefficient field is
+// in use and that variant has no coefficient-field kernels; then the first
+// one that has them and whose tile the grid fills.
+int sweep_variant(const fe_ctx* c) {
+  if (!c->use_cfield || has_sp(c->variant, c->grid.dtype)) return c->variant;
+  int last = c->variant;
+  for (int v = 0; v < (int)variants().size(); ++v) {
+    if (!variant_ok(v, c->grid.dtype) || !has_sp(v, c->grid.dtype)) continue;
+    const Variant& x = variants()[v];
+    if (x.tx <= std::max(c->grid.nx, 8) && x.ty <= std::max(c->grid.ny, 8)) return v;
+    last = v;
+  }
+  return last;
+}
+
+int fields_in_use(const fe_ctx* c) { return (c->use_cfield ? 1 : 0) | (c->use_mfield ? 2 : 0); }
+
 int default_variant(const fe_grid& g) {
   const int dt = g.dtype;
   // variants are listed best-first for large grids: take the first whose tile
@@ -329,10 +361,11 @@ int default_variant(const fe_grid& g) {
 template <typename T>
 int launch_sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, const double* shift_in,
                  double* shift_out, double* energy_dev, const StepRule& rule) {
-  const Geometry geo = geometry(c, c->variant, c->lz);
+  const int vi = sweep_variant(c);
+  const Geometry geo = geometry(c, vi, c->lz);
   if ((size_t)geo.per_inst > c->max_blocks) return set_error(FE_EINVAL, "internal: partials workspace too small");
-  const Variant& v = variants()[c->variant];
-  const Kernels<T>& k = kernels_of<T>(v);
+  const Variant& v = variants()[vi];
+  const Kernels<T>& k = kernels_of<T>(v, c->use_cfield);
   fe::SweepArgs<T> a;
   a.src = static_cast<const T*>(src);
   a.dst = static_cast<T*>(dst);
@@ -348,6 +381,7 @@ int launch_sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst,
   a.m1 = static_cast<T*>(c->d_m1);
   a.m2 = static_cast<T*>(c->d_m2);
   a.adam_t = c->d_adam_t;
+  a.cfield = c->use_cfield ? static_cast<const T*>(c->d_cfield) : nullptr;
   a.tau = T(rule.tau);
   a.beta1 = T(rule.beta1);
   a.beta2 = T(rule.beta2);
@@ -457,11 +491,12 @@ int flow_field(fe_ctx* c, hipStream_t s, const void* A, T* out, double sigma_k, 
   const fe::BlurTaps<T> k = blur_taps<T>(sigma_k);
   const T inv2h = T(1.0 / (2.0 * c->grid.h));
   T* w0 = static_cast<T*>(c->d_w0);
+  const T* mf = c->use_mfield ? static_cast<const T*>(c->d_mfield) : nullptr;
   if (k.r == 0) {
-    hipLaunchKernelGGL((fe::blur_x<T, true>), x_grid(d), dim3(64, 4), 0, s, (const T*)A, out, c->d_mass, d,
+    hipLaunchKernelGGL((fe::blur_x<T, true>), x_grid(d), dim3(64, 4), 0, s, (const T*)A, out, c->d_mass, mf, d,
                        inv2h, k, clk, beta1, beta2);
   } else {
-    hipLaunchKernelGGL((fe::blur_x<T, true>), x_grid(d), dim3(64, 4), 0, s, (const T*)A, w0, c->d_mass, d,
+    hipLaunchKernelGGL((fe::blur_x<T, true>), x_grid(d), dim3(64, 4), 0, s, (const T*)A, w0, c->d_mass, mf, d,
                        inv2h, k, clk, beta1, beta2);
     blur_yz<T>(s, d, k, w0, static_cast<T*>(c->d_w1), out);
   }
@@ -486,8 +521,8 @@ int flow_iteration(fe_ctx* c, hipStream_t s, void* A, const FlowRule& fr) {
   // gu = k * gb: x pass into w0, y pass into w1, z pass into w0
   T* gu = w1;
   if (k.r > 0) {
-    hipLaunchKernelGGL((fe::blur_x<T, false>), x_grid(d), dim3(64, 4), 0, s, (const T*)w1, w0, nullptr, d, T(0),
-                       k, nullptr, 0.0, 0.0);
+    hipLaunchKernelGGL((fe::blur_x<T, false>), x_grid(d), dim3(64, 4), 0, s, (const T*)w1, w0, nullptr,
+                       (const T*)nullptr, d, T(0), k, nullptr, 0.0, 0.0);
     blur_yz<T>(s, d, k, w0, w1, w0);
     gu = w0;
   }
@@ -558,6 +593,7 @@ int diagnostics(fe_ctx* c, const void* u, void* curv, double* hist, int nbins, d
   fe::SweepArgs<T> a{};
   a.src = static_cast<const T*>(u);
   a.prm = static_cast<const fe::InstParams<T>*>(c->d_prm);
+  a.cfield = c->use_cfield ? static_cast<const T*>(c->d_cfield) : nullptr;
   a.k = grid_consts<T>(h);
   a.nx = c->grid.nx;
   a.ny = c->grid.ny;
@@ -622,7 +658,8 @@ int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int 
     if (rc) return rc;
   }
   if (gpairs > 0) {
-    GraphKey key{u, rule.mode, rule.tau, rule.beta1, rule.beta2, rule.adam_eps, 0.0, gpairs, c->variant, c->lz};
+    GraphKey key{u,      rule.mode,           rule.tau, rule.beta1,     rule.beta2, rule.adam_eps, 0.0,
+                 gpairs, sweep_variant(c), c->lz,    fields_in_use(c)};
     auto it = c->graphs.find(key);
     hipGraphExec_t exec = nullptr;
     if (it == c->graphs.end()) {
@@ -743,6 +780,7 @@ int fe_set_params(fe_ctx* c, const double* eps, const double* p_coeffs) {
   DeviceGuard dg(c->device);
   c->eps.assign(eps, eps + c->grid.batch);
   c->coeffs.assign(p_coeffs, p_coeffs + 6 * c->grid.batch);
+  c->use_cfield = false;   // its scaling depends on eps: the caller sets it again
   return upload_params(c);
 }
 
@@ -759,6 +797,72 @@ int fe_set_orientation(fe_ctx* c, const double* mu, const double* theta) {
   c->mu.assign(mu, mu + c->grid.batch);
   c->theta.assign(theta, theta + 3 * c->grid.batch);
   return upload_params(c);
+}
+
+int fe_set_coeff_field(fe_ctx* c, const void* a_field) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!a_field) {
+    c->use_cfield = false;
+    return FE_OK;
+  }
+  DeviceGuard dg(c->device);
+  const size_t n = field_elems(c->grid);
+  if (!c->d_cfield && hipMalloc(&c->d_cfield, 6 * n * elem_size(c->grid)) != hipSuccess) {
+    c->d_cfield = nullptr;
+    return set_error(FE_ENOMEM, "coefficient field allocation failed");
+  }
+  const double h = c->grid.h, h3 = h * h * h;
+  const int B = c->grid.batch;
+  std::vector<double> k(3 * B);
+  for (int b = 0; b < B; ++b) {
+    const double e = c->eps[b], sc = e / (h * h);
+    k[3 * b] = h3 * sc * sc / (2.0 * e);
+    k[3 * b + 1] = h3 * sc / (4.0 * h);
+    k[3 * b + 2] = h3 * e / (4.0 * h * h);
+  }
+  double* d_k = nullptr;
+  if (hipMalloc((void**)&d_k, sizeof(double) * k.size()) != hipSuccess)
+    return set_error(FE_ENOMEM, "coefficient factor allocation failed");
+  hipError_t e1 = hipMemcpyAsync(d_k, k.data(), sizeof(double) * k.size(), hipMemcpyHostToDevice, c->stream);
+  const size_t vol = n / B;
+  const int nblk = (int)std::min<size_t>((n + 255) / 256, 65536);
+  if (e1 == hipSuccess) {
+    if (c->grid.dtype == FE_F32)
+      hipLaunchKernelGGL(fe::scale_coeff_field<float>, dim3(nblk), dim3(256), 0, c->stream,
+                         static_cast<const float*>(a_field), static_cast<float*>(c->d_cfield), vol, B,
+                         (const double*)d_k);
+    else
+      hipLaunchKernelGGL(fe::scale_coeff_field<double>, dim3(nblk), dim3(256), 0, c->stream,
+                         static_cast<const double*>(a_field), static_cast<double*>(c->d_cfield), vol, B,
+                         (const double*)d_k);
+    e1 = hipGetLastError();
+  }
+  // the factors (and the host vector) must outlive the conversion
+  const hipError_t e2 = hipStreamSynchronize(c->stream);
+  (void)hipFree(d_k);
+  if (e1 != hipSuccess) return set_error(FE_EHIP, "coefficient field conversion failed: %s", hipGetErrorString(e1));
+  if (e2 != hipSuccess) return set_error(FE_EHIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e2));
+  c->use_cfield = true;
+  return FE_OK;
+}
+
+int fe_set_mass_field(fe_ctx* c, const void* m_field) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!m_field) {
+    c->use_mfield = false;
+    return FE_OK;
+  }
+  DeviceGuard dg(c->device);
+  const size_t bytes = field_elems(c->grid) * elem_size(c->grid);
+  if (!c->d_mfield && hipMalloc(&c->d_mfield, bytes) != hipSuccess) {
+    c->d_mfield = nullptr;
+    return set_error(FE_ENOMEM, "mass field allocation failed");
+  }
+  FE_HIP(hipMemcpyAsync(c->d_mfield, m_field, bytes, hipMemcpyDeviceToDevice, c->stream));
+  c->use_mfield = true;
+  return FE_OK;
 }
 
 int fe_set_stream(fe_ctx* c, void* stream) {
@@ -842,7 +946,7 @@ int fe_hminus_step(fe_ctx* c, void* A, const double* m0, double sigma_k, double 
   g_last_error.clear();
   if (!c) return set_error(FE_EINVAL, "ctx is NULL");
   if (!A) return set_error(FE_EINVAL, "A is NULL");
-  if (!m0) return set_error(FE_EINVAL, "m0 is NULL");
+  if (!m0 && !c->use_mfield) return set_error(FE_EINVAL, "m0 is NULL and no mass field is set");
   if (nsteps < 0) return set_error(FE_EINVAL, "nsteps must be >= 0");
   if (!(sigma_k >= 0.0) || std::ceil(4.0 * sigma_k) > fe::kBlurMaxR)
     return set_error(FE_EINVAL, "sigma_k must lie in [0, %g]", fe::kBlurMaxR / 4.0);
@@ -854,7 +958,7 @@ int fe_hminus_step(fe_ctx* c, void* A, const double* m0, double sigma_k, double 
     return set_error(FE_EINVAL, "nz * batch and ny * batch must be <= 65535 for the flow kernels");
   if (u_out == A) return set_error(FE_EINVAL, "u_out must not alias A");
   for (int b = 0; b < c->grid.batch; ++b)
-    if (!std::isfinite(m0[b])) return set_error(FE_EINVAL, "m0[%d] is not finite", b);
+    if (m0 && !std::isfinite(m0[b])) return set_error(FE_EINVAL, "m0[%d] is not finite", b);
   DeviceGuard dg(c->device);
   const size_t bytes = field_elems(c->grid) * elem_size(c->grid);
   if (!c->d_w0) {
@@ -870,7 +974,7 @@ int fe_hminus_step(fe_ctx* c, void* A, const double* m0, double sigma_k, double 
     int rc = flow_reset_launch(c);
     if (rc) return rc;
   }
-  FE_HIP(hipMemcpyAsync(c->d_mass, m0, sizeof(double) * c->grid.batch, hipMemcpyHostToDevice, c->stream));
+  if (m0) FE_HIP(hipMemcpyAsync(c->d_mass, m0, sizeof(double) * c->grid.batch, hipMemcpyHostToDevice, c->stream));
   const FlowRule fr{sigma_k, lr, beta1, beta2, adam_eps};
   constexpr int kGraphIters = 8;
   const int gi = nsteps >= kGraphIters ? kGraphIters : 0;
@@ -879,7 +983,7 @@ int fe_hminus_step(fe_ctx* c, void* A, const double* m0, double sigma_k, double 
     if (rc) return rc;
   }
   if (gi > 0) {
-    GraphKey key{A, kFlowMode, lr, beta1, beta2, adam_eps, sigma_k, gi, c->variant, c->lz};
+    GraphKey key{A, kFlowMode, lr, beta1, beta2, adam_eps, sigma_k, gi, sweep_variant(c), c->lz, fields_in_use(c)};
     auto it = c->graphs.find(key);
     hipGraphExec_t exec = nullptr;
     if (it == c->graphs.end()) {
@@ -1033,7 +1137,8 @@ void fe_destroy(fe_ctx* c) {
   if (c->d_m1) (void)hipFree(c->d_m1);
   if (c->d_m2) (void)hipFree(c->d_m2);
   if (c->d_adam_t) (void)hipFree(c->d_adam_t);
-  for (void* p : {c->d_w0, c->d_w1, c->d_am1, c->d_am2, (void*)c->d_flow_clk, (void*)c->d_diag})
+  for (void* p : {c->d_w0, c->d_w1, c->d_am1, c->d_am2, (void*)c->d_flow_clk, (void*)c->d_diag, c->d_cfield,
+                  c->d_mfield})
     if (p) (void)hipFree(p);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;

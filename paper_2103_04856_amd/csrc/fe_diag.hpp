@@ -2,7 +2,8 @@
 //   - the diffuse mean and Gaussian curvatures and the diffuse principal
 //     curvatures of eqs. (Heps), (Keps), (kepsa), (kepsb) (Sec. 3.1), with
 //     |grad u| regularised as rho = sqrt(|g|^2 + xi^2) as in the energy;
-//   - the energy F_h, the Cahn-Hilliard area A_eps of eq. (CH_eps) and the
+//   - the energy F_h (with the coefficient field when one is set), the
+//     Cahn-Hilliard area A_eps of eq. (CH_eps) and the
 //     normalised discrepancy of Sec. 4.5, with min u and max u (the paper's
 //     viability test);
 //   - a histogram of (kappa1, kappa2) weighted by h^3 eps |grad u|^2, the
@@ -111,7 +112,9 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
       const T* pp = su[sp] + c;
       const Forward<T> fw = forward_chain(load_stencil<T, UX>(pc, pm, pp),
                                           [&]() { return load_stencil<T, UX>(pc, pm, pp); }, prm, a.k);
-      acc_f += double(density_of(fw, prm));
+      const size_t gi = (size_t)p * plane + (size_t)(y0 + iy) * a.nx + (x0 + ix);
+      acc_f += double(density_of(
+          fw, a.cfield ? with_coeffs(prm, load_coeffs(a.cfield + (size_t)bt.inst * 6 * vol, vol, gi)) : prm));
       const T grad_part = T(di.ca) * fw.Q;
       const T w2 = T(1) - fw.c * fw.c;
       const T well_part = T(di.cb) * w2 * w2;
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
         const T sq = fw.X > T(0) ? sqrt_t(fw.X) : T(0);
         const T k1 = (fw.tr + sq) * rs, k2 = (fw.tr - sq) * rs;
         if (d.curv) {
-          const size_t o = (size_t)bt.inst * 4 * vol + (size_t)p * plane + (size_t)(y0 + iy) * a.nx + (x0 + ix);
+          const size_t o = (size_t)bt.inst * 4 * vol + gi;
           d.curv[o] = T(2) * fw.tr * rs;
           d.curv[o + vol] = T(2) * (fw.tr * fw.tr - fw.n2) * (d.inv_h2 * rcp_t(fw.R));
           d.curv[o + 2 * vol] = k1;

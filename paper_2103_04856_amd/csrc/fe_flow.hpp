@@ -63,16 +63,17 @@ __device__ __forceinline__ T taps_dot(const BlurTaps<T>& k, const T* v, int step
 // (block (64, 4), each thread on kBlurRows / 4 rows; grid (ceil(nx/64),
 // ceil(ny/kBlurRows), nz * batch)); each row's segment and its periodic halo
 // of r go through LDS. With DIV the loaded value is div A + m0 (the field of
-// Algorithm 1) and block (0,0,0) advances the clock (when given); without, it
-// is in[]. r = 0 is a plain copy (or div). All loads of a thread are issued
+// Algorithm 1; m(x) from mfield instead of the instance's m0 when given, the
+// space-dependent mass of Sec. 5.2) and block (0,0,0) advances the clock (when
+// given); without, it is in[]. r = 0 is a plain copy (or div). All loads of a thread are issued
 // before the first LDS write, so a block keeps many in flight.
 constexpr int kBlurRows = 16;
 
 template <typename T, bool DIV>
 __global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __restrict__ out,
-                                              const double* __restrict__ m0, FieldDims d, T inv2h,
-                                              BlurTaps<T> k, FlowClock* __restrict__ clk, double beta1,
-                                              double beta2) {
+                                              const double* __restrict__ m0, const T* __restrict__ mfield,
+                                              FieldDims d, T inv2h, BlurTaps<T> k, FlowClock* __restrict__ clk,
+                                              double beta1, double beta2) {
   constexpr int kW = 64 + 2 * kBlurMaxR;
   constexpr int kPer = (kW + 63) / 64;          // segment elements per thread and row
   constexpr int kR = kBlurRows / 4;             // rows per thread
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __res
   const size_t plane = (size_t)d.nx * d.ny, vol = plane * d.nz;
   const T* base = in + (size_t)b * (DIV ? 3 : 1) * vol;
   const int nseg = 64 + 2 * k.r;
-  T v[kR][kPer][6];          // the non-DIV form uses [0] only
+  T v[kR][kPer][7];          // the non-DIV form uses [0] only; [6] holds m(x)
 #pragma unroll
   for (int i = 0; i < kR; ++i) {
     const int y = blockIdx.y * kBlurRows + threadIdx.y + 4 * i;
@@ -109,12 +110,13 @@ __global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __res
         v[i][j][3] = Ay[(size_t)z * plane + (size_t)wrap_down(y - 1, d.ny) * d.nx + x];
         v[i][j][4] = Az[(size_t)wrap_up(z + 1, d.nz) * plane + (size_t)y * d.nx + x];
         v[i][j][5] = Az[(size_t)wrap_down(z - 1, d.nz) * plane + (size_t)y * d.nx + x];
+        if (mfield) v[i][j][6] = mfield[(size_t)b * vol + row + x];
       } else {
         v[i][j][0] = base[row + x];
       }
     }
   }
-  const T mass = DIV ? T(m0[b]) : T(0);
+  const T mass = (DIV && !mfield) ? T(m0[b]) : T(0);
 #pragma unroll
   for (int i = 0; i < kR; ++i) {
     const int y = blockIdx.y * kBlurRows + threadIdx.y + 4 * i;
@@ -125,7 +127,8 @@ __global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __res
       if (e >= nseg) continue;
       if (DIV)
         s[threadIdx.y + 4 * i][e] =
-            mass + ((v[i][j][0] - v[i][j][1]) + (v[i][j][2] - v[i][j][3]) + (v[i][j][4] - v[i][j][5])) * inv2h;
+            (mfield ? v[i][j][6] : mass) +
+            ((v[i][j][0] - v[i][j][1]) + (v[i][j][2] - v[i][j][3]) + (v[i][j][4] - v[i][j][5])) * inv2h;
       else
         s[threadIdx.y + 4 * i][e] = v[i][j][0];
     }

@@ -94,6 +94,8 @@ struct SweepArgs {
   T* m1;                        // Adam: first moment, same layout as src
   T* m2;                        // Adam: second moment
   const int* adam_t;            // Adam: step number t >= 1 (device, advanced by the finalisation)
+  const T* cfield;              // space-dependent coefficients: [batch][6][nz][ny][nx] scaled C1..C6,
+                                // read by the SP instantiations only
   GridConsts<T> k;
   T tau;                        // GD step size, or Adam learning rate
   T beta1, beta2, adam_eps;     // Adam
@@ -101,6 +103,32 @@ struct SweepArgs {
   int ntx, nty, nzc, lz;        // tiles in x and y, z chunks, planes per chunk
   int batch;
 };
+
+// The six scaled coefficients of one voxel from the coefficient field (Sec. 5.2:
+// a(x) acts at the voxel where the density is evaluated).
+template <typename T>
+struct VoxelCoeffs {
+  T c[6];
+};
+
+template <typename T>
+__device__ __forceinline__ VoxelCoeffs<T> load_coeffs(const T* __restrict__ cf, size_t vol, size_t i) {
+  VoxelCoeffs<T> r;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) r.c[k] = cf[k * vol + i];
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ InstParams<T> with_coeffs(InstParams<T> p, const VoxelCoeffs<T>& v) {
+  p.C1 = v.c[0];
+  p.C2 = v.c[1];
+  p.C3 = v.c[2];
+  p.C4 = v.c[3];
+  p.C5 = v.c[4];
+  p.C6 = v.c[5];
+  return p;
+}
 
 // End of a sweep block: reduce the block's sums into its partial; the last block
 // of an instance to finish adds that instance's partials in a fixed order and
@@ -191,7 +219,11 @@ __device__ __forceinline__ BlockTile block_tile(const SweepArgs<T>& a) {
 // seven values the neighbours read go through LDS; the one-voxel border of
 // the ring is shared out afterwards. Four u slots keep plane p-1 readable by
 // the gather while the next plane is staged, so two barriers per plane suffice.
-template <typename T, int TX, int TY, int NT, int MODE>
+//
+// SP: the coefficients C1..C6 come per voxel from a.cfield (loaded for every
+// ring voxel of a plane right after the plane is staged, so their latency
+// overlaps the barrier) instead of from the instance's parameters.
+template <typename T, int TX, int TY, int NT, int MODE, bool SP = false>
 __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   constexpr int UX = TX + 4, UY = TY + 4;      // u window: interior + halo 2
   constexpr int RX = TX + 2, RY = TY + 2;      // adjoint ring: interior + 1
@@ -253,6 +285,21 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
     const int k = b - 2 * RX;
     return (1 + (k >> 1)) * RX + ((k & 1) ? RX - 1 : 0);
   };
+  // SP: in-plane offsets of this thread's ring voxels and their coefficients
+  const size_t vol = plane * a.nz;
+  const T* cfb = SP ? a.cfield + (size_t)bt.inst * 6 * vol : nullptr;
+  int coff[SP ? NW : 1];
+  VoxelCoeffs<T> cv[SP ? NW : 1];
+  if (SP) {
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const int item = tid + j * NT;
+      int v = 0;
+      if (item < NI) v = (item / TX + 1) * RX + item % TX + 1;
+      else if (item < NI + NB) v = border_pos(item - NI);
+      coff[j] = wrap_index(y0 - 1 + v / RX, a.ny) * a.nx + wrap_index(x0 - 1 + v % RX, a.nx);
+    }
+  }
 
   double acc_f = 0.0, acc_m = 0.0;
   T c_prev[NO], l_prev[NO], l_pp[NO];
@@ -294,17 +341,23 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
         }
       }
     }
+    if (SP) {
+      const size_t zoff = (size_t)wrap_index(p, a.nz) * plane;
+#pragma unroll
+      for (int j = 0; j < NW; ++j)
+        if (tid + j * NT < NI + NB) cv[j] = load_coeffs(cfb, vol, zoff + coff[j]);
+    }
     __syncthreads();
 
     // ---- forward + adjoint on the ring-extended plane p ----
     const bool out_plane = (p >= k0) && (p < kend);
-    auto eval = [&](int v, VoxelAdjoint<T>& ad) {
+    auto eval = [&](int v, VoxelAdjoint<T>& ad, const InstParams<T>& pv) {
       const int c = (v / RX + 1) * UX + v % RX + 1;
       const T* pc = su[sc] + c;
       const T* pm = su[sm] + c;
       const T* pp = su[sp] + c;
       const T f = voxel_density_adjoint(load_stencil<T, UX>(pc, pm, pp),
-                                        [&]() { return load_stencil<T, UX>(pc, pm, pp); }, prm, a.k, ad);
+                                        [&]() { return load_stencil<T, UX>(pc, pm, pp); }, pv, a.k, ad);
       sx[GX][v] = ad.gx; sx[GY][v] = ad.gy;
       sx[BXX][v] = ad.nbxx; sx[BYY][v] = ad.nbyy;
       sx[BXY][v] = ad.nbxy; sx[BXZ][v] = ad.nbxz; sx[BYZ][v] = ad.nbyz;
@@ -322,7 +375,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
         const int ix = item % TX, iy = item / TX;
         const int v = inner ? (iy + 1) * RX + ix + 1 : border_pos(item - NI);
         VoxelAdjoint<T> ad;
-        const T f = eval(v, ad);
+        const T f = eval(v, ad, SP ? with_coeffs(prm, cv[j]) : prm);
         if (j < NO && inner) {
           own_ub[j] = ad.ub;
           own_gz[j] = ad.gz;
@@ -385,8 +438,9 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   finish_block<NT, MODE>(a, bt.inst, bt.logical, bt.per_inst, acc_f, acc_m, sred);
 }
 
-// Forward only: per-block sums of the energy density and of u.
-template <typename T, int TX, int TY, int NT>
+// Forward only: per-block sums of the energy density and of u. SP: per-voxel
+// coefficients from a.cfield.
+template <typename T, int TX, int TY, int NT, bool SP = false>
 __global__ __launch_bounds__(NT) void energy_sweep(SweepArgs<T> a) {
   constexpr int UX = TX + 2, UY = TY + 2;      // halo 1 suffices for the forward stencil
   constexpr int NU = (UX * UY + NT - 1) / NT;
@@ -418,6 +472,10 @@ __global__ __launch_bounds__(NT) void energy_sweep(SweepArgs<T> a) {
     }
   };
 
+  const size_t vol = plane * a.nz;
+  const T* cfb = SP ? a.cfield + (size_t)bt.inst * 6 * vol : nullptr;
+  VoxelCoeffs<T> cv[SP ? NO : 1];
+
   double acc_f = 0.0, acc_m = 0.0;
   load_plane(k0 - 1, 0);
   load_plane(k0, 1);
@@ -425,6 +483,17 @@ __global__ __launch_bounds__(NT) void energy_sweep(SweepArgs<T> a) {
     const int p = k0 + it;
     const int sm = it % 3, sc = (it + 1) % 3, sp = (it + 2) % 3;
     load_plane(p + 1, sp);
+    if (SP) {
+#pragma unroll
+      for (int j = 0; j < NO; ++j) {
+        const int w = tid + j * NT;
+        const int gx = x0 + w % TX, gy = y0 + w / TX;
+        if (w < TX * TY && gx < a.nx && gy < a.ny)
+          cv[j] = load_coeffs(cfb, vol, (size_t)p * plane + (size_t)gy * a.nx + gx);
+        else
+          cv[j] = VoxelCoeffs<T>{};
+      }
+    }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
@@ -436,7 +505,8 @@ __global__ __launch_bounds__(NT) void energy_sweep(SweepArgs<T> a) {
       const T* pm = su[sm] + c;
       const T* pp = su[sp] + c;
       const T f = voxel_density(load_stencil<T, UX>(pc, pm, pp),
-                                [&]() { return load_stencil<T, UX>(pc, pm, pp); }, prm, a.k);
+                                [&]() { return load_stencil<T, UX>(pc, pm, pp); },
+                                SP ? with_coeffs(prm, cv[j]) : prm, a.k);
       if (x0 + ix < a.nx && y0 + iy < a.ny) {
         acc_f += double(f);
         acc_m += double(pc[0]);
@@ -456,6 +526,32 @@ __global__ __launch_bounds__(256) void add_shift(const T* src, T* dst, const dou
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const int b = (int)(i / per_inst);
     dst[i] = src[i] + T(shift[b]);
+  }
+}
+
+// Scaled coefficient field from a(x) = (a20, a11, a02, a10, a01, a00)(x)
+// ([batch][6][vol] in, [batch][6][vol] out), the per-voxel form of the
+// per-instance C1..C6 (see fe_voxel.hpp): with kq = h^3 s^2 / (2 eps),
+// kl = h^3 s / (4h), k0 = h^3 eps / (4h^2) of instance b (k[3b..3b+2]),
+// C1 = kq (a20 + a02 - a11), C2 = kq a11, C3 = kq (a20 - a02),
+// C4 = kl (a10 + a01), C5 = kl (a10 - a01), C6 = k0 a00.
+template <typename T>
+__global__ __launch_bounds__(256) void scale_coeff_field(const T* __restrict__ a, T* __restrict__ c, size_t vol,
+                                                         int batch, const double* __restrict__ k) {
+  const size_t n = vol * (size_t)batch;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t b = i / vol, j = i - b * vol;
+    const T* ab = a + b * 6 * vol + j;
+    T* cb = c + b * 6 * vol + j;
+    const double a20 = ab[0], a11 = ab[vol], a02 = ab[2 * vol], a10 = ab[3 * vol], a01 = ab[4 * vol],
+                 a00 = ab[5 * vol];
+    const double kq = k[3 * b], kl = k[3 * b + 1], k0 = k[3 * b + 2];
+    cb[0] = T(kq * (a20 + a02 - a11));
+    cb[vol] = T(kq * a11);
+    cb[2 * vol] = T(kq * (a20 - a02));
+    cb[3 * vol] = T(kl * (a10 + a01));
+    cb[4 * vol] = T(kl * (a10 - a01));
+    cb[5 * vol] = T(k0 * a00);
   }
 }
 

@@ -57,6 +57,8 @@ SIGNATURES = {
     "fe_hminus_reset": (ctypes.c_int, [_P]),
     "fe_diagnostics": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_double, _DP]),
     "fe_set_orientation": (ctypes.c_int, [_P, _DP, _DP]),
+    "fe_set_coeff_field": (ctypes.c_int, [_P, _P]),
+    "fe_set_mass_field": (ctypes.c_int, [_P, _P]),
     "fe_num_variants": (ctypes.c_int, []),
     "fe_variant_info": (ctypes.c_int, [ctypes.c_int, _IP, _IP, _IP, _IP]),
     "fe_set_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
@@ -139,7 +141,7 @@ class FeContext:
         if isinstance(eps, (int, float)):
             eps = [float(eps)] * B
         eps = [float(e) for e in eps]
-        flat = [float(c) for c in torch.as_tensor(coeffs, dtype=torch.float64).reshape(-1).tolist()]
+        flat = [float(c) for c in np.asarray(coeffs, dtype=np.float64).reshape(-1)]
         if len(flat) == 6:
             flat = flat * B
         if len(eps) != B or len(flat) != 6 * B:
@@ -182,6 +184,27 @@ class FeContext:
         self._sync_stream()
         _check(lib().fe_set_params(self._h, _dbl(eps_l), _dbl(coeff_l)))
         self.eps, self.coeffs = eps_l, [coeff_l[6 * b:6 * b + 6] for b in range(self.shape[0])]
+
+    def set_coeff_field(self, a_field):
+        """Space-dependent coefficients a(x) [B, 6, nz, ny, nx] (Sec. 5.2), or None for the
+        per-instance ones. The library keeps a scaled copy."""
+        if a_field is None:
+            _check(lib().fe_set_coeff_field(self._h, _P(0)))
+            return
+        exp = (self.shape[0], 6) + self.shape[1:]
+        if not isinstance(a_field, torch.Tensor) or a_field.device.type != "cuda" or a_field.dtype != self.dtype \
+                or tuple(a_field.shape) != exp or not a_field.is_contiguous():
+            raise ValueError(f"a_field must be a contiguous {self.dtype} device tensor of shape {exp}")
+        self._sync_stream()
+        _check(lib().fe_set_coeff_field(self._h, _P(a_field.data_ptr())))
+
+    def set_mass_field(self, m_field):
+        """Space-dependent mass m(x) [B, nz, ny, nx] for hminus_step (Sec. 5.2), or None."""
+        if m_field is None:
+            _check(lib().fe_set_mass_field(self._h, _P(0)))
+            return
+        self._sync_stream()
+        _check(lib().fe_set_mass_field(self._h, self._field(m_field, "m_field")))
 
     def set_orientation(self, mu, theta):
         """Orientation term eps mu (theta . grad u)^2 of Sec. 5.2, per instance (mu = 0: off)."""
@@ -258,7 +281,7 @@ class FeContext:
         B = self.shape[0]
         if isinstance(m0, (int, float)):
             m0 = [float(m0)] * B
-        if len(m0) != B:
+        if m0 is not None and len(m0) != B:
             raise ValueError(f"need {B} m0 values")
         exp = (B, 3) + self.shape[1:]
         if not isinstance(A, torch.Tensor) or A.device.type != "cuda" or A.dtype != self.dtype \
@@ -266,7 +289,8 @@ class FeContext:
             raise ValueError(f"A must be a contiguous {self.dtype} device tensor of shape {exp}")
         out = (ctypes.c_double * B)()
         self._sync_stream()
-        _check(lib().fe_hminus_step(self._h, _P(A.data_ptr()), _dbl(m0), float(sigma_k), float(lr),
+        _check(lib().fe_hminus_step(self._h, _P(A.data_ptr()), _dbl(m0) if m0 is not None else None,
+                                    float(sigma_k), float(lr),
                                     float(betas[0]), float(betas[1]), float(adam_eps), int(nsteps),
                                     self._field(u_out, "u_out") if u_out is not None else _P(0), out))
         return torch.tensor(list(out), dtype=torch.float64)

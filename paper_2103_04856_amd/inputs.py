@@ -91,3 +91,32 @@ def white_noise_vector_field(n, seed, std, batch=None):
     rng = np.random.default_rng(seed)
     shape = (3, n, n, n) if batch is None else (batch, 3, n, n, n)
     return rng.normal(0.0, std, size=shape)
+
+
+def interpolated_parameters(shape, params, masses, repeat_ends=True):
+    """Space-dependent generation parameters varying along x only, for a grid of
+    `shape` = (nz, ny, nx): the x-axis is cut into equal cells whose mid-planes
+    carry the given parameter sets, and the values in between are linear
+    interpolations between neighbouring mid-planes, periodic across the
+    boundary. With repeat_ends the first and last sets are each used twice
+    (p1, p1, p2, ..., pk, pk), the layout of the paper's spatialised example.
+
+    params: k coefficient vectors (a20, a11, a02, a10, a01, a00); masses: k values.
+    Returns (a_field [6, nz, ny, nx], m_field [nz, ny, nx]) in float64.
+    """
+    nz, ny, nx = shape
+    P = np.asarray(params, dtype=np.float64)
+    M = np.asarray(masses, dtype=np.float64)
+    if repeat_ends:
+        P = np.concatenate([P[:1], P, P[-1:]])
+        M = np.concatenate([M[:1], M, M[-1:]])
+    k = len(P)
+    xc = (np.arange(nx) + 0.5) / nx * k - 0.5        # position in cell units from the first mid-plane
+    i0 = np.floor(xc).astype(np.int64)
+    t = xc - i0
+    lo, hi = i0 % k, (i0 + 1) % k
+    a_x = P[lo] * (1 - t)[:, None] + P[hi] * t[:, None]      # [nx, 6]
+    m_x = M[lo] * (1 - t) + M[hi] * t
+    a_field = np.broadcast_to(a_x.T[:, None, None, :], (6, nz, ny, nx)).copy()
+    m_field = np.broadcast_to(m_x[None, None, :], (nz, ny, nx)).copy()
+    return a_field, m_field
