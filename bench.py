@@ -54,25 +54,31 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def csrc_hash():
+# The sources that define the sweep kernels (their per-voxel arithmetic, tiling
+# and memory access); the counter record holds only while these are unchanged.
+KERNEL_SOURCES = ("fe_voxel.hpp", "fe_kernels.hpp")
+
+
+def kernel_hash():
     import hashlib
     d = os.path.join(ROOT, "paper_2103_04856_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, z_chunk):
     """HBM bytes per launch from the committed counter runs, if they were taken on
-    the kernel sources of this build (else None)."""
+    this kernel, launch shape and kernel sources (else None)."""
     try:
         with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("csrc_sha256_prefix") != csrc_hash() or t.get("kernel") != kernel:
+    if t.get("kernel_sources_sha256_prefix") != kernel_hash() or t.get("kernel") != kernel \
+            or t.get("z_chunk") != z_chunk:
         return None
     return t.get("traffic_bytes")
 
@@ -328,7 +334,7 @@ def main():
     tflops = FLOPS_PER_VOXEL * vox / (step_us * 1e-6) / 1e12
     vinfo = fe.variants()[variant]
     kname = f"grad_sweep<float,{vinfo[0]},{vinfo[1]},{vinfo[2]},1>"
-    traffic = measured_traffic(kname)
+    traffic = measured_traffic(kname, zc)
     alu = {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
            "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic}
     hbm = {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
