@@ -15,6 +15,8 @@ Modules:
   closed_forms  continuum values on tanh-profile spheres, cylinders and planes by
                 co-area quadrature (Sec. 3.2)
   params        coefficient vectors: eq. (redundant), Helfrich, inside-out swap
+  l2flow        Algorithm 2: replicate boundaries, the blur with replicate padding,
+                and L-BFGS (Sec. 4.2)
 """
 
 from .fe_oracle import (XI, double_well, double_well_prime, fd_gradient, fd_hessian,
@@ -22,11 +24,12 @@ from .fe_oracle import (XI, double_well, double_well_prime, fd_gradient, fd_hess
                         energy, energy_abs, adjoint_fields, energy_grad, mass_projected_step,
                         descend, adam_projected_step, descend_adam, energy_grad_batch,
                         fd_divergence, gaussian_weights, gaussian_blur, hminus_energy,
-                        hminus_energy_grad, hminus_adam_step, hminus_descend)
+                        hminus_energy_grad, hminus_adam_step, hminus_descend,
+                        transpose_stencils)
 
 __all__ = ["XI", "double_well", "double_well_prime", "fd_gradient", "fd_hessian",
            "fd_laplacian", "feps_coefficients", "softplus", "logistic", "pointwise", "energy",
            "energy_abs", "adjoint_fields", "energy_grad", "mass_projected_step", "descend",
            "adam_projected_step", "descend_adam", "energy_grad_batch", "fd_divergence",
            "gaussian_weights", "gaussian_blur", "hminus_energy", "hminus_energy_grad",
-           "hminus_adam_step", "hminus_descend"]
+           "hminus_adam_step", "hminus_descend", "transpose_stencils"]

@@ -273,6 +273,14 @@ def energy_grad(u, h, eps, a, xi=XI, mode="smooth", orient=None):
     the second and mixed differences are self-adjoint.
     """
     ubar, gamma, theta, fw = adjoint_fields(u, h, eps, a, xi, mode, orient)
+    E = float(h ** 3 * np.sum(fw["f"]))
+    return E, h ** 3 * transpose_stencils(ubar, gamma, theta, h)
+
+
+def transpose_stencils(ubar, gamma, theta, h):
+    """sum over the stencils' transposes of the per-voxel adjoints: the derivative of
+    sum_i f_i with respect to every sample, given df_i/du_i (ubar), df_i/dg_a (gamma)
+    and df_i/dH_k (theta) at every voxel i of a periodic grid."""
     grad = ubar.copy()
     for a_ in range(3):
         # transpose of the central difference
@@ -284,8 +292,7 @@ def energy_grad(u, h, eps, a, xi=XI, mode="smooth", orient=None):
         th = theta[3 + k]
         grad += (_at(th, _pair(a_, 1, b_, 1)) - _at(th, _pair(a_, 1, b_, -1))
                  - _at(th, _pair(a_, -1, b_, 1)) + _at(th, _pair(a_, -1, b_, -1))) / (4.0 * h * h)
-    E = float(h ** 3 * np.sum(fw["f"]))
-    return E, h ** 3 * grad
+    return grad
 
 
 # --------------------------------------------------------------------------
