@@ -227,6 +227,47 @@ int fe_hminus_reset(fe_ctx* ctx);
 int fe_diagnostics(fe_ctx* ctx, const void* u, void* curv, double* hist, int nbins, double kmax, double* stats);
 
 /*
+ * Algorithm 2 (Sec. 4.2): the L2 flow of F_h(k * u) with replicate boundary
+ * conditions, driven by L-BFGS, on one field (the validation flow of the
+ * paper's Willmore experiments). The box field [nz][ny][nx] is held inside a
+ * padded copy whose padding repeats the nearest box voxel wherever a stencil
+ * or the blur reads outside the box; F_h sums the density over the box only,
+ * and derivatives that land on padding are added back onto the voxels it
+ * copies, so the gradient is exact for that finite sum.
+ *
+ * L-BFGS (Nocedal and Wright's two-loop recursion, H0 = s'y / y'y, no line
+ * search): each step runs up to max_iter inner iterations of fixed length lr
+ * (the very first one scaled by min(1, 1/|g|_1)), keeps the last `history`
+ * pairs (s, y) with s'y > 1e-10, and stops early on max|g| <= tolerance_grad,
+ * g'd > -tolerance_change, max|lr d| <= tolerance_change, a loss change below
+ * tolerance_change, or after max_iter * 5 / 4 evaluations. Defaults: lr 1,
+ * history 10, max_iter 20 (Sec. 4.2), tolerances 1e-7 and 1e-9.
+ */
+typedef struct fe_l2 fe_l2;
+
+/* grid: the box (batch must be 1); eps, p_coeffs[6] as in fe_create; blur
+ * 0 <= sigma_k <= 4 voxels (0: none). Allocates the padded fields and the
+ * optimiser's history on the device. */
+int fe_l2_create(const fe_grid* grid, double eps, const double* p_coeffs, double sigma_k, void* stream,
+                 fe_l2** out);
+/* Optimiser settings (1 <= history <= 64, max_iter >= 1); resets its state. */
+int fe_l2_set_lbfgs(fe_l2* flow, double lr, int history, int max_iter, double tolerance_grad,
+                    double tolerance_change);
+/* Copy the box field u (device, [nz][ny][nx], the grid's precision) in as the
+ * variable, and reset the optimiser's state. */
+int fe_l2_load(fe_l2* flow, const void* u);
+/* Copy the variable out to the box field u (device). */
+int fe_l2_store(fe_l2* flow, void* u);
+/* Load u, then F_h(k * u) into *energy (host) and its gradient into g (device
+ * box field, or NULL). Synchronises. */
+int fe_l2_energy_grad(fe_l2* flow, const void* u, void* g, double* energy);
+/* nsteps optimiser steps from the current variable and state; energies (host
+ * [nsteps] or NULL) receives the loss at the start of each step. */
+int fe_l2_step(fe_l2* flow, int nsteps, double* energies);
+int fe_l2_set_stream(fe_l2* flow, void* stream);
+void fe_l2_destroy(fe_l2* flow);
+
+/*
  * Launch-shape selection. Variants are numbered 0 .. fe_num_variants()-1;
  * fe_variant_info describes one (x and y interior tile, threads per block,
  * element size it supports). fe_set_launch picks a variant and a z-chunk

@@ -96,6 +96,8 @@ struct SweepArgs {
   const int* adam_t;            // Adam: step number t >= 1 (device, advanced by the finalisation)
   const T* cfield;              // space-dependent coefficients: [batch][6][nz][ny][nx] scaled C1..C6,
                                 // read by the SP instantiations only
+  int box_lo[3], box_hi[3];     // BOX instantiations: the voxels (x, y, z) whose density is summed;
+                                // the others only supply samples (a padded field)
   GridConsts<T> k;
   T tau;                        // GD step size, or Adam learning rate
   T beta1, beta2, adam_eps;     // Adam
@@ -223,7 +225,10 @@ __device__ __forceinline__ BlockTile block_tile(const SweepArgs<T>& a) {
 // SP: the coefficients C1..C6 come per voxel from a.cfield (loaded for every
 // ring voxel of a plane right after the plane is staged, so their latency
 // overlaps the barrier) instead of from the instance's parameters.
-template <typename T, int TX, int TY, int NT, int MODE, bool SP = false>
+// BOX: only voxels inside [box_lo, box_hi) carry a density; the others (the
+// padding of a non-periodic field) have zero adjoints, and the gradient is
+// written at every voxel, padding included, for the caller to fold back.
+template <typename T, int TX, int TY, int NT, int MODE, bool SP = false, bool BOX = false>
 __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   constexpr int UX = TX + 4, UY = TY + 4;      // u window: interior + halo 2
   constexpr int RX = TX + 2, RY = TY + 2;      // adjoint ring: interior + 1
@@ -351,8 +356,20 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
 
     // ---- forward + adjoint on the ring-extended plane p ----
     const bool out_plane = (p >= k0) && (p < kend);
+    const int pz = BOX ? wrap_index(p, a.nz) : 0;
+    const bool zin = !BOX || (pz >= a.box_lo[2] && pz < a.box_hi[2]);
     auto eval = [&](int v, VoxelAdjoint<T>& ad, const InstParams<T>& pv) {
       const int c = (v / RX + 1) * UX + v % RX + 1;
+      if (BOX) {
+        const int gx = wrap_index(x0 - 1 + v % RX, a.nx), gy = wrap_index(y0 - 1 + v / RX, a.ny);
+        if (!zin || gx < a.box_lo[0] || gx >= a.box_hi[0] || gy < a.box_lo[1] || gy >= a.box_hi[1]) {
+          ad = VoxelAdjoint<T>{};
+          sx[GX][v] = T(0); sx[GY][v] = T(0);
+          sx[BXX][v] = T(0); sx[BYY][v] = T(0);
+          sx[BXY][v] = T(0); sx[BXZ][v] = T(0); sx[BYZ][v] = T(0);
+          return T(0);
+        }
+      }
       const T* pc = su[sc] + c;
       const T* pm = su[sm] + c;
       const T* pp = su[sp] + c;

@@ -59,6 +59,16 @@ SIGNATURES = {
     "fe_set_orientation": (ctypes.c_int, [_P, _DP, _DP]),
     "fe_set_coeff_field": (ctypes.c_int, [_P, _P]),
     "fe_set_mass_field": (ctypes.c_int, [_P, _P]),
+    "fe_l2_create": (ctypes.c_int, [ctypes.POINTER(FeGrid), ctypes.c_double, _DP, ctypes.c_double, _P,
+                                    ctypes.POINTER(_P)]),
+    "fe_l2_set_lbfgs": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double]),
+    "fe_l2_load": (ctypes.c_int, [_P, _P]),
+    "fe_l2_store": (ctypes.c_int, [_P, _P]),
+    "fe_l2_energy_grad": (ctypes.c_int, [_P, _P, _P, _DP]),
+    "fe_l2_step": (ctypes.c_int, [_P, ctypes.c_int, _DP]),
+    "fe_l2_set_stream": (ctypes.c_int, [_P, _P]),
+    "fe_l2_destroy": (None, [_P]),
     "fe_num_variants": (ctypes.c_int, []),
     "fe_variant_info": (ctypes.c_int, [ctypes.c_int, _IP, _IP, _IP, _IP]),
     "fe_set_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
@@ -352,6 +362,80 @@ class FeContext:
                                  ctypes.byref(best)))
         v, z = self.get_launch()
         return v, z, best.value
+
+
+class FeL2Flow:
+    """Algorithm 2 (Sec. 4.2) on one box field [nz, ny, nx]: the L2 flow of F_h(k * u)
+    with replicate boundaries, driven by L-BFGS (lr 1, history 10, 20 iterations per
+    step unless set otherwise). Everything runs in libfe."""
+
+    def __init__(self, shape, h, eps, coeffs, sigma_k=1.0, dtype=torch.float32, device=None):
+        nz, ny, nx = (int(v) for v in shape)
+        self.shape = (nz, ny, nx)
+        self.dtype = dtype
+        if dtype not in (torch.float32, torch.float64):
+            raise TypeError("dtype must be torch.float32 or torch.float64")
+        self.device = (torch.device("cuda", torch.cuda.current_device()) if device is None
+                       else torch.device(device))
+        coeffs = [float(c) for c in np.asarray(coeffs, dtype=np.float64).reshape(-1)]
+        if len(coeffs) != 6:
+            raise ValueError("need 6 coefficients")
+        grid = FeGrid(nx, ny, nz, 1, float(h), FE_F32 if dtype == torch.float32 else FE_F64)
+        handle = _P()
+        with torch.cuda.device(self.device):
+            _check(lib().fe_l2_create(ctypes.byref(grid), float(eps), _dbl(coeffs), float(sigma_k),
+                                      _P(torch.cuda.current_stream().cuda_stream), ctypes.byref(handle)))
+        self._h = handle
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fe_l2_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        _check(lib().fe_l2_set_stream(self._h, _P(torch.cuda.current_stream(self.device).cuda_stream)))
+
+    def _box(self, t, name):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != self.dtype \
+                or not t.is_contiguous() or tuple(t.shape[-3:]) != self.shape or t.numel() != np.prod(self.shape):
+            raise ValueError(f"{name} must be a contiguous {self.dtype} device tensor of shape {self.shape}")
+        return _P(t.data_ptr())
+
+    def set_lbfgs(self, lr=1.0, history=10, max_iter=20, tolerance_grad=1e-7, tolerance_change=1e-9):
+        _check(lib().fe_l2_set_lbfgs(self._h, float(lr), int(history), int(max_iter), float(tolerance_grad),
+                                     float(tolerance_change)))
+
+    def load(self, u):
+        self._sync_stream()
+        _check(lib().fe_l2_load(self._h, self._box(u, "u")))
+
+    def store(self, u=None):
+        if u is None:
+            u = torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        self._sync_stream()
+        _check(lib().fe_l2_store(self._h, self._box(u, "u")))
+        return u
+
+    def energy_grad(self, u):
+        """Loads u (resets the optimiser) and returns (F_h(k * u), dF/du)."""
+        g = torch.empty(self.shape, dtype=self.dtype, device=u.device)
+        E = ctypes.c_double()
+        self._sync_stream()
+        _check(lib().fe_l2_energy_grad(self._h, self._box(u, "u"), _P(g.data_ptr()), ctypes.byref(E)))
+        return E.value, g
+
+    def step(self, nsteps=1):
+        """nsteps optimiser steps; returns the loss at the start of each."""
+        out = (ctypes.c_double * max(nsteps, 1))()
+        self._sync_stream()
+        _check(lib().fe_l2_step(self._h, int(nsteps), out))
+        return [out[i] for i in range(nsteps)]
 
 
 class FeEnergy(torch.autograd.Function):

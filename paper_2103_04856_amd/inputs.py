@@ -120,3 +120,12 @@ def interpolated_parameters(shape, params, masses, repeat_ends=True):
     a_field = np.broadcast_to(a_x.T[:, None, None, :], (6, nz, ny, nx)).copy()
     m_field = np.broadcast_to(m_x[None, None, :], (nz, ny, nx)).copy()
     return a_field, m_field
+
+
+def tanh_torus(n, R, r, eps, centre=(0.5, 0.5, 0.5)):
+    """Solid torus around the z axis through `centre`: major radius R, tube radius r,
+    d = r - sqrt((rho - R)^2 + z^2) with rho the distance to the axis."""
+    Z, Y, X = _mesh(n)
+    x, y, z = X - centre[0], Y - centre[1], Z - centre[2]
+    d = r - np.sqrt((np.sqrt(x * x + y * y) - R) ** 2 + z * z)
+    return np.tanh(d / (math.sqrt(2.0) * eps))
