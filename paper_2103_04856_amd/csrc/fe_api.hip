@@ -768,7 +768,7 @@ struct fe_l2 {
   std::vector<void*> S, Y;       // history, oldest first (pointers rotate, memory stays)
   std::vector<double> rho;
   int hist_len = 0;
-  double* d_red = nullptr;       // reduction partials and result
+  double* d_red = nullptr;       // reduction partials, then the scalar slots (kL2Slots)
   // settings
   double lr = 1.0, tol_grad = 1e-7, tol_change = 1e-9;
   int history = 10, max_iter = 20, max_eval = 25;
@@ -781,13 +781,22 @@ namespace {
 
 int l2_launch_1d(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 65536); }
 
+// Scalar slots after the partials in d_red: 0 energy, 1 max|g|, 2 max|d|, 3 g'd,
+// 4 |g|_1, 5 y's, 6 y'y, 7 scratch dot, 8.. the s_i'q dots of the two-loop
+// recursion (one per history entry).
+constexpr int kSlotE = 0, kSlotGmax = 1, kSlotDmax = 2, kSlotGtd = 3, kSlotL1 = 4, kSlotYs = 5, kSlotYy = 6,
+              kSlotDot = 7, kSlotAlpha = 8;
+constexpr int kL2MaxHistory = 64;
+constexpr int kL2Slots = kSlotAlpha + kL2MaxHistory;
+
+// Reduction of a (and b) into scalar slot `slot`, stream-ordered, no sync.
 template <typename T>
-int l2_reduce(fe_l2* L, int op, const void* a, const void* b, double& out) {
+int l2_reduce_dev(fe_l2* L, int op, const void* a, const void* b, int slot) {
   hipStream_t s = L->ctx->stream;
   const T* pa = static_cast<const T*>(a);
   const T* pb = static_cast<const T*>(b);
   double* part = L->d_red;
-  double* res = L->d_red + fe::kVecBlocks;
+  double* res = L->d_red + fe::kVecBlocks + slot;
   if (op == 0)
     hipLaunchKernelGGL((fe::vec_reduce<T, 0>), dim3(fe::kVecBlocks), dim3(256), 0, s, pa, pb, L->n, part);
   else if (op == 1)
@@ -799,8 +808,24 @@ int l2_reduce(fe_l2* L, int op, const void* a, const void* b, double& out) {
   else
     hipLaunchKernelGGL(fe::vec_finish<0>, dim3(1), dim3(256), 0, s, (const double*)part, fe::kVecBlocks, res);
   FE_HIP(hipGetLastError());
-  FE_HIP(hipMemcpyAsync(&out, res, sizeof(double), hipMemcpyDeviceToHost, s));
-  FE_HIP(hipStreamSynchronize(s));
+  return FE_OK;
+}
+
+// Host copies of scalar slots [first, first + count) (one sync).
+int l2_read_slots(fe_l2* L, int first, int count, double* out) {
+  FE_HIP(hipMemcpyAsync(out, L->d_red + fe::kVecBlocks + first, sizeof(double) * count, hipMemcpyDeviceToHost,
+                        L->ctx->stream));
+  FE_HIP(hipStreamSynchronize(L->ctx->stream));
+  return FE_OK;
+}
+
+// y += (ka sc[ia] + kb sc[ib]) x with device scalars
+template <typename T>
+int l2_axpy_dev(fe_l2* L, int ia, double ka, int ib, double kb, const void* x, void* y) {
+  hipLaunchKernelGGL(fe::vec_axpy_dev<T>, dim3(l2_launch_1d(L->n)), dim3(256), 0, L->ctx->stream,
+                     (const double*)(L->d_red + fe::kVecBlocks), ia, ka, ib, kb, static_cast<const T*>(x),
+                     static_cast<T*>(y), L->n);
+  FE_HIP(hipGetLastError());
   return FE_OK;
 }
 
@@ -831,9 +856,10 @@ void l2_blur(fe_l2* L, const T* in, T* tmp1, T* tmp2, T* out) {
   blur_yz<T>(s, d, k, tmp1, tmp2, out);
 }
 
-// loss = F_h(k * x) with replicate boundaries; g = its gradient (zero padding).
+// F_h(k * x) with replicate boundaries into the energy slot and g = its
+// gradient (zero padding), stream-ordered.
 template <typename T>
-int l2_eval(fe_l2* L, double& loss) {
+int l2_eval_dev(fe_l2* L) {
   hipStream_t s = L->ctx->stream;
   const int nb = l2_launch_1d(L->n);
   T* x = static_cast<T*>(L->x);
@@ -859,7 +885,20 @@ int l2_eval(fe_l2* L, double& loss) {
     hipLaunchKernelGGL(fe::fold_pads<T>, dim3(nb), dim3(256), 0, s, (const T*)w0, g, L->box);
   }
   FE_HIP(hipGetLastError());
-  return copy_energy_out(L->ctx, &loss);
+  FE_HIP(hipMemcpyAsync(L->d_red + fe::kVecBlocks + kSlotE, L->ctx->d_energy, sizeof(double),
+                        hipMemcpyDeviceToDevice, s));
+  return FE_OK;
+}
+
+// As l2_eval_dev, with the loss copied to the host (syncs).
+template <typename T>
+int l2_eval(fe_l2* L, double& loss) {
+  int rc = l2_eval_dev<T>(L);
+  if (rc) return rc;
+  rc = l2_read_slots(L, kSlotE, 1, &loss);
+  if (rc) return rc;
+  if (!std::isfinite(loss)) return set_error(FE_ENONFINITE, "energy is not finite");
+  return FE_OK;
 }
 
 // One optimiser step of L-BFGS without line search (Nocedal and Wright, the
@@ -868,16 +907,20 @@ int l2_eval(fe_l2* L, double& loss) {
 // a pair (s, y) enters the history only if s'y > 1e-10. Stops early on
 // max|g| <= tol_grad, a non-descent direction (g'd > -tol_change), a step
 // max|t d| <= tol_change, or a loss change below tol_change. `loss0` receives
-// the loss at the start of the step.
+// the loss at the start of the step. The recursion's dot products stay in
+// device scalar slots; the host reads scalars only where it branches on them
+// (about three syncs per iteration).
 template <typename T>
 int l2_step(fe_l2* L, double& loss0) {
-  double loss = 0.0;
-  int rc = l2_eval<T>(L, loss);
+  int rc = l2_eval_dev<T>(L);
   if (rc) return rc;
+  if ((rc = l2_reduce_dev<T>(L, 2, L->g, nullptr, kSlotGmax))) return rc;
+  double sc[2];
+  if ((rc = l2_read_slots(L, kSlotE, 2, sc))) return rc;
+  double loss = sc[0], gmax = sc[1];
+  if (!std::isfinite(loss)) return set_error(FE_ENONFINITE, "energy is not finite");
   loss0 = loss;
   int evals = 1;
-  double gmax = 0.0;
-  if ((rc = l2_reduce<T>(L, 2, L->g, nullptr, gmax))) return rc;
   if (gmax <= L->tol_grad) return FE_OK;
   bool opt_cond = false;
   for (int it = 1; it <= L->max_iter; ++it) {
@@ -888,16 +931,17 @@ int l2_step(fe_l2* L, double& loss0) {
       L->rho.clear();
       L->H_diag = 1.0;
     } else {
-      // y = g - prev_g (in q), s = t d (in w0)
+      // y = g - prev_g (in q), s = t d (in w0); accept the pair if y's > 1e-10
       hipLaunchKernelGGL(fe::vec_sub<T>, dim3(l2_launch_1d(L->n)), dim3(256), 0, L->ctx->stream,
                          static_cast<const T*>(L->g), static_cast<const T*>(L->prev_g), static_cast<T*>(L->q), L->n);
       FE_HIP(hipGetLastError());
-      double ys = 0.0, yy = 0.0;
-      // s = t d in w0 (scratch), ys = y's
       if ((rc = l2_axpby<T>(L, L->t, L->d, 0.0, L->w0))) return rc;
-      if ((rc = l2_reduce<T>(L, 0, L->q, L->w0, ys))) return rc;
+      if ((rc = l2_reduce_dev<T>(L, 0, L->q, L->w0, kSlotYs))) return rc;
+      if ((rc = l2_reduce_dev<T>(L, 0, L->q, L->q, kSlotYy))) return rc;
+      double yy2[2];
+      if ((rc = l2_read_slots(L, kSlotYs, 2, yy2))) return rc;
+      const double ys = yy2[0], yy = yy2[1];
       if (ys > 1e-10) {
-        if ((rc = l2_reduce<T>(L, 0, L->q, L->q, yy))) return rc;
         if (L->hist_len == L->history) {         // drop the oldest: rotate the slots
           std::rotate(L->S.begin(), L->S.begin() + 1, L->S.end());
           std::rotate(L->Y.begin(), L->Y.begin() + 1, L->Y.end());
@@ -912,48 +956,46 @@ int l2_step(fe_l2* L, double& loss0) {
       }
       // two-loop recursion: q = -g; newest to oldest: a_i = rho_i s_i'q, q -= a_i y_i;
       // d = H_diag q; oldest to newest: b_i = rho_i y_i'd, d += (a_i - b_i) s_i
-      std::vector<double> al(L->hist_len);
       if ((rc = l2_axpby<T>(L, -1.0, L->g, 0.0, L->q))) return rc;
       for (int i = L->hist_len - 1; i >= 0; --i) {
-        double sq = 0.0;
-        if ((rc = l2_reduce<T>(L, 0, L->S[i], L->q, sq))) return rc;
-        al[i] = sq * L->rho[i];
-        if ((rc = l2_axpby<T>(L, -al[i], L->Y[i], 1.0, L->q))) return rc;
+        if ((rc = l2_reduce_dev<T>(L, 0, L->S[i], L->q, kSlotAlpha + i))) return rc;
+        if ((rc = l2_axpy_dev<T>(L, kSlotAlpha + i, -L->rho[i], -1, 0.0, L->Y[i], L->q))) return rc;
       }
       if ((rc = l2_axpby<T>(L, L->H_diag, L->q, 0.0, L->d))) return rc;
       for (int i = 0; i < L->hist_len; ++i) {
-        double yd = 0.0;
-        if ((rc = l2_reduce<T>(L, 0, L->Y[i], L->d, yd))) return rc;
-        const double be = yd * L->rho[i];
-        if ((rc = l2_axpby<T>(L, al[i] - be, L->S[i], 1.0, L->d))) return rc;
+        if ((rc = l2_reduce_dev<T>(L, 0, L->Y[i], L->d, kSlotDot))) return rc;
+        if ((rc = l2_axpy_dev<T>(L, kSlotAlpha + i, L->rho[i], kSlotDot, -L->rho[i], L->S[i], L->d))) return rc;
       }
     }
     if ((rc = l2_copy<T>(L, L->g, L->prev_g))) return rc;
     L->prev_loss = loss;
-    if (L->n_iter == 1) {
-      double l1 = 0.0;
-      if ((rc = l2_reduce<T>(L, 1, L->g, nullptr, l1))) return rc;
-      L->t = std::min(1.0, 1.0 / l1) * L->lr;
-    } else {
-      L->t = L->lr;
-    }
-    double gtd = 0.0;
-    if ((rc = l2_reduce<T>(L, 0, L->g, L->d, gtd))) return rc;
+    const bool first = L->n_iter == 1;
+    if ((rc = l2_reduce_dev<T>(L, 0, L->g, L->d, kSlotGtd))) return rc;
+    if (first && (rc = l2_reduce_dev<T>(L, 1, L->g, nullptr, kSlotL1))) return rc;
+    double gl[2];
+    if ((rc = l2_read_slots(L, kSlotGtd, first ? 2 : 1, gl))) return rc;
+    L->t = first ? std::min(1.0, 1.0 / gl[1]) * L->lr : L->lr;
+    const double gtd = gl[0];
     if (gtd > -L->tol_change) break;
     int ls_evals = 0;
     if ((rc = l2_axpby<T>(L, L->t, L->d, 1.0, L->x))) return rc;
+    if ((rc = l2_reduce_dev<T>(L, 2, L->d, nullptr, kSlotDmax))) return rc;
+    double dmax = 0.0;
     if (it != L->max_iter) {
-      if ((rc = l2_eval<T>(L, loss))) return rc;
-      if ((rc = l2_reduce<T>(L, 2, L->g, nullptr, gmax))) return rc;
-      opt_cond = gmax <= L->tol_grad;
+      if ((rc = l2_eval_dev<T>(L))) return rc;
+      if ((rc = l2_reduce_dev<T>(L, 2, L->g, nullptr, kSlotGmax))) return rc;
+      double egd[3];
+      if ((rc = l2_read_slots(L, kSlotE, 3, egd))) return rc;
+      loss = egd[0];
+      if (!std::isfinite(loss)) return set_error(FE_ENONFINITE, "energy is not finite");
+      opt_cond = egd[1] <= L->tol_grad;
+      dmax = egd[2];
       ls_evals = 1;
     }
     evals += ls_evals;
     if (it == L->max_iter) break;
     if (evals >= L->max_eval) break;
     if (opt_cond) break;
-    double dmax = 0.0;
-    if ((rc = l2_reduce<T>(L, 2, L->d, nullptr, dmax))) return rc;
     if (dmax * std::fabs(L->t) <= L->tol_change) break;
     if (std::fabs(loss - L->prev_loss) < L->tol_change) break;
   }
@@ -1329,8 +1371,10 @@ int fe_l2_create(const fe_grid* grid, double eps, const double* p_coeffs, double
   pg.nx += 2 * W;
   pg.ny += 2 * W;
   pg.nz += 2 * W;
-  if ((long)pg.nz > 65535 || (long)pg.ny > 65535)
-    return l2_free(L), set_error(FE_EINVAL, "grid too large for the flow kernels");
+  if ((long)pg.nz > 65535 || (long)pg.ny > 65535) {
+    l2_free(L);
+    return set_error(FE_EINVAL, "grid too large for the flow kernels");
+  }
   rc = fe_create(&pg, &eps, p_coeffs, stream, &L->ctx);
   if (rc) {
     l2_free(L);
@@ -1359,7 +1403,7 @@ int fe_l2_create(const fe_grid* grid, double eps, const double* p_coeffs, double
       return set_error(FE_EHIP, "hipMemsetAsync failed");
     }
   }
-  if (hipMalloc((void**)&L->d_red, sizeof(double) * (fe::kVecBlocks + 1)) != hipSuccess) {
+  if (hipMalloc((void**)&L->d_red, sizeof(double) * (fe::kVecBlocks + kL2Slots)) != hipSuccess) {
     L->d_red = nullptr;
     l2_free(L);
     return set_error(FE_ENOMEM, "L2 flow reduction buffer allocation failed");
@@ -1377,20 +1421,32 @@ int fe_l2_set_lbfgs(fe_l2* L, double lr, int history, int max_iter, double toler
   g_last_error.clear();
   if (!L) return set_error(FE_EINVAL, "flow is NULL");
   if (!(lr > 0.0) || !std::isfinite(lr)) return set_error(FE_EINVAL, "lr must be finite and > 0");
-  if (history < 1 || history > 64) return set_error(FE_EINVAL, "history must lie in [1, 64]");
+  if (history < 1 || history > kL2MaxHistory)
+    return set_error(FE_EINVAL, "history must lie in [1, %d]", kL2MaxHistory);
   if (max_iter < 1) return set_error(FE_EINVAL, "max_iter must be >= 1");
   if (!(tolerance_grad >= 0.0) || !(tolerance_change >= 0.0))
     return set_error(FE_EINVAL, "tolerances must be >= 0");
   DeviceGuard dg(L->ctx->device);
-  for (void* p : L->S)
-    if (p) (void)hipFree(p);
-  for (void* p : L->Y)
-    if (p) (void)hipFree(p);
-  L->S.assign(history, nullptr);
-  L->Y.assign(history, nullptr);
-  for (int i = 0; i < history; ++i)
-    if (hipMalloc(&L->S[i], L->n * L->esz) != hipSuccess || hipMalloc(&L->Y[i], L->n * L->esz) != hipSuccess)
+  if (history != (int)L->S.size()) {
+    // allocate the new history first, so that a failure leaves the old one intact
+    std::vector<void*> S(history, nullptr), Y(history, nullptr);
+    bool ok = true;
+    for (int i = 0; i < history && ok; ++i)
+      ok = hipMalloc(&S[i], L->n * L->esz) == hipSuccess && hipMalloc(&Y[i], L->n * L->esz) == hipSuccess;
+    if (!ok) {
+      for (void* p : S)
+        if (p) (void)hipFree(p);
+      for (void* p : Y)
+        if (p) (void)hipFree(p);
       return set_error(FE_ENOMEM, "L-BFGS history allocation failed");
+    }
+    for (void* p : L->S)
+      if (p) (void)hipFree(p);
+    for (void* p : L->Y)
+      if (p) (void)hipFree(p);
+    L->S.swap(S);
+    L->Y.swap(Y);
+  }
   L->lr = lr;
   L->history = history;
   L->max_iter = max_iter;

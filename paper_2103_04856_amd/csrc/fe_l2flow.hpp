@@ -86,7 +86,8 @@ __global__ __launch_bounds__(256) void vec_reduce(const T* __restrict__ a, const
   if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
 }
 
-// out[0] = reduction of the nblk partials (one block, fixed order).
+// out[0] = reduction of the nblk partials (one block, fixed order); the result may
+// go to any slot of a device scalar array.
 template <int OP>
 __global__ __launch_bounds__(256) void vec_finish(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
   __shared__ double s[256];
@@ -106,6 +107,17 @@ template <typename T>
 __global__ __launch_bounds__(256) void vec_axpby(T alpha, const T* __restrict__ x, T beta, T* __restrict__ y, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     y[i] = alpha * x[i] + beta * y[i];
+}
+
+// y = (ka sc[ia] + kb sc[ib]) x + y, the coefficient formed from device scalars
+// (ib < 0: no second term), so that the two-loop recursion needs no host sync.
+template <typename T>
+__global__ __launch_bounds__(256) void vec_axpy_dev(const double* __restrict__ sc, int ia, double ka, int ib,
+                                                    double kb, const T* __restrict__ x, T* __restrict__ y,
+                                                    size_t n) {
+  const T alpha = T(ka * sc[ia] + (ib >= 0 ? kb * sc[ib] : 0.0));
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = alpha * x[i] + y[i];
 }
 
 // z = x - y
