@@ -509,11 +509,36 @@ dim3 axis_grid(const fe::FieldDims& d, int axis) {
                    : dim3(ceil_div(d.nx, 64), ceil_div(d.nz, fe::kAxisChunk), ceil_div(d.ny, 4) * d.batch);
 }
 
+// The x pass (with the divergence when DIV), dispatched to the fixed-radius
+// instantiation when there is one.
+template <typename T, bool DIV>
+void blur_x_pass(hipStream_t s, const fe::FieldDims& d, const fe::BlurTaps<T>& k, const T* in, T* out,
+                 const double* m0, const T* mfield, T inv2h, fe::FlowClock* clk, double beta1, double beta2) {
+  const dim3 g = x_grid(d), b(64, 4);
+  if (k.r == 4)
+    hipLaunchKernelGGL((fe::blur_x<T, DIV, 4>), g, b, 0, s, in, out, m0, mfield, d, inv2h, k, clk, beta1, beta2);
+  else if (k.r == 8)
+    hipLaunchKernelGGL((fe::blur_x<T, DIV, 8>), g, b, 0, s, in, out, m0, mfield, d, inv2h, k, clk, beta1, beta2);
+  else
+    hipLaunchKernelGGL((fe::blur_x<T, DIV>), g, b, 0, s, in, out, m0, mfield, d, inv2h, k, clk, beta1, beta2);
+}
+
+template <typename T, int AXIS>
+void blur_axis_pass(hipStream_t s, const fe::FieldDims& d, const fe::BlurTaps<T>& k, const T* in, T* out) {
+  const dim3 g = axis_grid(d, AXIS), b(64, 4);
+  if (k.r == 4)
+    hipLaunchKernelGGL((fe::blur_axis<T, AXIS, 4>), g, b, 0, s, in, out, d, k);
+  else if (k.r == 8)
+    hipLaunchKernelGGL((fe::blur_axis<T, AXIS, 8>), g, b, 0, s, in, out, d, k);
+  else
+    hipLaunchKernelGGL((fe::blur_axis<T, AXIS>), g, b, 0, s, in, out, d, k);
+}
+
 // out = k * f along y then z, through `tmp` (f is left as it was; out may be f).
 template <typename T>
 void blur_yz(hipStream_t s, const fe::FieldDims& d, const fe::BlurTaps<T>& k, const T* f, T* tmp, T* out) {
-  hipLaunchKernelGGL((fe::blur_axis<T, 1>), axis_grid(d, 1), dim3(64, 4), 0, s, f, tmp, d, k);
-  hipLaunchKernelGGL((fe::blur_axis<T, 2>), axis_grid(d, 2), dim3(64, 4), 0, s, (const T*)tmp, out, d, k);
+  blur_axis_pass<T, 1>(s, d, k, f, tmp);
+  blur_axis_pass<T, 2>(s, d, k, tmp, out);
 }
 
 // u = k * (div A + m0) into `out` (a user field or the work field w0, never
@@ -528,11 +553,9 @@ int flow_field(fe_ctx* c, hipStream_t s, const void* A, T* out, double sigma_k, 
   T* w0 = static_cast<T*>(c->d_w0);
   const T* mf = c->use_mfield ? static_cast<const T*>(c->d_mfield) : nullptr;
   if (k.r == 0) {
-    hipLaunchKernelGGL((fe::blur_x<T, true>), x_grid(d), dim3(64, 4), 0, s, (const T*)A, out, c->d_mass, mf, d,
-                       inv2h, k, clk, beta1, beta2);
+    blur_x_pass<T, true>(s, d, k, (const T*)A, out, c->d_mass, mf, inv2h, clk, beta1, beta2);
   } else {
-    hipLaunchKernelGGL((fe::blur_x<T, true>), x_grid(d), dim3(64, 4), 0, s, (const T*)A, w0, c->d_mass, mf, d,
-                       inv2h, k, clk, beta1, beta2);
+    blur_x_pass<T, true>(s, d, k, (const T*)A, w0, c->d_mass, mf, inv2h, clk, beta1, beta2);
     blur_yz<T>(s, d, k, w0, static_cast<T*>(c->d_w1), out);
   }
   FE_HIP(hipGetLastError());
@@ -556,8 +579,7 @@ int flow_iteration(fe_ctx* c, hipStream_t s, void* A, const FlowRule& fr) {
   // gu = k * gb: x pass into w0, y pass into w1, z pass into w0
   T* gu = w1;
   if (k.r > 0) {
-    hipLaunchKernelGGL((fe::blur_x<T, false>), x_grid(d), dim3(64, 4), 0, s, (const T*)w1, w0, nullptr,
-                       (const T*)nullptr, d, T(0), k, nullptr, 0.0, 0.0);
+    blur_x_pass<T, false>(s, d, k, (const T*)w1, w0, nullptr, nullptr, T(0), nullptr, 0.0, 0.0);
     blur_yz<T>(s, d, k, w0, w1, w0);
     gu = w0;
   }
@@ -851,8 +873,7 @@ void l2_blur(fe_l2* L, const T* in, T* tmp1, T* tmp2, T* out) {
   const fe::FieldDims d{L->box.nx, L->box.ny, L->box.nz, 1};
   const fe::BlurTaps<T> k = blur_taps<T>(L->sigma_k);
   hipStream_t s = L->ctx->stream;
-  hipLaunchKernelGGL((fe::blur_x<T, false>), x_grid(d), dim3(64, 4), 0, s, in, tmp1, nullptr, (const T*)nullptr,
-                     d, T(0), k, nullptr, 0.0, 0.0);
+  blur_x_pass<T, false>(s, d, k, in, tmp1, nullptr, nullptr, T(0), nullptr, 0.0, 0.0);
   blur_yz<T>(s, d, k, tmp1, tmp2, out);
 }
 

@@ -47,15 +47,21 @@ __device__ __forceinline__ int wrap_any(int v, int n) {
 __device__ __forceinline__ int wrap_up(int v, int n) { return v >= n ? v - n : v; }
 __device__ __forceinline__ int wrap_down(int v, int n) { return v < 0 ? v + n : v; }
 
-// sum_j w_j v[j * step], j = 0..2r. The loop runs to the largest r with a
-// uniform guard, so the taps are read at fixed offsets (kernel arguments in
-// scalar registers) rather than indexed at run time.
-template <typename T>
+// The blur kernels take the radius as a template argument R for the common
+// widths (sigma_k = 1 and 2 give r = 4 and 8), so their tap loops are fixed;
+// R = -1 is the general form, whose loops run to the largest radius under a
+// uniform guard. Either way the taps are read at fixed offsets (kernel
+// arguments in scalar registers), never indexed at run time.
+template <int R>
+constexpr int radius_bound() { return R >= 0 ? R : kBlurMaxR; }
+
+// sum_j w_j v[j * step], j = 0..2r
+template <typename T, int R>
 __device__ __forceinline__ T taps_dot(const BlurTaps<T>& k, const T* v, int step) {
   T acc = T(0);
 #pragma unroll
-  for (int j = 0; j <= 2 * kBlurMaxR; ++j)
-    if (j <= 2 * k.r) acc += k.w[j] * v[j * step];
+  for (int j = 0; j <= 2 * radius_bound<R>(); ++j)
+    if (R >= 0 || j <= 2 * k.r) acc += k.w[j] * v[j * step];
   return acc;
 }
 
@@ -69,7 +75,7 @@ __device__ __forceinline__ T taps_dot(const BlurTaps<T>& k, const T* v, int step
 // before the first LDS write, so a block keeps many in flight.
 constexpr int kBlurRows = 16;
 
-template <typename T, bool DIV>
+template <typename T, bool DIV, int R = -1>
 __global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __restrict__ out,
                                               const double* __restrict__ m0, const T* __restrict__ mfield,
                                               FieldDims d, T inv2h, BlurTaps<T> k, FlowClock* __restrict__ clk,
@@ -89,7 +95,8 @@ __global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __res
   const int x0 = blockIdx.x * 64;
   const size_t plane = (size_t)d.nx * d.ny, vol = plane * d.nz;
   const T* base = in + (size_t)b * (DIV ? 3 : 1) * vol;
-  const int nseg = 64 + 2 * k.r;
+  const int r = R >= 0 ? R : k.r;
+  const int nseg = 64 + 2 * r;
   T v[kR][kPer][7];          // the non-DIV form uses [0] only; [6] holds m(x)
 #pragma unroll
   for (int i = 0; i < kR; ++i) {
@@ -100,7 +107,7 @@ __global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __res
     for (int j = 0; j < kPer; ++j) {
       const int e = threadIdx.x + 64 * j;
       if (e >= nseg) continue;
-      const int x = wrap_any(x0 - k.r + e, d.nx);
+      const int x = wrap_any(x0 - r + e, d.nx);
       if (DIV) {
         v[i][j][0] = base[row + wrap_up(x + 1, d.nx)];
         v[i][j][1] = base[row + wrap_down(x - 1, d.nx)];
@@ -141,7 +148,7 @@ __global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __res
     const int y = blockIdx.y * kBlurRows + threadIdx.y + 4 * i;
     if (y >= d.ny) continue;
     out[(size_t)b * vol + (size_t)z * plane + (size_t)y * d.nx + x] =
-        taps_dot(k, &s[threadIdx.y + 4 * i][threadIdx.x], 1);
+        taps_dot<T, R>(k, &s[threadIdx.y + 4 * i][threadIdx.x], 1);
   }
 }
 
@@ -154,10 +161,11 @@ __global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __res
 // AXIS = 2.
 constexpr int kAxisChunk = 16;
 
-template <typename T, int AXIS>
+template <typename T, int AXIS, int R = -1>
 __global__ __launch_bounds__(256) void blur_axis(const T* __restrict__ in, T* __restrict__ out, FieldDims d,
                                                  BlurTaps<T> k) {
-  constexpr int kWin = kAxisChunk + 2 * kBlurMaxR;
+  constexpr int kWin = kAxisChunk + 2 * radius_bound<R>();
+  const int r = R >= 0 ? R : k.r;
   const int n_axis = AXIS == 1 ? d.ny : d.nz;
   const int n_other = AXIS == 1 ? d.nz : d.ny;
   const int og = (n_other + 3) / 4;
@@ -171,14 +179,14 @@ __global__ __launch_bounds__(256) void blur_axis(const T* __restrict__ in, T* __
   T v[kWin];
 #pragma unroll
   for (int i = 0; i < kWin; ++i)
-    if (i < kAxisChunk + 2 * k.r) v[i] = in[base + (size_t)wrap_any(p0 - k.r + i, n_axis) * stride];
+    if (R >= 0 || i < kAxisChunk + 2 * r) v[i] = in[base + (size_t)wrap_any(p0 - r + i, n_axis) * stride];
 #pragma unroll
   for (int o = 0; o < kAxisChunk; ++o) {
     if (p0 + o >= n_axis) break;
     T acc = T(0);
 #pragma unroll
-    for (int j = 0; j <= 2 * kBlurMaxR; ++j)
-      if (j <= 2 * k.r) acc += k.w[j] * v[o + j];
+    for (int j = 0; j <= 2 * radius_bound<R>(); ++j)
+      if (R >= 0 || j <= 2 * r) acc += k.w[j] * v[o + j];
     out[base + (size_t)(p0 + o) * stride] = acc;
   }
 }
