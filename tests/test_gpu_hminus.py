@@ -154,3 +154,22 @@ def test_rejects_bad_arguments():
     with pytest.raises(ValueError):
         ctx.hminus_step(A[:, :2].contiguous(), [0.0], 1)
     assert torch.count_nonzero(A).item() == 0
+
+
+@pytest.mark.parametrize("sigma_k,n", [(4.0, 12), (0.25, 10), (3.0, 20), (1.5, 9)])
+def test_blur_radii_and_small_grids_match_oracle_fp64(sigma_k, n):
+    """Blur widths off the fixed-radius kernels (r = 1, 6, 12) and the widest one (r = 16)
+    on grids smaller than the kernel, where the periodic blur wraps several times."""
+    h = 1.0 / n
+    ctx = fe.FeContext((1, n, n, n), h, 2 * h, ASYM_C3, dtype=torch.float64)
+    Ad = to_dev(_a0(n, 13)[None], torch.float64)
+    ud = torch.empty((1, n, n, n), dtype=torch.float64, device="cuda")
+    Ao = oracle_input(Ad)[0]
+    m1 = np.zeros_like(Ao)
+    m2 = np.zeros_like(Ao)
+    Eg = ctx.hminus_step(Ad, [0.05], 1, sigma_k=sigma_k, u_out=ud)
+    Ao, m1, m2, Eo, _ = fo.hminus_adam_step(Ao, m1, m2, 1, h, 2 * h, ASYM_C3, 0.05, sigma_k)
+    assert abs(Eg[0].item() - Eo) <= 1e-10 * abs(Eo)
+    assert rel_l2(Ad.cpu().numpy()[0], Ao) <= 1e-11
+    uo = fo.gaussian_blur(fo.fd_divergence(Ao, h) + 0.05, sigma_k)
+    assert rel_l2(ud.cpu().numpy()[0], uo) <= 1e-11
