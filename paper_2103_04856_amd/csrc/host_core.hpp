@@ -1,0 +1,881 @@
+// Core host side of the C ABI: errors, launch variants, the context, the
+// per-instance constants, the sweeps, the graph-replayed step loops, the
+// autotuner, and the entry points for them. Included once by fe_api.hip.
+#pragma once
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define FE_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return set_error(FE_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));          \
+  } while (0)
+
+constexpr double kXi = 1e-6;   // Sec. 4.1: offset of |grad u| and scale of the smoothed x^+
+constexpr int kGraphPairs = 8;  // descent steps per captured graph: 2 x kGraphPairs
+
+// ---------------------------------------------------------------------------
+// Launch variants: interior tile (TX x TY) and threads per block.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+using SweepFn = void (*)(fe::SweepArgs<T>);
+
+template <typename T>
+struct Kernels {
+  SweepFn<T> grad = nullptr;
+  SweepFn<T> step = nullptr;
+  SweepFn<T> adam = nullptr;
+  SweepFn<T> energy = nullptr;
+};
+
+struct Variant {
+  int tx, ty, nt;
+  int dtype_mask;   // bit 0: FE_F32, bit 1: FE_F64
+  Kernels<float> k32;
+  Kernels<double> k64;
+  Kernels<float> k32sp;    // with a coefficient field (only some variants have them)
+  Kernels<double> k64sp;
+  SweepFn<float> k32box = nullptr;    // gradient with a box mask (padded, non-periodic fields)
+  SweepFn<double> k64box = nullptr;
+};
+
+template <typename T, int TX, int TY, int NT, bool SP = false>
+Kernels<T> make_kernels() {
+  Kernels<T> k;
+  k.grad = fe::grad_sweep<T, TX, TY, NT, fe::kGrad, SP>;
+  k.step = fe::grad_sweep<T, TX, TY, NT, fe::kStepGD, SP>;
+  k.adam = fe::grad_sweep<T, TX, TY, NT, fe::kStepAdam, SP>;
+  k.energy = fe::energy_sweep<T, TX, TY, NT, SP>;
+  return k;
+}
+
+// Static LDS of grad_sweep is (4 (TX+4)(TY+4) + 7 (TX+2)(TY+2)) sizeof(T) plus
+// 16 bytes per wave; gfx950 allows up to 160 KiB per workgroup. The block size
+// need not divide the tile (the last round of a thread may be idle).
+const std::vector<Variant>& variants() {
+  static const std::vector<Variant> v = [] {
+    std::vector<Variant> r;
+    auto add32 = [&](int tx, int ty, int nt, Kernels<float> k, Kernels<float> ksp = {},
+                     SweepFn<float> kbox = nullptr) {
+      Variant x{tx, ty, nt, 1, k, {}, ksp, {}, kbox, nullptr};
+      r.push_back(x);
+    };
+    auto add64 = [&](int tx, int ty, int nt, Kernels<double> k, Kernels<double> ksp = {},
+                     SweepFn<double> kbox = nullptr) {
+      Variant x{tx, ty, nt, 2, {}, k, {}, ksp, nullptr, kbox};
+      r.push_back(x);
+    };
+    // the coefficient-field kernels exist for one large, one small and the
+    // smallest tile of each precision
+    add32(64, 16, 512, make_kernels<float, 64, 16, 512>(), make_kernels<float, 64, 16, 512, true>(),
+          fe::grad_sweep<float, 64, 16, 512, fe::kGrad, false, true>);
+    add32(64, 32, 1024, make_kernels<float, 64, 32, 1024>());
+    add32(32, 32, 512, make_kernels<float, 32, 32, 512>());
+    add32(64, 32, 768, make_kernels<float, 64, 32, 768>());
+    add32(64, 16, 1024, make_kernels<float, 64, 16, 1024>());
+    add32(64, 8, 512, make_kernels<float, 64, 8, 512>());
+    add32(32, 16, 512, make_kernels<float, 32, 16, 512>());
+    add32(32, 8, 256, make_kernels<float, 32, 8, 256>(), make_kernels<float, 32, 8, 256, true>(),
+          fe::grad_sweep<float, 32, 8, 256, fe::kGrad, false, true>);
+    add32(16, 16, 256, make_kernels<float, 16, 16, 256>());
+    add32(16, 8, 128, make_kernels<float, 16, 8, 128>());
+    add32(8, 8, 64, make_kernels<float, 8, 8, 64>(), make_kernels<float, 8, 8, 64, true>(),
+          fe::grad_sweep<float, 8, 8, 64, fe::kGrad, false, true>);
+    add64(32, 16, 512, make_kernels<double, 32, 16, 512>(), make_kernels<double, 32, 16, 512, true>(),
+          fe::grad_sweep<double, 32, 16, 512, fe::kGrad, false, true>);
+    add64(32, 8, 256, make_kernels<double, 32, 8, 256>());
+    add64(16, 16, 256, make_kernels<double, 16, 16, 256>());
+    add64(16, 8, 128, make_kernels<double, 16, 8, 128>(), make_kernels<double, 16, 8, 128, true>(),
+          fe::grad_sweep<double, 16, 8, 128, fe::kGrad, false, true>);
+    add64(8, 8, 64, make_kernels<double, 8, 8, 64>(), make_kernels<double, 8, 8, 64, true>(),
+          fe::grad_sweep<double, 8, 8, 64, fe::kGrad, false, true>);
+    return r;
+  }();
+  return v;
+}
+
+template <typename T>
+const Kernels<T>& kernels_of(const Variant& v, bool sp = false);
+template <>
+const Kernels<float>& kernels_of<float>(const Variant& v, bool sp) { return sp ? v.k32sp : v.k32; }
+template <>
+const Kernels<double>& kernels_of<double>(const Variant& v, bool sp) { return sp ? v.k64sp : v.k64; }
+template <typename T>
+SweepFn<T> box_kernel_of(const Variant& v);
+template <>
+SweepFn<float> box_kernel_of<float>(const Variant& v) { return v.k32box; }
+template <>
+SweepFn<double> box_kernel_of<double>(const Variant& v) { return v.k64box; }
+
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+
+// Step-rule hyper-parameters (baked into captured graphs).
+struct StepRule {
+  int mode;        // fe::kStepGD or fe::kStepAdam
+  double tau;      // GD step size or Adam learning rate
+  double beta1, beta2, adam_eps;
+};
+
+struct GraphKey {
+  void* u;                      // the field (or vector field) the graph updates in place
+  int mode;                     // fe::SweepMode of a step loop, or kFlowMode
+  double tau, beta1, beta2, adam_eps, sigma;
+  int pairs;                    // step pairs (or flow iterations) per graph
+  int variant;
+  int lz;
+  int fields;                   // bit 0: coefficient field in use, bit 1: mass field in use
+  bool operator<(const GraphKey& o) const {
+    return std::tie(u, mode, tau, beta1, beta2, adam_eps, sigma, pairs, variant, lz, fields) <
+           std::tie(o.u, o.mode, o.tau, o.beta1, o.beta2, o.adam_eps, o.sigma, o.pairs, o.variant, o.lz,
+                    o.fields);
+  }
+};
+constexpr int kFlowMode = 100;
+
+struct fe_ctx {
+  fe_grid grid{};
+  int device = 0;
+  hipStream_t stream = nullptr;       // caller's stream (may be null = default)
+  hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
+  std::vector<double> eps, coeffs;    // host copies [batch], [batch][6]
+  std::vector<double> mu, theta;      // orientation term [batch], [batch][3] (mu = 0: off)
+  void* d_prm = nullptr;              // InstParams<T>[batch]
+  double* d_partials = nullptr;       // [batch][max_blocks][2]
+  int* d_counters = nullptr;          // [batch + 1] finished-block counters (zero between launches)
+  double* d_energy = nullptr;         // [batch]
+  double* d_mass = nullptr;           // [batch]
+  double* d_shift = nullptr;          // [2][batch]
+  void* d_pingpong = nullptr;         // one field, allocated by the first fe_step
+  void* d_m1 = nullptr;               // Adam moments, allocated by the first fe_step_adam
+  void* d_m2 = nullptr;
+  int* d_adam_t = nullptr;            // Adam step number (device)
+  void* d_w0 = nullptr;               // H^-1 flow: two scalar work fields
+  void* d_w1 = nullptr;
+  void* d_am1 = nullptr;              // H^-1 flow: Adam moments of A ([batch][3] fields each)
+  void* d_am2 = nullptr;
+  fe::FlowClock* d_flow_clk = nullptr; // H^-1 flow: Adam step number and bias corrections (device)
+  double* d_diag = nullptr;           // diagnostics: per-instance constants, stats, block partials
+  size_t diag_bytes = 0;
+  void* d_cfield = nullptr;           // scaled coefficient field [batch][6][nz][ny][nx] (Sec. 5.2)
+  bool use_cfield = false;
+  void* d_mfield = nullptr;           // mass field m(x) [batch][nz][ny][nx] of the flow (Sec. 5.2)
+  bool use_mfield = false;
+  bool use_box = false;               // padded non-periodic field: density only inside the box
+  int box_lo[3] = {0, 0, 0}, box_hi[3] = {0, 0, 0};
+  size_t max_blocks = 0;              // per instance, over all variants and z chunks
+  int variant = -1;
+  int lz = 0;                         // 0 = automatic
+  int num_cu = 256;                   // compute units of the device
+  std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+size_t elem_size(const fe_grid& g) { return g.dtype == FE_F64 ? 8 : 4; }
+size_t field_elems(const fe_grid& g) { return (size_t)g.nx * g.ny * g.nz * g.batch; }
+
+int check_grid(const fe_grid* g) {
+  if (!g) return set_error(FE_EINVAL, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1)
+    return set_error(FE_EINVAL, "grid sizes must be >= 1 (got %d x %d x %d)", g->nx, g->ny, g->nz);
+  if (g->batch < 1) return set_error(FE_EINVAL, "batch must be >= 1 (got %d)", g->batch);
+  if (!(g->h > 0.0) || !std::isfinite(g->h)) return set_error(FE_EINVAL, "h must be finite and > 0");
+  if (g->dtype != FE_F32 && g->dtype != FE_F64) return set_error(FE_EINVAL, "dtype must be FE_F32 or FE_F64");
+  const double n = (double)g->nx * g->ny * g->nz;
+  if (n * g->batch > 4.0e9 || (double)g->nx * g->ny > 2.0e9)
+    return set_error(FE_EINVAL, "grid too large for 32-bit plane indexing");
+  return FE_OK;
+}
+
+int check_params(int batch, const double* eps, const double* a) {
+  if (!eps || !a) return set_error(FE_EINVAL, "eps and p_coeffs must not be NULL");
+  for (int b = 0; b < batch; ++b) {
+    if (!(eps[b] > 0.0) || !std::isfinite(eps[b]))
+      return set_error(FE_EINVAL, "eps[%d] must be finite and > 0", b);
+    for (int i = 0; i < 6; ++i)
+      if (!std::isfinite(a[6 * b + i])) return set_error(FE_EINVAL, "p_coeffs[%d][%d] is not finite", b, i);
+  }
+  return FE_OK;
+}
+
+// Per-instance constants: c1..c6 of eq. (Feps) folded with the unit scales of
+// the raw-difference formulation (s = eps/h^2, 1/(2h), h^3, eps/(4h^2)).
+template <typename T>
+void fill_params(const fe_ctx* c, std::vector<fe::InstParams<T>>& out) {
+  const double h = c->grid.h, h3 = h * h * h;
+  out.resize(c->grid.batch);
+  for (int b = 0; b < c->grid.batch; ++b) {
+    const double e = c->eps[b];
+    const double* a = &c->coeffs[6 * b];
+    const double a20 = a[0], a11 = a[1], a02 = a[2], a10 = a[3], a01 = a[4], a00 = a[5];
+    const double c1 = (a20 + a02 - a11) / (2.0 * e), c2 = a11 / (2.0 * e), c3 = (a20 - a02) / (2.0 * e);
+    const double c4 = (a10 + a01) / 2.0, c5 = (a10 - a01) / 2.0, c6 = a00;
+    const double sc = e / (h * h);
+    fe::InstParams<T>& p = out[b];
+    p.lam_d = 1.0 / (e * sc);
+    p.lam = T(p.lam_d);
+    p.C1 = T(h3 * c1 * sc * sc);
+    p.C2 = T(h3 * c2 * sc * sc);
+    p.C3 = T(h3 * c3 * sc * sc);
+    p.C4 = T(h3 * c4 * sc / (2.0 * h));
+    p.C5 = T(h3 * c5 * sc / (2.0 * h));
+    p.C6 = T(h3 * c6 * e / (4.0 * h * h));
+    p.xi = T(kXi / (sc * sc));
+    p.inv_xi = T(sc * sc / kXi);
+    p.Co = T(h3 * e * c->mu[b] / (4.0 * h * h));
+    p.thx = T(c->theta[3 * b]);
+    p.thy = T(c->theta[3 * b + 1]);
+    p.thz = T(c->theta[3 * b + 2]);
+  }
+}
+
+template <typename T>
+fe::GridConsts<T> grid_consts(double h) {
+  fe::GridConsts<T> k;
+  k.reg_d = 4.0 * h * h * kXi * kXi;
+  k.reg = T(k.reg_d);
+  return k;
+}
+
+int upload_params(fe_ctx* c) {
+  if (c->grid.dtype == FE_F32) {
+    std::vector<fe::InstParams<float>> p;
+    fill_params(c, p);
+    FE_HIP(hipMemcpyAsync(c->d_prm, p.data(), p.size() * sizeof(p[0]), hipMemcpyHostToDevice, c->stream));
+  } else {
+    std::vector<fe::InstParams<double>> p;
+    fill_params(c, p);
+    FE_HIP(hipMemcpyAsync(c->d_prm, p.data(), p.size() * sizeof(p[0]), hipMemcpyHostToDevice, c->stream));
+  }
+  // the host vectors die here: make sure the copies have consumed them
+  FE_HIP(hipStreamSynchronize(c->stream));
+  return FE_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+bool variant_ok(int v, int dtype) {
+  if (v < 0 || v >= (int)variants().size()) return false;
+  return variants()[v].dtype_mask & (dtype == FE_F64 ? 2 : 1);
+}
+
+// Launch geometry of the chosen variant.
+struct Geometry {
+  int ntx, nty, nzc, lz, per_inst;
+};
+
+// Blocks of the step sweep of `variant` that one compute unit holds at once.
+int block_slots(const fe_ctx* c, int variant) {
+  const Variant& v = variants()[variant];
+  const void* fn = c->grid.dtype == FE_F32 ? (const void*)v.k32.step : (const void*)v.k64.step;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, v.nt, 0) != hipSuccess || n < 1) n = 1;
+  return n;
+}
+
+Geometry geometry(const fe_ctx* c, int variant, int lz_req) {
+  const Variant& v = variants()[variant];
+  Geometry g;
+  g.ntx = ceil_div(c->grid.nx, v.tx);
+  g.nty = ceil_div(c->grid.ny, v.ty);
+  int lz = lz_req;
+  if (lz <= 0) {
+    // the longest power-of-two chunk (fewest recomputed boundary planes) that
+    // still fills every resident block slot of the device, and at least 4 planes
+    const double cols = (double)g.ntx * g.nty * c->grid.batch;
+    const double slots = (double)c->num_cu * block_slots(c, variant);
+    lz = 4;
+    while (2 * lz <= c->grid.nz && cols * ceil_div(c->grid.nz, 2 * lz) >= slots) lz *= 2;
+  }
+  lz = std::min(std::max(lz, 1), c->grid.nz);
+  g.lz = lz;
+  g.nzc = ceil_div(c->grid.nz, lz);
+  g.per_inst = g.ntx * g.nty * g.nzc;
+  return g;
+}
+
+bool has_sp(int v, int dtype) {
+  const Variant& x = variants()[v];
+  return dtype == FE_F32 ? x.k32sp.grad != nullptr : x.k64sp.grad != nullptr;
+}
+
+bool has_box(int v, int dtype) {
+  const Variant& x = variants()[v];
+  return dtype == FE_F32 ? x.k32box != nullptr : x.k64box != nullptr;
+}
+
+// The variant a sweep launches: the chosen one, unless a coefficient field is
+// in use and that variant has no coefficient-field kernels; then the first
+// one that has them and whose tile the grid fills.
+int sweep_variant(const fe_ctx* c) {
+  auto ok = [&](int v) {
+    return (!c->use_cfield || has_sp(v, c->grid.dtype)) && (!c->use_box || has_box(v, c->grid.dtype));
+  };
+  if (ok(c->variant)) return c->variant;
+  int last = c->variant;
+  for (int v = 0; v < (int)variants().size(); ++v) {
+    if (!variant_ok(v, c->grid.dtype) || !ok(v)) continue;
+    const Variant& x = variants()[v];
+    if (x.tx <= std::max(c->grid.nx, 8) && x.ty <= std::max(c->grid.ny, 8)) return v;
+    last = v;
+  }
+  return last;
+}
+
+int fields_in_use(const fe_ctx* c) { return (c->use_cfield ? 1 : 0) | (c->use_mfield ? 2 : 0); }
+
+int default_variant(const fe_grid& g) {
+  const int dt = g.dtype;
+  // variants are listed best-first for large grids: take the first whose tile
+  // the grid fills
+  for (int v = 0; v < (int)variants().size(); ++v) {
+    if (!variant_ok(v, dt)) continue;
+    const Variant& x = variants()[v];
+    if (x.tx <= std::max(g.nx, 8) && x.ty <= std::max(g.ny, 8)) return v;
+  }
+  for (int v = (int)variants().size() - 1; v >= 0; --v)
+    if (variant_ok(v, dt)) return v;
+  return 0;
+}
+
+// kind: -1 energy only, else a fe::SweepMode. One launch computes the sweep and
+// its per-instance sums: energy_dev[b] and, for steps, shift_out[b].
+template <typename T>
+int launch_sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, const double* shift_in,
+                 double* shift_out, double* energy_dev, const StepRule& rule) {
+  const int vi = sweep_variant(c);
+  const Geometry geo = geometry(c, vi, c->lz);
+  if ((size_t)geo.per_inst > c->max_blocks) return set_error(FE_EINVAL, "internal: partials workspace too small");
+  const Variant& v = variants()[vi];
+  const Kernels<T>& k = kernels_of<T>(v, c->use_cfield);
+  fe::SweepArgs<T> a;
+  a.src = static_cast<const T*>(src);
+  a.dst = static_cast<T*>(dst);
+  a.prm = static_cast<const fe::InstParams<T>*>(c->d_prm);
+  a.shift_in = shift_in;
+  a.partials = c->d_partials;
+  a.counters = c->d_counters;
+  a.energy = energy_dev;
+  a.mass = c->d_mass;
+  a.shift_out = shift_out;
+  a.inv_nvox = 1.0 / ((double)c->grid.nx * c->grid.ny * c->grid.nz);
+  a.k = grid_consts<T>(c->grid.h);
+  a.m1 = static_cast<T*>(c->d_m1);
+  a.m2 = static_cast<T*>(c->d_m2);
+  a.adam_t = c->d_adam_t;
+  a.cfield = c->use_cfield ? static_cast<const T*>(c->d_cfield) : nullptr;
+  a.tau = T(rule.tau);
+  a.beta1 = T(rule.beta1);
+  a.beta2 = T(rule.beta2);
+  a.adam_eps = T(rule.adam_eps);
+  a.nx = c->grid.nx;
+  a.ny = c->grid.ny;
+  a.nz = c->grid.nz;
+  a.ntx = geo.ntx;
+  a.nty = geo.nty;
+  a.nzc = geo.nzc;
+  a.lz = geo.lz;
+  a.batch = c->grid.batch;
+  const dim3 grid((unsigned)(geo.per_inst * c->grid.batch));
+  const dim3 block((unsigned)v.nt);
+  SweepFn<T> fn = kind < 0 ? k.energy
+                 : kind == fe::kGrad ? k.grad
+                 : kind == fe::kStepGD ? k.step : k.adam;
+  if (c->use_box) {
+    if (kind != fe::kGrad || c->use_cfield) return set_error(FE_EINVAL, "internal: box sweeps are gradient-only");
+    fn = box_kernel_of<T>(v);
+    for (int i = 0; i < 3; ++i) {
+      a.box_lo[i] = c->box_lo[i];
+      a.box_hi[i] = c->box_hi[i];
+    }
+  }
+  hipLaunchKernelGGL(fn, grid, block, 0, s, a);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+int sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, const double* shift_in,
+          double* shift_out, double* energy_dev, const StepRule& rule) {
+  return c->grid.dtype == FE_F32
+             ? launch_sweep<float>(c, s, kind, src, dst, shift_in, shift_out, energy_dev, rule)
+             : launch_sweep<double>(c, s, kind, src, dst, shift_in, shift_out, energy_dev, rule);
+}
+
+int copy_energy_out(fe_ctx* c, double* energy) {
+  if (!energy) return FE_OK;
+  FE_HIP(hipMemcpyAsync(energy, c->d_energy, sizeof(double) * c->grid.batch, hipMemcpyDeviceToHost, c->stream));
+  FE_HIP(hipStreamSynchronize(c->stream));
+  for (int b = 0; b < c->grid.batch; ++b)
+    if (!std::isfinite(energy[b])) return set_error(FE_ENONFINITE, "energy[%d] is not finite", b);
+  return FE_OK;
+}
+
+void drop_graphs(fe_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
+// One descent step: src (+ shift_in) -> dst, then shift_out = mass - mean(dst).
+int step_once(fe_ctx* c, hipStream_t s, const void* src, void* dst, const double* shift_in, double* shift_out,
+              const StepRule& rule) {
+  return sweep(c, s, rule.mode, src, dst, shift_in, shift_out, c->d_energy, rule);
+}
+
+int adam_reset_launch(fe_ctx* c) {
+  const size_t n = field_elems(c->grid);
+  const int nblk = (int)std::min<size_t>((n + 255) / 256, 65536);
+  if (c->grid.dtype == FE_F32)
+    hipLaunchKernelGGL(fe::adam_reset<float>, dim3(nblk), dim3(256), 0, c->stream, (float*)c->d_m1,
+                       (float*)c->d_m2, n, c->d_adam_t);
+  else
+    hipLaunchKernelGGL(fe::adam_reset<double>, dim3(nblk), dim3(256), 0, c->stream, (double*)c->d_m1,
+                       (double*)c->d_m2, n, c->d_adam_t);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int nsteps, double* energy) {
+  if (!u) return set_error(FE_EINVAL, "u is NULL");
+  if (!mass) return set_error(FE_EINVAL, "mass is NULL");
+  if (nsteps < 0) return set_error(FE_EINVAL, "nsteps must be >= 0");
+  for (int b = 0; b < c->grid.batch; ++b)
+    if (!std::isfinite(mass[b])) return set_error(FE_EINVAL, "mass[%d] is not finite", b);
+  if (nsteps == 0) return FE_OK;
+  DeviceGuard dg(c->device);
+  const int B = c->grid.batch;
+  if (!c->d_pingpong) {
+    if (hipMalloc(&c->d_pingpong, field_elems(c->grid) * elem_size(c->grid)) != hipSuccess) {
+      c->d_pingpong = nullptr;
+      return set_error(FE_ENOMEM, "ping-pong field allocation failed");
+    }
+  }
+  FE_HIP(hipMemcpyAsync(c->d_mass, mass, sizeof(double) * B, hipMemcpyHostToDevice, c->stream));
+  double* s0 = c->d_shift;        // shift of the ping-pong field
+  double* s1 = c->d_shift + B;    // shift of u
+  hipLaunchKernelGGL(fe::fill_f64, dim3(ceil_div(B, 64)), dim3(64), 0, c->stream, s1, B, 0.0);
+  FE_HIP(hipGetLastError());
+  void* A = c->d_pingpong;
+
+  // pairs of steps u -> A -> u: whole blocks of kGraphPairs pairs are replayed
+  // from one captured graph (the same graph for any nsteps), the rest launch
+  // directly
+  const int npairs = nsteps / 2;
+  const int gpairs = npairs >= kGraphPairs ? kGraphPairs : 0;
+  for (int i = 0; i < (gpairs ? npairs % gpairs : npairs); ++i) {
+    int rc = step_once(c, c->stream, u, A, s1, s0, rule);
+    if (rc == FE_OK) rc = step_once(c, c->stream, A, u, s0, s1, rule);
+    if (rc) return rc;
+  }
+  if (gpairs > 0) {
+    GraphKey key{u,      rule.mode,           rule.tau, rule.beta1,     rule.beta2, rule.adam_eps, 0.0,
+                 gpairs, sweep_variant(c), c->lz,    fields_in_use(c)};
+    auto it = c->graphs.find(key);
+    hipGraphExec_t exec = nullptr;
+    if (it == c->graphs.end()) {
+      hipGraph_t graph = nullptr;
+      FE_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      int rc = FE_OK;
+      for (int i = 0; i < gpairs && rc == FE_OK; ++i) {
+        rc = step_once(c, c->cap_stream, u, A, s1, s0, rule);
+        if (rc == FE_OK) rc = step_once(c, c->cap_stream, A, u, s0, s1, rule);
+      }
+      hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
+      if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (ec != hipSuccess) return set_error(FE_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+      hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) return set_error(FE_EHIP, "graph instantiate failed: %s", hipGetErrorString(ei));
+      if (c->graphs.size() > 16) drop_graphs(c);
+      c->graphs[key] = exec;
+    } else {
+      exec = it->second;
+    }
+    for (int r = 0; r < npairs / gpairs; ++r) FE_HIP(hipGraphLaunch(exec, c->stream));
+  }
+  const size_t per_inst = (size_t)c->grid.nx * c->grid.ny * c->grid.nz;
+  const int nblk = (int)std::min<size_t>((field_elems(c->grid) + 255) / 256, 65536);
+  const void* last = u;
+  const double* shift = s1;
+  if (nsteps % 2) {
+    int rc = step_once(c, c->stream, u, A, s1, s0, rule);
+    if (rc) return rc;
+    last = A;
+    shift = s0;
+  }
+  if (c->grid.dtype == FE_F32)
+    hipLaunchKernelGGL(fe::add_shift<float>, dim3(nblk), dim3(256), 0, c->stream, (const float*)last, (float*)u,
+                       shift, per_inst, B);
+  else
+    hipLaunchKernelGGL(fe::add_shift<double>, dim3(nblk), dim3(256), 0, c->stream, (const double*)last,
+                       (double*)u, shift, per_inst, B);
+  FE_HIP(hipGetLastError());
+  return copy_energy_out(c, energy);
+}
+
+}  // namespace
+
+extern "C" {
+
+int fe_create(const fe_grid* grid, const double* eps, const double* p_coeffs, void* stream, fe_ctx** out) {
+  g_last_error.clear();
+  if (!out) return set_error(FE_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  rc = check_params(grid->batch, eps, p_coeffs);
+  if (rc) return rc;
+
+  fe_ctx* c = new (std::nothrow) fe_ctx();
+  if (!c) return set_error(FE_ENOMEM, "host allocation failed");
+  c->grid = *grid;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->eps.assign(eps, eps + grid->batch);
+  c->coeffs.assign(p_coeffs, p_coeffs + 6 * grid->batch);
+  c->mu.assign(grid->batch, 0.0);
+  c->theta.assign(3 * grid->batch, 0.0);
+  c->variant = default_variant(*grid);
+  c->lz = 0;
+
+  auto fail = [&](int code) {
+    fe_destroy(c);
+    return code;
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) return fail(set_error(FE_EHIP, "hipGetDevice failed"));
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && ncu > 0)
+      c->num_cu = ncu;
+  }
+  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return fail(set_error(FE_EHIP, "hipStreamCreateWithFlags failed"));
+
+  // partials workspace: the largest per-instance block count of any variant at z chunk 1
+  size_t mb = 0;
+  for (int v = 0; v < (int)variants().size(); ++v) {
+    if (!variant_ok(v, grid->dtype)) continue;
+    const Variant& x = variants()[v];
+    mb = std::max(mb, (size_t)ceil_div(grid->nx, x.tx) * ceil_div(grid->ny, x.ty) * grid->nz);
+  }
+  c->max_blocks = mb;
+  const size_t prm_bytes = grid->dtype == FE_F32 ? sizeof(fe::InstParams<float>) : sizeof(fe::InstParams<double>);
+  if (hipMalloc(&c->d_prm, prm_bytes * grid->batch) != hipSuccess ||
+      hipMalloc((void**)&c->d_partials, sizeof(double) * 2 * mb * grid->batch) != hipSuccess ||
+      hipMalloc((void**)&c->d_energy, sizeof(double) * grid->batch) != hipSuccess ||
+      hipMalloc((void**)&c->d_mass, sizeof(double) * grid->batch) != hipSuccess ||
+      hipMalloc((void**)&c->d_shift, sizeof(double) * 2 * grid->batch) != hipSuccess ||
+      hipMalloc((void**)&c->d_counters, sizeof(int) * (grid->batch + 1)) != hipSuccess)
+    return fail(set_error(FE_ENOMEM, "device workspace allocation failed"));
+  hipLaunchKernelGGL(fe::fill_i32, dim3(ceil_div(grid->batch + 1, 64)), dim3(64), 0, c->stream, c->d_counters,
+                     grid->batch + 1, 0);
+  if (hipGetLastError() != hipSuccess) return fail(set_error(FE_EHIP, "counter initialisation failed"));
+  rc = upload_params(c);
+  if (rc) return fail(rc);
+  *out = c;
+  return FE_OK;
+}
+
+int fe_set_params(fe_ctx* c, const double* eps, const double* p_coeffs) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  int rc = check_params(c->grid.batch, eps, p_coeffs);
+  if (rc) return rc;
+  DeviceGuard dg(c->device);
+  c->eps.assign(eps, eps + c->grid.batch);
+  c->coeffs.assign(p_coeffs, p_coeffs + 6 * c->grid.batch);
+  c->use_cfield = false;   // its scaling depends on eps: the caller sets it again
+  return upload_params(c);
+}
+
+int fe_set_orientation(fe_ctx* c, const double* mu, const double* theta) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!mu || !theta) return set_error(FE_EINVAL, "mu and theta must not be NULL");
+  for (int b = 0; b < c->grid.batch; ++b) {
+    if (!std::isfinite(mu[b])) return set_error(FE_EINVAL, "mu[%d] is not finite", b);
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(theta[3 * b + k])) return set_error(FE_EINVAL, "theta[%d] is not finite", b);
+  }
+  DeviceGuard dg(c->device);
+  c->mu.assign(mu, mu + c->grid.batch);
+  c->theta.assign(theta, theta + 3 * c->grid.batch);
+  return upload_params(c);
+}
+
+int fe_set_coeff_field(fe_ctx* c, const void* a_field) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!a_field) {
+    c->use_cfield = false;
+    return FE_OK;
+  }
+  DeviceGuard dg(c->device);
+  const size_t n = field_elems(c->grid);
+  if (!c->d_cfield && hipMalloc(&c->d_cfield, 6 * n * elem_size(c->grid)) != hipSuccess) {
+    c->d_cfield = nullptr;
+    return set_error(FE_ENOMEM, "coefficient field allocation failed");
+  }
+  const double h = c->grid.h, h3 = h * h * h;
+  const int B = c->grid.batch;
+  std::vector<double> k(3 * B);
+  for (int b = 0; b < B; ++b) {
+    const double e = c->eps[b], sc = e / (h * h);
+    k[3 * b] = h3 * sc * sc / (2.0 * e);
+    k[3 * b + 1] = h3 * sc / (4.0 * h);
+    k[3 * b + 2] = h3 * e / (4.0 * h * h);
+  }
+  double* d_k = nullptr;
+  if (hipMalloc((void**)&d_k, sizeof(double) * k.size()) != hipSuccess)
+    return set_error(FE_ENOMEM, "coefficient factor allocation failed");
+  hipError_t e1 = hipMemcpyAsync(d_k, k.data(), sizeof(double) * k.size(), hipMemcpyHostToDevice, c->stream);
+  const size_t vol = n / B;
+  const int nblk = (int)std::min<size_t>((n + 255) / 256, 65536);
+  if (e1 == hipSuccess) {
+    if (c->grid.dtype == FE_F32)
+      hipLaunchKernelGGL(fe::scale_coeff_field<float>, dim3(nblk), dim3(256), 0, c->stream,
+                         static_cast<const float*>(a_field), static_cast<float*>(c->d_cfield), vol, B,
+                         (const double*)d_k);
+    else
+      hipLaunchKernelGGL(fe::scale_coeff_field<double>, dim3(nblk), dim3(256), 0, c->stream,
+                         static_cast<const double*>(a_field), static_cast<double*>(c->d_cfield), vol, B,
+                         (const double*)d_k);
+    e1 = hipGetLastError();
+  }
+  // the factors (and the host vector) must outlive the conversion
+  const hipError_t e2 = hipStreamSynchronize(c->stream);
+  (void)hipFree(d_k);
+  if (e1 != hipSuccess) return set_error(FE_EHIP, "coefficient field conversion failed: %s", hipGetErrorString(e1));
+  if (e2 != hipSuccess) return set_error(FE_EHIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e2));
+  c->use_cfield = true;
+  return FE_OK;
+}
+
+int fe_set_mass_field(fe_ctx* c, const void* m_field) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!m_field) {
+    c->use_mfield = false;
+    return FE_OK;
+  }
+  DeviceGuard dg(c->device);
+  const size_t bytes = field_elems(c->grid) * elem_size(c->grid);
+  if (!c->d_mfield && hipMalloc(&c->d_mfield, bytes) != hipSuccess) {
+    c->d_mfield = nullptr;
+    return set_error(FE_ENOMEM, "mass field allocation failed");
+  }
+  FE_HIP(hipMemcpyAsync(c->d_mfield, m_field, bytes, hipMemcpyDeviceToDevice, c->stream));
+  c->use_mfield = true;
+  return FE_OK;
+}
+
+int fe_set_stream(fe_ctx* c, void* stream) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  c->stream = static_cast<hipStream_t>(stream);
+  return FE_OK;
+}
+
+int fe_energy_grad_async(fe_ctx* c, const void* u, void* g, double* energy_dev) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!u) return set_error(FE_EINVAL, "u is NULL");
+  if (g == u) return set_error(FE_EINVAL, "g must not alias u");
+  DeviceGuard dg(c->device);
+  const StepRule none{fe::kGrad, 0.0, 0.0, 0.0, 0.0};
+  return sweep(c, c->stream, g ? fe::kGrad : -1, u, g, nullptr, nullptr, energy_dev ? energy_dev : c->d_energy,
+               none);
+}
+
+int fe_energy(fe_ctx* c, const void* u, double* energy) {
+  int rc = fe_energy_grad_async(c, u, nullptr, c ? c->d_energy : nullptr);
+  if (rc) return rc;
+  DeviceGuard dg(c->device);
+  return copy_energy_out(c, energy);
+}
+
+int fe_energy_grad(fe_ctx* c, const void* u, void* g, double* energy) {
+  if (c && !g) return set_error(FE_EINVAL, "g is NULL (use fe_energy for the energy only)");
+  int rc = fe_energy_grad_async(c, u, g, c ? c->d_energy : nullptr);
+  if (rc) return rc;
+  DeviceGuard dg(c->device);
+  return copy_energy_out(c, energy);
+}
+
+int fe_step(fe_ctx* c, void* u, const double* mass, double tau, int nsteps, double* energy) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!(tau > 0.0) || !std::isfinite(tau)) return set_error(FE_EINVAL, "tau must be finite and > 0");
+  const StepRule rule{fe::kStepGD, tau, 0.0, 0.0, 0.0};
+  return run_steps(c, u, mass, rule, nsteps, energy);
+}
+
+int fe_step_adam(fe_ctx* c, void* u, const double* mass, double lr, double beta1, double beta2, double adam_eps,
+                 int nsteps, double* energy) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!(lr > 0.0) || !std::isfinite(lr)) return set_error(FE_EINVAL, "lr must be finite and > 0");
+  if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+    return set_error(FE_EINVAL, "beta1 and beta2 must lie in [0, 1)");
+  if (!(adam_eps > 0.0) || !std::isfinite(adam_eps)) return set_error(FE_EINVAL, "adam_eps must be finite and > 0");
+  if (!c->d_m1) {
+    DeviceGuard dg(c->device);
+    const size_t bytes = field_elems(c->grid) * elem_size(c->grid);
+    if (hipMalloc(&c->d_m1, bytes) != hipSuccess || hipMalloc(&c->d_m2, bytes) != hipSuccess ||
+        hipMalloc((void**)&c->d_adam_t, sizeof(int)) != hipSuccess) {
+      if (c->d_m1) (void)hipFree(c->d_m1);
+      if (c->d_m2) (void)hipFree(c->d_m2);
+      if (c->d_adam_t) (void)hipFree(c->d_adam_t);
+      c->d_m1 = c->d_m2 = nullptr;
+      c->d_adam_t = nullptr;
+      return set_error(FE_ENOMEM, "Adam moment allocation failed");
+    }
+    int rc = adam_reset_launch(c);
+    if (rc) return rc;
+  }
+  const StepRule rule{fe::kStepAdam, lr, beta1, beta2, adam_eps};
+  return run_steps(c, u, mass, rule, nsteps, energy);
+}
+
+int fe_adam_reset(fe_ctx* c) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!c->d_m1) return FE_OK;   // nothing allocated yet: the first fe_step_adam starts from zero
+  DeviceGuard dg(c->device);
+  return adam_reset_launch(c);
+}
+
+int fe_num_variants(void) { return (int)variants().size(); }
+
+int fe_variant_info(int variant, int* tile_x, int* tile_y, int* threads, int* dtype_mask) {
+  if (variant < 0 || variant >= (int)variants().size()) return set_error(FE_EINVAL, "no variant %d", variant);
+  const Variant& v = variants()[variant];
+  if (tile_x) *tile_x = v.tx;
+  if (tile_y) *tile_y = v.ty;
+  if (threads) *threads = v.nt;
+  if (dtype_mask) *dtype_mask = v.dtype_mask;
+  return FE_OK;
+}
+
+int fe_set_launch(fe_ctx* c, int variant, int z_chunk) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!variant_ok(variant, c->grid.dtype))
+    return set_error(FE_EINVAL, "variant %d does not exist or does not support this dtype", variant);
+  if (z_chunk < 0) return set_error(FE_EINVAL, "z_chunk must be >= 0");
+  c->variant = variant;
+  c->lz = z_chunk;
+  return FE_OK;
+}
+
+int fe_get_launch(const fe_ctx* c, int* variant, int* z_chunk) {
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (variant) *variant = c->variant;
+  if (z_chunk) *z_chunk = geometry(c, c->variant, c->lz).lz;
+  return FE_OK;
+}
+
+int fe_autotune(fe_ctx* c, const void* u, void* g, int iters, double* best_us) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!u || !g || u == g) return set_error(FE_EINVAL, "u and g must be distinct device fields");
+  if (iters < 1) return set_error(FE_EINVAL, "iters must be >= 1");
+  DeviceGuard dg(c->device);
+  const int keep_v = c->variant, keep_lz = c->lz;
+  hipEvent_t e0, e1;
+  FE_HIP(hipEventCreate(&e0));
+  FE_HIP(hipEventCreate(&e1));
+  double best = 1e300;
+  int best_v = keep_v, best_lz = keep_lz;
+  const int lzs[] = {4, 8, 16, 32, 64, 128};
+  int rc = FE_OK;
+  for (int v = 0; v < (int)variants().size() && rc == FE_OK; ++v) {
+    if (!variant_ok(v, c->grid.dtype)) continue;
+    const Variant& x = variants()[v];
+    if (x.tx > 2 * c->grid.nx || x.ty > 2 * c->grid.ny) continue;
+    for (int lz : lzs) {
+      if (lz > c->grid.nz) continue;
+      c->variant = v;
+      c->lz = lz;
+      rc = fe_energy_grad_async(c, u, g, nullptr);   // warm-up
+      if (rc) break;
+      if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = set_error(FE_EHIP, "hipEventRecord failed"); break; }
+      for (int i = 0; i < iters && rc == FE_OK; ++i) rc = fe_energy_grad_async(c, u, g, nullptr);
+      if (rc) break;
+      if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = set_error(FE_EHIP, "event timing failed");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const double us = 1000.0 * ms / iters;
+      if (us < best) {
+        best = us;
+        best_v = v;
+        best_lz = lz;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->variant = best_v;
+  c->lz = best_lz;
+  if (rc) return rc;
+  if (best_us) *best_us = best;
+  return FE_OK;
+}
+
+void fe_destroy(fe_ctx* c) {
+  if (!c) return;
+  DeviceGuard dg(c->device);
+  drop_graphs(c);
+  if (c->d_prm) (void)hipFree(c->d_prm);
+  if (c->d_partials) (void)hipFree(c->d_partials);
+  if (c->d_energy) (void)hipFree(c->d_energy);
+  if (c->d_mass) (void)hipFree(c->d_mass);
+  if (c->d_shift) (void)hipFree(c->d_shift);
+  if (c->d_counters) (void)hipFree(c->d_counters);
+  if (c->d_pingpong) (void)hipFree(c->d_pingpong);
+  if (c->d_m1) (void)hipFree(c->d_m1);
+  if (c->d_m2) (void)hipFree(c->d_m2);
+  if (c->d_adam_t) (void)hipFree(c->d_adam_t);
+  for (void* p : {c->d_w0, c->d_w1, c->d_am1, c->d_am2, (void*)c->d_flow_clk, (void*)c->d_diag, c->d_cfield,
+                  c->d_mfield})
+    if (p) (void)hipFree(p);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  delete c;
+}
+
+const char* fe_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
