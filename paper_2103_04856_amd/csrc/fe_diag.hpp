@@ -123,7 +123,7 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
       umin = fw.c < umin ? fw.c : umin;
       umax = fw.c > umax ? fw.c : umax;
       if (d.curv || d.hist) {
-        const T rs = rsqrt_t(fw.R) * d.inv_h;            // 1 / (h sqrt R)
+        const T rs = fw.rs * d.inv_h;                    // 1 / (h sqrt R)
         const T sq = fw.X > T(0) ? sqrt_t(fw.X) : T(0);
         const T k1 = (fw.tr + sq) * rs, k2 = (fw.tr - sq) * rs;
         if (d.curv) {

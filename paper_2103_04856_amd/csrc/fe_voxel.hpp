@@ -103,7 +103,7 @@ struct Forward {
   T oxy, oxz, oyz;              // o_ab
   T dxx, dyy, dzz;              // 2 m_aa - T~
   T tr, n2, X;                  // T~, N~, X~
-  T Q, sw, R, Rinv;             // |a|^2, lam W'(u) / R, R, 1/R
+  T Q, sw, R, Rinv, rs;         // |a|^2, lam W'(u) / R, R, 1/R, 1/sqrt(R)
 };
 
 // Adjoint of one voxel: derivatives of f~ with respect to the raw stencil
@@ -163,6 +163,7 @@ __device__ __forceinline__ Forward<T> forward_fp64(const Stencil19<T>& s, const 
   o.sw = T(sw);
   o.R = T(R);
   o.Rinv = T(Rinv);
+  o.rs = T(1.0 / __builtin_sqrt(R));
   return o;
 }
 
@@ -186,7 +187,8 @@ __device__ __forceinline__ Forward<float> forward_fp32(const Stencil19<float>& s
   const float axx = o.ax * o.ax, ayy = o.ay * o.ay, azz = o.az * o.az;
   o.Q = axx + ayy + azz;
   o.R = o.Q + k.reg;
-  o.Rinv = rcp_t(o.R);
+  o.rs = rsqrt_t(o.R);           // one reciprocal square root serves 1/R and rho
+  o.Rinv = o.rs * o.rs;
   o.sw = c * (p.lam * (c * c) - p.lam) * o.Rinv;
   const float sw4 = 4.0f * o.sw;
   o.mxx = o.sw * axx - bxx;
@@ -254,7 +256,7 @@ __device__ __forceinline__ T density_of(const Forward<T>& fw, const InstParams<T
   T P, sig;
   softplus_xi(fw.X, p, P, sig);
   const T S = P > T(0) ? P * rsqrt_t(P) : T(0);
-  const T rho = fw.R * rsqrt_t(fw.R);
+  const T rho = fw.R * fw.rs;
   T f = p.C1 * fw.n2 + fw.tr * (p.C2 * fw.tr + p.C3 * S + p.C4 * rho) + p.C5 * rho * S + p.C6 * fw.Q;
   if (p.Co != T(0)) {                              // eps mu (theta . g)^2 = Co (theta . a)^2 / h^3
     const T ta = p.thx * fw.ax + p.thy * fw.ay + p.thz * fw.az;
@@ -280,7 +282,7 @@ __device__ __forceinline__ T voxel_density_adjoint(const Stencil19<T>& s, Reload
   softplus_xi(fw.X, p, P, sig);
   const T rsP = P > T(0) ? rsqrt_t(P) : T(0);
   const T S = P * rsP;
-  const T rs = rsqrt_t(fw.R);
+  const T rs = fw.rs;
   const T rho = fw.R * rs;                         // 2h rho
 
   T f = p.C1 * fw.n2 + tr * (p.C2 * tr + p.C3 * S + p.C4 * rho) + p.C5 * rho * S + p.C6 * fw.Q;
