@@ -278,54 +278,8 @@ def cpu_baseline(n=256, budget_s=10.0, max_evals=3):
                 sample=f"{evals} FP64 energy+gradient evaluation(s) of the full 256^3 field ({dt:.1f} s)")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--tune", action="store_true",
-                    help="run the launch-shape autotuner first (default: the library's default shape)")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run one plain 64 MiB device copy (reference for HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
-              file=sys.stderr)
-        sys.exit(2)
-    if not torch.cuda.is_available():
-        print("no ROCm device visible", file=sys.stderr)
-        sys.exit(1)
-    fe.lib()
-
-    if args.copy_probe:
-        a = torch.empty(16 * 2 ** 20, dtype=torch.float32, device="cuda").fill_(1.0)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-
-    n = 256
-    vox = n ** 3
-    log(f"device {torch.cuda.get_device_name(0)}; 256^3 FP32 step loop ...")
-    ctx, u, ms_step, ms_grad, ms_diag = bench_single(n, args.steps, args.warmup, args.tune)
-    variant, zc = ctx.get_launch()
-    log(f"  {ms_step * 1e3:.1f} us/step, energy+grad sweep {ms_grad * 1e3:.1f} us, diagnostics {ms_diag * 1e3:.1f} us")
-    value = vox / (ms_step * 1e-3)
-
-    extra = {}
-    if not args.no_batched:
-        log("16 x 128^3 batched vs 16 single-instance calls ...")
-        ms_b, ms_s = bench_batched(128, 16, max(args.steps // 2, 10), args.warmup, args.tune)
-        vb = 16 * 128 ** 3
-        extra["batched_16x128"] = {
-            "value": vb / (ms_b * 1e-3), "ms_per_step": ms_b,
-            "sequential_singles_value": vb / (ms_s * 1e-3), "sequential_singles_ms_per_step": ms_s,
-            "unit": "voxel energy+gradient evals/s", "step_rule": "mass-projected Adam, lr 1e-3"}
-        log(f"  batched {ms_b * 1e3:.1f} us/step, singles {ms_s * 1e3:.1f} us/step")
-
+def other_workloads(args, extra, n, vox):
+    """Algorithm 1, the coefficient-field workloads and Algorithm 2, into `extra`."""
     log("Algorithm 1 (H^-1 flow) at 100^3 ...")
     ms_h, G0, G1, done = bench_hminus(100, max(args.steps, 64))
     extra["hminus_flow_100"] = {
@@ -365,6 +319,60 @@ def main():
                   "20 iterations/step x 24 steps, from a tanh torus R=0.24 r=0.14, FP32",
         "paper_context": "Sec. 4.2 reports F/sigma within 0.4% of 8 pi^2 and the ratio within 3% of 1/sqrt 2"}
     log(f"  {dt_t:.2f} s for {it_t} iterations; F/(8 pi^2 sigma) {f_t:.4f}, r/R {ratio_t:.4f}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--main-only", action="store_true",
+                    help="only the 256^3 workload (step, sweep, diagnostics): for counter runs")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the launch-shape autotuner first (default: the library's default shape)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 64 MiB device copy (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    if not torch.cuda.is_available():
+        print("no ROCm device visible", file=sys.stderr)
+        sys.exit(1)
+    fe.lib()
+
+    if args.copy_probe:
+        a = torch.empty(16 * 2 ** 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    n = 256
+    vox = n ** 3
+    log(f"device {torch.cuda.get_device_name(0)}; 256^3 FP32 step loop ...")
+    ctx, u, ms_step, ms_grad, ms_diag = bench_single(n, args.steps, args.warmup, args.tune)
+    variant, zc = ctx.get_launch()
+    log(f"  {ms_step * 1e3:.1f} us/step, energy+grad sweep {ms_grad * 1e3:.1f} us, diagnostics {ms_diag * 1e3:.1f} us")
+    value = vox / (ms_step * 1e-3)
+
+    extra = {}
+    if not args.no_batched and not args.main_only:
+        log("16 x 128^3 batched vs 16 single-instance calls ...")
+        ms_b, ms_s = bench_batched(128, 16, max(args.steps // 2, 10), args.warmup, args.tune)
+        vb = 16 * 128 ** 3
+        extra["batched_16x128"] = {
+            "value": vb / (ms_b * 1e-3), "ms_per_step": ms_b,
+            "sequential_singles_value": vb / (ms_s * 1e-3), "sequential_singles_ms_per_step": ms_s,
+            "unit": "voxel energy+gradient evals/s", "step_rule": "mass-projected Adam, lr 1e-3"}
+        log(f"  batched {ms_b * 1e3:.1f} us/step, singles {ms_s * 1e3:.1f} us/step")
+
+    if not args.main_only:
+        other_workloads(args, extra, n, vox)
 
     step_us = ms_step * 1e3
     bytes_step = BYTES_PER_VOXEL_STEP * vox
