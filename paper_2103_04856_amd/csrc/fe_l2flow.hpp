@@ -22,16 +22,16 @@ struct PadBox {
 
 __device__ __forceinline__ int clamp_to(int v, int lo, int hi) { return v < lo ? lo : (v >= hi ? hi - 1 : v); }
 
+// Launch shape of the padding kernels: one thread per sample of a row of 256,
+// grid (ceil(nx/256), ny, nz).
 // Fill every pad sample with the nearest box voxel (reads box voxels only).
 template <typename T>
 __global__ __launch_bounds__(256) void pad_replicate(T* __restrict__ f, PadBox b) {
-  const size_t n = (size_t)b.nx * b.ny * b.nz;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const int x = (int)(i % b.nx), y = (int)((i / b.nx) % b.ny), z = (int)(i / ((size_t)b.nx * b.ny));
-    const int cx = clamp_to(x, b.lo[0], b.hi[0]), cy = clamp_to(y, b.lo[1], b.hi[1]),
-              cz = clamp_to(z, b.lo[2], b.hi[2]);
-    if (cx != x || cy != y || cz != z) f[i] = f[((size_t)cz * b.ny + cy) * b.nx + cx];
-  }
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= b.nx) return;
+  const int cx = clamp_to(x, b.lo[0], b.hi[0]), cy = clamp_to(y, b.lo[1], b.hi[1]), cz = clamp_to(z, b.lo[2], b.hi[2]);
+  if (cx != x || cy != y || cz != z)
+    f[((size_t)z * b.ny + y) * b.nx + x] = f[((size_t)cz * b.ny + cy) * b.nx + cx];
 }
 
 // out = P^T g: every box voxel gathers the pad samples that copy it (on a box
@@ -39,45 +39,61 @@ __global__ __launch_bounds__(256) void pad_replicate(T* __restrict__ f, PadBox b
 // samples of out are zero. g and out must differ.
 template <typename T>
 __global__ __launch_bounds__(256) void fold_pads(const T* __restrict__ g, T* __restrict__ out, PadBox b) {
-  const size_t n = (size_t)b.nx * b.ny * b.nz;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const int x = (int)(i % b.nx), y = (int)((i / b.nx) % b.ny), z = (int)(i / ((size_t)b.nx * b.ny));
-    const bool in = x >= b.lo[0] && x < b.hi[0] && y >= b.lo[1] && y < b.hi[1] && z >= b.lo[2] && z < b.hi[2];
-    if (!in) {
-      out[i] = T(0);
-      continue;
-    }
-    const int x0 = x == b.lo[0] ? 0 : x, x1 = x == b.hi[0] - 1 ? b.nx - 1 : x;
-    const int y0 = y == b.lo[1] ? 0 : y, y1 = y == b.hi[1] - 1 ? b.ny - 1 : y;
-    const int z0 = z == b.lo[2] ? 0 : z, z1 = z == b.hi[2] - 1 ? b.nz - 1 : z;
-    if (x0 == x1 && y0 == y1 && z0 == z1) {
-      out[i] = g[i];
-      continue;
-    }
-    T acc = T(0);
-    for (int zz = z0; zz <= z1; ++zz)
-      for (int yy = y0; yy <= y1; ++yy)
-        for (int xx = x0; xx <= x1; ++xx) acc += g[((size_t)zz * b.ny + yy) * b.nx + xx];
-    out[i] = acc;
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= b.nx) return;
+  const size_t i = ((size_t)z * b.ny + y) * b.nx + x;
+  const bool in = x >= b.lo[0] && x < b.hi[0] && y >= b.lo[1] && y < b.hi[1] && z >= b.lo[2] && z < b.hi[2];
+  if (!in) {
+    out[i] = T(0);
+    return;
   }
+  const int x0 = x == b.lo[0] ? 0 : x, x1 = x == b.hi[0] - 1 ? b.nx - 1 : x;
+  const int y0 = y == b.lo[1] ? 0 : y, y1 = y == b.hi[1] - 1 ? b.ny - 1 : y;
+  const int z0 = z == b.lo[2] ? 0 : z, z1 = z == b.hi[2] - 1 ? b.nz - 1 : z;
+  if (x0 == x1 && y0 == y1 && z0 == z1) {
+    out[i] = g[i];
+    return;
+  }
+  T acc = T(0);
+  for (int zz = z0; zz <= z1; ++zz)
+    for (int yy = y0; yy <= y1; ++yy)
+      for (int xx = x0; xx <= x1; ++xx) acc += g[((size_t)zz * b.ny + yy) * b.nx + xx];
+  out[i] = acc;
 }
 
 // ---- vector operations of the optimiser (FP64 reductions, fixed order) ----
 
-constexpr int kVecBlocks = 512;
+constexpr int kVecBlocks = 1024;
+
+template <int OP>
+__device__ __forceinline__ double vec_combine(double acc, double v) {
+  return OP == 2 ? fmax(acc, v) : acc + v;
+}
 
 // partial[k] for block k: sum of a*b (OP 0), |a| (OP 1), or max |a| (OP 2).
+// Each thread keeps four independent accumulators over four strided elements
+// per round, so four loads are in flight; the fixed grid and fixed order keep
+// the result deterministic.
 template <typename T, int OP>
 __global__ __launch_bounds__(256) void vec_reduce(const T* __restrict__ a, const T* __restrict__ b, size_t n,
                                                   double* __restrict__ partial) {
   __shared__ double s[256];
-  double acc = 0.0;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    if (OP == 0) acc += double(a[i]) * double(b[i]);
-    else if (OP == 1) acc += fabs(double(a[i]));
-    else acc = fmax(acc, fabs(double(a[i])));
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const size_t j = i + k * stride;
+      const double v = OP == 0 ? double(a[j]) * double(b[j]) : fabs(double(a[j]));
+      acc[k] = vec_combine<OP>(acc[k], v);
+    }
   }
-  s[threadIdx.x] = acc;
+  for (; i < n; i += stride) {
+    const double v = OP == 0 ? double(a[i]) * double(b[i]) : fabs(double(a[i]));
+    acc[0] = vec_combine<OP>(acc[0], v);
+  }
+  s[threadIdx.x] = vec_combine<OP>(vec_combine<OP>(acc[0], acc[1]), vec_combine<OP>(acc[2], acc[3]));
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) s[threadIdx.x] = OP == 2 ? fmax(s[threadIdx.x], s[threadIdx.x + w]) : s[threadIdx.x] + s[threadIdx.x + w];

@@ -114,28 +114,28 @@ void l2_blur(fe_l2* L, const T* in, T* tmp1, T* tmp2, T* out) {
 template <typename T>
 int l2_eval_dev(fe_l2* L) {
   hipStream_t s = L->ctx->stream;
-  const int nb = l2_launch_1d(L->n);
+  const dim3 pg((L->box.nx + 255) / 256, L->box.ny, L->box.nz);   // the padding kernels' grid
   T* x = static_cast<T*>(L->x);
   T* g = static_cast<T*>(L->g);
   T* w0 = static_cast<T*>(L->w0);
   T* w1 = static_cast<T*>(L->w1);
   T* w2 = static_cast<T*>(L->w2);
-  hipLaunchKernelGGL(fe::pad_replicate<T>, dim3(nb), dim3(256), 0, s, x, L->box);
+  hipLaunchKernelGGL(fe::pad_replicate<T>, pg, dim3(256), 0, s, x, L->box);
   const T* ub = x;
   if (L->r > 0) {
     l2_blur<T>(L, x, w0, w1, w2);             // w2 = k * x
-    hipLaunchKernelGGL(fe::pad_replicate<T>, dim3(nb), dim3(256), 0, s, w2, L->box);
+    hipLaunchKernelGGL(fe::pad_replicate<T>, pg, dim3(256), 0, s, w2, L->box);
     ub = w2;
   }
   const StepRule none{fe::kGrad, 0.0, 0.0, 0.0, 0.0};
   int rc = sweep(L->ctx, s, fe::kGrad, ub, w0, nullptr, nullptr, L->ctx->d_energy, none);   // w0 = g_ext
   if (rc) return rc;
   if (L->r > 0) {
-    hipLaunchKernelGGL(fe::fold_pads<T>, dim3(nb), dim3(256), 0, s, (const T*)w0, w1, L->box);   // w1 = gb
+    hipLaunchKernelGGL(fe::fold_pads<T>, pg, dim3(256), 0, s, (const T*)w0, w1, L->box);   // w1 = gb
     l2_blur<T>(L, w1, w0, w2, w1);           // w1 = k * gb (zero-extended)
-    hipLaunchKernelGGL(fe::fold_pads<T>, dim3(nb), dim3(256), 0, s, (const T*)w1, g, L->box);
+    hipLaunchKernelGGL(fe::fold_pads<T>, pg, dim3(256), 0, s, (const T*)w1, g, L->box);
   } else {
-    hipLaunchKernelGGL(fe::fold_pads<T>, dim3(nb), dim3(256), 0, s, (const T*)w0, g, L->box);
+    hipLaunchKernelGGL(fe::fold_pads<T>, pg, dim3(256), 0, s, (const T*)w0, g, L->box);
   }
   FE_HIP(hipGetLastError());
   FE_HIP(hipMemcpyAsync(L->d_red + fe::kVecBlocks + kSlotE, L->ctx->d_energy, sizeof(double),
