@@ -1,0 +1,57 @@
+"""Launch shapes: the gradient does not depend on the tile, the block size or the
+z chunk beyond rounding (every voxel's arithmetic and the gather's order are the
+same; the compiler may contract multiply-adds differently in each
+instantiation), the energy differs only in its summation order; the autotuner
+keeps what it picks and its results."""
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2103_04856_amd import fe, inputs
+
+from gpu_helpers import ALL_TERMS, log, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_gradient_is_independent_of_the_launch(dtype):
+    shape = (28, 36, 40)
+    u = to_dev(np.random.default_rng(3).uniform(-1, 1, size=shape), dtype)
+    ctx = fe.FeContext((1,) + shape, 1 / 40, 2 / 40, ALL_TERMS, dtype=dtype)
+    mask = 1 if dtype == torch.float32 else 2
+    ref = None
+    worst = 0.0
+    gtol, etol = (2e-6, 1e-6) if dtype == torch.float32 else (1e-13, 1e-12)
+    for vi, v in enumerate(fe.variants()):
+        if not v[3] & mask:
+            continue
+        for zc in (0, 3, 7):
+            ctx.set_launch(vi, zc)
+            E, g = ctx.energy_grad(u)
+            if ref is None:
+                ref = (E[0].item(), g.clone())
+                continue
+            d = (torch.linalg.vector_norm((g - ref[1]).double()) / torch.linalg.vector_norm(ref[1].double())).item()
+            worst = max(worst, d)
+            assert d <= gtol, (v[:3], zc, d)
+            assert abs(E[0].item() - ref[0]) <= etol * abs(ref[0]), (v[:3], zc)
+    log(f"  {dtype}: largest gradient difference between launch shapes {worst:.1e}")
+
+
+def test_autotune_keeps_its_choice_and_the_results():
+    n = 48
+    u = to_dev(inputs.uniform_noise(n, 9), torch.float32)
+    ctx = fe.FeContext((1, n, n, n), 1 / n, 2 / n, ALL_TERMS, dtype=torch.float32)
+    E0, g0 = ctx.energy_grad(u)
+    v, z, us = ctx.autotune(u, iters=2)
+    log(f"  autotune 48^3: variant {fe.variants()[v][:3]} z chunk {z}: {us:.1f} us")
+    assert us > 0 and ctx.get_launch() == (v, z)
+    E1, g1 = ctx.energy_grad(u)
+    d = (torch.linalg.vector_norm((g1 - g0).double()) / torch.linalg.vector_norm(g0.double())).item()
+    assert d <= 2e-6
+    assert abs(E1[0].item() - E0[0].item()) <= 1e-6 * abs(E0[0].item())
+    # and it is reproducible at that launch
+    E2, g2 = ctx.energy_grad(u)
+    assert torch.equal(g2, g1) and E2[0].item() == E1[0].item()
