@@ -9,8 +9,9 @@
 //
 // One iteration is: blur_x<DIV> (div A + m0, blurred along x), blur_axis<1>,
 // blur_axis<2>, the sweep, blur_x of dF/du, blur_axis<1>, blur_axis<2>,
-// adam_vector_field. Without blur (r = 0) only the first kernel, the sweep and
-// the Adam kernel run. Every kernel is a 64-wide row of x per wave, so loads
+// adam_vector_field; for the radii 4 and 8 the blur of dF/du runs blur_xy
+// (x and y in one pass) and blur_axis<2>. Without blur (r = 0) only the first kernel, the sweep and the
+// Adam kernel run. Every kernel is a 64-wide row of x per wave, so loads
 // and stores are coalesced; the blur halos are staged in LDS.
 #pragma once
 
@@ -188,6 +189,92 @@ __global__ __launch_bounds__(256) void blur_axis(const T* __restrict__ in, T* __
     for (int j = 0; j <= 2 * radius_bound<R>(); ++j)
       if (R >= 0 || j <= 2 * r) acc += k.w[j] * v[o + j];
     out[base + (size_t)(p0 + o) * stride] = acc;
+  }
+}
+
+// Blur along x and then y in one pass, for the fixed radii R (> 0): a block
+// owns 64 x-values by kXYRows y-values of one plane. The tile and its halo of
+// R in x and y are staged in LDS, blurred along x into a second LDS array over
+// all rows of the halo, then along y. Both blurs run from register windows: in
+// the x pass a thread forms four consecutive outputs of a row from 4 + 2R
+// staged values, in the y pass four consecutive outputs of a column. The
+// result equals blur_x followed by blur_axis<1> (each output is formed by the
+// same sums in the same order). Block (64, 8); grid (ceil(nx/64),
+// ceil(ny/kXYRows), nz * batch).
+constexpr int kXYRows = 32;
+
+template <typename T, int R>
+__global__ __launch_bounds__(512) void blur_xy(const T* __restrict__ in, T* __restrict__ out, FieldDims d,
+                                               BlurTaps<T> k) {
+  static_assert(R > 0 && 2 * R <= 64 && R % 2 == 0, "blur_xy needs a fixed even radius");
+  constexpr int NT = 512;
+  constexpr int W = 64 + 2 * R, H = kXYRows + 2 * R;
+  constexpr int OUT = 4;                        // outputs per thread and pass
+  static_assert(kXYRows == OUT * (NT / 64), "one y window per thread");
+  __shared__ T s_in[H][W];
+  __shared__ T s_mid[H][64];
+  const int tid = threadIdx.y * 64 + threadIdx.x;
+  const int z = blockIdx.z % d.nz, b = blockIdx.z / d.nz;
+  const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kXYRows;
+  const size_t plane = (size_t)d.nx * d.ny, vol = plane * d.nz;
+  const T* src = in + (size_t)b * vol + (size_t)z * plane;
+  // Stage the tile with its halo: wave w takes the rows w, w + 8, ... (their y
+  // is wave-uniform, so it lives in scalar registers), lane l the columns l
+  // and, for l < 2R, 64 + l. All loads of a thread are issued before the
+  // first LDS write.
+  constexpr int RPW = (H + NT / 64 - 1) / (NT / 64);   // rows per wave
+  const int wy = __builtin_amdgcn_readfirstlane(threadIdx.y);
+  const int lane = threadIdx.x;
+  const int xc0 = wrap_any(x0 - R + lane, d.nx), xc1 = wrap_any(x0 - R + 64 + lane, d.nx);
+  T v[RPW][2];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int rr = wy + (NT / 64) * i;
+    if (rr >= H) continue;
+    const T* row = src + (size_t)wrap_any(y0 - R + rr, d.ny) * d.nx;
+    v[i][0] = row[xc0];
+    if (lane < 2 * R) v[i][1] = row[xc1];
+  }
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int rr = wy + (NT / 64) * i;
+    if (rr >= H) continue;
+    s_in[rr][lane] = v[i][0];
+    if (lane < 2 * R) s_in[rr][64 + lane] = v[i][1];
+  }
+  __syncthreads();
+  // x blur of every staged row: thread -> (row, quad of four x-values)
+#pragma unroll
+  for (int p = 0; p < (H * 16 + NT - 1) / NT; ++p) {
+    const int q = tid % 16, rr = tid / 16 + p * (NT / 16);
+    if (rr < H) {
+      T w[OUT + 2 * R];
+#pragma unroll
+      for (int i = 0; i < OUT + 2 * R; ++i) w[i] = s_in[rr][4 * q + i];
+#pragma unroll
+      for (int o = 0; o < OUT; ++o) {
+        T acc = T(0);
+#pragma unroll
+        for (int j = 0; j <= 2 * R; ++j) acc += k.w[j] * w[o + j];
+        s_mid[rr][4 * q + o] = acc;
+      }
+    }
+  }
+  __syncthreads();
+  // y blur from a register window of this thread's column
+  const int x = x0 + threadIdx.x;
+  if (x >= d.nx) return;
+  T col[OUT + 2 * R];
+#pragma unroll
+  for (int i = 0; i < OUT + 2 * R; ++i) col[i] = s_mid[threadIdx.y * OUT + i][threadIdx.x];
+#pragma unroll
+  for (int o = 0; o < OUT; ++o) {
+    const int y = y0 + threadIdx.y * OUT + o;
+    if (y >= d.ny) break;
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j <= 2 * R; ++j) acc += k.w[j] * col[o + j];
+    out[(size_t)b * vol + (size_t)z * plane + (size_t)y * d.nx + x] = acc;
   }
 }
 

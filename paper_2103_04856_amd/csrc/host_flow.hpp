@@ -44,6 +44,19 @@ void blur_x_pass(hipStream_t s, const fe::FieldDims& d, const fe::BlurTaps<T>& k
     hipLaunchKernelGGL((fe::blur_x<T, DIV>), g, b, 0, s, in, out, m0, mfield, d, inv2h, k, clk, beta1, beta2);
 }
 
+// The fused x-then-y pass, for the radii that have one (r = 4 and 8).
+bool has_xy_pass(int r) { return r == 4 || r == 8; }
+dim3 xy_grid(const fe::FieldDims& d) { return dim3(ceil_div(d.nx, 64), ceil_div(d.ny, fe::kXYRows), d.nz * d.batch); }
+
+template <typename T>
+void blur_xy_pass(hipStream_t s, const fe::FieldDims& d, const fe::BlurTaps<T>& k, const T* in, T* out) {
+  const dim3 g = xy_grid(d), b(64, 8);
+  if (k.r == 4)
+    hipLaunchKernelGGL((fe::blur_xy<T, 4>), g, b, 0, s, in, out, d, k);
+  else
+    hipLaunchKernelGGL((fe::blur_xy<T, 8>), g, b, 0, s, in, out, d, k);
+}
+
 template <typename T, int AXIS>
 void blur_axis_pass(hipStream_t s, const fe::FieldDims& d, const fe::BlurTaps<T>& k, const T* in, T* out) {
   const dim3 g = axis_grid(d, AXIS), b(64, 4);
@@ -64,7 +77,9 @@ void blur_yz(hipStream_t s, const fe::FieldDims& d, const fe::BlurTaps<T>& k, co
 
 // u = k * (div A + m0) into `out` (a user field or the work field w0, never
 // w1): x pass into w0, y pass into w1, z pass into out. `clk` advances the
-// flow clock (iterations only).
+// flow clock (iterations only). The fused x-y pass is not used here: with the
+// divergence its staging costs more than the pass it saves once the grid
+// outgrows one wave of blocks (16 x 100^3: 162 us against 93 + 47 us).
 template <typename T>
 int flow_field(fe_ctx* c, hipStream_t s, const void* A, T* out, double sigma_k, fe::FlowClock* clk,
                double beta1, double beta2) {
@@ -97,9 +112,13 @@ int flow_iteration(fe_ctx* c, hipStream_t s, void* A, const FlowRule& fr) {
   const StepRule none{fe::kGrad, 0.0, 0.0, 0.0, 0.0};
   rc = sweep(c, s, fe::kGrad, w0, w1, nullptr, nullptr, c->d_energy, none);
   if (rc) return rc;
-  // gu = k * gb: x pass into w0, y pass into w1, z pass into w0
+  // gu = k * gb: x pass into w0, y pass into w1, z pass into w0 (for r = 4, 8
+  // the fused x-y pass into w0 and the z pass into w1)
   T* gu = w1;
-  if (k.r > 0) {
+  if (has_xy_pass(k.r)) {
+    blur_xy_pass<T>(s, d, k, (const T*)w1, w0);
+    blur_axis_pass<T, 2>(s, d, k, w0, w1);
+  } else if (k.r > 0) {
     blur_x_pass<T, false>(s, d, k, (const T*)w1, w0, nullptr, nullptr, T(0), nullptr, 0.0, 0.0);
     blur_yz<T>(s, d, k, w0, w1, w0);
     gu = w0;

@@ -98,13 +98,19 @@ int l2_copy(fe_l2* L, const void* src, void* dst) {
   return FE_OK;
 }
 
-// The three separable blur passes on the padded array (periodic within it):
-// in -> tmp1 (x) -> tmp2 (y) -> out (z); in and out may coincide, tmp1/tmp2 not.
+// The separable blur passes on the padded array (periodic within it):
+// in -> tmp1 (x) -> tmp2 (y) -> out (z), or in -> tmp1 (fused x-y) -> out (z)
+// for r = 4, 8; in and out may coincide, tmp1/tmp2 not.
 template <typename T>
 void l2_blur(fe_l2* L, const T* in, T* tmp1, T* tmp2, T* out) {
   const fe::FieldDims d{L->box.nx, L->box.ny, L->box.nz, 1};
   const fe::BlurTaps<T> k = blur_taps<T>(L->sigma_k);
   hipStream_t s = L->ctx->stream;
+  if (has_xy_pass(k.r)) {
+    blur_xy_pass<T>(s, d, k, in, tmp1);
+    blur_axis_pass<T, 2>(s, d, k, tmp1, out);
+    return;
+  }
   blur_x_pass<T, false>(s, d, k, in, tmp1, nullptr, nullptr, T(0), nullptr, 0.0, 0.0);
   blur_yz<T>(s, d, k, tmp1, tmp2, out);
 }
