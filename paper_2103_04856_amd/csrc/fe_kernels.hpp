@@ -219,8 +219,10 @@ __device__ __forceinline__ BlockTile block_tile(const SweepArgs<T>& a) {
 // plane p-1. Each thread evaluates the interior voxels it later gathers, so
 // their centre-only adjoints (du, da_z, db_aa) stay in registers and only the
 // seven values the neighbours read go through LDS; the one-voxel border of
-// the ring is shared out afterwards. Four u slots keep plane p-1 readable by
-// the gather while the next plane is staged, so two barriers per plane suffice.
+// the ring is shared out afterwards. The gather takes u at its output voxels
+// from registers (read while that plane was the centre plane), so no u slot is
+// read after the second barrier: three rotating u slots and two barriers per
+// plane suffice.
 //
 // SP: the coefficients C1..C6 come per voxel from a.cfield (loaded for every
 // ring voxel of a plane right after the plane is staged, so their latency
@@ -240,7 +242,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   enum { GX = 0, GY, BXX, BYY, BXY, BXZ, BYZ, NFIELD };
   constexpr bool STEP = MODE != kGrad;
 
-  __shared__ T su[4][UY * UX];
+  __shared__ T su[3][UY * UX];
   __shared__ T sx[NFIELD][RY * RX];
   __shared__ double sred[NT / kWave][2];
 
@@ -308,11 +310,12 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
 
   double acc_f = 0.0, acc_m = 0.0;
   T c_prev[NO], l_prev[NO], l_pp[NO];
+  T u_prev[NO];                                // u at this thread's output voxels of plane p-1
   T m1c[NO], m2c[NO], m1n[NO], m2n[NO];        // Adam moments: current and next output plane
 #pragma unroll
-  for (int j = 0; j < NO; ++j) c_prev[j] = l_prev[j] = l_pp[j] = m1n[j] = m2n[j] = T(0);
+  for (int j = 0; j < NO; ++j) c_prev[j] = l_prev[j] = l_pp[j] = u_prev[j] = m1n[j] = m2n[j] = T(0);
 
-  // plane q lives in slot (q - k0 + 2) & 3
+  // plane q lives in slot (q - k0 + 2) mod 3; the three slots rotate
   fetch(k0 - 2);
   stage(0);
   fetch(k0 - 1);
@@ -320,9 +323,9 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   fetch(k0);
 
   const int nit = (kend - k0) + 2;             // forward planes k0-1 .. kend
+  int sm = 0, sc = 1, sp = 2;                  // slots of p-1, p, p+1
   for (int it = 0; it < nit; ++it) {
     const int p = k0 - 1 + it;
-    const int sm = it & 3, sc = (it + 1) & 3, sp = (it + 2) & 3;   // slots of p-1, p, p+1
     stage(sp);
     if (it + 1 < nit) fetch(p + 2);            // in flight during this plane's compute
     // Adam moments of output plane p (written in the next iteration), loaded a
@@ -383,7 +386,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
     // Interior and border voxels are dealt out from one index space, so the
     // per-thread counts differ by at most one (the border goes to the threads
     // whose interior share is shorter).
-    T own_ub[NO], own_gz[NO], own_bxx[NO], own_byy[NO], own_bzz[NO];
+    T own_ub[NO], own_gz[NO], own_bxx[NO], own_byy[NO], own_bzz[NO], own_u[NO];
 #pragma unroll
     for (int j = 0; j < NW; ++j) {
       const int item = tid + j * NT;
@@ -394,6 +397,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
         VoxelAdjoint<T> ad;
         const T f = eval(v, ad, SP ? with_coeffs(prm, cv[j]) : prm);
         if (j < NO && inner) {
+          own_u[j] = su[sc][(iy + 2) * UX + ix + 2];
           own_ub[j] = ad.ub;
           own_gz[j] = ad.gz;
           own_bxx[j] = ad.nbxx;
@@ -422,7 +426,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
           if (gx < a.nx && gy < a.ny) {
             const T g = (c_prev[j] - upn) + l_pp[j];
             const size_t idx = (size_t)(p - 1) * plane + (size_t)gy * a.nx + gx;
-            const T uc = su[sm][(iy + 2) * UX + ix + 2];
+            const T uc = u_prev[j];
             if (MODE == kStepGD) {
               const T un = uc - a.tau * g;
               dstb[idx] = un;
@@ -448,8 +452,14 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
         l_pp[j] = l_prev[j];
         l_prev[j] = lo;
         c_prev[j] = cin;
+        u_prev[j] = own_u[j];
       }
     }
+    // plane p+2 goes where p-1 was: its last reader has passed the second barrier
+    const int t = sm;
+    sm = sc;
+    sc = sp;
+    sp = t;
   }
 
   finish_block<NT, MODE>(a, bt.inst, bt.logical, bt.per_inst, acc_f, acc_m, sred);
