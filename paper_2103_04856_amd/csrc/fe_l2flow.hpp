@@ -62,78 +62,182 @@ __global__ __launch_bounds__(256) void fold_pads(const T* __restrict__ g, T* __r
 }
 
 // ---- vector operations of the optimiser (FP64 reductions, fixed order) ----
+//
+// Every reduction runs on kVecBlocks blocks of kVecThreads threads and leaves
+// one FP64 partial per block in a bank of its own. The value of a reduction is
+// the combination of its bank in one fixed order (bank_value), formed where it
+// is needed: by every block of a later vector pass that takes it as a
+// coefficient, or by vec_finish for the host. No block waits for another and
+// no pass needs a device-wide fence, which on this GPU costs more than the
+// pass itself when every block issues one.
 
-constexpr int kVecBlocks = 1024;
+constexpr int kVecBlocks = 256;
+constexpr int kVecThreads = 1024;
 
 template <int OP>
 __device__ __forceinline__ double vec_combine(double acc, double v) {
   return OP == 2 ? fmax(acc, v) : acc + v;
 }
 
-// partial[k] for block k: sum of a*b (OP 0), |a| (OP 1), or max |a| (OP 2).
-// Each thread keeps four independent accumulators over four strided elements
-// per round, so four loads are in flight; the fixed grid and fixed order keep
-// the result deterministic.
-template <typename T, int OP>
-__global__ __launch_bounds__(256) void vec_reduce(const T* __restrict__ a, const T* __restrict__ b, size_t n,
-                                                  double* __restrict__ partial) {
-  __shared__ double s[256];
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i + 3 * stride < n; i += 4 * stride) {
+// The value of a bank of kVecBlocks partials: lane l of the block's first wave
+// combines partials l, l + 64, l + 128, l + 192 in that order, then a butterfly
+// over the wave (each step combines a lane with its partner, and the two orders
+// of a commutative operation agree bit for bit, so all lanes finish equal).
+// The result is broadcast to the whole block; call from every thread.
+template <int OP>
+__device__ __forceinline__ double bank_value(const double* __restrict__ bank) {
+  static_assert(kVecBlocks == 4 * 64, "bank_value reads four partials per lane");
+  __shared__ double s_val;
+  if (threadIdx.x < 64) {
+    double a = bank[threadIdx.x];
+    a = vec_combine<OP>(a, bank[threadIdx.x + 64]);
+    a = vec_combine<OP>(a, bank[threadIdx.x + 128]);
+    a = vec_combine<OP>(a, bank[threadIdx.x + 192]);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const size_t j = i + k * stride;
-      const double v = OP == 0 ? double(a[j]) * double(b[j]) : fabs(double(a[j]));
-      acc[k] = vec_combine<OP>(acc[k], v);
+    for (int off = 32; off > 0; off >>= 1) a = vec_combine<OP>(a, __shfl_xor(a, off, 64));
+    if (threadIdx.x == 0) s_val = a;
+  }
+  __syncthreads();
+  const double v = s_val;
+  __syncthreads();   // s_val may be reused by a later call
+  return v;
+}
+
+// The block's combination of one value per thread into bank[blockIdx.x], in a
+// fixed order (each wave's butterfly, then the waves in order).
+template <int OP>
+__device__ __forceinline__ void vec_block_partial(double acc, double* __restrict__ bank) {
+  __shared__ double s_w[kVecThreads / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc = vec_combine<OP>(acc, __shfl_xor(acc, off, 64));
+  if (threadIdx.x % 64 == 0) s_w[threadIdx.x / 64] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = s_w[0];
+    for (int k = 1; k < kVecThreads / 64; ++k) a = vec_combine<OP>(a, s_w[k]);
+    bank[blockIdx.x] = a;
+  }
+}
+
+// Four consecutive vector elements, moved with 16-byte loads and stores (the
+// vectors are whole device allocations, so element 4k is 16-byte aligned).
+template <typename T>
+struct alignas(16) Pack4 {
+  T v[4];
+};
+
+// bank <- partials of sum a*b (OP 0), sum |a| (OP 1) or max |a| (OP 2),
+// accumulated in FP64 with one accumulator per element of a pack. Grid-stride
+// over packs of four, two packs of each vector in flight per thread; block 0
+// takes the n % 4 tail.
+template <typename T, int OP>
+__global__ __launch_bounds__(kVecThreads) void vec_reduce(const T* __restrict__ a, const T* __restrict__ b, size_t n,
+                                                          double* __restrict__ bank) {
+  const size_t n4 = n / 4, stride = (size_t)gridDim.x * blockDim.x;
+  const Pack4<T>* pa = reinterpret_cast<const Pack4<T>*>(a);
+  const Pack4<T>* pb = reinterpret_cast<const Pack4<T>*>(b);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < n4; i0 += 2 * stride) {
+    Pack4<T> va[2], vb[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const size_t i = i0 + u * stride;
+      va[u] = Pack4<T>{};
+      vb[u] = Pack4<T>{};
+      if (i < n4) {
+        va[u] = pa[i];
+        if (OP == 0) vb[u] = pb[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        acc[k] = vec_combine<OP>(acc[k], OP == 0 ? double(va[u].v[k]) * double(vb[u].v[k]) : fabs(double(va[u].v[k])));
+  }
+  if (blockIdx.x == 0 && threadIdx.x < n - 4 * n4) {
+    const size_t j = 4 * n4 + threadIdx.x;
+    acc[0] = vec_combine<OP>(acc[0], OP == 0 ? double(a[j]) * double(b[j]) : fabs(double(a[j])));
+  }
+  vec_block_partial<OP>(vec_combine<OP>(vec_combine<OP>(acc[0], acc[1]), vec_combine<OP>(acc[2], acc[3])), bank);
+}
+
+// Coefficient of a vector pass, ka v(bank_a) + kb v(bank_b) + kc in FP64, from
+// the values of two dot-product banks (a null bank: that term is absent).
+struct VecCoef {
+  const double* bank_a;
+  double ka;
+  const double* bank_b;
+  double kb;
+  double kc;
+};
+
+// y = alpha x + y (ACC) or y = alpha x, alpha = the coefficient rounded once to
+// the vector precision; then, when w is given, bank <- partials of w . y (the
+// updated y). Each step of the L-BFGS two-loop recursion is one such pass: the
+// update by one history entry and the dot product that the next entry needs,
+// with no host synchronisation. Layout of the work as in vec_reduce.
+template <typename T, bool ACC>
+__global__ __launch_bounds__(kVecThreads) void vec_update_dot(VecCoef cf, const T* __restrict__ x, T* __restrict__ y,
+                                                              const T* __restrict__ w, size_t n,
+                                                              double* __restrict__ bank) {
+  const double ca = cf.bank_a ? bank_value<0>(cf.bank_a) : 0.0;
+  const double cb = cf.bank_b ? bank_value<0>(cf.bank_b) : 0.0;
+  const T alpha = T(cf.ka * ca + cf.kb * cb + cf.kc);
+  const size_t n4 = n / 4, stride = (size_t)gridDim.x * blockDim.x;
+  const Pack4<T>* px = reinterpret_cast<const Pack4<T>*>(x);
+  Pack4<T>* py = reinterpret_cast<Pack4<T>*>(y);
+  const Pack4<T>* pw = reinterpret_cast<const Pack4<T>*>(w);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < n4; i0 += 2 * stride) {
+    Pack4<T> vx[2], vy[2], vw[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const size_t i = i0 + u * stride;
+      vx[u] = vy[u] = vw[u] = Pack4<T>{};
+      if (i < n4) {
+        vx[u] = px[i];
+        if (ACC) vy[u] = py[i];
+        if (w) vw[u] = pw[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const size_t i = i0 + u * stride;
+      Pack4<T> r;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) r.v[k] = ACC ? alpha * vx[u].v[k] + vy[u].v[k] : alpha * vx[u].v[k];
+      if (i < n4) {
+        py[i] = r;
+        if (w) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc[k] += double(vw[u].v[k]) * double(r.v[k]);
+        }
+      }
     }
   }
-  for (; i < n; i += stride) {
-    const double v = OP == 0 ? double(a[i]) * double(b[i]) : fabs(double(a[i]));
-    acc[0] = vec_combine<OP>(acc[0], v);
+  if (blockIdx.x == 0 && threadIdx.x < n - 4 * n4) {
+    const size_t j = 4 * n4 + threadIdx.x;
+    const T v = ACC ? alpha * x[j] + y[j] : alpha * x[j];
+    y[j] = v;
+    if (w) acc[0] += double(w[j]) * double(v);
   }
-  s[threadIdx.x] = vec_combine<OP>(vec_combine<OP>(acc[0], acc[1]), vec_combine<OP>(acc[2], acc[3]));
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) s[threadIdx.x] = OP == 2 ? fmax(s[threadIdx.x], s[threadIdx.x + w]) : s[threadIdx.x] + s[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+  if (w) vec_block_partial<0>((acc[0] + acc[1]) + (acc[2] + acc[3]), bank);
 }
 
-// out[0] = reduction of the nblk partials (one block, fixed order); the result may
-// go to any slot of a device scalar array.
-template <int OP>
-__global__ __launch_bounds__(256) void vec_finish(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
-  __shared__ double s[256];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += 256) acc = OP == 2 ? fmax(acc, partial[i]) : acc + partial[i];
-  s[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) s[threadIdx.x] = OP == 2 ? fmax(s[threadIdx.x], s[threadIdx.x + w]) : s[threadIdx.x] + s[threadIdx.x + w];
-    __syncthreads();
+// Values of up to four banks for the host: out[k] = bank_value<op[k]>(bank[k]).
+struct BankList {
+  const double* bank[4];
+  double* out[4];
+  int op[4];
+  int count;
+};
+
+__global__ __launch_bounds__(64) void vec_finish(BankList l) {
+  for (int k = 0; k < l.count; ++k) {
+    const double v = l.op[k] == 2 ? bank_value<2>(l.bank[k]) : bank_value<0>(l.bank[k]);
+    if (threadIdx.x == 0) *l.out[k] = v;
   }
-  if (threadIdx.x == 0) out[0] = s[0];
-}
-
-// y = alpha x + beta y  (alpha and beta in the vector precision, as the vectors are)
-template <typename T>
-__global__ __launch_bounds__(256) void vec_axpby(T alpha, const T* __restrict__ x, T beta, T* __restrict__ y, size_t n) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    y[i] = alpha * x[i] + beta * y[i];
-}
-
-// y = (ka sc[ia] + kb sc[ib]) x + y, the coefficient formed from device scalars
-// (ib < 0: no second term), so that the two-loop recursion needs no host sync.
-template <typename T>
-__global__ __launch_bounds__(256) void vec_axpy_dev(const double* __restrict__ sc, int ia, double ka, int ib,
-                                                    double kb, const T* __restrict__ x, T* __restrict__ y,
-                                                    size_t n) {
-  const T alpha = T(ka * sc[ia] + (ib >= 0 ? kb * sc[ib] : 0.0));
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    y[i] = alpha * x[i] + y[i];
 }
 
 // z = x - y

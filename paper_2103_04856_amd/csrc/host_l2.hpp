@@ -35,61 +35,95 @@ namespace {
 
 int l2_launch_1d(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 65536); }
 
-// Scalar slots after the partials in d_red: 0 energy, 1 max|g|, 2 max|d|, 3 g'd,
-// 4 |g|_1, 5 y's, 6 y'y, 7 scratch dot, 8.. the s_i'q dots of the two-loop
-// recursion (one per history entry).
+// Scalars of the optimiser. Each reduction has a slot: 0 energy, 1 max|g|,
+// 2 max|d|, 3 g'd, 4 |g|_1, 5 y's, 6 y'y, 7 and 8 the y_i'd dots of the second
+// loop (used in turn, so no pass reads the bank it writes), 9.. the s_i'q dots
+// of the first loop of the two-loop recursion (one per history entry). d_red
+// holds one bank of kVecBlocks partials per slot, then one value per slot for
+// the host (the energy is written there directly).
 constexpr int kSlotE = 0, kSlotGmax = 1, kSlotDmax = 2, kSlotGtd = 3, kSlotL1 = 4, kSlotYs = 5, kSlotYy = 6,
-              kSlotDot = 7, kSlotAlpha = 8;
+              kSlotDot = 7, kSlotDot2 = 8, kSlotAlpha = 9;
 constexpr int kL2MaxHistory = 64;
 constexpr int kL2Slots = kSlotAlpha + kL2MaxHistory;
+constexpr size_t kL2RedDoubles = (size_t)kL2Slots * fe::kVecBlocks + kL2Slots;
 
-// Reduction of a (and b) into scalar slot `slot`, stream-ordered, no sync.
+double* l2_bank(fe_l2* L, int slot) { return L->d_red + (size_t)slot * fe::kVecBlocks; }
+double* l2_vals(fe_l2* L) { return L->d_red + (size_t)kL2Slots * fe::kVecBlocks; }
+int l2_slot_op(int slot) { return slot == kSlotGmax || slot == kSlotDmax ? 2 : slot == kSlotL1 ? 1 : 0; }
+
+const dim3 kVecGrid(fe::kVecBlocks), kVecBlock(fe::kVecThreads);
+
+// Reduction of a (and b) into the bank of `slot`, stream-ordered, no sync.
 template <typename T>
 int l2_reduce_dev(fe_l2* L, int op, const void* a, const void* b, int slot) {
   hipStream_t s = L->ctx->stream;
   const T* pa = static_cast<const T*>(a);
   const T* pb = static_cast<const T*>(b);
-  double* part = L->d_red;
-  double* res = L->d_red + fe::kVecBlocks + slot;
+  double* bank = l2_bank(L, slot);
   if (op == 0)
-    hipLaunchKernelGGL((fe::vec_reduce<T, 0>), dim3(fe::kVecBlocks), dim3(256), 0, s, pa, pb, L->n, part);
+    hipLaunchKernelGGL((fe::vec_reduce<T, 0>), kVecGrid, kVecBlock, 0, s, pa, pb, L->n, bank);
   else if (op == 1)
-    hipLaunchKernelGGL((fe::vec_reduce<T, 1>), dim3(fe::kVecBlocks), dim3(256), 0, s, pa, pb, L->n, part);
+    hipLaunchKernelGGL((fe::vec_reduce<T, 1>), kVecGrid, kVecBlock, 0, s, pa, pb, L->n, bank);
   else
-    hipLaunchKernelGGL((fe::vec_reduce<T, 2>), dim3(fe::kVecBlocks), dim3(256), 0, s, pa, pb, L->n, part);
-  if (op == 2)
-    hipLaunchKernelGGL(fe::vec_finish<2>, dim3(1), dim3(256), 0, s, (const double*)part, fe::kVecBlocks, res);
-  else
-    hipLaunchKernelGGL(fe::vec_finish<0>, dim3(1), dim3(256), 0, s, (const double*)part, fe::kVecBlocks, res);
+    hipLaunchKernelGGL((fe::vec_reduce<T, 2>), kVecGrid, kVecBlock, 0, s, pa, pb, L->n, bank);
   FE_HIP(hipGetLastError());
   return FE_OK;
 }
 
-// Host copies of scalar slots [first, first + count) (one sync).
+// Host copies of the values of slots [first, first + count) (one sync): the
+// banks among them are combined on the device first.
 int l2_read_slots(fe_l2* L, int first, int count, double* out) {
-  FE_HIP(hipMemcpyAsync(out, L->d_red + fe::kVecBlocks + first, sizeof(double) * count, hipMemcpyDeviceToHost,
-                        L->ctx->stream));
+  fe::BankList bl{};
+  for (int k = first; k < first + count; ++k) {
+    if (k == kSlotE) continue;
+    if (bl.count == 4) return set_error(FE_EINVAL, "internal: too many slots in one read");
+    bl.bank[bl.count] = l2_bank(L, k);
+    bl.out[bl.count] = l2_vals(L) + k;
+    bl.op[bl.count] = l2_slot_op(k);
+    ++bl.count;
+  }
+  if (bl.count) {
+    hipLaunchKernelGGL(fe::vec_finish, dim3(1), dim3(64), 0, L->ctx->stream, bl);
+    FE_HIP(hipGetLastError());
+  }
+  FE_HIP(hipMemcpyAsync(out, l2_vals(L) + first, sizeof(double) * count, hipMemcpyDeviceToHost, L->ctx->stream));
   FE_HIP(hipStreamSynchronize(L->ctx->stream));
   return FE_OK;
 }
 
-// y += (ka sc[ia] + kb sc[ib]) x with device scalars
+// Coefficient ka v(ia) + kb v(ib) + kc of a vector pass, from the values of
+// dot-product slots (ia, ib < 0: that term is absent).
+struct L2Coef {
+  int ia;
+  double ka;
+  int ib;
+  double kb;
+  double kc;
+};
+
+// y = alpha x (+ y when acc); then, when w is given, w . y into the bank of
+// slot `out`. One pass, no sync.
 template <typename T>
-int l2_axpy_dev(fe_l2* L, int ia, double ka, int ib, double kb, const void* x, void* y) {
-  hipLaunchKernelGGL(fe::vec_axpy_dev<T>, dim3(l2_launch_1d(L->n)), dim3(256), 0, L->ctx->stream,
-                     (const double*)(L->d_red + fe::kVecBlocks), ia, ka, ib, kb, static_cast<const T*>(x),
-                     static_cast<T*>(y), L->n);
+int l2_update(fe_l2* L, const L2Coef& k, bool acc, const void* x, void* y, const void* w = nullptr, int out = 0) {
+  hipStream_t s = L->ctx->stream;
+  const fe::VecCoef cf{k.ia >= 0 ? l2_bank(L, k.ia) : nullptr, k.ka, k.ib >= 0 ? l2_bank(L, k.ib) : nullptr, k.kb,
+                       k.kc};
+  const T* px = static_cast<const T*>(x);
+  T* py = static_cast<T*>(y);
+  const T* pw = static_cast<const T*>(w);
+  double* bank = l2_bank(L, out);
+  if (acc)
+    hipLaunchKernelGGL((fe::vec_update_dot<T, true>), kVecGrid, kVecBlock, 0, s, cf, px, py, pw, L->n, bank);
+  else
+    hipLaunchKernelGGL((fe::vec_update_dot<T, false>), kVecGrid, kVecBlock, 0, s, cf, px, py, pw, L->n, bank);
   FE_HIP(hipGetLastError());
   return FE_OK;
 }
 
-// y = alpha x + beta y
+// y = alpha x (+ y when acc) with a host coefficient
 template <typename T>
-int l2_axpby(fe_l2* L, double alpha, const void* x, double beta, void* y) {
-  hipLaunchKernelGGL(fe::vec_axpby<T>, dim3(l2_launch_1d(L->n)), dim3(256), 0, L->ctx->stream, T(alpha),
-                     static_cast<const T*>(x), T(beta), static_cast<T*>(y), L->n);
-  FE_HIP(hipGetLastError());
-  return FE_OK;
+int l2_scale_add(fe_l2* L, double alpha, const void* x, bool acc, void* y) {
+  return l2_update<T>(L, L2Coef{-1, 0.0, -1, 0.0, alpha}, acc, x, y);
 }
 
 template <typename T>
@@ -144,7 +178,7 @@ int l2_eval_dev(fe_l2* L) {
     hipLaunchKernelGGL(fe::fold_pads<T>, pg, dim3(256), 0, s, (const T*)w0, g, L->box);
   }
   FE_HIP(hipGetLastError());
-  FE_HIP(hipMemcpyAsync(L->d_red + fe::kVecBlocks + kSlotE, L->ctx->d_energy, sizeof(double),
+  FE_HIP(hipMemcpyAsync(l2_vals(L) + kSlotE, L->ctx->d_energy, sizeof(double),
                         hipMemcpyDeviceToDevice, s));
   return FE_OK;
 }
@@ -185,7 +219,7 @@ int l2_step(fe_l2* L, double& loss0) {
   for (int it = 1; it <= L->max_iter; ++it) {
     ++L->n_iter;
     if (L->n_iter == 1) {
-      if ((rc = l2_axpby<T>(L, -1.0, L->g, 0.0, L->d))) return rc;
+      if ((rc = l2_scale_add<T>(L, -1.0, L->g, false, L->d))) return rc;
       L->hist_len = 0;
       L->rho.clear();
       L->H_diag = 1.0;
@@ -194,7 +228,7 @@ int l2_step(fe_l2* L, double& loss0) {
       hipLaunchKernelGGL(fe::vec_sub<T>, dim3(l2_launch_1d(L->n)), dim3(256), 0, L->ctx->stream,
                          static_cast<const T*>(L->g), static_cast<const T*>(L->prev_g), static_cast<T*>(L->q), L->n);
       FE_HIP(hipGetLastError());
-      if ((rc = l2_axpby<T>(L, L->t, L->d, 0.0, L->w0))) return rc;
+      if ((rc = l2_scale_add<T>(L, L->t, L->d, false, L->w0))) return rc;
       if ((rc = l2_reduce_dev<T>(L, 0, L->q, L->w0, kSlotYs))) return rc;
       if ((rc = l2_reduce_dev<T>(L, 0, L->q, L->q, kSlotYy))) return rc;
       double yy2[2];
@@ -214,16 +248,24 @@ int l2_step(fe_l2* L, double& loss0) {
         L->H_diag = ys / yy;
       }
       // two-loop recursion: q = -g; newest to oldest: a_i = rho_i s_i'q, q -= a_i y_i;
-      // d = H_diag q; oldest to newest: b_i = rho_i y_i'd, d += (a_i - b_i) s_i
-      if ((rc = l2_axpby<T>(L, -1.0, L->g, 0.0, L->q))) return rc;
-      for (int i = L->hist_len - 1; i >= 0; --i) {
-        if ((rc = l2_reduce_dev<T>(L, 0, L->S[i], L->q, kSlotAlpha + i))) return rc;
-        if ((rc = l2_axpy_dev<T>(L, kSlotAlpha + i, -L->rho[i], -1, 0.0, L->Y[i], L->q))) return rc;
-      }
-      if ((rc = l2_axpby<T>(L, L->H_diag, L->q, 0.0, L->d))) return rc;
-      for (int i = 0; i < L->hist_len; ++i) {
-        if ((rc = l2_reduce_dev<T>(L, 0, L->Y[i], L->d, kSlotDot))) return rc;
-        if ((rc = l2_axpy_dev<T>(L, kSlotAlpha + i, L->rho[i], kSlotDot, -L->rho[i], L->S[i], L->d))) return rc;
+      // d = H_diag q; oldest to newest: b_i = rho_i y_i'd, d += (a_i - b_i) s_i.
+      // Each pass updates q (or d) and forms the dot product of the next entry.
+      const int m = L->hist_len;
+      if ((rc = l2_update<T>(L, L2Coef{-1, 0.0, -1, 0.0, -1.0}, false, L->g, L->q, m > 0 ? L->S[m - 1] : nullptr,
+                             m > 0 ? kSlotAlpha + m - 1 : 0)))
+        return rc;
+      for (int i = m - 1; i >= 0; --i)
+        if ((rc = l2_update<T>(L, L2Coef{kSlotAlpha + i, -L->rho[i], -1, 0.0, 0.0}, true, L->Y[i], L->q,
+                               i > 0 ? L->S[i - 1] : nullptr, i > 0 ? kSlotAlpha + i - 1 : 0)))
+          return rc;
+      if ((rc = l2_update<T>(L, L2Coef{-1, 0.0, -1, 0.0, L->H_diag}, false, L->q, L->d, m > 0 ? L->Y[0] : nullptr,
+                             kSlotDot)))
+        return rc;
+      for (int i = 0; i < m; ++i) {
+        const int cur = (i & 1) ? kSlotDot2 : kSlotDot, nxt = (i & 1) ? kSlotDot : kSlotDot2;
+        if ((rc = l2_update<T>(L, L2Coef{kSlotAlpha + i, L->rho[i], cur, -L->rho[i], 0.0}, true, L->S[i], L->d,
+                               i + 1 < m ? L->Y[i + 1] : nullptr, nxt)))
+          return rc;
       }
     }
     if ((rc = l2_copy<T>(L, L->g, L->prev_g))) return rc;
@@ -237,7 +279,7 @@ int l2_step(fe_l2* L, double& loss0) {
     const double gtd = gl[0];
     if (gtd > -L->tol_change) break;
     int ls_evals = 0;
-    if ((rc = l2_axpby<T>(L, L->t, L->d, 1.0, L->x))) return rc;
+    if ((rc = l2_scale_add<T>(L, L->t, L->d, true, L->x))) return rc;
     if ((rc = l2_reduce_dev<T>(L, 2, L->d, nullptr, kSlotDmax))) return rc;
     double dmax = 0.0;
     if (it != L->max_iter) {
@@ -329,10 +371,14 @@ int fe_l2_create(const fe_grid* grid, double eps, const double* p_coeffs, double
       return set_error(FE_EHIP, "hipMemsetAsync failed");
     }
   }
-  if (hipMalloc((void**)&L->d_red, sizeof(double) * (fe::kVecBlocks + kL2Slots)) != hipSuccess) {
+  if (hipMalloc((void**)&L->d_red, sizeof(double) * kL2RedDoubles) != hipSuccess) {
     L->d_red = nullptr;
     l2_free(L);
     return set_error(FE_ENOMEM, "L2 flow reduction buffer allocation failed");
+  }
+  if (hipMemsetAsync(L->d_red, 0, sizeof(double) * kL2RedDoubles, c->stream) != hipSuccess) {
+    l2_free(L);
+    return set_error(FE_EHIP, "hipMemsetAsync failed");
   }
   rc = fe_l2_set_lbfgs(L, 1.0, 10, 20, 1e-7, 1e-9);
   if (rc) {
