@@ -16,9 +16,11 @@
 //     pipeline, so each output voxel is written exactly once;
 //   * sums (energy, mass of the stepped field) are accumulated per thread in
 //     FP64, reduced with wavefront shuffles and one LDS pass, and written as
-//     one partial per block; the last block of each instance adds that
-//     instance's partials in a fixed order (deterministic) and writes the
-//     energy and the mass shift, so one launch is one whole step.
+//     one partial per block. Whoever needs an instance's totals adds its
+//     partials in one fixed order (deterministic): the next step's blocks,
+//     for the shift that projects the stepped field back onto its target
+//     mean, or sweep_finish for the energy. No block waits for another, and
+//     a step is one launch with no device-wide fence.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -75,7 +77,7 @@ __device__ __forceinline__ int xcd_logical_block(int linear, int total) {
 // What the fused sweep writes.
 enum SweepMode {
   kGrad = 0,      // dst = dF_h/du (h^3 included); partial[1] = sum of src
-  kStepGD = 1,    // dst = u - tau dF_h/du, u = src + shift_in[b]; partial[1] = sum of dst
+  kStepGD = 1,    // dst = u - tau dF_h/du, u = src + shift of src; partial[1] = sum of dst
   kStepAdam = 2,  // dst = u - lr mhat / (sqrt(vhat) + adam_eps), moments updated in place
 };
 
@@ -84,16 +86,16 @@ struct SweepArgs {
   const T* src;                 // [batch][nz][ny][nx]
   T* dst;                       // gradient or stepped field; unused by the energy sweep
   const InstParams<T>* prm;     // [batch]
-  const double* shift_in;       // steps: per-instance uniform shift of src (nullable)
-  double* partials;             // [batch][blocks_per_instance][2]
-  int* counters;                // [batch + 1] finished-block counters, zero between launches
-  double* energy;               // [batch] out: h^3 sum f
+  const double* prev_partials;  // steps: the partials of the step that wrote src; the instance's shift
+                                // mass - mean(src) formed from them is added to src (null: no shift)
+  double* partials;             // out: [batch][blocks_per_instance][2] per-block sums of the energy
+                                // density and of the field (steps: the stepped field, else src)
   const double* mass;           // steps: [batch] target means
-  double* shift_out;            // steps: [batch] out: mass - mean(dst)
   double inv_nvox;
   T* m1;                        // Adam: first moment, same layout as src
   T* m2;                        // Adam: second moment
-  const int* adam_t;            // Adam: step number t >= 1 (device, advanced by the finalisation)
+  const int* adam_t;            // Adam: base step number t0 (device, advanced by adam_tick)
+  int t_add;                    // Adam: this step's number is t0 + t_add
   const T* cfield;              // space-dependent coefficients: [batch][6][nz][ny][nx] scaled C1..C6,
                                 // read by the SP instantiations only
   int box_lo[3], box_hi[3];     // BOX instantiations: the voxels (x, y, z) whose density is summed;
@@ -132,47 +134,43 @@ __device__ __forceinline__ InstParams<T> with_coeffs(InstParams<T> p, const Voxe
   return p;
 }
 
-// End of a sweep block: reduce the block's sums into its partial; the last block
-// of an instance to finish adds that instance's partials in a fixed order and
-// writes the energy (and, for steps, the shift that projects the stepped field
-// back onto its target mean). The last of those advances the Adam step number.
-// Counters are reset by the blocks that observe them full, so every launch (and
-// every graph replay) starts from zero without a memset.
-template <int NT, int MODE, typename T>
-__device__ __forceinline__ void finish_block(const SweepArgs<T>& a, int inst, int logical, int per_inst,
-                                             double acc_f, double acc_m, double (*sred)[2]) {
-  __shared__ int s_last;
+// End of a sweep block: the block's two sums go to its partial. They are
+// combined per instance by instance_sums, in one fixed order, wherever they
+// are needed (the next step's shift, sweep_finish), so no block waits for
+// another and a launch needs no device-wide fence.
+template <int NT, typename T>
+__device__ __forceinline__ void write_partials(const SweepArgs<T>& a, int logical, double acc_f, double acc_m,
+                                               double (*sred)[2]) {
   block_sum2<NT>(acc_f, acc_m, sred);
   if (threadIdx.x == 0) {
     double* out = a.partials + (size_t)logical * 2;
     out[0] = acc_f;
     out[1] = acc_m;
-    __threadfence();
-    s_last = atomicAdd(&a.counters[inst], 1) == per_inst - 1;
   }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  const double* pp = a.partials + (size_t)inst * per_inst * 2;
-  double sf = 0.0, sm = 0.0;
-  for (int i = threadIdx.x; i < per_inst; i += NT) {
-    sf += pp[2 * i];
-    sm += pp[2 * i + 1];
+}
+
+// Per-instance sums of the block partials of a sweep: lane l of the calling
+// wave adds the partials of blocks l, l + 64, l + 128, ... in that order, then
+// a butterfly over the wave combines the lanes. Each butterfly step adds a lane
+// and its partner, and the two orders of an addition agree bit for bit, so
+// every lane of every wave that calls this gets the same bits. Call from all
+// 64 lanes of a wave.
+__device__ __forceinline__ void instance_sums(const double* __restrict__ partials, int inst, int per_inst,
+                                              double& sf, double& sm) {
+  const int lane = threadIdx.x % kWave;
+  const double* pp = partials + (size_t)inst * per_inst * 2;
+  double f = 0.0, m = 0.0;
+  for (int k = lane; k < per_inst; k += kWave) {
+    f += pp[2 * k];
+    m += pp[2 * k + 1];
   }
-  __syncthreads();   // sred is reused
-  block_sum2<NT>(sf, sm, sred);
-  if (threadIdx.x == 0) {
-    a.energy[inst] = sf;
-    if (MODE == kStepGD || MODE == kStepAdam) a.shift_out[inst] = a.mass[inst] - sm * a.inv_nvox;
-    atomicExch(&a.counters[inst], 0);
-    if (MODE == kStepAdam) {
-      __threadfence();
-      if (atomicAdd(&a.counters[a.batch], 1) == a.batch - 1) {
-        atomicAdd(const_cast<int*>(a.adam_t), 1);
-        atomicExch(&a.counters[a.batch], 0);
-      }
-    }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    f += __shfl_xor(f, off, kWave);
+    m += __shfl_xor(m, off, kWave);
   }
+  sf = f;
+  sm = m;
 }
 
 // The 19 stencil samples around the LDS position pc (plane p), pm (p-1), pp (p+1).
@@ -254,11 +252,10 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   const T* srcb = a.src + inst_off;
   T* dstb = a.dst + inst_off;
   const InstParams<T> prm = a.prm[bt.inst];
-  const T shift = (STEP && a.shift_in) ? T(a.shift_in[bt.inst]) : T(0);
   // Adam bias corrections 1/(1 - beta^t)
   T bc1 = T(1), bc2 = T(1);
   if (MODE == kStepAdam) {
-    const int t = *a.adam_t;
+    const int t = *a.adam_t + a.t_add;
     bc1 = T(1.0 / (1.0 - ::pow(double(a.beta1), double(t))));
     bc2 = T(1.0 / (1.0 - ::pow(double(a.beta2), double(t))));
   }
@@ -272,6 +269,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
     uoff[j] = (e < UX * UY) ? wrap_index(y0 - 2 + ey, a.ny) * a.nx + wrap_index(x0 - 2 + ex, a.nx) : 0;
   }
   T pre[NU];
+  T shift = T(0);                              // steps: the uniform shift of src, set below
   auto fetch = [&](int p) {
     const T* sp = srcb + (size_t)wrap_index(p, a.nz) * plane;
 #pragma unroll
@@ -317,6 +315,15 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
 
   // plane q lives in slot (q - k0 + 2) mod 3; the three slots rotate
   fetch(k0 - 2);
+  // the shift of src, formed by the first wave while the first plane loads
+  __shared__ double s_shift;
+  if (STEP && tid < kWave) {
+    double sf = 0.0, sm = 0.0;
+    if (a.prev_partials) instance_sums(a.prev_partials, bt.inst, bt.per_inst, sf, sm);
+    if (tid == 0) s_shift = a.prev_partials ? a.mass[bt.inst] - sm * a.inv_nvox : 0.0;
+  }
+  __syncthreads();
+  if (STEP) shift = T(s_shift);
   stage(0);
   fetch(k0 - 1);
   stage(1);
@@ -462,7 +469,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
     sp = t;
   }
 
-  finish_block<NT, MODE>(a, bt.inst, bt.logical, bt.per_inst, acc_f, acc_m, sred);
+  write_partials<NT>(a, bt.logical, acc_f, acc_m, sred);
 }
 
 // Forward only: per-block sums of the energy density and of u. SP: per-voxel
@@ -542,7 +549,27 @@ __global__ __launch_bounds__(NT) void energy_sweep(SweepArgs<T> a) {
     __syncthreads();
   }
 
-  finish_block<NT, kGrad>(a, bt.inst, bt.logical, bt.per_inst, acc_f, acc_m, sred);
+  write_partials<NT>(a, bt.logical, acc_f, acc_m, sred);
+}
+
+// Per-instance results of a sweep from its block partials, one wave per
+// instance (grid: batch blocks of 64): energy[b] (when given), and, when shift
+// is given, shift[b] = mass[b] - mean of the field the sweep summed.
+__global__ __launch_bounds__(64) void sweep_finish(const double* __restrict__ partials, int per_inst,
+                                                   double* __restrict__ energy, const double* __restrict__ mass,
+                                                   double inv_nvox, double* __restrict__ shift) {
+  const int b = blockIdx.x;
+  double sf, sm;
+  instance_sums(partials, b, per_inst, sf, sm);
+  if (threadIdx.x == 0) {
+    if (energy) energy[b] = sf;
+    if (shift) shift[b] = mass[b] - sm * inv_nvox;
+  }
+}
+
+// Advance the Adam step number by n (one thread; the only writer).
+__global__ __launch_bounds__(64) void adam_tick(int* t, int n) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *t += n;
 }
 
 // dst[b][i] = src[b][i] + shift[b] (src may equal dst).
@@ -583,11 +610,6 @@ __global__ __launch_bounds__(256) void scale_coeff_field(const T* __restrict__ a
 }
 
 __global__ __launch_bounds__(64) void fill_f64(double* p, int n, double v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-__global__ __launch_bounds__(64) void fill_i32(int* p, int n, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }

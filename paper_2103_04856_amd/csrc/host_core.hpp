@@ -160,11 +160,10 @@ struct fe_ctx {
   std::vector<double> eps, coeffs;    // host copies [batch], [batch][6]
   std::vector<double> mu, theta;      // orientation term [batch], [batch][3] (mu = 0: off)
   void* d_prm = nullptr;              // InstParams<T>[batch]
-  double* d_partials = nullptr;       // [batch][max_blocks][2]
-  int* d_counters = nullptr;          // [batch + 1] finished-block counters (zero between launches)
+  double* d_partials = nullptr;       // [2][batch][max_blocks][2]: block partials of two sweeps (steps alternate)
   double* d_energy = nullptr;         // [batch]
   double* d_mass = nullptr;           // [batch]
-  double* d_shift = nullptr;          // [2][batch]
+  double* d_shift = nullptr;          // [batch]: the shift of the last step's output
   void* d_pingpong = nullptr;         // one field, allocated by the first fe_step
   void* d_m1 = nullptr;               // Adam moments, allocated by the first fe_step_adam
   void* d_m2 = nullptr;
@@ -367,11 +366,16 @@ int default_variant(const fe_grid& g) {
   return 0;
 }
 
-// kind: -1 energy only, else a fe::SweepMode. One launch computes the sweep and
-// its per-instance sums: energy_dev[b] and, for steps, shift_out[b].
+// Block-partial buffer i (0 or 1) of the context.
+double* partials_buf(fe_ctx* c, int i) { return c->d_partials + (size_t)i * 2 * c->max_blocks * c->grid.batch; }
+
+// kind: -1 energy only, else a fe::SweepMode. One launch; the block partials go
+// to `partials`. Steps add to src the shift formed from prev_partials (the
+// partials of the step that wrote src; null: no shift); Adam steps use the
+// step number t0 + t_add.
 template <typename T>
-int launch_sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, const double* shift_in,
-                 double* shift_out, double* energy_dev, const StepRule& rule) {
+int launch_sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, const double* prev_partials,
+                 double* partials, const StepRule& rule, int t_add) {
   const int vi = sweep_variant(c);
   const Geometry geo = geometry(c, vi, c->lz);
   if ((size_t)geo.per_inst > c->max_blocks) return set_error(FE_EINVAL, "internal: partials workspace too small");
@@ -381,17 +385,15 @@ int launch_sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst,
   a.src = static_cast<const T*>(src);
   a.dst = static_cast<T*>(dst);
   a.prm = static_cast<const fe::InstParams<T>*>(c->d_prm);
-  a.shift_in = shift_in;
-  a.partials = c->d_partials;
-  a.counters = c->d_counters;
-  a.energy = energy_dev;
+  a.prev_partials = prev_partials;
+  a.partials = partials;
   a.mass = c->d_mass;
-  a.shift_out = shift_out;
   a.inv_nvox = 1.0 / ((double)c->grid.nx * c->grid.ny * c->grid.nz);
   a.k = grid_consts<T>(c->grid.h);
   a.m1 = static_cast<T*>(c->d_m1);
   a.m2 = static_cast<T*>(c->d_m2);
   a.adam_t = c->d_adam_t;
+  a.t_add = t_add;
   a.cfield = c->use_cfield ? static_cast<const T*>(c->d_cfield) : nullptr;
   a.tau = T(rule.tau);
   a.beta1 = T(rule.beta1);
@@ -423,11 +425,27 @@ int launch_sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst,
   return FE_OK;
 }
 
-int sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, const double* shift_in,
-          double* shift_out, double* energy_dev, const StepRule& rule) {
-  return c->grid.dtype == FE_F32
-             ? launch_sweep<float>(c, s, kind, src, dst, shift_in, shift_out, energy_dev, rule)
-             : launch_sweep<double>(c, s, kind, src, dst, shift_in, shift_out, energy_dev, rule);
+int sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, const double* prev_partials,
+          double* partials, const StepRule& rule, int t_add = 0) {
+  return c->grid.dtype == FE_F32 ? launch_sweep<float>(c, s, kind, src, dst, prev_partials, partials, rule, t_add)
+                                 : launch_sweep<double>(c, s, kind, src, dst, prev_partials, partials, rule, t_add);
+}
+
+// Per-instance totals of the sweep that wrote `partials` (same launch shape):
+// energy_dev[b] and, when shift is given, shift[b] = mass[b] - mean of its field.
+int finish_sums(fe_ctx* c, hipStream_t s, const double* partials, double* energy_dev, double* shift) {
+  const Geometry geo = geometry(c, sweep_variant(c), c->lz);
+  hipLaunchKernelGGL(fe::sweep_finish, dim3(c->grid.batch), dim3(64), 0, s, partials, geo.per_inst, energy_dev,
+                     (const double*)c->d_mass, 1.0 / ((double)c->grid.nx * c->grid.ny * c->grid.nz), shift);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+// A gradient (or energy-only, kind -1) sweep and its energies into energy_dev.
+int sweep_energy(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, double* energy_dev) {
+  const StepRule none{fe::kGrad, 0.0, 0.0, 0.0, 0.0};
+  int rc = sweep(c, s, kind, src, dst, nullptr, partials_buf(c, 0), none);
+  return rc ? rc : finish_sums(c, s, partials_buf(c, 0), energy_dev, nullptr);
 }
 
 int copy_energy_out(fe_ctx* c, double* energy) {
@@ -444,10 +462,10 @@ void drop_graphs(fe_ctx* c) {
   c->graphs.clear();
 }
 
-// One descent step: src (+ shift_in) -> dst, then shift_out = mass - mean(dst).
-int step_once(fe_ctx* c, hipStream_t s, const void* src, void* dst, const double* shift_in, double* shift_out,
-              const StepRule& rule) {
-  return sweep(c, s, rule.mode, src, dst, shift_in, shift_out, c->d_energy, rule);
+int adam_tick_launch(fe_ctx* c, hipStream_t s, int n) {
+  hipLaunchKernelGGL(fe::adam_tick, dim3(1), dim3(64), 0, s, c->d_adam_t, n);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
 }
 
 int adam_reset_launch(fe_ctx* c) {
@@ -479,23 +497,35 @@ int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int 
     }
   }
   FE_HIP(hipMemcpyAsync(c->d_mass, mass, sizeof(double) * B, hipMemcpyHostToDevice, c->stream));
-  double* s0 = c->d_shift;        // shift of the ping-pong field
-  double* s1 = c->d_shift + B;    // shift of u
-  hipLaunchKernelGGL(fe::fill_f64, dim3(ceil_div(B, 64)), dim3(64), 0, c->stream, s1, B, 0.0);
-  FE_HIP(hipGetLastError());
   void* A = c->d_pingpong;
+  double* P0 = partials_buf(c, 0);
+  double* P1 = partials_buf(c, 1);
+  const bool adam = rule.mode == fe::kStepAdam;
+  // Steps launched since the Adam step number was last advanced; step j of
+  // them uses t0 + j.
+  int pending = 0;
+  auto step = [&](hipStream_t s, const void* src, void* dst, const double* prev, double* out, int t_add) {
+    return sweep(c, s, rule.mode, src, dst, prev, out, rule, t_add);
+  };
+  auto tick = [&](hipStream_t s, int n) { return adam && n > 0 ? adam_tick_launch(c, s, n) : FE_OK; };
 
-  // pairs of steps u -> A -> u: whole blocks of kGraphPairs pairs are replayed
-  // from one captured graph (the same graph for any nsteps), the rest launch
-  // directly
-  const int npairs = nsteps / 2;
+  // The first step, u -> A, takes u as it is; every later step adds the shift
+  // that the partials of its predecessor give. The rest come in pairs A -> u
+  // (partials P1), u -> A (partials P0): whole blocks of kGraphPairs pairs are
+  // replayed from one captured graph (the same graph for any nsteps), the
+  // others launch directly.
+  int rc = step(c->stream, u, A, nullptr, P0, pending++);
+  if (rc) return rc;
+  const int npairs = (nsteps - 1) / 2;
   const int gpairs = npairs >= kGraphPairs ? kGraphPairs : 0;
   for (int i = 0; i < (gpairs ? npairs % gpairs : npairs); ++i) {
-    int rc = step_once(c, c->stream, u, A, s1, s0, rule);
-    if (rc == FE_OK) rc = step_once(c, c->stream, A, u, s0, s1, rule);
+    rc = step(c->stream, A, u, P0, P1, pending++);
+    if (rc == FE_OK) rc = step(c->stream, u, A, P1, P0, pending++);
     if (rc) return rc;
   }
   if (gpairs > 0) {
+    if ((rc = tick(c->stream, pending))) return rc;
+    pending = 0;
     GraphKey key{u,      rule.mode,           rule.tau, rule.beta1,     rule.beta2, rule.adam_eps, 0.0,
                  gpairs, sweep_variant(c), c->lz,    fields_in_use(c)};
     auto it = c->graphs.find(key);
@@ -503,11 +533,11 @@ int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int 
     if (it == c->graphs.end()) {
       hipGraph_t graph = nullptr;
       FE_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-      int rc = FE_OK;
       for (int i = 0; i < gpairs && rc == FE_OK; ++i) {
-        rc = step_once(c, c->cap_stream, u, A, s1, s0, rule);
-        if (rc == FE_OK) rc = step_once(c, c->cap_stream, A, u, s0, s1, rule);
+        rc = step(c->cap_stream, A, u, P0, P1, 2 * i);
+        if (rc == FE_OK) rc = step(c->cap_stream, u, A, P1, P0, 2 * i + 1);
       }
+      if (rc == FE_OK) rc = tick(c->cap_stream, 2 * gpairs);
       hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
       if (rc) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -524,16 +554,19 @@ int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int 
     }
     for (int r = 0; r < npairs / gpairs; ++r) FE_HIP(hipGraphLaunch(exec, c->stream));
   }
+  const void* last = A;
+  const double* last_p = P0;
+  if ((nsteps - 1) % 2) {
+    if ((rc = step(c->stream, A, u, P0, P1, pending++))) return rc;
+    last = u;
+    last_p = P1;
+  }
+  if ((rc = tick(c->stream, pending))) return rc;
+  // the energy of the last step's input and the shift of its output
+  double* shift = c->d_shift;
+  if ((rc = finish_sums(c, c->stream, last_p, c->d_energy, shift))) return rc;
   const size_t per_inst = (size_t)c->grid.nx * c->grid.ny * c->grid.nz;
   const int nblk = (int)std::min<size_t>((field_elems(c->grid) + 255) / 256, 65536);
-  const void* last = u;
-  const double* shift = s1;
-  if (nsteps % 2) {
-    int rc = step_once(c, c->stream, u, A, s1, s0, rule);
-    if (rc) return rc;
-    last = A;
-    shift = s0;
-  }
   if (c->grid.dtype == FE_F32)
     hipLaunchKernelGGL(fe::add_shift<float>, dim3(nblk), dim3(256), 0, c->stream, (const float*)last, (float*)u,
                        shift, per_inst, B);
@@ -591,15 +624,11 @@ int fe_create(const fe_grid* grid, const double* eps, const double* p_coeffs, vo
   c->max_blocks = mb;
   const size_t prm_bytes = grid->dtype == FE_F32 ? sizeof(fe::InstParams<float>) : sizeof(fe::InstParams<double>);
   if (hipMalloc(&c->d_prm, prm_bytes * grid->batch) != hipSuccess ||
-      hipMalloc((void**)&c->d_partials, sizeof(double) * 2 * mb * grid->batch) != hipSuccess ||
+      hipMalloc((void**)&c->d_partials, sizeof(double) * 4 * mb * grid->batch) != hipSuccess ||
       hipMalloc((void**)&c->d_energy, sizeof(double) * grid->batch) != hipSuccess ||
       hipMalloc((void**)&c->d_mass, sizeof(double) * grid->batch) != hipSuccess ||
-      hipMalloc((void**)&c->d_shift, sizeof(double) * 2 * grid->batch) != hipSuccess ||
-      hipMalloc((void**)&c->d_counters, sizeof(int) * (grid->batch + 1)) != hipSuccess)
+      hipMalloc((void**)&c->d_shift, sizeof(double) * grid->batch) != hipSuccess)
     return fail(set_error(FE_ENOMEM, "device workspace allocation failed"));
-  hipLaunchKernelGGL(fe::fill_i32, dim3(ceil_div(grid->batch + 1, 64)), dim3(64), 0, c->stream, c->d_counters,
-                     grid->batch + 1, 0);
-  if (hipGetLastError() != hipSuccess) return fail(set_error(FE_EHIP, "counter initialisation failed"));
   rc = upload_params(c);
   if (rc) return fail(rc);
   *out = c;
@@ -712,9 +741,7 @@ int fe_energy_grad_async(fe_ctx* c, const void* u, void* g, double* energy_dev) 
   if (!u) return set_error(FE_EINVAL, "u is NULL");
   if (g == u) return set_error(FE_EINVAL, "g must not alias u");
   DeviceGuard dg(c->device);
-  const StepRule none{fe::kGrad, 0.0, 0.0, 0.0, 0.0};
-  return sweep(c, c->stream, g ? fe::kGrad : -1, u, g, nullptr, nullptr, energy_dev ? energy_dev : c->d_energy,
-               none);
+  return sweep_energy(c, c->stream, g ? fe::kGrad : -1, u, g, energy_dev ? energy_dev : c->d_energy);
 }
 
 int fe_energy(fe_ctx* c, const void* u, double* energy) {
@@ -864,7 +891,6 @@ void fe_destroy(fe_ctx* c) {
   if (c->d_energy) (void)hipFree(c->d_energy);
   if (c->d_mass) (void)hipFree(c->d_mass);
   if (c->d_shift) (void)hipFree(c->d_shift);
-  if (c->d_counters) (void)hipFree(c->d_counters);
   if (c->d_pingpong) (void)hipFree(c->d_pingpong);
   if (c->d_m1) (void)hipFree(c->d_m1);
   if (c->d_m2) (void)hipFree(c->d_m2);

@@ -98,7 +98,8 @@ int flow_field(fe_ctx* c, hipStream_t s, const void* A, T* out, double sigma_k, 
   return FE_OK;
 }
 
-// One iteration of Algorithm 1 on A (in place), energies into d_energy.
+// One iteration of Algorithm 1 on A (in place); the energy of its field stays
+// in the block partials (partials_buf 0) for finish_sums.
 template <typename T>
 int flow_iteration(fe_ctx* c, hipStream_t s, void* A, const FlowRule& fr) {
   T* w0 = static_cast<T*>(c->d_w0);
@@ -108,9 +109,9 @@ int flow_iteration(fe_ctx* c, hipStream_t s, void* A, const FlowRule& fr) {
   // ub = k * (div A + m0) in w0
   int rc = flow_field<T>(c, s, A, w0, fr.sigma_k, c->d_flow_clk, fr.beta1, fr.beta2);
   if (rc) return rc;
-  // gb = dF/du at ub, in w1 (energy of ub into d_energy)
+  // gb = dF/du at ub, in w1 (the energy of ub stays in the block partials)
   const StepRule none{fe::kGrad, 0.0, 0.0, 0.0, 0.0};
-  rc = sweep(c, s, fe::kGrad, w0, w1, nullptr, nullptr, c->d_energy, none);
+  rc = sweep(c, s, fe::kGrad, w0, w1, nullptr, partials_buf(c, 0), none);
   if (rc) return rc;
   // gu = k * gb: x pass into w0, y pass into w1, z pass into w0 (for r = 4, 8
   // the fused x-y pass into w0 and the z pass into w1)
@@ -227,6 +228,8 @@ int fe_hminus_step(fe_ctx* c, void* A, const double* m0, double sigma_k, double 
     if (energy) for (int b = 0; b < c->grid.batch; ++b) energy[b] = 0.0;
     return FE_OK;
   }
+  int rc = finish_sums(c, c->stream, partials_buf(c, 0), c->d_energy, nullptr);   // the last iteration's G
+  if (rc) return rc;
   return copy_energy_out(c, energy);
 }
 

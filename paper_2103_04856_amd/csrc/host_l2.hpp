@@ -167,8 +167,7 @@ int l2_eval_dev(fe_l2* L) {
     hipLaunchKernelGGL(fe::pad_replicate<T>, pg, dim3(256), 0, s, w2, L->box);
     ub = w2;
   }
-  const StepRule none{fe::kGrad, 0.0, 0.0, 0.0, 0.0};
-  int rc = sweep(L->ctx, s, fe::kGrad, ub, w0, nullptr, nullptr, L->ctx->d_energy, none);   // w0 = g_ext
+  int rc = sweep_energy(L->ctx, s, fe::kGrad, ub, w0, L->ctx->d_energy);   // w0 = g_ext
   if (rc) return rc;
   if (L->r > 0) {
     hipLaunchKernelGGL(fe::fold_pads<T>, pg, dim3(256), 0, s, (const T*)w0, w1, L->box);   // w1 = gb
