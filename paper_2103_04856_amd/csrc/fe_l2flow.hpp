@@ -22,38 +22,97 @@ struct PadBox {
 
 __device__ __forceinline__ int clamp_to(int v, int lo, int hi) { return v < lo ? lo : (v >= hi ? hi - 1 : v); }
 
-// Launch shape of the padding kernels: one thread per sample of a row of 256,
-// grid (ceil(nx/256), ny, nz).
 // Fill every pad sample with the nearest box voxel (reads box voxels only).
+// Threads enumerate the pad shell alone, in three regions: the planes below
+// and above the box in z, then within the box's z range the rows below and
+// above it in y, then within the box's y and z ranges the runs left and right
+// of it in x. Grid: ceil(shell / 256) blocks of 256 (pad_shell_size).
+__host__ __device__ __forceinline__ size_t pad_shell_size(const PadBox& b) {
+  const size_t bx = b.hi[0] - b.lo[0], by = b.hi[1] - b.lo[1], bz = b.hi[2] - b.lo[2];
+  const size_t px = b.nx - bx, py = b.ny - by, pz = b.nz - bz;
+  return pz * b.ny * b.nx + bz * py * b.nx + bz * by * px;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void pad_replicate(T* __restrict__ f, PadBox b) {
-  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
-  if (x >= b.nx) return;
+  const size_t bx = b.hi[0] - b.lo[0], by = b.hi[1] - b.lo[1], bz = b.hi[2] - b.lo[2];
+  const size_t px = b.nx - bx, py = b.ny - by, pz = b.nz - bz;
+  const size_t nA = pz * b.ny * b.nx, nB = bz * py * b.nx, nC = bz * by * px;
+  size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int x, y, z;
+  if (j < nA) {
+    const size_t plane = (size_t)b.nx * b.ny;
+    const int k = (int)(j / plane), r = (int)(j % plane);
+    z = k < b.lo[2] ? k : b.hi[2] + (k - b.lo[2]);
+    y = r / b.nx;
+    x = r % b.nx;
+  } else if ((j -= nA) < nB) {
+    const size_t per = py * b.nx;
+    const int k = (int)(j / per), r = (int)(j % per);
+    const int ky = r / b.nx;
+    z = b.lo[2] + k;
+    y = ky < b.lo[1] ? ky : b.hi[1] + (ky - b.lo[1]);
+    x = r % b.nx;
+  } else if ((j -= nB) < nC) {
+    const int row = (int)(j / px), kx = (int)(j % px);
+    z = b.lo[2] + row / (int)by;
+    y = b.lo[1] + row % (int)by;
+    x = kx < b.lo[0] ? kx : b.hi[0] + (kx - b.lo[0]);
+  } else {
+    return;
+  }
   const int cx = clamp_to(x, b.lo[0], b.hi[0]), cy = clamp_to(y, b.lo[1], b.hi[1]), cz = clamp_to(z, b.lo[2], b.hi[2]);
-  if (cx != x || cy != y || cz != z)
-    f[((size_t)z * b.ny + y) * b.nx + x] = f[((size_t)cz * b.ny + cy) * b.nx + cx];
+  f[((size_t)z * b.ny + y) * b.nx + x] = f[((size_t)cz * b.ny + cy) * b.nx + cx];
 }
 
 // out = P^T g: every box voxel gathers the pad samples that copy it (on a box
-// face, the whole run of pad samples beyond it along each clamped axis); pad
-// samples of out are zero. g and out must differ.
-template <typename T>
+// face, the run of pad samples beyond it along each clamped axis, the voxel
+// included); pad samples of out are zero; voxels off the box surface copy g.
+// W > 0: every pad is W wide, so a run on one face is W + 1 samples at fixed
+// offsets (unrolled, all loads in flight); W = 0: general runs. Edges and
+// corners (two or three clamped axes) take the general loop. One thread per
+// sample of a plane: grid (ceil(nx ny / 256), nz). g and out must differ.
+template <typename T, int W>
 __global__ __launch_bounds__(256) void fold_pads(const T* __restrict__ g, T* __restrict__ out, PadBox b) {
-  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
-  if (x >= b.nx) return;
-  const size_t i = ((size_t)z * b.ny + y) * b.nx + x;
+  const int ip = blockIdx.x * 256 + threadIdx.x, z = blockIdx.y;
+  if (ip >= b.nx * b.ny) return;
+  const int y = ip / b.nx, x = ip - y * b.nx;
+  const size_t i = (size_t)z * b.nx * b.ny + ip;
   const bool in = x >= b.lo[0] && x < b.hi[0] && y >= b.lo[1] && y < b.hi[1] && z >= b.lo[2] && z < b.hi[2];
   if (!in) {
     out[i] = T(0);
     return;
   }
-  const int x0 = x == b.lo[0] ? 0 : x, x1 = x == b.hi[0] - 1 ? b.nx - 1 : x;
-  const int y0 = y == b.lo[1] ? 0 : y, y1 = y == b.hi[1] - 1 ? b.ny - 1 : y;
-  const int z0 = z == b.lo[2] ? 0 : z, z1 = z == b.hi[2] - 1 ? b.nz - 1 : z;
-  if (x0 == x1 && y0 == y1 && z0 == z1) {
+  const bool fx = x == b.lo[0] || x == b.hi[0] - 1, fy = y == b.lo[1] || y == b.hi[1] - 1,
+             fz = z == b.lo[2] || z == b.hi[2] - 1;
+  const int nf = int(fx) + int(fy) + int(fz);
+  if (nf == 0) {
     out[i] = g[i];
     return;
   }
+  if (W > 0 && nf == 1) {
+    // the run from the voxel outwards along its one clamped axis
+    const int lo = fx ? b.lo[0] : fy ? b.lo[1] : b.lo[2];
+    const int c = fx ? x : fy ? y : z;
+    const long step = fx ? 1 : fy ? (long)b.nx : (long)b.nx * b.ny;
+    const long dir = c == lo ? -step : step;
+    T v[W + 1];
+#pragma unroll
+    for (int k = 0; k <= W; ++k) v[k] = g[(long)i + k * dir];
+    T acc = T(0);                // in increasing index order, as the general loop adds
+    if (dir < 0) {
+#pragma unroll
+      for (int k = W; k >= 0; --k) acc += v[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k <= W; ++k) acc += v[k];
+    }
+    out[i] = acc;
+    return;
+  }
+  const int x0 = x == b.lo[0] ? 0 : x, x1 = x == b.hi[0] - 1 ? b.nx - 1 : x;
+  const int y0 = y == b.lo[1] ? 0 : y, y1 = y == b.hi[1] - 1 ? b.ny - 1 : y;
+  const int z0 = z == b.lo[2] ? 0 : z, z1 = z == b.hi[2] - 1 ? b.nz - 1 : z;
   T acc = T(0);
   for (int zz = z0; zz <= z1; ++zz)
     for (int yy = y0; yy <= y1; ++yy)

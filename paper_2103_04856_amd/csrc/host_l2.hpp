@@ -126,12 +126,6 @@ int l2_scale_add(fe_l2* L, double alpha, const void* x, bool acc, void* y) {
   return l2_update<T>(L, L2Coef{-1, 0.0, -1, 0.0, alpha}, acc, x, y);
 }
 
-template <typename T>
-int l2_copy(fe_l2* L, const void* src, void* dst) {
-  FE_HIP(hipMemcpyAsync(dst, src, L->n * sizeof(T), hipMemcpyDeviceToDevice, L->ctx->stream));
-  return FE_OK;
-}
-
 // The separable blur passes on the padded array (periodic within it):
 // in -> tmp1 (x) -> tmp2 (y) -> out (z), or in -> tmp1 (fused x-y) -> out (z)
 // for r = 4, 8; in and out may coincide, tmp1/tmp2 not.
@@ -149,36 +143,57 @@ void l2_blur(fe_l2* L, const T* in, T* tmp1, T* tmp2, T* out) {
   blur_yz<T>(s, d, k, tmp1, tmp2, out);
 }
 
+// The padding kernels: replicate padding over the pad shell, and its
+// transpose (fixed-width runs for the pad widths 1, 4 and 8).
+template <typename T>
+void l2_pad(fe_l2* L, T* f) {
+  const size_t n = fe::pad_shell_size(L->box);
+  if (n == 0) return;
+  hipLaunchKernelGGL(fe::pad_replicate<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, L->ctx->stream, f,
+                     L->box);
+}
+
+template <typename T>
+void l2_fold(fe_l2* L, const T* g, T* out) {
+  const dim3 grid((unsigned)ceil_div(L->box.nx * L->box.ny, 256), (unsigned)L->box.nz);
+  hipStream_t s = L->ctx->stream;
+  const int W = L->box.lo[0];
+  if (W == 4)
+    hipLaunchKernelGGL((fe::fold_pads<T, 4>), grid, dim3(256), 0, s, g, out, L->box);
+  else if (W == 8)
+    hipLaunchKernelGGL((fe::fold_pads<T, 8>), grid, dim3(256), 0, s, g, out, L->box);
+  else if (W == 1)
+    hipLaunchKernelGGL((fe::fold_pads<T, 1>), grid, dim3(256), 0, s, g, out, L->box);
+  else
+    hipLaunchKernelGGL((fe::fold_pads<T, 0>), grid, dim3(256), 0, s, g, out, L->box);
+}
+
 // F_h(k * x) with replicate boundaries into the energy slot and g = its
 // gradient (zero padding), stream-ordered.
 template <typename T>
 int l2_eval_dev(fe_l2* L) {
-  hipStream_t s = L->ctx->stream;
-  const dim3 pg((L->box.nx + 255) / 256, L->box.ny, L->box.nz);   // the padding kernels' grid
   T* x = static_cast<T*>(L->x);
   T* g = static_cast<T*>(L->g);
   T* w0 = static_cast<T*>(L->w0);
   T* w1 = static_cast<T*>(L->w1);
   T* w2 = static_cast<T*>(L->w2);
-  hipLaunchKernelGGL(fe::pad_replicate<T>, pg, dim3(256), 0, s, x, L->box);
+  l2_pad<T>(L, x);
   const T* ub = x;
   if (L->r > 0) {
     l2_blur<T>(L, x, w0, w1, w2);             // w2 = k * x
-    hipLaunchKernelGGL(fe::pad_replicate<T>, pg, dim3(256), 0, s, w2, L->box);
+    l2_pad<T>(L, w2);
     ub = w2;
   }
-  int rc = sweep_energy(L->ctx, s, fe::kGrad, ub, w0, L->ctx->d_energy);   // w0 = g_ext
+  int rc = sweep_energy(L->ctx, L->ctx->stream, fe::kGrad, ub, w0, l2_vals(L) + kSlotE);   // w0 = g_ext
   if (rc) return rc;
   if (L->r > 0) {
-    hipLaunchKernelGGL(fe::fold_pads<T>, pg, dim3(256), 0, s, (const T*)w0, w1, L->box);   // w1 = gb
+    l2_fold<T>(L, w0, w1);                    // w1 = gb
     l2_blur<T>(L, w1, w0, w2, w1);           // w1 = k * gb (zero-extended)
-    hipLaunchKernelGGL(fe::fold_pads<T>, pg, dim3(256), 0, s, (const T*)w1, g, L->box);
+    l2_fold<T>(L, w1, g);
   } else {
-    hipLaunchKernelGGL(fe::fold_pads<T>, pg, dim3(256), 0, s, (const T*)w0, g, L->box);
+    l2_fold<T>(L, w0, g);
   }
   FE_HIP(hipGetLastError());
-  FE_HIP(hipMemcpyAsync(l2_vals(L) + kSlotE, L->ctx->d_energy, sizeof(double),
-                        hipMemcpyDeviceToDevice, s));
   return FE_OK;
 }
 
@@ -240,8 +255,9 @@ int l2_step(fe_l2* L, double& loss0) {
           L->rho.erase(L->rho.begin());
           --L->hist_len;
         }
-        if ((rc = l2_copy<T>(L, L->q, L->Y[L->hist_len]))) return rc;
-        if ((rc = l2_copy<T>(L, L->w0, L->S[L->hist_len]))) return rc;
+        // the new pair takes over the buffers of y and s; theirs become scratch
+        std::swap(L->q, L->Y[L->hist_len]);
+        std::swap(L->w0, L->S[L->hist_len]);
         L->rho.push_back(1.0 / ys);
         ++L->hist_len;
         L->H_diag = ys / yy;
@@ -267,11 +283,13 @@ int l2_step(fe_l2* L, double& loss0) {
           return rc;
       }
     }
-    if ((rc = l2_copy<T>(L, L->g, L->prev_g))) return rc;
+    // prev_g takes over the gradient's buffer; the next evaluation writes g anew
+    // (until then the current gradient is prev_g)
+    std::swap(L->g, L->prev_g);
     L->prev_loss = loss;
     const bool first = L->n_iter == 1;
-    if ((rc = l2_reduce_dev<T>(L, 0, L->g, L->d, kSlotGtd))) return rc;
-    if (first && (rc = l2_reduce_dev<T>(L, 1, L->g, nullptr, kSlotL1))) return rc;
+    if ((rc = l2_reduce_dev<T>(L, 0, L->prev_g, L->d, kSlotGtd))) return rc;
+    if (first && (rc = l2_reduce_dev<T>(L, 1, L->prev_g, nullptr, kSlotL1))) return rc;
     double gl[2];
     if ((rc = l2_read_slots(L, kSlotGtd, first ? 2 : 1, gl))) return rc;
     L->t = first ? std::min(1.0, 1.0 / gl[1]) * L->lr : L->lr;
