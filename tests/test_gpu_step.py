@@ -123,6 +123,21 @@ def test_adam_first_steps_match_oracle():
         assert torch.equal(ud2, ud)
 
 
+def test_adam_long_call_matches_oracle():
+    """One call of 37 Adam steps (the first step, two directly launched pairs and a
+    replay of the 16-step graph): the step numbers in the bias corrections advance
+    across direct launches and graph replays exactly as the oracle's do."""
+    n = 12
+    h = 1.0 / n
+    u0 = inputs.uniform_noise(n, 1009)
+    ud = to_dev(u0, torch.float64)
+    ctx = fe.FeContext((1, n, n, n), h, 2 * h, ASYM_C3, dtype=torch.float64)
+    E = ctx.step_adam(ud, [-0.2], 37)
+    uo, Es = fo.descend_adam(oracle_input(to_dev(u0, torch.float64)), h, 2 * h, ASYM_C3, -0.2, 37)
+    assert rel_l2(ud.cpu().numpy(), uo) <= 1e-10
+    assert abs(E[0].item() - Es[-1]) <= 1e-10 * abs(Es[-1])
+
+
 def test_adam_graph_replay_equals_single_steps():
     n = 16
     h = 1.0 / n
