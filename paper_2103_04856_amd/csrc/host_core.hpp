@@ -308,12 +308,24 @@ Geometry geometry(const fe_ctx* c, int variant, int lz_req) {
   g.nty = ceil_div(c->grid.ny, v.ty);
   int lz = lz_req;
   if (lz <= 0) {
-    // the longest power-of-two chunk (fewest recomputed boundary planes) that
-    // still fills every resident block slot of the device, and at least 4 planes
+    const int nz = c->grid.nz;
     const double cols = (double)g.ntx * g.nty * c->grid.batch;
     const double slots = (double)c->num_cu * block_slots(c, variant);
-    lz = 4;
-    while (2 * lz <= c->grid.nz && cols * ceil_div(c->grid.nz, 2 * lz) >= slots) lz *= 2;
+    if (cols * ceil_div(nz, 4) < slots) {
+      // too few columns to fill the resident block slots even with short
+      // chunks: one block per compute unit, with the chunks that gives (one
+      // block alone on a CU is slower per plane than two sharing it, but the
+      // extra boundary planes of chunks short enough for two cost more)
+      const int nzc = std::max(1, (int)(c->num_cu / cols));
+      lz = std::max(2, ceil_div(nz, nzc));
+    } else {
+      // the longest power-of-two chunk (fewest recomputed boundary planes)
+      // that still fills every resident block slot, at least 4 planes; then
+      // the same number of chunks made equal, so no chunk runs short
+      lz = 4;
+      while (2 * lz <= nz && cols * ceil_div(nz, 2 * lz) >= slots) lz *= 2;
+      lz = ceil_div(nz, ceil_div(nz, lz));
+    }
   }
   lz = std::min(std::max(lz, 1), c->grid.nz);
   g.lz = lz;
@@ -844,14 +856,23 @@ int fe_autotune(fe_ctx* c, const void* u, void* g, int iters, double* best_us) {
   FE_HIP(hipEventCreate(&e1));
   double best = 1e300;
   int best_v = keep_v, best_lz = keep_lz;
-  const int lzs[] = {4, 8, 16, 32, 64, 128};
   int rc = FE_OK;
   for (int v = 0; v < (int)variants().size() && rc == FE_OK; ++v) {
     if (!variant_ok(v, c->grid.dtype)) continue;
     const Variant& x = variants()[v];
     if (x.tx > 2 * c->grid.nx || x.ty > 2 * c->grid.ny) continue;
+    // z chunks: powers of two from 4, the equal-chunk length with as many
+    // chunks as each, and the automatic choice
+    std::vector<int> lzs;
+    const int nz = c->grid.nz;
+    for (int p = 4; p <= 128 && p <= nz; p *= 2) {
+      lzs.push_back(p);
+      lzs.push_back(ceil_div(nz, ceil_div(nz, p)));
+    }
+    lzs.push_back(geometry(c, v, 0).lz);
+    std::sort(lzs.begin(), lzs.end());
+    lzs.erase(std::unique(lzs.begin(), lzs.end()), lzs.end());
     for (int lz : lzs) {
-      if (lz > c->grid.nz) continue;
       c->variant = v;
       c->lz = lz;
       rc = fe_energy_grad_async(c, u, g, nullptr);   // warm-up
