@@ -10,7 +10,7 @@
 // One iteration is: blur_x<DIV> (div A + m0, blurred along x), blur_axis<1>,
 // blur_axis<2>, the sweep, blur_x of dF/du, blur_axis<1>, blur_axis<2>,
 // adam_vector_field; for the radii 4 and 8 the blur of dF/du runs blur_xy
-// (x and y in one pass) and blur_axis<2>. Without blur (r = 0) only the first kernel, the sweep and the
+// (x and y in one pass) and adam_zblur (the z pass fused with Adam). Without blur (r = 0) only the first kernel, the sweep and the
 // Adam kernel run. Every kernel is a 64-wide row of x per wave, so loads
 // and stores are coalesced; the blur halos are staged in LDS.
 #pragma once
@@ -318,6 +318,82 @@ __global__ __launch_bounds__(256) void adam_vector_field(const T* __restrict__ g
     m1[i0 + a * vol] = mo;
     m2[i0 + a * vol] = vo;
     A[i0 + a * vol] = av[a] - lr * (mo * bc1) * rcp_t(sqrt_t(vo * bc2) + adam_eps);
+  }
+}
+
+// The z blur of w and Adam on A in one pass, for the fixed radii R: g = blur_z(w)
+// never goes to memory. A block owns 64 x 4 columns and kAdamZ consecutive
+// planes. Phase 1: every column of the tile and its one-column ring (66 x 6)
+// is blurred along z over the planes z0 - 1 .. z0 + kAdamZ from a register
+// window of kAdamZ + 2 + 2R samples (each thread one or two columns), into LDS.
+// Phase 2: each thread updates its column's voxels plane by plane, with the
+// neighbours of the central differences from LDS. Sums and update are formed
+// in the same order as blur_axis<2> followed by adam_vector_field.
+// Block (64, 4); grid (ceil(nx/64), ceil(ny/4), ceil(nz/kAdamZ) * batch).
+constexpr int kAdamZ = 16;
+
+template <typename T, int R>
+__global__ __launch_bounds__(256) void adam_zblur(const T* __restrict__ w, T* __restrict__ A, T* __restrict__ m1,
+                                                  T* __restrict__ m2, FieldDims d, BlurTaps<T> k, T inv2h, T lr,
+                                                  T beta1, T beta2, T adam_eps, const FlowClock* __restrict__ clk) {
+  static_assert(R > 0 && R <= kBlurMaxR, "adam_zblur needs a fixed radius");
+  constexpr int CX = 66, CY = 6, NC = CX * CY;  // tile columns with their ring
+  constexpr int NP = kAdamZ + 2;                // blurred planes z0 - 1 .. z0 + kAdamZ
+  constexpr int NWIN = NP + 2 * R;              // samples per column
+  __shared__ T sg[NP][NC];
+  const int tid = threadIdx.y * 64 + threadIdx.x;
+  const int nzc = (d.nz + kAdamZ - 1) / kAdamZ;
+  const int z0 = (blockIdx.z % nzc) * kAdamZ, b = blockIdx.z / nzc;
+  const int x0 = blockIdx.x * 64, y0 = blockIdx.y * 4;
+  const size_t plane = (size_t)d.nx * d.ny, vol = plane * d.nz;
+  const T* wb = w + (size_t)b * vol;
+  // phase 1: the z blur of the columns of the tile and its ring
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc) {
+    const int c = tid + 256 * cc;
+    if (c >= NC) continue;
+    const int gx = wrap_any(x0 - 1 + c % CX, d.nx), gy = wrap_any(y0 - 1 + c / CX, d.ny);
+    const T* col = wb + (size_t)gy * d.nx + gx;
+    T v[NWIN];
+#pragma unroll
+    for (int i = 0; i < NWIN; ++i) v[i] = col[(size_t)wrap_any(z0 - 1 - R + i, d.nz) * plane];
+#pragma unroll
+    for (int o = 0; o < NP; ++o) {
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j <= 2 * R; ++j) acc += k.w[j] * v[o + j];
+      sg[o][c] = acc;
+    }
+  }
+  __syncthreads();
+  // phase 2: Adam on the tile's voxels, plane by plane
+  const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
+  if (x >= d.nx || y >= d.ny) return;
+  const int cc = (threadIdx.y + 1) * CX + threadIdx.x + 1;
+  const T bc1 = T(clk->bc1), bc2 = T(clk->bc2);
+  for (int o = 0; o < kAdamZ; ++o) {
+    const int z = z0 + o;
+    if (z >= d.nz) break;
+    const size_t i0 = (size_t)b * 3 * vol + (size_t)z * plane + (size_t)y * d.nx + x;
+    T av[3], m1v[3], m2v[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      av[a] = A[i0 + a * vol];
+      m1v[a] = m1[i0 + a * vol];
+      m2v[a] = m2[i0 + a * vol];
+    }
+    const T gxp = sg[o + 1][cc + 1], gxm = sg[o + 1][cc - 1];
+    const T gyp = sg[o + 1][cc + CX], gym = sg[o + 1][cc - CX];
+    const T gzp = sg[o + 2][cc], gzm = sg[o][cc];
+    const T grad[3] = {-(gxp - gxm) * inv2h, -(gyp - gym) * inv2h, -(gzp - gzm) * inv2h};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T mo = beta1 * m1v[a] + (T(1) - beta1) * grad[a];
+      const T vo = beta2 * m2v[a] + (T(1) - beta2) * grad[a] * grad[a];
+      m1[i0 + a * vol] = mo;
+      m2[i0 + a * vol] = vo;
+      A[i0 + a * vol] = av[a] - lr * (mo * bc1) * rcp_t(sqrt_t(vo * bc2) + adam_eps);
+    }
   }
 }
 

@@ -113,20 +113,31 @@ int flow_iteration(fe_ctx* c, hipStream_t s, void* A, const FlowRule& fr) {
   const StepRule none{fe::kGrad, 0.0, 0.0, 0.0, 0.0};
   rc = sweep(c, s, fe::kGrad, w0, w1, nullptr, partials_buf(c, 0), none);
   if (rc) return rc;
-  // gu = k * gb: x pass into w0, y pass into w1, z pass into w0 (for r = 4, 8
-  // the fused x-y pass into w0 and the z pass into w1)
-  T* gu = w1;
+  const T inv2h = T(1.0 / (2.0 * c->grid.h));
+  const fe::FlowClock* clk = c->d_flow_clk;
   if (has_xy_pass(k.r)) {
+    // r = 4, 8: the fused x-y pass into w0, then the z pass fused with Adam
     blur_xy_pass<T>(s, d, k, (const T*)w1, w0);
-    blur_axis_pass<T, 2>(s, d, k, w0, w1);
-  } else if (k.r > 0) {
+    const dim3 g(ceil_div(d.nx, 64), ceil_div(d.ny, 4), ceil_div(d.nz, fe::kAdamZ) * d.batch), b(64, 4);
+    if (k.r == 4)
+      hipLaunchKernelGGL((fe::adam_zblur<T, 4>), g, b, 0, s, (const T*)w0, (T*)A, (T*)c->d_am1, (T*)c->d_am2, d,
+                         k, inv2h, T(fr.lr), T(fr.beta1), T(fr.beta2), T(fr.adam_eps), clk);
+    else
+      hipLaunchKernelGGL((fe::adam_zblur<T, 8>), g, b, 0, s, (const T*)w0, (T*)A, (T*)c->d_am1, (T*)c->d_am2, d,
+                         k, inv2h, T(fr.lr), T(fr.beta1), T(fr.beta2), T(fr.adam_eps), clk);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+  }
+  // gu = k * gb: x pass into w0, y pass into w1, z pass into w0
+  T* gu = w1;
+  if (k.r > 0) {
     blur_x_pass<T, false>(s, d, k, (const T*)w1, w0, nullptr, nullptr, T(0), nullptr, 0.0, 0.0);
     blur_yz<T>(s, d, k, w0, w1, w0);
     gu = w0;
   }
   hipLaunchKernelGGL(fe::adam_vector_field<T>, row_grid(d), dim3(64, 4), 0, s, (const T*)gu, (T*)A,
-                     (T*)c->d_am1, (T*)c->d_am2, d, T(1.0 / (2.0 * c->grid.h)), T(fr.lr), T(fr.beta1),
-                     T(fr.beta2), T(fr.adam_eps), (const fe::FlowClock*)c->d_flow_clk);
+                     (T*)c->d_am1, (T*)c->d_am2, d, inv2h, T(fr.lr), T(fr.beta1), T(fr.beta2), T(fr.adam_eps),
+                     clk);
   FE_HIP(hipGetLastError());
   return FE_OK;
 }
