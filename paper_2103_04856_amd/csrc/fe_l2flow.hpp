@@ -221,67 +221,187 @@ __global__ __launch_bounds__(kVecThreads) void vec_reduce(const T* __restrict__ 
   vec_block_partial<OP>(vec_combine<OP>(vec_combine<OP>(acc[0], acc[1]), vec_combine<OP>(acc[2], acc[3])), bank);
 }
 
-// Coefficient of a vector pass, ka v(bank_a) + kb v(bank_b) + kc in FP64, from
-// the values of two dot-product banks (a null bank: that term is absent).
-struct VecCoef {
-  const double* bank_a;
-  double ka;
-  const double* bank_b;
-  double kb;
-  double kc;
+// ---- the L-BFGS direction through Gram matrices ----
+//
+// The two-loop recursion only ever combines the history vectors s_i, y_i and
+// the gradient g linearly, and its scalars are inner products of those
+// vectors. So the host runs the recursion on the inner products (FP64, kept
+// up to date as pairs enter and leave the history) and the device makes two
+// passes per iteration: vec_gram forms the new pair and every inner product
+// the recursion needs, vec_lincomb forms the direction from the coefficients.
+
+// Threads per vec_gram block: a full block for FP32; a quarter for FP64, whose
+// accumulators and packs need twice the registers.
+template <typename T>
+constexpr int gram_threads() { return sizeof(T) == 4 ? kVecThreads : kVecThreads / 4; }
+constexpr int kDotVecs = 12;    // history vectors per vec_gram pass
+constexpr int kCombVecs = 16;   // vectors per vec_lincomb pass
+
+template <typename T>
+struct DotList {
+  const T* v[kDotVecs];
+  int count;
 };
 
-// y = alpha x + y (ACC) or y = alpha x, alpha = the coefficient rounded once to
-// the vector precision; then, when w is given, bank <- partials of w . y (the
-// updated y). Each step of the L-BFGS two-loop recursion is one such pass: the
-// update by one history entry and the dot product that the next entry needs,
-// with no host synchronisation. Layout of the work as in vec_reduce.
-template <typename T, bool ACC>
-__global__ __launch_bounds__(kVecThreads) void vec_update_dot(VecCoef cf, const T* __restrict__ x, T* __restrict__ y,
-                                                              const T* __restrict__ w, size_t n,
-                                                              double* __restrict__ bank) {
-  const double ca = cf.bank_a ? bank_value<0>(cf.bank_a) : 0.0;
-  const double cb = cf.bank_b ? bank_value<0>(cf.bank_b) : 0.0;
-  const T alpha = T(cf.ka * ca + cf.kb * cb + cf.kc);
-  const size_t n4 = n / 4, stride = (size_t)gridDim.x * blockDim.x;
-  const Pack4<T>* px = reinterpret_cast<const Pack4<T>*>(x);
-  Pack4<T>* py = reinterpret_cast<Pack4<T>*>(y);
-  const Pack4<T>* pw = reinterpret_cast<const Pack4<T>*>(w);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < n4; i0 += 2 * stride) {
-    Pack4<T> vx[2], vy[2], vw[2];
+template <typename T>
+struct CombList {
+  const T* v[kCombVecs];
+  double c[kCombVecs];
+  int count;
+};
+
+// The partials of NV values per block, each in a fixed order (the wave's
+// butterfly, then the waves in order), into bank k * kVecBlocks + blockIdx.x.
+template <int NV, int NT>
+__device__ __forceinline__ void vec_block_partials(double (&acc)[NV], int nv, double* __restrict__ banks) {
+  __shared__ double s_w[NV][NT / 64];
+  // every value takes the butterfly (fixed trip counts keep acc in registers)
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const size_t i = i0 + u * stride;
-      vx[u] = vy[u] = vw[u] = Pack4<T>{};
-      if (i < n4) {
-        vx[u] = px[i];
-        if (ACC) vy[u] = py[i];
-        if (w) vw[u] = pw[i];
+  for (int k = 0; k < NV; ++k) {
+    double a = acc[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if (threadIdx.x % 64 == 0) s_w[k][threadIdx.x / 64] = a;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nv; k += NT) {
+    double a = s_w[k][0];
+    for (int wv = 1; wv < NT / 64; ++wv) a += s_w[k][wv];
+    banks[(size_t)k * kVecBlocks + blockIdx.x] = a;
+  }
+}
+
+// One pass of the Gram update. FORM: first y = g - prev_g and s = t d, stored,
+// and the banks 0..4 get y.y, y.s, y.g, g.g, g.s; the listed vectors V_k then
+// give y.V_k and g.V_k in banks NB + 2k and NB + 2k + 1 (NB = 5). Without
+// FORM, y is read and NB = 0. All kDotVecs list entries are read (the host
+// points unused ones at g, and only the first `count` reach the banks), so
+// the loops have fixed trip counts and every value stays in registers. FP64
+// accumulation, packs of four, block 0 takes the n % 4 tail. Grid: kVecBlocks
+// blocks of gram_threads<T>().
+template <typename T, bool FORM>
+__global__ __launch_bounds__(gram_threads<T>()) void vec_gram(const T* __restrict__ g, const T* __restrict__ prev_g,
+                                                              const T* __restrict__ d, double t, T* __restrict__ y,
+                                                              T* __restrict__ s, DotList<T> L, size_t n,
+                                                              double* __restrict__ banks) {
+  constexpr int NB = FORM ? 5 : 0;
+  constexpr int NV = NB + 2 * kDotVecs;
+  const T tt = T(t);
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  const size_t n4 = n / 4, stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+    const Pack4<T> pg = reinterpret_cast<const Pack4<T>*>(g)[i];
+    Pack4<T> py, ps;
+    if constexpr (FORM) {
+      const Pack4<T> pp = reinterpret_cast<const Pack4<T>*>(prev_g)[i];
+      const Pack4<T> pd = reinterpret_cast<const Pack4<T>*>(d)[i];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        py.v[e] = pg.v[e] - pp.v[e];
+        ps.v[e] = tt * pd.v[e];
       }
+      reinterpret_cast<Pack4<T>*>(y)[i] = py;
+      reinterpret_cast<Pack4<T>*>(s)[i] = ps;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double ye = py.v[e], ge = pg.v[e], se = ps.v[e];
+        acc[0] += ye * ye;
+        acc[1] += ye * se;
+        acc[2] += ye * ge;
+        acc[3] += ge * ge;
+        acc[4] += ge * se;
+      }
+    } else {
+      py = reinterpret_cast<const Pack4<T>*>(y)[i];
     }
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const size_t i = i0 + u * stride;
-      Pack4<T> r;
+    for (int k = 0; k < kDotVecs; ++k) {
+      const Pack4<T> pv = reinterpret_cast<const Pack4<T>*>(L.v[k])[i];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) r.v[k] = ACC ? alpha * vx[u].v[k] + vy[u].v[k] : alpha * vx[u].v[k];
-      if (i < n4) {
-        py[i] = r;
-        if (w) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) acc[k] += double(vw[u].v[k]) * double(r.v[k]);
-        }
+      for (int e = 0; e < 4; ++e) {
+        acc[NB + 2 * k] += double(py.v[e]) * double(pv.v[e]);
+        acc[NB + 2 * k + 1] += double(pg.v[e]) * double(pv.v[e]);
       }
     }
   }
   if (blockIdx.x == 0 && threadIdx.x < n - 4 * n4) {
     const size_t j = 4 * n4 + threadIdx.x;
-    const T v = ACC ? alpha * x[j] + y[j] : alpha * x[j];
-    y[j] = v;
-    if (w) acc[0] += double(w[j]) * double(v);
+    const double ge = g[j];
+    double ye;
+    if constexpr (FORM) {
+      const T yt = g[j] - prev_g[j], st = tt * d[j];
+      y[j] = yt;
+      s[j] = st;
+      ye = yt;
+      const double se = st;
+      acc[0] += ye * ye;
+      acc[1] += ye * se;
+      acc[2] += ye * ge;
+      acc[3] += ge * ge;
+      acc[4] += ge * se;
+    } else {
+      ye = y[j];
+    }
+#pragma unroll
+    for (int k = 0; k < kDotVecs; ++k) {
+      const double ve = L.v[k][j];
+      acc[NB + 2 * k] += ye * ve;
+      acc[NB + 2 * k + 1] += ge * ve;
+    }
   }
-  if (w) vec_block_partial<0>((acc[0] + acc[1]) + (acc[2] + acc[3]), bank);
+  vec_block_partials<NV, gram_threads<T>()>(acc, NB + 2 * L.count, banks);
+}
+
+// out = sum_k c_k V_k (+ out when acc), accumulated in FP64 and rounded once;
+// when dmax is given, its bank gets the partials of max |out|. All W list
+// entries are read (the host pads a short list with zero coefficients on a
+// listed vector), so the loop has a fixed trip count. Layout of the work as in
+// vec_reduce.
+template <typename T, int W>
+__global__ __launch_bounds__(kVecThreads) void vec_lincomb(CombList<T> L, T* __restrict__ out, int acc, size_t n,
+                                                           double* __restrict__ dmax) {
+  static_assert(W >= 1 && W <= kCombVecs, "vec_lincomb width");
+  const size_t n4 = n / 4, stride = (size_t)gridDim.x * blockDim.x;
+  double mx = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    if (acc) {
+      const Pack4<T> po = reinterpret_cast<const Pack4<T>*>(out)[i];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[e] = double(po.v[e]);
+    }
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const Pack4<T> pv = reinterpret_cast<const Pack4<T>*>(L.v[k])[i];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[e] += L.c[k] * double(pv.v[e]);
+    }
+    Pack4<T> r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      r.v[e] = T(a[e]);
+      mx = fmax(mx, fabs(double(r.v[e])));
+    }
+    reinterpret_cast<Pack4<T>*>(out)[i] = r;
+  }
+  if (blockIdx.x == 0 && threadIdx.x < n - 4 * n4) {
+    const size_t j = 4 * n4 + threadIdx.x;
+    double a = acc ? double(out[j]) : 0.0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) a += L.c[k] * double(L.v[k][j]);
+    out[j] = T(a);
+    mx = fmax(mx, fabs(double(out[j])));
+  }
+  if (dmax) vec_block_partial<2>(mx, dmax);
+}
+
+// Values of `count` consecutive sum banks: out[k] = bank_value<0>(bank k).
+// Grid: count blocks of 64.
+__global__ __launch_bounds__(64) void vec_finish_sums(const double* __restrict__ banks, double* __restrict__ out) {
+  const double v = bank_value<0>(banks + (size_t)blockIdx.x * kVecBlocks);
+  if (threadIdx.x == 0) out[blockIdx.x] = v;
 }
 
 // Values of up to four banks for the host: out[k] = bank_value<op[k]>(bank[k]).
@@ -297,14 +417,6 @@ __global__ __launch_bounds__(64) void vec_finish(BankList l) {
     const double v = l.op[k] == 2 ? bank_value<2>(l.bank[k]) : bank_value<0>(l.bank[k]);
     if (threadIdx.x == 0) *l.out[k] = v;
   }
-}
-
-// z = x - y
-template <typename T>
-__global__ __launch_bounds__(256) void vec_sub(const T* __restrict__ x, const T* __restrict__ y, T* __restrict__ z,
-                                               size_t n) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    z[i] = x[i] - y[i];
 }
 
 // Copy between the box of a padded array and a dense box field [nz][ny][nx].

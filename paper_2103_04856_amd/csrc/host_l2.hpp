@@ -21,8 +21,9 @@ struct fe_l2 {
   void* q = nullptr;             // two-loop scratch
   std::vector<void*> S, Y;       // history, oldest first (pointers rotate, memory stays)
   std::vector<double> rho;
+  std::vector<double> SY, YY;    // [history][history]: s_a . y_b (a <= b) and y_a . y_b of the history
   int hist_len = 0;
-  double* d_red = nullptr;       // reduction partials, then the scalar slots (kL2Slots)
+  double* d_red = nullptr;       // reduction banks, then their values (kL2Banks each)
   // settings
   double lr = 1.0, tol_grad = 1e-7, tol_change = 1e-9;
   int history = 10, max_iter = 20, max_eval = 25;
@@ -35,20 +36,18 @@ namespace {
 
 int l2_launch_1d(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 65536); }
 
-// Scalars of the optimiser. Each reduction has a slot: 0 energy, 1 max|g|,
-// 2 max|d|, 3 g'd, 4 |g|_1, 5 y's, 6 y'y, 7 and 8 the y_i'd dots of the second
-// loop (used in turn, so no pass reads the bank it writes), 9.. the s_i'q dots
-// of the first loop of the two-loop recursion (one per history entry). d_red
+// Scalars of the optimiser. Named slots: 0 energy, 1 max|g|, 2 max|d|, 3 g'd
+// and 4 |g|_1 (first iteration); then the inner products of the Gram pass
+// (y.y, y.s, y.g, g.g, g.s, then y.V_k, g.V_k for each history vector). d_red
 // holds one bank of kVecBlocks partials per slot, then one value per slot for
 // the host (the energy is written there directly).
-constexpr int kSlotE = 0, kSlotGmax = 1, kSlotDmax = 2, kSlotGtd = 3, kSlotL1 = 4, kSlotYs = 5, kSlotYy = 6,
-              kSlotDot = 7, kSlotDot2 = 8, kSlotAlpha = 9;
+constexpr int kSlotE = 0, kSlotGmax = 1, kSlotDmax = 2, kSlotGtd = 3, kSlotL1 = 4, kSlotGram = 5;
 constexpr int kL2MaxHistory = 64;
-constexpr int kL2Slots = kSlotAlpha + kL2MaxHistory;
-constexpr size_t kL2RedDoubles = (size_t)kL2Slots * fe::kVecBlocks + kL2Slots;
+constexpr int kL2Banks = kSlotGram + 5 + 4 * kL2MaxHistory;
+constexpr size_t kL2RedDoubles = (size_t)kL2Banks * fe::kVecBlocks + kL2Banks;
 
 double* l2_bank(fe_l2* L, int slot) { return L->d_red + (size_t)slot * fe::kVecBlocks; }
-double* l2_vals(fe_l2* L) { return L->d_red + (size_t)kL2Slots * fe::kVecBlocks; }
+double* l2_vals(fe_l2* L) { return L->d_red + (size_t)kL2Banks * fe::kVecBlocks; }
 int l2_slot_op(int slot) { return slot == kSlotGmax || slot == kSlotDmax ? 2 : slot == kSlotL1 ? 1 : 0; }
 
 const dim3 kVecGrid(fe::kVecBlocks), kVecBlock(fe::kVecThreads);
@@ -70,8 +69,8 @@ int l2_reduce_dev(fe_l2* L, int op, const void* a, const void* b, int slot) {
   return FE_OK;
 }
 
-// Host copies of the values of slots [first, first + count) (one sync): the
-// banks among them are combined on the device first.
+// Host copies of the values of named slots [first, first + count) (one sync):
+// the banks among them are combined on the device first.
 int l2_read_slots(fe_l2* L, int first, int count, double* out) {
   fe::BankList bl{};
   for (int k = first; k < first + count; ++k) {
@@ -91,39 +90,80 @@ int l2_read_slots(fe_l2* L, int first, int count, double* out) {
   return FE_OK;
 }
 
-// Coefficient ka v(ia) + kb v(ib) + kc of a vector pass, from the values of
-// dot-product slots (ia, ib < 0: that term is absent).
-struct L2Coef {
-  int ia;
-  double ka;
-  int ib;
-  double kb;
-  double kc;
-};
-
-// y = alpha x (+ y when acc); then, when w is given, w . y into the bank of
-// slot `out`. One pass, no sync.
+// out = sum_k c[k] v[k] (+ out when acc), in passes of up to kCombVecs vectors;
+// with dmax, the last pass leaves max |out| in the bank of kSlotDmax. No sync.
 template <typename T>
-int l2_update(fe_l2* L, const L2Coef& k, bool acc, const void* x, void* y, const void* w = nullptr, int out = 0) {
-  hipStream_t s = L->ctx->stream;
-  const fe::VecCoef cf{k.ia >= 0 ? l2_bank(L, k.ia) : nullptr, k.ka, k.ib >= 0 ? l2_bank(L, k.ib) : nullptr, k.kb,
-                       k.kc};
-  const T* px = static_cast<const T*>(x);
-  T* py = static_cast<T*>(y);
-  const T* pw = static_cast<const T*>(w);
-  double* bank = l2_bank(L, out);
-  if (acc)
-    hipLaunchKernelGGL((fe::vec_update_dot<T, true>), kVecGrid, kVecBlock, 0, s, cf, px, py, pw, L->n, bank);
-  else
-    hipLaunchKernelGGL((fe::vec_update_dot<T, false>), kVecGrid, kVecBlock, 0, s, cf, px, py, pw, L->n, bank);
-  FE_HIP(hipGetLastError());
+int l2_lincomb(fe_l2* L, const std::vector<const void*>& v, const std::vector<double>& c, bool acc, void* out,
+               bool dmax) {
+  const size_t K = v.size();
+  for (size_t k0 = 0; k0 < K; k0 += fe::kCombVecs) {
+    fe::CombList<T> cl{};
+    cl.count = (int)std::min<size_t>(fe::kCombVecs, K - k0);
+    // pass widths 1, 4, 8 or 16; the padding repeats the first vector with c = 0
+    const int w = cl.count == 1 ? 1 : cl.count <= 4 ? 4 : cl.count <= 8 ? 8 : fe::kCombVecs;
+    for (int k = 0; k < w; ++k) {
+      cl.v[k] = static_cast<const T*>(v[k < cl.count ? k0 + k : k0]);
+      cl.c[k] = k < cl.count ? c[k0 + k] : 0.0;
+    }
+    const int a = (acc || k0 > 0) ? 1 : 0;
+    double* dm = (dmax && k0 + fe::kCombVecs >= K) ? l2_bank(L, kSlotDmax) : nullptr;
+    T* po = static_cast<T*>(out);
+    hipStream_t s = L->ctx->stream;
+    if (w == 1)
+      hipLaunchKernelGGL((fe::vec_lincomb<T, 1>), kVecGrid, kVecBlock, 0, s, cl, po, a, L->n, dm);
+    else if (w == 4)
+      hipLaunchKernelGGL((fe::vec_lincomb<T, 4>), kVecGrid, kVecBlock, 0, s, cl, po, a, L->n, dm);
+    else if (w == 8)
+      hipLaunchKernelGGL((fe::vec_lincomb<T, 8>), kVecGrid, kVecBlock, 0, s, cl, po, a, L->n, dm);
+    else
+      hipLaunchKernelGGL((fe::vec_lincomb<T, fe::kCombVecs>), kVecGrid, kVecBlock, 0, s, cl, po, a, L->n, dm);
+    FE_HIP(hipGetLastError());
+  }
   return FE_OK;
 }
 
 // y = alpha x (+ y when acc) with a host coefficient
 template <typename T>
 int l2_scale_add(fe_l2* L, double alpha, const void* x, bool acc, void* y) {
-  return l2_update<T>(L, L2Coef{-1, 0.0, -1, 0.0, alpha}, acc, x, y);
+  return l2_lincomb<T>(L, {x}, {alpha}, acc, y, false);
+}
+
+// The Gram pass: y = g - prev_g into L->q, s = t d into L->w0, and the inner
+// products y.y, y.s, y.g, g.g, g.s and, for every vector v of `hist`, y.v and
+// g.v, copied to `out` in that order (one sync).
+template <typename T>
+int l2_gram(fe_l2* L, const std::vector<const void*>& hist, std::vector<double>& out) {
+  hipStream_t s = L->ctx->stream;
+  const T* g = static_cast<const T*>(L->g);
+  T* y = static_cast<T*>(L->q);
+  const size_t K = hist.size();
+  int bank = kSlotGram;
+  size_t k0 = 0;
+  do {
+    fe::DotList<T> dl{};
+    dl.count = (int)std::min<size_t>(fe::kDotVecs, K - k0);
+    for (int k = 0; k < fe::kDotVecs; ++k) dl.v[k] = k < dl.count ? static_cast<const T*>(hist[k0 + k]) : g;
+    if (k0 == 0) {
+      hipLaunchKernelGGL((fe::vec_gram<T, true>), kVecGrid, dim3(fe::gram_threads<T>()), 0, s, g,
+                         static_cast<const T*>(L->prev_g), static_cast<const T*>(L->d), L->t, y,
+                         static_cast<T*>(L->w0), dl, L->n, l2_bank(L, bank));
+      bank += 5;
+    } else {
+      hipLaunchKernelGGL((fe::vec_gram<T, false>), kVecGrid, dim3(fe::gram_threads<T>()), 0, s, g, nullptr, nullptr, 0.0,
+                         y, nullptr, dl, L->n, l2_bank(L, bank));
+    }
+    FE_HIP(hipGetLastError());
+    bank += 2 * dl.count;
+    k0 += dl.count;
+  } while (k0 < K);
+  const int nv = bank - kSlotGram;
+  hipLaunchKernelGGL(fe::vec_finish_sums, dim3(nv), dim3(64), 0, s, (const double*)l2_bank(L, kSlotGram),
+                     l2_vals(L) + kSlotGram);
+  FE_HIP(hipGetLastError());
+  out.resize(nv);
+  FE_HIP(hipMemcpyAsync(out.data(), l2_vals(L) + kSlotGram, sizeof(double) * nv, hipMemcpyDeviceToHost, s));
+  FE_HIP(hipStreamSynchronize(s));
+  return FE_OK;
 }
 
 // The separable blur passes on the padded array (periodic within it):
@@ -232,72 +272,109 @@ int l2_step(fe_l2* L, double& loss0) {
   bool opt_cond = false;
   for (int it = 1; it <= L->max_iter; ++it) {
     ++L->n_iter;
-    if (L->n_iter == 1) {
-      if ((rc = l2_scale_add<T>(L, -1.0, L->g, false, L->d))) return rc;
+    const bool first = L->n_iter == 1;
+    double gtd = 0.0, gl1 = 0.0;
+    if (first) {
+      if ((rc = l2_lincomb<T>(L, {L->g}, {-1.0}, false, L->d, true))) return rc;   // d = -g
       L->hist_len = 0;
       L->rho.clear();
       L->H_diag = 1.0;
+      if ((rc = l2_reduce_dev<T>(L, 0, L->g, L->d, kSlotGtd))) return rc;
+      if ((rc = l2_reduce_dev<T>(L, 1, L->g, nullptr, kSlotL1))) return rc;
+      double gl[2];
+      if ((rc = l2_read_slots(L, kSlotGtd, 2, gl))) return rc;
+      gtd = gl[0];
+      gl1 = gl[1];
     } else {
-      // y = g - prev_g (in q), s = t d (in w0); accept the pair if y's > 1e-10
-      hipLaunchKernelGGL(fe::vec_sub<T>, dim3(l2_launch_1d(L->n)), dim3(256), 0, L->ctx->stream,
-                         static_cast<const T*>(L->g), static_cast<const T*>(L->prev_g), static_cast<T*>(L->q), L->n);
-      FE_HIP(hipGetLastError());
-      if ((rc = l2_scale_add<T>(L, L->t, L->d, false, L->w0))) return rc;
-      if ((rc = l2_reduce_dev<T>(L, 0, L->q, L->w0, kSlotYs))) return rc;
-      if ((rc = l2_reduce_dev<T>(L, 0, L->q, L->q, kSlotYy))) return rc;
-      double yy2[2];
-      if ((rc = l2_read_slots(L, kSlotYs, 2, yy2))) return rc;
-      const double ys = yy2[0], yy = yy2[1];
+      // The Gram pass: y = g - prev_g (in q), s = t d (in w0) and the inner
+      // products of y and g with each other, with s and with every history vector.
+      int m = L->hist_len;
+      const int H = L->history;
+      std::vector<const void*> hist;
+      for (int i = 0; i < m; ++i) hist.push_back(L->S[i]);
+      for (int i = 0; i < m; ++i) hist.push_back(L->Y[i]);
+      std::vector<double> gv;
+      if ((rc = l2_gram<T>(L, hist, gv))) return rc;
+      const double yy = gv[0], ys = gv[1], yg = gv[2], gg = gv[3], gs = gv[4];
+      std::vector<double> yS(m), gS(m), yY(m), gY(m);
+      for (int i = 0; i < m; ++i) {
+        yS[i] = gv[5 + 2 * i];
+        gS[i] = gv[6 + 2 * i];
+        yY[i] = gv[5 + 2 * (m + i)];
+        gY[i] = gv[6 + 2 * (m + i)];
+      }
+      double* SY = L->SY.data();
+      double* YY = L->YY.data();
+      // accept the pair if y's > 1e-10 (the oldest leaves a full history)
       if (ys > 1e-10) {
-        if (L->hist_len == L->history) {         // drop the oldest: rotate the slots
+        if (m == H) {
           std::rotate(L->S.begin(), L->S.begin() + 1, L->S.end());
           std::rotate(L->Y.begin(), L->Y.begin() + 1, L->Y.end());
           L->rho.erase(L->rho.begin());
-          --L->hist_len;
+          for (int a = 0; a + 1 < m; ++a)
+            for (int b = 0; b + 1 < m; ++b) {
+              SY[a * H + b] = SY[(a + 1) * H + b + 1];
+              YY[a * H + b] = YY[(a + 1) * H + b + 1];
+            }
+          for (auto* v : {&yS, &gS, &yY, &gY}) v->erase(v->begin());
+          --m;
         }
         // the new pair takes over the buffers of y and s; theirs become scratch
-        std::swap(L->q, L->Y[L->hist_len]);
-        std::swap(L->w0, L->S[L->hist_len]);
+        std::swap(L->q, L->Y[m]);
+        std::swap(L->w0, L->S[m]);
+        for (int a = 0; a < m; ++a) {
+          SY[a * H + m] = yS[a];                 // s_a . y_new
+          YY[a * H + m] = YY[m * H + a] = yY[a];
+        }
+        SY[m * H + m] = ys;
+        YY[m * H + m] = yy;
+        gS.push_back(gs);
+        gY.push_back(yg);
         L->rho.push_back(1.0 / ys);
-        ++L->hist_len;
+        L->hist_len = ++m;
         L->H_diag = ys / yy;
       }
-      // two-loop recursion: q = -g; newest to oldest: a_i = rho_i s_i'q, q -= a_i y_i;
-      // d = H_diag q; oldest to newest: b_i = rho_i y_i'd, d += (a_i - b_i) s_i.
-      // Each pass updates q (or d) and forms the dot product of the next entry.
-      const int m = L->hist_len;
-      if ((rc = l2_update<T>(L, L2Coef{-1, 0.0, -1, 0.0, -1.0}, false, L->g, L->q, m > 0 ? L->S[m - 1] : nullptr,
-                             m > 0 ? kSlotAlpha + m - 1 : 0)))
-        return rc;
-      for (int i = m - 1; i >= 0; --i)
-        if ((rc = l2_update<T>(L, L2Coef{kSlotAlpha + i, -L->rho[i], -1, 0.0, 0.0}, true, L->Y[i], L->q,
-                               i > 0 ? L->S[i - 1] : nullptr, i > 0 ? kSlotAlpha + i - 1 : 0)))
-          return rc;
-      if ((rc = l2_update<T>(L, L2Coef{-1, 0.0, -1, 0.0, L->H_diag}, false, L->q, L->d, m > 0 ? L->Y[0] : nullptr,
-                             kSlotDot)))
-        return rc;
-      for (int i = 0; i < m; ++i) {
-        const int cur = (i & 1) ? kSlotDot2 : kSlotDot, nxt = (i & 1) ? kSlotDot : kSlotDot2;
-        if ((rc = l2_update<T>(L, L2Coef{kSlotAlpha + i, L->rho[i], cur, -L->rho[i], 0.0}, true, L->S[i], L->d,
-                               i + 1 < m ? L->Y[i + 1] : nullptr, nxt)))
-          return rc;
+      // The two-loop recursion on the inner products, newest to oldest:
+      //   a_i = rho_i s_i.q with q = -g - sum_{j>i} a_j y_j,
+      // then r = H q (q = -g - sum_j a_j y_j), oldest to newest:
+      //   b_i = rho_i y_i.r with r = H q + sum_{j<i} (a_j - b_j) s_j,
+      // and d = H q + sum_i (a_i - b_i) s_i = -H g - H sum_j a_j y_j + sum_i (a_i - b_i) s_i.
+      const double Hd = L->H_diag;
+      std::vector<double> al(m), be(m);
+      for (int i = m - 1; i >= 0; --i) {
+        double sq = -gS[i];
+        for (int j = i + 1; j < m; ++j) sq -= al[j] * SY[i * H + j];
+        al[i] = L->rho[i] * sq;
       }
+      for (int i = 0; i < m; ++i) {
+        double yq = -gY[i];
+        for (int j = 0; j < m; ++j) yq -= al[j] * YY[i * H + j];
+        double yr = Hd * yq;
+        for (int j = 0; j < i; ++j) yr += (al[j] - be[j]) * SY[j * H + i];
+        be[i] = L->rho[i] * yr;
+      }
+      std::vector<const void*> vv{L->g};
+      std::vector<double> cc{-Hd};
+      gtd = -Hd * gg;
+      for (int i = 0; i < m; ++i) {
+        vv.push_back(L->S[i]);
+        cc.push_back(al[i] - be[i]);
+        gtd += (al[i] - be[i]) * gS[i];
+      }
+      for (int j = 0; j < m; ++j) {
+        vv.push_back(L->Y[j]);
+        cc.push_back(-Hd * al[j]);
+        gtd += -Hd * al[j] * gY[j];
+      }
+      if ((rc = l2_lincomb<T>(L, vv, cc, false, L->d, true))) return rc;
     }
     // prev_g takes over the gradient's buffer; the next evaluation writes g anew
-    // (until then the current gradient is prev_g)
     std::swap(L->g, L->prev_g);
     L->prev_loss = loss;
-    const bool first = L->n_iter == 1;
-    if ((rc = l2_reduce_dev<T>(L, 0, L->prev_g, L->d, kSlotGtd))) return rc;
-    if (first && (rc = l2_reduce_dev<T>(L, 1, L->prev_g, nullptr, kSlotL1))) return rc;
-    double gl[2];
-    if ((rc = l2_read_slots(L, kSlotGtd, first ? 2 : 1, gl))) return rc;
-    L->t = first ? std::min(1.0, 1.0 / gl[1]) * L->lr : L->lr;
-    const double gtd = gl[0];
+    L->t = first ? std::min(1.0, 1.0 / gl1) * L->lr : L->lr;
     if (gtd > -L->tol_change) break;
     int ls_evals = 0;
-    if ((rc = l2_scale_add<T>(L, L->t, L->d, true, L->x))) return rc;
-    if ((rc = l2_reduce_dev<T>(L, 2, L->d, nullptr, kSlotDmax))) return rc;
+    if ((rc = l2_scale_add<T>(L, L->t, L->d, true, L->x))) return rc;   // max |d| is in its slot already
     double dmax = 0.0;
     if (it != L->max_iter) {
       if ((rc = l2_eval_dev<T>(L))) return rc;
@@ -445,6 +522,8 @@ int fe_l2_set_lbfgs(fe_l2* L, double lr, int history, int max_iter, double toler
   L->n_iter = 0;
   L->hist_len = 0;
   L->rho.clear();
+  L->SY.assign((size_t)history * history, 0.0);
+  L->YY.assign((size_t)history * history, 0.0);
   return FE_OK;
 }
 
