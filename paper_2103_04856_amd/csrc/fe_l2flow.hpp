@@ -68,10 +68,12 @@ __global__ __launch_bounds__(256) void pad_replicate(T* __restrict__ f, PadBox b
 // out = P^T g: every box voxel gathers the pad samples that copy it (on a box
 // face, the run of pad samples beyond it along each clamped axis, the voxel
 // included); pad samples of out are zero; voxels off the box surface copy g.
-// W > 0: every pad is W wide, so a run on one face is W + 1 samples at fixed
-// offsets (unrolled, all loads in flight); W = 0: general runs. Edges and
-// corners (two or three clamped axes) take the general loop. One thread per
-// sample of a plane: grid (ceil(nx ny / 256), nz). g and out must differ.
+// W > 0: every pad is W wide and the box is at least 2 voxels along every
+// axis, so a run on one face is W + 1 samples at fixed offsets and an edge or a
+// corner gathers (W+1)^2 or (W+1)^3 of them (unrolled, loads in flight);
+// W = 0: general runs, for any box (a box 1 voxel thick has runs on both of
+// its sides). One thread per sample of a plane: grid (ceil(nx ny / 256), nz).
+// g and out must differ.
 template <typename T, int W>
 __global__ __launch_bounds__(256) void fold_pads(const T* __restrict__ g, T* __restrict__ out, PadBox b) {
   const int ip = blockIdx.x * 256 + threadIdx.x, z = blockIdx.y;
@@ -113,6 +115,40 @@ __global__ __launch_bounds__(256) void fold_pads(const T* __restrict__ g, T* __r
   const int x0 = x == b.lo[0] ? 0 : x, x1 = x == b.hi[0] - 1 ? b.nx - 1 : x;
   const int y0 = y == b.lo[1] ? 0 : y, y1 = y == b.hi[1] - 1 ? b.ny - 1 : y;
   const int z0 = z == b.lo[2] ? 0 : z, z1 = z == b.hi[2] - 1 ? b.nz - 1 : z;
+  if (W > 0) {
+    // An edge or a corner: the (W+1)^2 block spanned by the runs along two
+    // clamped axes, every load in flight. On an edge the third axis is fixed;
+    // on a corner the block is in (y, x) and z runs over its W + 1 planes.
+    // Blocks are summed in increasing index order, as the general loop adds.
+    const long sx = 1, sy = b.nx, sz = (long)b.nx * b.ny;
+    long sp = sy, sq = sx, so = sz;
+    int no = fz ? W + 1 : 1;
+    if (nf == 2 && fz) {
+      no = 1;
+      if (!fy) {
+        sp = sz;
+        sq = sx;
+        so = sy;
+      } else {
+        sp = sz;
+        sq = sy;
+        so = sx;
+      }
+    }
+    const T* p0 = g + ((size_t)z0 * b.ny + y0) * b.nx + x0;
+    T acc = T(0);
+    for (int ko = 0; ko < no; ++ko) {
+      T v[(W + 1) * (W + 1)];
+#pragma unroll
+      for (int kp = 0; kp <= W; ++kp)
+#pragma unroll
+        for (int kq = 0; kq <= W; ++kq) v[kp * (W + 1) + kq] = p0[ko * so + kp * sp + kq * sq];
+#pragma unroll
+      for (int k = 0; k < (W + 1) * (W + 1); ++k) acc += v[k];
+    }
+    out[i] = acc;
+    return;
+  }
   T acc = T(0);
   for (int zz = z0; zz <= z1; ++zz)
     for (int yy = y0; yy <= y1; ++yy)

@@ -184,7 +184,8 @@ void l2_blur(fe_l2* L, const T* in, T* tmp1, T* tmp2, T* out) {
 }
 
 // The padding kernels: replicate padding over the pad shell, and its
-// transpose (fixed-width runs for the pad widths 1, 4 and 8).
+// transpose (fixed-width runs for the pad widths 1, 4 and 8 on boxes at least
+// 2 voxels thick, general runs otherwise).
 template <typename T>
 void l2_pad(fe_l2* L, T* f) {
   const size_t n = fe::pad_shell_size(L->box);
@@ -197,7 +198,10 @@ template <typename T>
 void l2_fold(fe_l2* L, const T* g, T* out) {
   const dim3 grid((unsigned)ceil_div(L->box.nx * L->box.ny, 256), (unsigned)L->box.nz);
   hipStream_t s = L->ctx->stream;
-  const int W = L->box.lo[0];
+  // the fixed-width forms need a box at least 2 voxels thick on every axis
+  bool thick = true;
+  for (int a = 0; a < 3; ++a) thick = thick && L->box.hi[a] - L->box.lo[a] >= 2;
+  const int W = thick ? L->box.lo[0] : 0;
   if (W == 4)
     hipLaunchKernelGGL((fe::fold_pads<T, 4>), grid, dim3(256), 0, s, g, out, L->box);
   else if (W == 8)

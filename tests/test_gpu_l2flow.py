@@ -47,6 +47,25 @@ def test_energy_and_gradient_match_oracle(dtype, sigma_k):
     assert rel_l2(g.cpu().double().numpy(), go) <= tol["grad"]
 
 
+@pytest.mark.parametrize("shape,sigma_k", [((1, 9, 13), 0.0), ((7, 1, 5), 1.0), ((6, 5, 2), 1.0),
+                                           ((2, 3, 2), 2.0), ((9, 6, 1), 2.0)])
+def test_thin_boxes_match_oracle(shape, sigma_k):
+    """Boxes one or two voxels thick, FP64, noise in [-1, 1], every term of p. One
+    voxel thick, a box voxel is both faces of that axis and gathers the pad runs
+    on both sides; two thick, every voxel is on a face, and edges and corners
+    meet (pad widths 1, 4 and 8)."""
+    h = 0.1
+    eps = 2.5 * h
+    u0 = np.random.default_rng(11).uniform(-1.0, 1.0, shape)
+    ud = to_dev(u0, torch.float64)
+    flow = fe.FeL2Flow(shape, h, eps, ALL_TERMS, sigma_k=sigma_k, dtype=torch.float64)
+    E, g = flow.energy_grad(ud)
+    Eo, go = l2flow.energy_grad_replicate(oracle_input(ud), h, eps, ALL_TERMS, sigma_k)
+    tol = TOL[torch.float64]
+    assert abs(E - Eo) <= tol["energy"] * abs(Eo), (E, Eo)
+    assert rel_l2(g.cpu().double().numpy(), go) <= tol["grad"]
+
+
 def test_lbfgs_steps_match_torch_lbfgs_on_the_oracle():
     """FP64, 16^3 noisy ball, blur sigma_k = 1, p = H^2: four steps of five inner
     iterations against torch.optim.LBFGS (lr 1, history 3 so that the history wraps)
