@@ -196,7 +196,8 @@ int fe_set_orientation(fe_ctx* ctx, const double* mu, const double* theta);
  *   u_out    device field [batch][nz][ny][nx] or NULL: receives k * (div A + m0)
  *            at the final A (the field whose zero level set is the texture).
  *   energy   host [batch] or NULL: G before the last update (synchronises).
- * Requires nz * batch and ny * batch <= 65535. Allocates two work fields and
+ * Requires nz * batch <= 65535, planes (nx * ny samples) under 4 GiB and
+ * nz * nx < 2^31 (FE_EINVAL otherwise). Allocates two work fields and
  * the six moment fields of A on first use; replays captured graphs.
  */
 int fe_hminus_step(fe_ctx* ctx, void* A, const double* m0, double sigma_k, double lr, double beta1,
@@ -246,7 +247,9 @@ int fe_diagnostics(fe_ctx* ctx, const void* u, void* curv, double* hist, int nbi
 typedef struct fe_l2 fe_l2;
 
 /* grid: the box (batch must be 1); eps, p_coeffs[6] as in fe_create; blur
- * 0 <= sigma_k <= 4 voxels (0: none). Allocates the padded fields and the
+ * 0 <= sigma_k <= 4 voxels (0: none). The box padded by max(1, ceil(4 sigma_k))
+ * on every side must have ny, nz <= 65535, planes under 4 GiB and
+ * nz * nx < 2^31 (FE_EINVAL otherwise). Allocates the padded fields and the
  * optimiser's history on the device. */
 int fe_l2_create(const fe_grid* grid, double eps, const double* p_coeffs, double sigma_k, void* stream,
                  fe_l2** out);

@@ -9,10 +9,12 @@
 //
 // One iteration is: blur_x<DIV> (div A + m0, blurred along x), blur_axis<1>,
 // blur_axis<2>, the sweep, blur_x of dF/du, blur_axis<1>, blur_axis<2>,
-// adam_vector_field; for the radii 4 and 8 the blur of dF/du runs blur_xy
-// (x and y in one pass) and adam_zblur (the z pass fused with Adam). Without blur (r = 0) only the first kernel, the sweep and the
-// Adam kernel run. Every kernel is a 64-wide row of x per wave, so loads
-// and stores are coalesced; the blur halos are staged in LDS.
+// adam_vector_field; for the radii 4 and 8 the x and y blurs of dF/du are one
+// pass (blur_xy). Without blur (r = 0) only the first kernel, the sweep and
+// the Adam kernel run. Every wave reads and writes consecutive voxels of a row
+// (blur_x, blur_xy: 64-wide row tiles with their halos in LDS) or of a plane
+// (blur_axis, adam_vector_field: flat runs of 256 voxels), so every access is
+// coalesced; tiles are placed on the XCDs by xcd_tile.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -47,6 +49,47 @@ __device__ __forceinline__ int wrap_any(int v, int n) {
 }
 __device__ __forceinline__ int wrap_up(int v, int n) { return v >= n ? v - n : v; }
 __device__ __forceinline__ int wrap_down(int v, int n) { return v < 0 ? v + n : v; }
+
+// base[i] for a wave-uniform base and an element offset below 2^32 bytes (the
+// flow entry points reject planes of 4 GiB or more): the load then takes the
+// scalar base and a 32-bit vector offset, and a lane spends no 64-bit address
+// arithmetic on it.
+template <typename T>
+__device__ __forceinline__ T load_u32(const T* base, unsigned i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(T));
+}
+
+template <typename T>
+__device__ __forceinline__ void store_u32(T* base, unsigned i, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T)) = v;
+}
+
+// Workgroups go to the chip's 8 XCDs in turn (workgroup i of the x-fastest
+// order to XCD i mod 8), and each XCD has an L2 of its own, so tiles with
+// consecutive numbers never share an L2. The flow kernels' tiles read each
+// other's halos (the ring and window rows and planes, and the cache lines that
+// straddle two tiles of a row), so they take their tile from xcd_tile: the
+// workgroups are renumbered so that every XCD runs one contiguous range of
+// tiles in x-fastest order, and neighbouring tiles meet in one L2 at about the
+// same time. The last (count mod 8) workgroups keep their numbers. Only the
+// placement changes: every tile computes the same sums.
+struct Tile3 {
+  int x, y, z;
+};
+
+__device__ __forceinline__ Tile3 xcd_tile() {
+  constexpr unsigned kXcds = 8;
+  const unsigned gx = gridDim.x, gy = gridDim.y;
+  const unsigned n = gx * gy * gridDim.z, per = n / kXcds;
+  unsigned b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  if (b < per * kXcds) b = (b % kXcds) * per + b / kXcds;
+  Tile3 t;
+  t.x = (int)(b % gx);
+  b /= gx;
+  t.y = (int)(b % gy);
+  t.z = (int)(b / gy);
+  return t;
+}
 
 // The blur kernels take the radius as a template argument R for the common
 // widths (sigma_k = 1 and 2 give r = 4 and 8), so their tap loops are fixed;
@@ -92,53 +135,69 @@ __global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __res
     clk->bc1 = 1.0 / (1.0 - ::pow(beta1, (double)t));
     clk->bc2 = 1.0 / (1.0 - ::pow(beta2, (double)t));
   }
-  const int z = blockIdx.z % d.nz, b = blockIdx.z / d.nz;
-  const int x0 = blockIdx.x * 64;
+  const Tile3 t = xcd_tile();
+  const int z = t.z % d.nz, b = t.z / d.nz;
+  const int x0 = t.x * 64;
   const size_t plane = (size_t)d.nx * d.ny, vol = plane * d.nz;
   const T* base = in + (size_t)b * (DIV ? 3 : 1) * vol;
   const int r = R >= 0 ? R : k.r;
   const int nseg = 64 + 2 * r;
+  // A wave's rows are uniform (threadIdx.y is the wave), so the row pointers
+  // live in scalar registers and every load takes a 32-bit lane offset: the
+  // segment's x positions and their periodic x neighbours, formed once.
+  const int wy = __builtin_amdgcn_readfirstlane(threadIdx.y);
+  int xs[kPer], xp[kPer], xm[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int x = wrap_any(x0 - r + (int)threadIdx.x + 64 * j, d.nx);
+    xs[j] = x;
+    xp[j] = wrap_up(x + 1, d.nx);
+    xm[j] = wrap_down(x - 1, d.nx);
+  }
   T v[kR][kPer][7];          // the non-DIV form uses [0] only; [6] holds m(x)
 #pragma unroll
   for (int i = 0; i < kR; ++i) {
-    const int y = blockIdx.y * kBlurRows + threadIdx.y + 4 * i;
+    const int y = t.y * kBlurRows + wy + 4 * i;
     if (y >= d.ny) continue;
-    const size_t row = (size_t)z * plane + (size_t)y * d.nx;
+    const T* row = base + (size_t)z * plane + (size_t)y * d.nx;
+    // the A_y rows y +- 1 and the A_z rows of the planes z +- 1 (DIV only)
+    const T* rowyp = DIV ? base + vol + (size_t)z * plane + (size_t)wrap_up(y + 1, d.ny) * d.nx : row;
+    const T* rowym = DIV ? base + vol + (size_t)z * plane + (size_t)wrap_down(y - 1, d.ny) * d.nx : row;
+    const T* rowzp = DIV ? base + 2 * vol + (size_t)wrap_up(z + 1, d.nz) * plane + (size_t)y * d.nx : row;
+    const T* rowzm = DIV ? base + 2 * vol + (size_t)wrap_down(z - 1, d.nz) * plane + (size_t)y * d.nx : row;
+    const T* rowm = (DIV && mfield) ? mfield + (size_t)b * vol + (size_t)z * plane + (size_t)y * d.nx : row;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
       const int e = threadIdx.x + 64 * j;
       if (e >= nseg) continue;
-      const int x = wrap_any(x0 - r + e, d.nx);
       if (DIV) {
-        v[i][j][0] = base[row + wrap_up(x + 1, d.nx)];
-        v[i][j][1] = base[row + wrap_down(x - 1, d.nx)];
-        const T* Ay = base + vol;
-        const T* Az = base + 2 * vol;
-        v[i][j][2] = Ay[(size_t)z * plane + (size_t)wrap_up(y + 1, d.ny) * d.nx + x];
-        v[i][j][3] = Ay[(size_t)z * plane + (size_t)wrap_down(y - 1, d.ny) * d.nx + x];
-        v[i][j][4] = Az[(size_t)wrap_up(z + 1, d.nz) * plane + (size_t)y * d.nx + x];
-        v[i][j][5] = Az[(size_t)wrap_down(z - 1, d.nz) * plane + (size_t)y * d.nx + x];
-        if (mfield) v[i][j][6] = mfield[(size_t)b * vol + row + x];
+        v[i][j][0] = load_u32(row, xp[j]);
+        v[i][j][1] = load_u32(row, xm[j]);
+        v[i][j][2] = load_u32(rowyp, xs[j]);
+        v[i][j][3] = load_u32(rowym, xs[j]);
+        v[i][j][4] = load_u32(rowzp, xs[j]);
+        v[i][j][5] = load_u32(rowzm, xs[j]);
+        if (mfield) v[i][j][6] = load_u32(rowm, xs[j]);
       } else {
-        v[i][j][0] = base[row + x];
+        v[i][j][0] = load_u32(row, xs[j]);
       }
     }
   }
   const T mass = (DIV && !mfield) ? T(m0[b]) : T(0);
 #pragma unroll
   for (int i = 0; i < kR; ++i) {
-    const int y = blockIdx.y * kBlurRows + threadIdx.y + 4 * i;
+    const int y = t.y * kBlurRows + wy + 4 * i;
     if (y >= d.ny) continue;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
       const int e = threadIdx.x + 64 * j;
       if (e >= nseg) continue;
       if (DIV)
-        s[threadIdx.y + 4 * i][e] =
+        s[wy + 4 * i][e] =
             (mfield ? v[i][j][6] : mass) +
             ((v[i][j][0] - v[i][j][1]) + (v[i][j][2] - v[i][j][3]) + (v[i][j][4] - v[i][j][5])) * inv2h;
       else
-        s[threadIdx.y + 4 * i][e] = v[i][j][0];
+        s[wy + 4 * i][e] = v[i][j][0];
     }
   }
   __syncthreads();
@@ -146,20 +205,21 @@ __global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __res
   if (x >= d.nx) return;
 #pragma unroll
   for (int i = 0; i < kR; ++i) {
-    const int y = blockIdx.y * kBlurRows + threadIdx.y + 4 * i;
+    const int y = t.y * kBlurRows + wy + 4 * i;
     if (y >= d.ny) continue;
-    out[(size_t)b * vol + (size_t)z * plane + (size_t)y * d.nx + x] =
-        taps_dot<T, R>(k, &s[threadIdx.y + 4 * i][threadIdx.x], 1);
+    T* orow = out + (size_t)b * vol + (size_t)z * plane + (size_t)y * d.nx;
+    orow[x] = taps_dot<T, R>(k, &s[wy + 4 * i][threadIdx.x], 1);
   }
 }
 
 // Blur along y (AXIS = 1) or z (AXIS = 2) with a register window: each thread
 // owns kAxisChunk consecutive outputs of one column, loads that segment and
-// its periodic halo of r once (coalesced across the 64 x-lanes of a wave) and
-// forms every output from registers, so the pass needs no LDS. Block (64, 4),
-// one column per thread; grid (ceil(nx/64), ceil(n_axis/kAxisChunk),
-// ceil(n_other/4) * batch), the other axis being z for AXIS = 1 and y for
-// AXIS = 2.
+// its periodic halo of r once and forms every output from registers, so the
+// pass needs no LDS. The columns are numbered flat over the two other axes
+// (for z, the voxels of a plane in memory order; for y, the x values of every
+// plane in turn), so a block is 256 consecutive columns and no lane idles on a
+// row that is not a multiple of 64 wide. Block 256; grid (ceil(columns / 256),
+// ceil(n_axis / kAxisChunk), batch).
 constexpr int kAxisChunk = 16;
 
 template <typename T, int AXIS, int R = -1>
@@ -167,28 +227,44 @@ __global__ __launch_bounds__(256) void blur_axis(const T* __restrict__ in, T* __
                                                  BlurTaps<T> k) {
   constexpr int kWin = kAxisChunk + 2 * radius_bound<R>();
   const int r = R >= 0 ? R : k.r;
+  const Tile3 t = xcd_tile();
   const int n_axis = AXIS == 1 ? d.ny : d.nz;
-  const int n_other = AXIS == 1 ? d.nz : d.ny;
-  const int og = (n_other + 3) / 4;
-  const int other = (blockIdx.z % og) * 4 + threadIdx.y, b = blockIdx.z / og;
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  if (x >= d.nx || other >= n_other) return;
-  const size_t stride = AXIS == 1 ? (size_t)d.nx : (size_t)d.nx * d.ny;
-  const size_t base = (size_t)b * d.nz * d.ny * d.nx +
-                      (AXIS == 1 ? (size_t)other * d.nx * d.ny : (size_t)other * d.nx) + x;
-  const int p0 = blockIdx.y * kAxisChunk;
+  const size_t plane = (size_t)d.nx * d.ny, vol = plane * d.nz;
+  const unsigned nflat = AXIS == 2 ? (unsigned)plane : (unsigned)d.nz * (unsigned)d.nx;
+  const unsigned q = (unsigned)t.x * 256u + threadIdx.x;
+  if (q >= nflat) return;
+  const int p0 = t.y * kAxisChunk;
+  const T* inb = in + (size_t)t.z * vol;
+  T* outb = out + (size_t)t.z * vol;
   T v[kWin];
+  if (AXIS == 2) {
 #pragma unroll
-  for (int i = 0; i < kWin; ++i)
-    if (R >= 0 || i < kAxisChunk + 2 * r) v[i] = in[base + (size_t)wrap_any(p0 - r + i, n_axis) * stride];
+    for (int i = 0; i < kWin; ++i)
+      if (R >= 0 || i < kAxisChunk + 2 * r) v[i] = load_u32(inb + (size_t)wrap_any(p0 - r + i, n_axis) * plane, q);
 #pragma unroll
-  for (int o = 0; o < kAxisChunk; ++o) {
-    if (p0 + o >= n_axis) break;
-    T acc = T(0);
+    for (int o = 0; o < kAxisChunk; ++o) {
+      if (p0 + o >= n_axis) break;
+      T acc = T(0);
 #pragma unroll
-    for (int j = 0; j <= 2 * radius_bound<R>(); ++j)
-      if (R >= 0 || j <= 2 * r) acc += k.w[j] * v[o + j];
-    out[base + (size_t)(p0 + o) * stride] = acc;
+      for (int j = 0; j <= 2 * radius_bound<R>(); ++j)
+        if (R >= 0 || j <= 2 * r) acc += k.w[j] * v[o + j];
+      store_u32(outb + (size_t)(p0 + o) * plane, q, acc);
+    }
+  } else {
+    const unsigned zq = q / (unsigned)d.nx, x = q - zq * (unsigned)d.nx;
+    const size_t lane = (size_t)zq * plane + x;
+#pragma unroll
+    for (int i = 0; i < kWin; ++i)
+      if (R >= 0 || i < kAxisChunk + 2 * r) v[i] = inb[lane + (size_t)wrap_any(p0 - r + i, n_axis) * d.nx];
+#pragma unroll
+    for (int o = 0; o < kAxisChunk; ++o) {
+      if (p0 + o >= n_axis) break;
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j <= 2 * radius_bound<R>(); ++j)
+        if (R >= 0 || j <= 2 * r) acc += k.w[j] * v[o + j];
+      outb[lane + (size_t)(p0 + o) * d.nx] = acc;
+    }
   }
 }
 
@@ -214,8 +290,9 @@ __global__ __launch_bounds__(512) void blur_xy(const T* __restrict__ in, T* __re
   __shared__ T s_in[H][W];
   __shared__ T s_mid[H][64];
   const int tid = threadIdx.y * 64 + threadIdx.x;
-  const int z = blockIdx.z % d.nz, b = blockIdx.z / d.nz;
-  const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kXYRows;
+  const Tile3 t = xcd_tile();
+  const int z = t.z % d.nz, b = t.z / d.nz;
+  const int x0 = t.x * 64, y0 = t.y * kXYRows;
   const size_t plane = (size_t)d.nx * d.ny, vol = plane * d.nz;
   const T* src = in + (size_t)b * vol + (size_t)z * plane;
   // Stage the tile with its halo: wave w takes the rows w, w + 8, ... (their y
@@ -280,34 +357,37 @@ __global__ __launch_bounds__(512) void blur_xy(const T* __restrict__ in, T* __re
 
 // Adam on A with dG/dA_a = -(g(i + e_a) - g(i - e_a)) / (2h), g = k * dF/du.
 // Moments and A are updated in place; the bias corrections come from the
-// clock, which this iteration's first kernel advanced.
-// Block (64, 4); grid (ceil(nx/64), ceil(ny/4), nz * batch).
+// clock, which this iteration's first kernel advanced. A block is 256
+// consecutive voxels of one plane in memory order (the x and y neighbours of a
+// voxel from its row and plane, periodic), so every lane has a voxel whatever
+// the row width. Block 256; grid (ceil(nx ny / 256), 1, nz * batch).
 template <typename T>
 __global__ __launch_bounds__(256) void adam_vector_field(const T* __restrict__ g, T* __restrict__ A,
                                                          T* __restrict__ m1, T* __restrict__ m2, FieldDims d,
                                                          T inv2h, T lr, T beta1, T beta2, T adam_eps,
                                                          const FlowClock* __restrict__ clk) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
-  const int z = blockIdx.z % d.nz, b = blockIdx.z / d.nz;
-  if (x >= d.nx || y >= d.ny) return;
-  const size_t plane = (size_t)d.nx * d.ny, vol = plane * d.nz;
-  const T* gb = g + (size_t)b * vol;
-  const size_t row = (size_t)z * plane + (size_t)y * d.nx;
-  // every load of the voxel is issued before the first use, so one memory
-  // round trip covers them
-  const T gxp = gb[row + wrap_up(x + 1, d.nx)], gxm = gb[row + wrap_down(x - 1, d.nx)];
-  const T gyp = gb[(size_t)z * plane + (size_t)wrap_up(y + 1, d.ny) * d.nx + x];
-  const T gym = gb[(size_t)z * plane + (size_t)wrap_down(y - 1, d.ny) * d.nx + x];
-  const T gzp = gb[(size_t)wrap_up(z + 1, d.nz) * plane + (size_t)y * d.nx + x];
-  const T gzm = gb[(size_t)wrap_down(z - 1, d.nz) * plane + (size_t)y * d.nx + x];
-  const size_t i0 = (size_t)b * 3 * vol + row + x;
+  const Tile3 t = xcd_tile();
+  const unsigned np = (unsigned)d.nx * (unsigned)d.ny;
+  const unsigned q = (unsigned)t.x * 256u + threadIdx.x;
+  if (q >= np) return;
+  const int z = t.z % d.nz, b = t.z / d.nz;
+  const int y = (int)(q / (unsigned)d.nx), x = (int)q - y * d.nx;
+  const size_t plane = np, vol = plane * d.nz;
+  const T* gp = g + (size_t)b * vol + (size_t)z * plane;     // uniform
+  const unsigned rowq = q - (unsigned)x;
+  const T gxp = load_u32(gp, rowq + (unsigned)wrap_up(x + 1, d.nx));
+  const T gxm = load_u32(gp, rowq + (unsigned)wrap_down(x - 1, d.nx));
+  const T gyp = load_u32(gp, (unsigned)(wrap_up(y + 1, d.ny) * d.nx + x));
+  const T gym = load_u32(gp, (unsigned)(wrap_down(y - 1, d.ny) * d.nx + x));
+  const T gzp = load_u32(g + (size_t)b * vol + (size_t)wrap_up(z + 1, d.nz) * plane, q);
+  const T gzm = load_u32(g + (size_t)b * vol + (size_t)wrap_down(z - 1, d.nz) * plane, q);
+  const size_t p0 = (size_t)b * 3 * vol + (size_t)z * plane;
   T av[3], m1v[3], m2v[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    av[a] = A[i0 + a * vol];
-    m1v[a] = m1[i0 + a * vol];
-    m2v[a] = m2[i0 + a * vol];
+    av[a] = load_u32(A + p0 + a * vol, q);
+    m1v[a] = load_u32(m1 + p0 + a * vol, q);
+    m2v[a] = load_u32(m2 + p0 + a * vol, q);
   }
   const T bc1 = T(clk->bc1), bc2 = T(clk->bc2);
   const T grad[3] = {-(gxp - gxm) * inv2h, -(gyp - gym) * inv2h, -(gzp - gzm) * inv2h};
@@ -315,85 +395,9 @@ __global__ __launch_bounds__(256) void adam_vector_field(const T* __restrict__ g
   for (int a = 0; a < 3; ++a) {
     const T mo = beta1 * m1v[a] + (T(1) - beta1) * grad[a];
     const T vo = beta2 * m2v[a] + (T(1) - beta2) * grad[a] * grad[a];
-    m1[i0 + a * vol] = mo;
-    m2[i0 + a * vol] = vo;
-    A[i0 + a * vol] = av[a] - lr * (mo * bc1) * rcp_t(sqrt_t(vo * bc2) + adam_eps);
-  }
-}
-
-// The z blur of w and Adam on A in one pass, for the fixed radii R: g = blur_z(w)
-// never goes to memory. A block owns 64 x 4 columns and kAdamZ consecutive
-// planes. Phase 1: every column of the tile and its one-column ring (66 x 6)
-// is blurred along z over the planes z0 - 1 .. z0 + kAdamZ from a register
-// window of kAdamZ + 2 + 2R samples (each thread one or two columns), into LDS.
-// Phase 2: each thread updates its column's voxels plane by plane, with the
-// neighbours of the central differences from LDS. Sums and update are formed
-// in the same order as blur_axis<2> followed by adam_vector_field.
-// Block (64, 4); grid (ceil(nx/64), ceil(ny/4), ceil(nz/kAdamZ) * batch).
-constexpr int kAdamZ = 16;
-
-template <typename T, int R>
-__global__ __launch_bounds__(256) void adam_zblur(const T* __restrict__ w, T* __restrict__ A, T* __restrict__ m1,
-                                                  T* __restrict__ m2, FieldDims d, BlurTaps<T> k, T inv2h, T lr,
-                                                  T beta1, T beta2, T adam_eps, const FlowClock* __restrict__ clk) {
-  static_assert(R > 0 && R <= kBlurMaxR, "adam_zblur needs a fixed radius");
-  constexpr int CX = 66, CY = 6, NC = CX * CY;  // tile columns with their ring
-  constexpr int NP = kAdamZ + 2;                // blurred planes z0 - 1 .. z0 + kAdamZ
-  constexpr int NWIN = NP + 2 * R;              // samples per column
-  __shared__ T sg[NP][NC];
-  const int tid = threadIdx.y * 64 + threadIdx.x;
-  const int nzc = (d.nz + kAdamZ - 1) / kAdamZ;
-  const int z0 = (blockIdx.z % nzc) * kAdamZ, b = blockIdx.z / nzc;
-  const int x0 = blockIdx.x * 64, y0 = blockIdx.y * 4;
-  const size_t plane = (size_t)d.nx * d.ny, vol = plane * d.nz;
-  const T* wb = w + (size_t)b * vol;
-  // phase 1: the z blur of the columns of the tile and its ring
-#pragma unroll
-  for (int cc = 0; cc < 2; ++cc) {
-    const int c = tid + 256 * cc;
-    if (c >= NC) continue;
-    const int gx = wrap_any(x0 - 1 + c % CX, d.nx), gy = wrap_any(y0 - 1 + c / CX, d.ny);
-    const T* col = wb + (size_t)gy * d.nx + gx;
-    T v[NWIN];
-#pragma unroll
-    for (int i = 0; i < NWIN; ++i) v[i] = col[(size_t)wrap_any(z0 - 1 - R + i, d.nz) * plane];
-#pragma unroll
-    for (int o = 0; o < NP; ++o) {
-      T acc = T(0);
-#pragma unroll
-      for (int j = 0; j <= 2 * R; ++j) acc += k.w[j] * v[o + j];
-      sg[o][c] = acc;
-    }
-  }
-  __syncthreads();
-  // phase 2: Adam on the tile's voxels, plane by plane
-  const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
-  if (x >= d.nx || y >= d.ny) return;
-  const int cc = (threadIdx.y + 1) * CX + threadIdx.x + 1;
-  const T bc1 = T(clk->bc1), bc2 = T(clk->bc2);
-  for (int o = 0; o < kAdamZ; ++o) {
-    const int z = z0 + o;
-    if (z >= d.nz) break;
-    const size_t i0 = (size_t)b * 3 * vol + (size_t)z * plane + (size_t)y * d.nx + x;
-    T av[3], m1v[3], m2v[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      av[a] = A[i0 + a * vol];
-      m1v[a] = m1[i0 + a * vol];
-      m2v[a] = m2[i0 + a * vol];
-    }
-    const T gxp = sg[o + 1][cc + 1], gxm = sg[o + 1][cc - 1];
-    const T gyp = sg[o + 1][cc + CX], gym = sg[o + 1][cc - CX];
-    const T gzp = sg[o + 2][cc], gzm = sg[o][cc];
-    const T grad[3] = {-(gxp - gxm) * inv2h, -(gyp - gym) * inv2h, -(gzp - gzm) * inv2h};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const T mo = beta1 * m1v[a] + (T(1) - beta1) * grad[a];
-      const T vo = beta2 * m2v[a] + (T(1) - beta2) * grad[a] * grad[a];
-      m1[i0 + a * vol] = mo;
-      m2[i0 + a * vol] = vo;
-      A[i0 + a * vol] = av[a] - lr * (mo * bc1) * rcp_t(sqrt_t(vo * bc2) + adam_eps);
-    }
+    store_u32(m1 + p0 + a * vol, q, mo);
+    store_u32(m2 + p0 + a * vol, q, vo);
+    store_u32(A + p0 + a * vol, q, av[a] - lr * (mo * bc1) * rcp_t(sqrt_t(vo * bc2) + adam_eps));
   }
 }
 

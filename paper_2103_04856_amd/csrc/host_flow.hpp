@@ -23,12 +23,19 @@ struct FlowRule {
 };
 
 // Launch shapes of the flow kernels.
-dim3 row_grid(const fe::FieldDims& d) { return dim3(ceil_div(d.nx, 64), ceil_div(d.ny, 4), d.nz * d.batch); }
 dim3 x_grid(const fe::FieldDims& d) { return dim3(ceil_div(d.nx, 64), ceil_div(d.ny, fe::kBlurRows), d.nz * d.batch); }
 dim3 axis_grid(const fe::FieldDims& d, int axis) {
-  return axis == 1 ? dim3(ceil_div(d.nx, 64), ceil_div(d.ny, fe::kAxisChunk), ceil_div(d.nz, 4) * d.batch)
-                   : dim3(ceil_div(d.nx, 64), ceil_div(d.nz, fe::kAxisChunk), ceil_div(d.ny, 4) * d.batch);
+  return axis == 1 ? dim3(ceil_div(d.nz * d.nx, 256), ceil_div(d.ny, fe::kAxisChunk), d.batch)
+                   : dim3(ceil_div(d.nx * d.ny, 256), ceil_div(d.nz, fe::kAxisChunk), d.batch);
 }
+// The flow kernels address a plane with 32-bit byte offsets and number the
+// columns of the y pass (nz * nx of them) in 32-bit integers.
+bool flow_dims_ok(const fe_grid& g) {
+  return (double)g.nx * g.ny * elem_size(g) < 4294967296.0 && (double)g.nz * g.nx < 2147483392.0;
+}
+
+// flat runs of 256 voxels of a plane, one plane per grid z
+dim3 plane_grid(const fe::FieldDims& d) { return dim3(ceil_div(d.nx * d.ny, 256), 1, d.nz * d.batch); }
 
 // The x pass (with the divergence when DIV), dispatched to the fixed-radius
 // instantiation when there is one.
@@ -59,7 +66,7 @@ void blur_xy_pass(hipStream_t s, const fe::FieldDims& d, const fe::BlurTaps<T>& 
 
 template <typename T, int AXIS>
 void blur_axis_pass(hipStream_t s, const fe::FieldDims& d, const fe::BlurTaps<T>& k, const T* in, T* out) {
-  const dim3 g = axis_grid(d, AXIS), b(64, 4);
+  const dim3 g = axis_grid(d, AXIS), b(256);
   if (k.r == 4)
     hipLaunchKernelGGL((fe::blur_axis<T, AXIS, 4>), g, b, 0, s, in, out, d, k);
   else if (k.r == 8)
@@ -115,29 +122,19 @@ int flow_iteration(fe_ctx* c, hipStream_t s, void* A, const FlowRule& fr) {
   if (rc) return rc;
   const T inv2h = T(1.0 / (2.0 * c->grid.h));
   const fe::FlowClock* clk = c->d_flow_clk;
+  // gu = k * gb: for r = 4, 8 the x-y pass into w0 and the z pass into w1;
+  // otherwise the x pass into w0, the y pass into w1, the z pass into w0
+  const T* gu = w1;
   if (has_xy_pass(k.r)) {
-    // r = 4, 8: the fused x-y pass into w0, then the z pass fused with Adam
     blur_xy_pass<T>(s, d, k, (const T*)w1, w0);
-    const dim3 g(ceil_div(d.nx, 64), ceil_div(d.ny, 4), ceil_div(d.nz, fe::kAdamZ) * d.batch), b(64, 4);
-    if (k.r == 4)
-      hipLaunchKernelGGL((fe::adam_zblur<T, 4>), g, b, 0, s, (const T*)w0, (T*)A, (T*)c->d_am1, (T*)c->d_am2, d,
-                         k, inv2h, T(fr.lr), T(fr.beta1), T(fr.beta2), T(fr.adam_eps), clk);
-    else
-      hipLaunchKernelGGL((fe::adam_zblur<T, 8>), g, b, 0, s, (const T*)w0, (T*)A, (T*)c->d_am1, (T*)c->d_am2, d,
-                         k, inv2h, T(fr.lr), T(fr.beta1), T(fr.beta2), T(fr.adam_eps), clk);
-    FE_HIP(hipGetLastError());
-    return FE_OK;
-  }
-  // gu = k * gb: x pass into w0, y pass into w1, z pass into w0
-  T* gu = w1;
-  if (k.r > 0) {
+    blur_axis_pass<T, 2>(s, d, k, (const T*)w0, w1);
+  } else if (k.r > 0) {
     blur_x_pass<T, false>(s, d, k, (const T*)w1, w0, nullptr, nullptr, T(0), nullptr, 0.0, 0.0);
     blur_yz<T>(s, d, k, w0, w1, w0);
     gu = w0;
   }
-  hipLaunchKernelGGL(fe::adam_vector_field<T>, row_grid(d), dim3(64, 4), 0, s, (const T*)gu, (T*)A,
-                     (T*)c->d_am1, (T*)c->d_am2, d, inv2h, T(fr.lr), T(fr.beta1), T(fr.beta2), T(fr.adam_eps),
-                     clk);
+  hipLaunchKernelGGL(fe::adam_vector_field<T>, plane_grid(d), dim3(256), 0, s, gu, (T*)A, (T*)c->d_am1,
+                     (T*)c->d_am2, d, inv2h, T(fr.lr), T(fr.beta1), T(fr.beta2), T(fr.adam_eps), clk);
   FE_HIP(hipGetLastError());
   return FE_OK;
 }
@@ -176,8 +173,9 @@ int fe_hminus_step(fe_ctx* c, void* A, const double* m0, double sigma_k, double 
   if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
     return set_error(FE_EINVAL, "beta1 and beta2 must lie in [0, 1)");
   if (!(adam_eps > 0.0) || !std::isfinite(adam_eps)) return set_error(FE_EINVAL, "adam_eps must be finite and > 0");
-  if ((long)c->grid.nz * c->grid.batch > 65535 || (long)c->grid.ny * c->grid.batch > 65535)
-    return set_error(FE_EINVAL, "nz * batch and ny * batch must be <= 65535 for the flow kernels");
+  if ((long)c->grid.nz * c->grid.batch > 65535)
+    return set_error(FE_EINVAL, "nz * batch must be <= 65535 for the flow kernels");
+  if (!flow_dims_ok(c->grid)) return set_error(FE_EINVAL, "planes of 4 GiB or more (or nz * nx >= 2^31) are too large for the flow kernels");
   if (u_out == A) return set_error(FE_EINVAL, "u_out must not alias A");
   for (int b = 0; b < c->grid.batch; ++b)
     if (m0 && !std::isfinite(m0[b])) return set_error(FE_EINVAL, "m0[%d] is not finite", b);

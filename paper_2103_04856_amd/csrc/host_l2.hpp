@@ -437,7 +437,7 @@ int fe_l2_create(const fe_grid* grid, double eps, const double* p_coeffs, double
   pg.nx += 2 * W;
   pg.ny += 2 * W;
   pg.nz += 2 * W;
-  if ((long)pg.nz > 65535 || (long)pg.ny > 65535) {
+  if ((long)pg.nz > 65535 || (long)pg.ny > 65535 || !flow_dims_ok(pg)) {
     l2_free(L);
     return set_error(FE_EINVAL, "grid too large for the flow kernels");
   }
