@@ -14,7 +14,7 @@
 // the Adam kernel run. Every wave reads and writes consecutive voxels of a row
 // (blur_x, blur_xy: 64-wide row tiles with their halos in LDS) or of a plane
 // (blur_axis, adam_vector_field: flat runs of 256 voxels), so every access is
-// coalesced; tiles are placed on the XCDs by xcd_tile.
+// coalesced; tiles are placed on the XCDs by xcd_tile (blur_xy excepted).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -71,18 +71,25 @@ __device__ __forceinline__ void store_u32(T* base, unsigned i, T v) {
 // straddle two tiles of a row), so they take their tile from xcd_tile: the
 // workgroups are renumbered so that every XCD runs one contiguous range of
 // tiles in x-fastest order, and neighbouring tiles meet in one L2 at about the
-// same time. The last (count mod 8) workgroups keep their numbers. Only the
-// placement changes: every tile computes the same sums.
+// same time. The last (count mod 8) workgroups keep their numbers. A grid of
+// at most about four workgroups per CU (kXcdRenumberFrom) keeps the hardware's
+// order: all of it is resident at once, so tiles that share halos run together
+// anyway, and gathering them on one XCD only queues their identical requests
+// there (100^3, the y and z blur passes with 280 workgroups: 5.6 and 8.3 us in
+// the hardware's order, 8.9 and 10.5 us renumbered). Only the placement
+// changes: every tile computes the same sums.
 struct Tile3 {
   int x, y, z;
 };
+
+constexpr unsigned kXcdRenumberFrom = 1024;
 
 __device__ __forceinline__ Tile3 xcd_tile() {
   constexpr unsigned kXcds = 8;
   const unsigned gx = gridDim.x, gy = gridDim.y;
   const unsigned n = gx * gy * gridDim.z, per = n / kXcds;
   unsigned b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-  if (b < per * kXcds) b = (b % kXcds) * per + b / kXcds;
+  if (n >= kXcdRenumberFrom && b < per * kXcds) b = (b % kXcds) * per + b / kXcds;
   Tile3 t;
   t.x = (int)(b % gx);
   b /= gx;
@@ -290,9 +297,11 @@ __global__ __launch_bounds__(512) void blur_xy(const T* __restrict__ in, T* __re
   __shared__ T s_in[H][W];
   __shared__ T s_mid[H][64];
   const int tid = threadIdx.y * 64 + threadIdx.x;
-  const Tile3 t = xcd_tile();
-  const int z = t.z % d.nz, b = t.z / d.nz;
-  const int x0 = t.x * 64, y0 = t.y * kXYRows;
+  // Tiles in the hardware's order: this pass is bound by its LDS and VALU
+  // work, not by its halo fetches (those hit MALL), and xcd_tile's placement
+  // measured slower for it (16 x 100^3: 656 against 648 us per iteration).
+  const int z = blockIdx.z % d.nz, b = blockIdx.z / d.nz;
+  const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kXYRows;
   const size_t plane = (size_t)d.nx * d.ny, vol = plane * d.nz;
   const T* src = in + (size_t)b * vol + (size_t)z * plane;
   // Stage the tile with its halo: wave w takes the rows w, w + 8, ... (their y
