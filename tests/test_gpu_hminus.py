@@ -120,6 +120,33 @@ def test_batched_equals_single_instances():
             assert Es[0].item() == Eb[b].item()
 
 
+def test_placement_does_not_change_results():
+    """16 instances of 64^3 in one context, against each instance alone. Batched, every
+    blur and Adam pass has 1024 workgroups or more, so they are renumbered across the
+    XCDs; alone, the y and z blurs have 64 and keep the hardware's order. Placement only
+    moves tiles, so A and u agree bit for bit (the energy's block partials may be summed
+    over other z chunks, so G agrees to rounding)."""
+    n, B = 64, 16
+    h = 1.0 / n
+    sets = [ASYM_C3, WILLMORE_QUARTER, (0.5, 0.1, 1.5, -2.0, -3.0, 0.0)]
+    eps = [(2.0 + 0.25 * (b % 3)) * h for b in range(B)]
+    coeffs = [sets[b % 3] for b in range(B)]
+    m0 = [-0.4 + 0.05 * b for b in range(B)]
+    for dtype in (torch.float32, torch.float64):
+        A0 = to_dev(_a0(n, 23, B), dtype)
+        Ab = A0.clone()
+        ub = torch.empty((B, n, n, n), dtype=dtype, device="cuda")
+        ctx = fe.FeContext((B, n, n, n), h, eps, coeffs, dtype=dtype)
+        Eb = ctx.hminus_step(Ab, m0, 10, sigma_k=2.0, u_out=ub).cpu().numpy()
+        for b in range(B):
+            cs = fe.FeContext((1, n, n, n), h, eps[b], coeffs[b], dtype=dtype)
+            As = A0[b:b + 1].clone()
+            us = torch.empty((1, n, n, n), dtype=dtype, device="cuda")
+            Es = cs.hminus_step(As, [m0[b]], 10, sigma_k=2.0, u_out=us).cpu().numpy()
+            assert torch.equal(As[0], Ab[b]) and torch.equal(us[0], ub[b]), (dtype, b)
+            assert abs(Es[0] - Eb[b]) <= 1e-9 * abs(Eb[b]), (dtype, b, Es[0], Eb[b])
+
+
 def test_fp32_tracks_fp64_and_energy_decreases():
     """48^3, eps = 2h, sigma_k = 2, Adam lr 1e-3 (the paper's settings at a smaller grid): G decreases
     over 40 iterations and the FP32 run stays within 2% of the FP64 one (Adam's first steps are
