@@ -270,8 +270,8 @@ __global__ __launch_bounds__(kVecThreads) void vec_reduce(const T* __restrict__ 
 // accumulators and packs need twice the registers.
 template <typename T>
 constexpr int gram_threads() { return sizeof(T) == 4 ? kVecThreads : kVecThreads / 4; }
-constexpr int kDotVecs = 12;    // history vectors per vec_gram pass
-constexpr int kCombVecs = 16;   // vectors per vec_lincomb pass
+constexpr int kDotVecs = 24;    // history vectors per vec_gram pass (all of them up to history 12)
+constexpr int kCombVecs = 24;   // vectors per vec_lincomb pass (all 2m + 1 of them up to history 11)
 
 template <typename T>
 struct DotList {
@@ -308,20 +308,22 @@ __device__ __forceinline__ void vec_block_partials(double (&acc)[NV], int nv, do
 }
 
 // One pass of the Gram update. FORM: first y = g - prev_g and s = t d, stored,
-// and the banks 0..4 get y.y, y.s, y.g, g.g, g.s; the listed vectors V_k then
-// give y.V_k and g.V_k in banks NB + 2k and NB + 2k + 1 (NB = 5). Without
-// FORM, y is read and NB = 0. All kDotVecs list entries are read (the host
-// points unused ones at g, and only the first `count` reach the banks), so
-// the loops have fixed trip counts and every value stays in registers. FP64
-// accumulation, packs of four, block 0 takes the n % 4 tail. Grid: kVecBlocks
-// blocks of gram_threads<T>().
-template <typename T, bool FORM>
+// and the banks 0..4 get y.y, y.s, y.g, g.g, g.s (NB = 5; otherwise NB = 0).
+// The first NL list vectors V_k then give g.V_k in bank NB + k. The products
+// of y with the history need no pass of their own: y.V = g.V - prev_g.V, and
+// the host kept prev_g.V from the previous pass. All NL list entries are read
+// (the host points unused ones at g, and only the first `count` reach the
+// banks), so the loops have fixed trip counts and every value stays in
+// registers. FP64 accumulation, packs of four, block 0 takes the n % 4 tail.
+// Grid: kVecBlocks blocks of gram_threads<T>().
+template <typename T, bool FORM, int NL>
 __global__ __launch_bounds__(gram_threads<T>()) void vec_gram(const T* __restrict__ g, const T* __restrict__ prev_g,
                                                               const T* __restrict__ d, double t, T* __restrict__ y,
                                                               T* __restrict__ s, DotList<T> L, size_t n,
                                                               double* __restrict__ banks) {
+  static_assert(NL >= 0 && NL <= kDotVecs && (FORM || NL > 0), "vec_gram list width");
   constexpr int NB = FORM ? 5 : 0;
-  constexpr int NV = NB + 2 * kDotVecs;
+  constexpr int NV = NB + NL;
   const T tt = T(t);
   double acc[NV];
 #pragma unroll
@@ -329,10 +331,10 @@ __global__ __launch_bounds__(gram_threads<T>()) void vec_gram(const T* __restric
   const size_t n4 = n / 4, stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
     const Pack4<T> pg = reinterpret_cast<const Pack4<T>*>(g)[i];
-    Pack4<T> py, ps;
     if constexpr (FORM) {
       const Pack4<T> pp = reinterpret_cast<const Pack4<T>*>(prev_g)[i];
       const Pack4<T> pd = reinterpret_cast<const Pack4<T>*>(d)[i];
+      Pack4<T> py, ps;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         py.v[e] = pg.v[e] - pp.v[e];
@@ -349,55 +351,44 @@ __global__ __launch_bounds__(gram_threads<T>()) void vec_gram(const T* __restric
         acc[3] += ge * ge;
         acc[4] += ge * se;
       }
-    } else {
-      py = reinterpret_cast<const Pack4<T>*>(y)[i];
     }
 #pragma unroll
-    for (int k = 0; k < kDotVecs; ++k) {
+    for (int k = 0; k < NL; ++k) {
       const Pack4<T> pv = reinterpret_cast<const Pack4<T>*>(L.v[k])[i];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        acc[NB + 2 * k] += double(py.v[e]) * double(pv.v[e]);
-        acc[NB + 2 * k + 1] += double(pg.v[e]) * double(pv.v[e]);
-      }
+      for (int e = 0; e < 4; ++e) acc[NB + k] += double(pg.v[e]) * double(pv.v[e]);
     }
   }
   if (blockIdx.x == 0 && threadIdx.x < n - 4 * n4) {
     const size_t j = 4 * n4 + threadIdx.x;
     const double ge = g[j];
-    double ye;
     if constexpr (FORM) {
       const T yt = g[j] - prev_g[j], st = tt * d[j];
       y[j] = yt;
       s[j] = st;
-      ye = yt;
-      const double se = st;
+      const double ye = yt, se = st;
       acc[0] += ye * ye;
       acc[1] += ye * se;
       acc[2] += ye * ge;
       acc[3] += ge * ge;
       acc[4] += ge * se;
-    } else {
-      ye = y[j];
     }
 #pragma unroll
-    for (int k = 0; k < kDotVecs; ++k) {
-      const double ve = L.v[k][j];
-      acc[NB + 2 * k] += ye * ve;
-      acc[NB + 2 * k + 1] += ge * ve;
-    }
+    for (int k = 0; k < NL; ++k) acc[NB + k] += ge * double(L.v[k][j]);
   }
-  vec_block_partials<NV, gram_threads<T>()>(acc, NB + 2 * L.count, banks);
+  vec_block_partials<NV, gram_threads<T>()>(acc, NB + L.count, banks);
 }
 
 // out = sum_k c_k V_k (+ out when acc), accumulated in FP64 and rounded once;
-// when dmax is given, its bank gets the partials of max |out|. All W list
+// when dmax is given, its bank gets the partials of max |out|; when x is
+// given, x += t out (FP64, rounded once) with the rounded out, which is the
+// optimiser's step folded into the pass that forms its direction. All W list
 // entries are read (the host pads a short list with zero coefficients on a
 // listed vector), so the loop has a fixed trip count. Layout of the work as in
 // vec_reduce.
 template <typename T, int W>
 __global__ __launch_bounds__(kVecThreads) void vec_lincomb(CombList<T> L, T* __restrict__ out, int acc, size_t n,
-                                                           double* __restrict__ dmax) {
+                                                           double* __restrict__ dmax, T* __restrict__ x, double t) {
   static_assert(W >= 1 && W <= kCombVecs, "vec_lincomb width");
   const size_t n4 = n / 4, stride = (size_t)gridDim.x * blockDim.x;
   double mx = 0.0;
@@ -421,14 +412,22 @@ __global__ __launch_bounds__(kVecThreads) void vec_lincomb(CombList<T> L, T* __r
       mx = fmax(mx, fabs(double(r.v[e])));
     }
     reinterpret_cast<Pack4<T>*>(out)[i] = r;
+    if (x) {
+      Pack4<T> px = reinterpret_cast<const Pack4<T>*>(x)[i];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) px.v[e] = T(double(px.v[e]) + t * double(r.v[e]));
+      reinterpret_cast<Pack4<T>*>(x)[i] = px;
+    }
   }
   if (blockIdx.x == 0 && threadIdx.x < n - 4 * n4) {
     const size_t j = 4 * n4 + threadIdx.x;
     double a = acc ? double(out[j]) : 0.0;
 #pragma unroll
     for (int k = 0; k < W; ++k) a += L.c[k] * double(L.v[k][j]);
-    out[j] = T(a);
-    mx = fmax(mx, fabs(double(out[j])));
+    const T r = T(a);
+    out[j] = r;
+    mx = fmax(mx, fabs(double(r)));
+    if (x) x[j] = T(double(x[j]) + t * double(r));
   }
   if (dmax) vec_block_partial<2>(mx, dmax);
 }

@@ -22,6 +22,7 @@ struct fe_l2 {
   std::vector<void*> S, Y;       // history, oldest first (pointers rotate, memory stays)
   std::vector<double> rho;
   std::vector<double> SY, YY;    // [history][history]: s_a . y_b (a <= b) and y_a . y_b of the history
+  std::vector<double> pgS, pgY;  // prev_g . s_a and prev_g . y_a for the current history
   int hist_len = 0;
   double* d_red = nullptr;       // reduction banks, then their values (kL2Banks each)
   // settings
@@ -38,12 +39,12 @@ int l2_launch_1d(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 65536
 
 // Scalars of the optimiser. Named slots: 0 energy, 1 max|g|, 2 max|d|, 3 g'd
 // and 4 |g|_1 (first iteration); then the inner products of the Gram pass
-// (y.y, y.s, y.g, g.g, g.s, then y.V_k, g.V_k for each history vector). d_red
+// (y.y, y.s, y.g, g.g, g.s, then g.V_k for each history vector). d_red
 // holds one bank of kVecBlocks partials per slot, then one value per slot for
 // the host (the energy is written there directly).
 constexpr int kSlotE = 0, kSlotGmax = 1, kSlotDmax = 2, kSlotGtd = 3, kSlotL1 = 4, kSlotGram = 5;
 constexpr int kL2MaxHistory = 64;
-constexpr int kL2Banks = kSlotGram + 5 + 4 * kL2MaxHistory;
+constexpr int kL2Banks = kSlotGram + 5 + 2 * kL2MaxHistory;
 constexpr size_t kL2RedDoubles = (size_t)kL2Banks * fe::kVecBlocks + kL2Banks;
 
 double* l2_bank(fe_l2* L, int slot) { return L->d_red + (size_t)slot * fe::kVecBlocks; }
@@ -94,29 +95,33 @@ int l2_read_slots(fe_l2* L, int first, int count, double* out) {
 // with dmax, the last pass leaves max |out| in the bank of kSlotDmax. No sync.
 template <typename T>
 int l2_lincomb(fe_l2* L, const std::vector<const void*>& v, const std::vector<double>& c, bool acc, void* out,
-               bool dmax) {
+               bool dmax, void* x = nullptr, double t = 0.0) {
   const size_t K = v.size();
   for (size_t k0 = 0; k0 < K; k0 += fe::kCombVecs) {
     fe::CombList<T> cl{};
     cl.count = (int)std::min<size_t>(fe::kCombVecs, K - k0);
-    // pass widths 1, 4, 8 or 16; the padding repeats the first vector with c = 0
-    const int w = cl.count == 1 ? 1 : cl.count <= 4 ? 4 : cl.count <= 8 ? 8 : fe::kCombVecs;
+    // pass widths 1, 4, 8, 16 or 24; the padding repeats the first vector with c = 0
+    const int w = cl.count == 1 ? 1 : cl.count <= 4 ? 4 : cl.count <= 8 ? 8 : cl.count <= 16 ? 16 : fe::kCombVecs;
     for (int k = 0; k < w; ++k) {
       cl.v[k] = static_cast<const T*>(v[k < cl.count ? k0 + k : k0]);
       cl.c[k] = k < cl.count ? c[k0 + k] : 0.0;
     }
     const int a = (acc || k0 > 0) ? 1 : 0;
-    double* dm = (dmax && k0 + fe::kCombVecs >= K) ? l2_bank(L, kSlotDmax) : nullptr;
+    const bool last = k0 + fe::kCombVecs >= K;
+    double* dm = (dmax && last) ? l2_bank(L, kSlotDmax) : nullptr;
+    T* px = last ? static_cast<T*>(x) : nullptr;
     T* po = static_cast<T*>(out);
     hipStream_t s = L->ctx->stream;
     if (w == 1)
-      hipLaunchKernelGGL((fe::vec_lincomb<T, 1>), kVecGrid, kVecBlock, 0, s, cl, po, a, L->n, dm);
+      hipLaunchKernelGGL((fe::vec_lincomb<T, 1>), kVecGrid, kVecBlock, 0, s, cl, po, a, L->n, dm, px, t);
     else if (w == 4)
-      hipLaunchKernelGGL((fe::vec_lincomb<T, 4>), kVecGrid, kVecBlock, 0, s, cl, po, a, L->n, dm);
+      hipLaunchKernelGGL((fe::vec_lincomb<T, 4>), kVecGrid, kVecBlock, 0, s, cl, po, a, L->n, dm, px, t);
     else if (w == 8)
-      hipLaunchKernelGGL((fe::vec_lincomb<T, 8>), kVecGrid, kVecBlock, 0, s, cl, po, a, L->n, dm);
+      hipLaunchKernelGGL((fe::vec_lincomb<T, 8>), kVecGrid, kVecBlock, 0, s, cl, po, a, L->n, dm, px, t);
+    else if (w == 16)
+      hipLaunchKernelGGL((fe::vec_lincomb<T, 16>), kVecGrid, kVecBlock, 0, s, cl, po, a, L->n, dm, px, t);
     else
-      hipLaunchKernelGGL((fe::vec_lincomb<T, fe::kCombVecs>), kVecGrid, kVecBlock, 0, s, cl, po, a, L->n, dm);
+      hipLaunchKernelGGL((fe::vec_lincomb<T, fe::kCombVecs>), kVecGrid, kVecBlock, 0, s, cl, po, a, L->n, dm, px, t);
     FE_HIP(hipGetLastError());
   }
   return FE_OK;
@@ -129,13 +134,47 @@ int l2_scale_add(fe_l2* L, double alpha, const void* x, bool acc, void* y) {
 }
 
 // The Gram pass: y = g - prev_g into L->q, s = t d into L->w0, and the inner
-// products y.y, y.s, y.g, g.g, g.s and, for every vector v of `hist`, y.v and
-// g.v, copied to `out` in that order (one sync).
+// products y.y, y.s, y.g, g.g, g.s and, for every vector v of `hist`, g.v,
+// copied to `out` in that order (one sync). Up to kDotVecs history vectors go
+// through one pass; a list of 8, 16 or 24 entries, the unused ones pointing at g.
+template <typename T>
+void gram_launch(fe_l2* L, bool form, const fe::DotList<T>& dl, int bank) {
+  hipStream_t s = L->ctx->stream;
+  const T* g = static_cast<const T*>(L->g);
+  const T* pg = static_cast<const T*>(L->prev_g);
+  const T* d = static_cast<const T*>(L->d);
+  T* y = static_cast<T*>(L->q);
+  T* sv = static_cast<T*>(L->w0);
+  double* bk = l2_bank(L, bank);
+  const dim3 grid = kVecGrid, blk(fe::gram_threads<T>());
+  const int nl = dl.count == 0 ? 0 : dl.count <= 8 ? 8 : dl.count <= 16 ? 16 : fe::kDotVecs;
+  if (form) {
+    if (nl == 0)
+      hipLaunchKernelGGL((fe::vec_gram<T, true, 0>), grid, blk, 0, s, g, pg, d, L->t, y, sv, dl, L->n, bk);
+    else if (nl == 8)
+      hipLaunchKernelGGL((fe::vec_gram<T, true, 8>), grid, blk, 0, s, g, pg, d, L->t, y, sv, dl, L->n, bk);
+    else if (nl == 16)
+      hipLaunchKernelGGL((fe::vec_gram<T, true, 16>), grid, blk, 0, s, g, pg, d, L->t, y, sv, dl, L->n, bk);
+    else
+      hipLaunchKernelGGL((fe::vec_gram<T, true, fe::kDotVecs>), grid, blk, 0, s, g, pg, d, L->t, y, sv, dl, L->n,
+                         bk);
+  } else {
+    if (nl == 8)
+      hipLaunchKernelGGL((fe::vec_gram<T, false, 8>), grid, blk, 0, s, g, nullptr, nullptr, 0.0, nullptr, nullptr, dl,
+                         L->n, bk);
+    else if (nl == 16)
+      hipLaunchKernelGGL((fe::vec_gram<T, false, 16>), grid, blk, 0, s, g, nullptr, nullptr, 0.0, nullptr, nullptr,
+                         dl, L->n, bk);
+    else
+      hipLaunchKernelGGL((fe::vec_gram<T, false, fe::kDotVecs>), grid, blk, 0, s, g, nullptr, nullptr, 0.0, nullptr,
+                         nullptr, dl, L->n, bk);
+  }
+}
+
 template <typename T>
 int l2_gram(fe_l2* L, const std::vector<const void*>& hist, std::vector<double>& out) {
   hipStream_t s = L->ctx->stream;
   const T* g = static_cast<const T*>(L->g);
-  T* y = static_cast<T*>(L->q);
   const size_t K = hist.size();
   int bank = kSlotGram;
   size_t k0 = 0;
@@ -143,17 +182,9 @@ int l2_gram(fe_l2* L, const std::vector<const void*>& hist, std::vector<double>&
     fe::DotList<T> dl{};
     dl.count = (int)std::min<size_t>(fe::kDotVecs, K - k0);
     for (int k = 0; k < fe::kDotVecs; ++k) dl.v[k] = k < dl.count ? static_cast<const T*>(hist[k0 + k]) : g;
-    if (k0 == 0) {
-      hipLaunchKernelGGL((fe::vec_gram<T, true>), kVecGrid, dim3(fe::gram_threads<T>()), 0, s, g,
-                         static_cast<const T*>(L->prev_g), static_cast<const T*>(L->d), L->t, y,
-                         static_cast<T*>(L->w0), dl, L->n, l2_bank(L, bank));
-      bank += 5;
-    } else {
-      hipLaunchKernelGGL((fe::vec_gram<T, false>), kVecGrid, dim3(fe::gram_threads<T>()), 0, s, g, nullptr, nullptr, 0.0,
-                         y, nullptr, dl, L->n, l2_bank(L, bank));
-    }
+    gram_launch<T>(L, k0 == 0, dl, bank);
     FE_HIP(hipGetLastError());
-    bank += 2 * dl.count;
+    bank += (k0 == 0 ? 5 : 0) + dl.count;
     k0 += dl.count;
   } while (k0 < K);
   const int nv = bank - kSlotGram;
@@ -278,10 +309,13 @@ int l2_step(fe_l2* L, double& loss0) {
     ++L->n_iter;
     const bool first = L->n_iter == 1;
     double gtd = 0.0, gl1 = 0.0;
+    bool moved = false;   // x already advanced by the direction pass
     if (first) {
       if ((rc = l2_lincomb<T>(L, {L->g}, {-1.0}, false, L->d, true))) return rc;   // d = -g
       L->hist_len = 0;
       L->rho.clear();
+      L->pgS.clear();
+      L->pgY.clear();
       L->H_diag = 1.0;
       if ((rc = l2_reduce_dev<T>(L, 0, L->g, L->d, kSlotGtd))) return rc;
       if ((rc = l2_reduce_dev<T>(L, 1, L->g, nullptr, kSlotL1))) return rc;
@@ -290,8 +324,10 @@ int l2_step(fe_l2* L, double& loss0) {
       gtd = gl[0];
       gl1 = gl[1];
     } else {
-      // The Gram pass: y = g - prev_g (in q), s = t d (in w0) and the inner
-      // products of y and g with each other, with s and with every history vector.
+      // The Gram pass: y = g - prev_g (in q), s = t d (in w0), the inner
+      // products of y and g with each other and with s, and g with every
+      // history vector; y with a history vector is g.v - prev_g.v, the latter
+      // kept from the previous pass (prev_g was that pass's g).
       int m = L->hist_len;
       const int H = L->history;
       std::vector<const void*> hist;
@@ -300,12 +336,14 @@ int l2_step(fe_l2* L, double& loss0) {
       std::vector<double> gv;
       if ((rc = l2_gram<T>(L, hist, gv))) return rc;
       const double yy = gv[0], ys = gv[1], yg = gv[2], gg = gv[3], gs = gv[4];
+      if ((int)L->pgS.size() != m || (int)L->pgY.size() != m)
+        return set_error(FE_EINVAL, "L-BFGS state out of step with its history");
       std::vector<double> yS(m), gS(m), yY(m), gY(m);
       for (int i = 0; i < m; ++i) {
-        yS[i] = gv[5 + 2 * i];
-        gS[i] = gv[6 + 2 * i];
-        yY[i] = gv[5 + 2 * (m + i)];
-        gY[i] = gv[6 + 2 * (m + i)];
+        gS[i] = gv[5 + i];
+        gY[i] = gv[5 + m + i];
+        yS[i] = gS[i] - L->pgS[i];
+        yY[i] = gY[i] - L->pgY[i];
       }
       double* SY = L->SY.data();
       double* YY = L->YY.data();
@@ -338,6 +376,9 @@ int l2_step(fe_l2* L, double& loss0) {
         L->hist_len = ++m;
         L->H_diag = ys / yy;
       }
+      // g becomes prev_g below: keep its products with the history as it now stands
+      L->pgS = gS;
+      L->pgY = gY;
       // The two-loop recursion on the inner products, newest to oldest:
       //   a_i = rho_i s_i.q with q = -g - sum_{j>i} a_j y_j,
       // then r = H q (q = -g - sum_j a_j y_j), oldest to newest:
@@ -370,7 +411,10 @@ int l2_step(fe_l2* L, double& loss0) {
         cc.push_back(-Hd * al[j]);
         gtd += -Hd * al[j] * gY[j];
       }
-      if ((rc = l2_lincomb<T>(L, vv, cc, false, L->d, true))) return rc;
+      // when the step will be taken (t = lr, g'd below -tol_change), the pass
+      // that forms d also moves x
+      moved = !(gtd > -L->tol_change);
+      if ((rc = l2_lincomb<T>(L, vv, cc, false, L->d, true, moved ? L->x : nullptr, L->lr))) return rc;
     }
     // prev_g takes over the gradient's buffer; the next evaluation writes g anew
     std::swap(L->g, L->prev_g);
@@ -378,7 +422,7 @@ int l2_step(fe_l2* L, double& loss0) {
     L->t = first ? std::min(1.0, 1.0 / gl1) * L->lr : L->lr;
     if (gtd > -L->tol_change) break;
     int ls_evals = 0;
-    if ((rc = l2_scale_add<T>(L, L->t, L->d, true, L->x))) return rc;   // max |d| is in its slot already
+    if (!moved && (rc = l2_scale_add<T>(L, L->t, L->d, true, L->x))) return rc;   // max |d| is in its slot already
     double dmax = 0.0;
     if (it != L->max_iter) {
       if ((rc = l2_eval_dev<T>(L))) return rc;
@@ -526,6 +570,8 @@ int fe_l2_set_lbfgs(fe_l2* L, double lr, int history, int max_iter, double toler
   L->n_iter = 0;
   L->hist_len = 0;
   L->rho.clear();
+  L->pgS.clear();
+  L->pgY.clear();
   L->SY.assign((size_t)history * history, 0.0);
   L->YY.assign((size_t)history * history, 0.0);
   return FE_OK;
@@ -549,6 +595,8 @@ int fe_l2_load(fe_l2* L, const void* u) {
   L->n_iter = 0;
   L->hist_len = 0;
   L->rho.clear();
+  L->pgS.clear();
+  L->pgY.clear();
   return FE_OK;
 }
 
