@@ -102,3 +102,17 @@ def test_calls_on_null_context_fail_cleanly(L):
     assert L.fe_hminus_reset(None) == fe.FE_EINVAL
     assert L.fe_diagnostics(None, None, None, None, 8, 10.0, None) == fe.FE_EINVAL
     L.fe_destroy(None)   # no-op
+
+
+@pytest.mark.parametrize("grid,sigma_k,msg", [
+    (dict(GOOD, batch=2), 1.0, "batch 1"),
+    (GOOD, -1.0, "sigma_k"),
+    (GOOD, 4.5, "sigma_k"),
+    (dict(GOOD, nx=40000, ny=40000, nz=1), 0.0, "too large"),   # padded planes of 6.4 GB
+    (dict(GOOD, nx=4, ny=70000, nz=4), 0.0, "too large"),       # padded ny beyond a grid dimension
+])
+def test_l2_create_rejects_before_device_work(L, grid, sigma_k, msg):
+    out = ctypes.c_void_p()
+    rc = L.fe_l2_create(ctypes.byref(fe.FeGrid(**grid)), 0.25, fe._dbl([1, 2, 1, 0, 0, 0]), sigma_k, None,
+                        ctypes.byref(out))
+    assert rc == fe.FE_EINVAL and not out.value and msg in L.fe_last_error().decode()
