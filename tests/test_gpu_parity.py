@@ -186,6 +186,45 @@ def test_full_size_sampled(cfg):
     assert rel <= TOL[torch.float32]["energy"]
 
 
+def test_full_size_step_in_the_bench_configuration():
+    """The path the benchmark times: 256^3 FP32 (u0 ~ U(-1, 1), seed 1005, eps = 1.5h, the
+    Helfrich-type p), mass-projected steps tau = 1e-3 in the context's default launch. A
+    step is u - tau g + c with one constant c that restores the mass, so once the sweep's
+    gradient is checked against the oracle on sampled voxels it must account for the
+    whole update up to that constant, and mean(u) must equal the mass. A 16-step call (a
+    replay of the captured step graph) must equal 15 steps and then one, bit for bit."""
+    n = 256
+    h = 1.0 / n
+    tau = 1e-3
+    log("case full step 256")
+    u0 = to_dev(inputs.uniform_noise(n, 1005), torch.float32)
+    ctx = fe.FeContext(u0.shape, h, 1.5 * h, HELFRICH_SC, dtype=torch.float32)
+    mass = [float(u0.double().mean().item())]
+
+    def check_step(ua, ub):
+        _, g = ctx.energy_grad(ua)
+        pre = ua.double() - tau * g.double()
+        ctx.step(ub, mass, tau, 1)
+        d = pre - ub.double()                       # -c at every voxel, up to FP32 rounding
+        spread = (d.max() - d.min()).item()
+        c = mass[0] - pre.mean().item()
+        assert spread <= 2e-6, spread
+        assert abs(-d.mean().item() - c) <= 1e-6, (d.mean().item(), c)
+        assert abs(ub.double().mean().item() - mass[0]) <= 1e-6
+        return g
+
+    g0 = check_step(u0, u0.clone())
+    _sampled_gradient_check(oracle_input(u0), g0.cpu().double().numpy(), h, 1.5 * h, HELFRICH_SC,
+                            TOL[torch.float32]["grad"], nsamp=12, seed=3)
+    ua = u0.clone()
+    ctx.step(ua, mass, tau, 16)
+    ub = u0.clone()
+    ctx.step(ub, mass, tau, 15)
+    check_step(ub.clone(), ub)
+    assert torch.equal(ua, ub)
+    assert torch.isfinite(ua).all()
+
+
 def test_full_size_batched_16x128_sampled():
     """16 x 128^3 FP32 with per-instance (eps, a): instances 0 and 15 in full, the
     rest by sampled gradients."""
