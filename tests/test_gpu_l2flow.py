@@ -66,24 +66,27 @@ def test_thin_boxes_match_oracle(shape, sigma_k):
     assert rel_l2(g.cpu().double().numpy(), go) <= tol["grad"]
 
 
-def test_lbfgs_steps_match_torch_lbfgs_on_the_oracle():
-    """FP64, 16^3 noisy ball, blur sigma_k = 1, p = H^2: four steps of five inner
-    iterations against torch.optim.LBFGS (lr 1, history 3 so that the history wraps)
-    driving the oracle's energy and gradient. eps = 2.5h keeps the trajectory free
-    of the wild steps that L-BFGS without line search can take (at eps = 2h one
-    iterate reaches F ~ 1e24); after such a step the two implementations' rounding
-    differences, though both correct, grow without bound."""
+@pytest.mark.parametrize("history,max_iter,nsteps", [(3, 5, 4), (14, 12, 2)])
+def test_lbfgs_steps_match_torch_lbfgs_on_the_oracle(history, max_iter, nsteps):
+    """FP64, 16^3 noisy ball, blur sigma_k = 1, p = H^2: steps of inner iterations
+    against torch.optim.LBFGS (lr 1) driving the oracle's energy and gradient; the
+    history wraps in both cases, and history 14 takes two passes of both the Gram
+    and the direction kernels (28 history vectors, 29 direction terms). eps = 2.5h
+    keeps the trajectory free of the wild steps that L-BFGS without line search can
+    take (at eps = 2h one iterate reaches F ~ 1e24); after such a step the two
+    implementations' rounding differences, though both correct, grow without bound."""
     n = 16
     h = 1.0 / n
     eps = 2.5 * h
     u0 = inputs.noisy_sphere(n, 0.3, eps, 0.02, 8)
     ud = to_dev(u0, torch.float64)
     flow = fe.FeL2Flow((n, n, n), h, eps, WILLMORE, sigma_k=1.0, dtype=torch.float64)
-    flow.set_lbfgs(lr=1.0, history=3, max_iter=5)
+    flow.set_lbfgs(lr=1.0, history=history, max_iter=max_iter)
     flow.load(ud)
-    Eg = flow.step(4)
+    Eg = flow.step(nsteps)
     ug = flow.store().cpu().numpy()
-    uo, Eo = l2flow.lbfgs_flow(oracle_input(ud), h, eps, WILLMORE, 1.0, 4, lr=1.0, history=3, max_iter=5)
+    uo, Eo = l2flow.lbfgs_flow(oracle_input(ud), h, eps, WILLMORE, 1.0, nsteps, lr=1.0, history=history,
+                               max_iter=max_iter)
     np.testing.assert_allclose(Eg, Eo, rtol=1e-9)
     assert rel_l2(ug, uo) <= 1e-8
     log(f"  energies {Eg}")
