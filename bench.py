@@ -38,9 +38,22 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 # Algorithmic work of one voxel update, counted on the method's formulas (each
-# +, -, x, /, sqrt counts one): stencils and M with its invariants and the
-# density 97, the reverse sweep 89, the transposed stencils 41, the step 3.
+# +, -, x, /, sqrt, exp, log counts one): stencils and M with its invariants and
+# the density 97, the reverse sweep 89, the transposed stencils 41, the step 3.
 FLOPS_PER_VOXEL = 230
+# Of these, the S~ terms take 45: forward 18 (X~ = 2 N2 - T^2: 3; the smoothed
+# positive part: 8; S~ = sqrt: 1; c3 T S~ and c5 rho S~ into f: 6) and reverse
+# 27 (df/dS~: 3; the logistic: 3; dS~/dX~: 2; kappa and 2 kappa: 2; the three
+# 2 m_aa - T~ and their 2 kappa terms: 12; C1 + 2 kappa: 1; the S~ parts of
+# df/dT~ and df/drho~: 4). Their coefficients c3 = (a20 - a02)/(2 eps) and
+# c5 = (a10 - a01)/2 vanish for p symmetric in k1, k2, and then the method
+# needs none of them.
+FLOPS_S_TERMS = 45
+
+
+def flops_per_voxel(a):
+    """Algorithmic operations per voxel update for p coefficients a = (a20, a11, a02, a10, a01, a00)."""
+    return FLOPS_PER_VOXEL - (FLOPS_S_TERMS if a[0] == a[2] and a[3] == a[4] else 0)
 # Algorithmic HBM bytes per voxel and step, FP32: read u, write the new u.
 BYTES_PER_VOXEL_STEP = 8
 BYTES_PER_VOXEL_GRAD = 8       # read u, write g
@@ -377,7 +390,8 @@ def main():
     step_us = ms_step * 1e3
     bytes_step = BYTES_PER_VOXEL_STEP * vox
     hbm_gbs = bytes_step / (step_us * 1e-6) / 1e9
-    tflops = FLOPS_PER_VOXEL * vox / (step_us * 1e-6) / 1e12
+    ops_voxel = flops_per_voxel(HELFRICH_SC)
+    tflops = ops_voxel * vox / (step_us * 1e-6) / 1e12
     vinfo = fe.variants()[variant]
     kname = f"grad_sweep<float,{vinfo[0]},{vinfo[1]},{vinfo[2]},1>"
     traffic = measured_traffic(kname, zc)
@@ -386,7 +400,7 @@ def main():
     hbm = {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": traffic}
     roof, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
-    roof = dict(roof, kernel=kname, duration_us=step_us)
+    roof = dict(roof, kernel=kname, duration_us=step_us, ops_per_voxel=ops_voxel)
     # the published FP32 vector peak counts packed two-wide FMAs; this build
     # compiles with packed FP32 disabled, so its attainable ALU ceiling is half
     roof["unpacked_fp32_peak"] = FP32_VECTOR_PEAK_TFLOPS / 2

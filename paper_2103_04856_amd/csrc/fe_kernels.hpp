@@ -383,8 +383,11 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
       const T* pc = su[sc] + c;
       const T* pm = su[sm] + c;
       const T* pp = su[sp] + c;
-      const T f = voxel_density_adjoint(load_stencil<T, UX>(pc, pm, pp),
-                                        [&]() { return load_stencil<T, UX>(pc, pm, pp); }, pv, a.k, ad);
+      // the body without S~ terms only where the instance has none and the
+      // registers allow it: the Adam sweep, already near the register limit of
+      // two blocks per CU, keeps the one full body
+      const T f = voxel_density_adjoint<SP || MODE == kStepAdam>(
+          load_stencil<T, UX>(pc, pm, pp), [&]() { return load_stencil<T, UX>(pc, pm, pp); }, pv, a.k, ad);
       sx[GX][v] = ad.gx; sx[GY][v] = ad.gy;
       sx[BXX][v] = ad.nbxx; sx[BYY][v] = ad.nbyy;
       sx[BXY][v] = ad.nbxy; sx[BXZ][v] = ad.nbxz; sx[BYZ][v] = ad.nbyz;
@@ -538,9 +541,9 @@ __global__ __launch_bounds__(NT) void energy_sweep(SweepArgs<T> a) {
       const T* pc = su[sc] + c;
       const T* pm = su[sm] + c;
       const T* pp = su[sp] + c;
-      const T f = voxel_density(load_stencil<T, UX>(pc, pm, pp),
-                                [&]() { return load_stencil<T, UX>(pc, pm, pp); },
-                                SP ? with_coeffs(prm, cv[j]) : prm, a.k);
+      const T f = voxel_density<SP>(load_stencil<T, UX>(pc, pm, pp),
+                                    [&]() { return load_stencil<T, UX>(pc, pm, pp); },
+                                    SP ? with_coeffs(prm, cv[j]) : prm, a.k);
       if (x0 + ix < a.nx && y0 + iy < a.ny) {
         acc_f += double(f);
         acc_m += double(pc[0]);

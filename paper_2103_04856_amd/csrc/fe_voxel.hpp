@@ -167,7 +167,22 @@ __device__ __forceinline__ Forward<T> forward_fp64(const Stencil19<T>& s, const 
   return o;
 }
 
+// Whether the density has the S~ terms: C3 (a20 - a02) and C5 (a10 - a01)
+// vanish for every p symmetric in kappa1 and kappa2 (Willmore, Helfrich), and
+// then S~, its softplus and dS~/dX~ meet only zero coefficients: f~ and its
+// derivatives do without them. The per-voxel functions below take NOS (no S~
+// terms) as a template argument; the sweeps pick the body once per call from
+// the instance's coefficients, so an instance takes the same arithmetic in
+// every batch it is part of.
+template <typename T>
+__device__ __forceinline__ bool has_s_terms(const InstParams<T>& p) {
+  return p.C3 != T(0) || p.C5 != T(0);
+}
+
 // The chain up to X~ in FP32, and whether X~ is too ill-conditioned for it.
+// With NOS, X~ is left 0 and never redone: the FP64 chain exists for X~, whose
+// derivative grows as 1/S~ near umbilic voxels.
+template <bool NOS = false>
 __device__ __forceinline__ Forward<float> forward_fp32(const Stencil19<float>& s, const InstParams<float>& p,
                                                        const GridConsts<float>& k, bool& redo) {
   Forward<float> o;
@@ -201,10 +216,15 @@ __device__ __forceinline__ Forward<float> forward_fp32(const Stencil19<float>& s
   const float d = o.mxx * o.mxx + o.myy * o.myy + o.mzz * o.mzz;
   const float od = o.oxy * o.oxy + o.oxz * o.oxz + o.oyz * o.oyz;
   o.n2 = od * 0.125f + d;
-  const float n2x2 = o.n2 + o.n2;
-  o.X = n2x2 - o.tr * o.tr;
-  const float scale = n2x2 + o.tr * o.tr;
-  redo = (scale > 4096.0f * p.xi) && (fabsf(o.X) < scale * (1.0f / 4096.0f));
+  if constexpr (NOS) {
+    o.X = 0.0f;
+    redo = false;
+  } else {
+    const float n2x2 = o.n2 + o.n2;
+    o.X = n2x2 - o.tr * o.tr;
+    const float scale = n2x2 + o.tr * o.tr;
+    redo = (scale > 4096.0f * p.xi) && (fabsf(o.X) < scale * (1.0f / 4096.0f));
+  }
   o.dxx = 2.0f * o.mxx - o.tr;
   o.dyy = 2.0f * o.myy - o.tr;
   o.dzz = 2.0f * o.mzz - o.tr;
@@ -213,19 +233,19 @@ __device__ __forceinline__ Forward<float> forward_fp32(const Stencil19<float>& s
 
 // The forward chain in the storage precision; reload() returns the stencil
 // again for the (rare) FP64 re-evaluation.
-template <typename Reload>
+template <bool NOS = false, typename Reload>
 __device__ __forceinline__ Forward<double> forward_chain(const Stencil19<double>& s, Reload,
                                                          const InstParams<double>& p,
                                                          const GridConsts<double>& k) {
   return forward_fp64(s, p, k);
 }
 
-template <typename Reload>
+template <bool NOS = false, typename Reload>
 __device__ __forceinline__ Forward<float> forward_chain(const Stencil19<float>& s, Reload reload,
                                                         const InstParams<float>& p,
                                                         const GridConsts<float>& k) {
   bool redo;
-  Forward<float> o = forward_fp32(s, p, k, redo);
+  Forward<float> o = forward_fp32<NOS>(s, p, k, redo);
   if (redo) o = forward_fp64(reload(), p, k);
   return o;
 }
@@ -251,13 +271,18 @@ __device__ __forceinline__ void softplus_xi(T X, const InstParams<T>& p, T& P, T
 
 // Forward only: the scaled energy density f~ = h^3 f at one voxel.
 // f~ from the forward chain's values.
-template <typename T>
+template <bool NOS = false, typename T>
 __device__ __forceinline__ T density_of(const Forward<T>& fw, const InstParams<T>& p) {
-  T P, sig;
-  softplus_xi(fw.X, p, P, sig);
-  const T S = P > T(0) ? P * rsqrt_t(P) : T(0);
   const T rho = fw.R * fw.rs;
-  T f = p.C1 * fw.n2 + fw.tr * (p.C2 * fw.tr + p.C3 * S + p.C4 * rho) + p.C5 * rho * S + p.C6 * fw.Q;
+  T f;
+  if constexpr (NOS) {
+    f = p.C1 * fw.n2 + fw.tr * (p.C2 * fw.tr + p.C4 * rho) + p.C6 * fw.Q;
+  } else {
+    T P, sig;
+    softplus_xi(fw.X, p, P, sig);
+    const T S = P > T(0) ? P * rsqrt_t(P) : T(0);
+    f = p.C1 * fw.n2 + fw.tr * (p.C2 * fw.tr + p.C3 * S + p.C4 * rho) + p.C5 * rho * S + p.C6 * fw.Q;
+  }
   if (p.Co != T(0)) {                              // eps mu (theta . g)^2 = Co (theta . a)^2 / h^3
     const T ta = p.thx * fw.ax + p.thy * fw.ay + p.thz * fw.az;
     f += p.Co * ta * ta;
@@ -265,43 +290,65 @@ __device__ __forceinline__ T density_of(const Forward<T>& fw, const InstParams<T
   return f;
 }
 
-template <typename T, typename Reload>
+template <bool NOS, typename T, typename Reload>
+__device__ __forceinline__ T voxel_density_body(const Stencil19<T>& s, Reload reload, const InstParams<T>& p,
+                                                const GridConsts<T>& k) {
+  return density_of<NOS>(forward_chain<NOS>(s, reload, p, k), p);
+}
+
+// FULL: the instance may have S~ terms at any voxel (a coefficient field), so
+// the full body runs without looking.
+template <bool FULL = false, typename T, typename Reload>
 __device__ __forceinline__ T voxel_density(const Stencil19<T>& s, Reload reload, const InstParams<T>& p,
                                            const GridConsts<T>& k) {
-  return density_of(forward_chain(s, reload, p, k), p);
+  if (FULL || has_s_terms(p)) return voxel_density_body<false>(s, reload, p, k);
+  return voxel_density_body<true>(s, reload, p, k);
 }
 
 // Forward and adjoint at one voxel. Returns f~ and writes its derivatives with
 // respect to u(i), a_a and (negated) b_ab.
-template <typename T, typename Reload>
-__device__ __forceinline__ T voxel_density_adjoint(const Stencil19<T>& s, Reload reload, const InstParams<T>& p,
-                                                   const GridConsts<T>& k, VoxelAdjoint<T>& a) {
-  const Forward<T> fw = forward_chain(s, reload, p, k);
+template <bool NOS, typename T, typename Reload>
+__device__ __forceinline__ T voxel_density_adjoint_body(const Stencil19<T>& s, Reload reload,
+                                                        const InstParams<T>& p, const GridConsts<T>& k,
+                                                        VoxelAdjoint<T>& a) {
+  const Forward<T> fw = forward_chain<NOS>(s, reload, p, k);
   const T tr = fw.tr;
-  T P, sig;
-  softplus_xi(fw.X, p, P, sig);
-  const T rsP = P > T(0) ? rsqrt_t(P) : T(0);
-  const T S = P * rsP;
+  T f, rhob, trb0, bxx, byy, bzz, cq;
   const T rs = fw.rs;
   const T rho = fw.R * rs;                         // 2h rho
-
-  T f = p.C1 * fw.n2 + tr * (p.C2 * tr + p.C3 * S + p.C4 * rho) + p.C5 * rho * S + p.C6 * fw.Q;
-
-  // ---- reverse sweep ----
-  const T Sb = p.C3 * tr + p.C5 * rho;             // df/dS~
-  const T rhob = p.C4 * tr + p.C5 * S;             // df/drho~
-  const T kap = Sb * sig * (T(0.5) * rsP);         // df/dX~  (dS~/dX~ = sig / (2S~); 0 where S~ = 0)
-  const T kap2 = kap + kap;
-  // df/dm_aa = 2 C1 m_aa + df/dT~ + 2 kap (2 m_aa - T~): the X~ part is written
-  // with the difference formed in the forward chain, so no two kap-sized
-  // terms cancel.
-  const T trb0 = T(2) * p.C2 * tr + p.C3 * S + p.C4 * rho;
   const T c1x2 = p.C1 + p.C1;
-  const T bxx = c1x2 * fw.mxx + trb0 + kap2 * fw.dxx;
-  const T byy = c1x2 * fw.myy + trb0 + kap2 * fw.dyy;
-  const T bzz = c1x2 * fw.mzz + trb0 + kap2 * fw.dzz;
+  if constexpr (NOS) {
+    f = p.C1 * fw.n2 + tr * (p.C2 * tr + p.C4 * rho) + p.C6 * fw.Q;
+    // ---- reverse sweep ----
+    rhob = p.C4 * tr;                              // df/drho~
+    trb0 = T(2) * p.C2 * tr + p.C4 * rho;
+    bxx = c1x2 * fw.mxx + trb0;
+    byy = c1x2 * fw.myy + trb0;
+    bzz = c1x2 * fw.mzz + trb0;
+    cq = p.C1;
+  } else {
+    T P, sig;
+    softplus_xi(fw.X, p, P, sig);
+    const T rsP = P > T(0) ? rsqrt_t(P) : T(0);
+    const T S = P * rsP;
+
+    f = p.C1 * fw.n2 + tr * (p.C2 * tr + p.C3 * S + p.C4 * rho) + p.C5 * rho * S + p.C6 * fw.Q;
+
+    // ---- reverse sweep ----
+    const T Sb = p.C3 * tr + p.C5 * rho;           // df/dS~
+    rhob = p.C4 * tr + p.C5 * S;                   // df/drho~
+    const T kap = Sb * sig * (T(0.5) * rsP);       // df/dX~  (dS~/dX~ = sig / (2S~); 0 where S~ = 0)
+    const T kap2 = kap + kap;
+    // df/dm_aa = 2 C1 m_aa + df/dT~ + 2 kap (2 m_aa - T~): the X~ part is
+    // written with the difference formed in the forward chain, so no two
+    // kap-sized terms cancel.
+    trb0 = T(2) * p.C2 * tr + p.C3 * S + p.C4 * rho;
+    bxx = c1x2 * fw.mxx + trb0 + kap2 * fw.dxx;
+    byy = c1x2 * fw.myy + trb0 + kap2 * fw.dyy;
+    bzz = c1x2 * fw.mzz + trb0 + kap2 * fw.dzz;
+    cq = p.C1 + kap2;
+  }
   // q_ab = 4 df/do_ab = (C1 + 2 kap) o_ab
-  const T cq = p.C1 + kap2;
   const T qxy = cq * fw.oxy, qxz = cq * fw.oxz, qyz = cq * fw.oyz;
   // m_aa = sw a_a^2 - b_aa,  o_ab = 4 sw a_a a_b - b_ab
   a.nbxx = bxx;
@@ -332,6 +379,15 @@ __device__ __forceinline__ T voxel_density_adjoint(const Stencil19<T>& s, Reload
     a.gz += t2 * p.thz;
   }
   return f;
+}
+
+// Forward and adjoint at one voxel, the body picked from the coefficients (FULL:
+// always the full body, for coefficient fields).
+template <bool FULL = false, typename T, typename Reload>
+__device__ __forceinline__ T voxel_density_adjoint(const Stencil19<T>& s, Reload reload, const InstParams<T>& p,
+                                                   const GridConsts<T>& k, VoxelAdjoint<T>& a) {
+  if (FULL || has_s_terms(p)) return voxel_density_adjoint_body<false>(s, reload, p, k, a);
+  return voxel_density_adjoint_body<true>(s, reload, p, k, a);
 }
 
 }  // namespace fe

@@ -105,6 +105,29 @@ def test_batched_equals_single_bitwise():
             assert torch.equal(gb[0], g[b])
 
 
+def test_symmetric_and_asymmetric_instances_in_one_launch():
+    """p symmetric in k1, k2 (c3 = c5 = 0: Helfrich, Willmore) takes the body without the
+    S terms; the others the full body; the choice is per instance. A launch that mixes
+    them, with one p having c5 only (a20 = a02, a10 != a01), matches the oracle and gives
+    each instance the bits of its own single-instance launch."""
+    n, B = 28, 4
+    h = 1.0 / n
+    coeffs = [HELFRICH_SC, ASYM_C3, WILLMORE_QUARTER, (1.0, 0.5, 1.0, -2.0, -1.0, 0.0)]
+    eps = [2 * h, 2 * h, 1.5 * h, 2 * h]
+    U = np.stack([inputs.uniform_noise(n, 4100 + b) for b in range(B)])
+    for dtype in (torch.float64, torch.float32):
+        log(f"case mixed symmetry {dtype}")
+        check_energy_grad(U, h, eps, coeffs, dtype)
+        ctx = fe.FeContext(U.shape, h, eps, coeffs, dtype=dtype)
+        ud = to_dev(U, dtype)
+        E, g = ctx.energy_grad(ud)
+        for b in range(B):
+            c1 = fe.FeContext((1, n, n, n), h, eps[b], coeffs[b], dtype=dtype)
+            c1.set_launch(*ctx.get_launch())
+            Eb, gb = c1.energy_grad(ud[b:b + 1].contiguous())
+            assert Eb[0].item() == E[b].item() and torch.equal(gb[0], g[b]), (dtype, b)
+
+
 def test_repeated_calls_are_bitwise_deterministic():
     n = 40
     u = to_dev(inputs.uniform_noise(n, 7), torch.float32)
