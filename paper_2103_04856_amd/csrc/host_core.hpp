@@ -79,12 +79,16 @@ const std::vector<Variant>& variants() {
       Variant x{tx, ty, nt, 2, {}, k, {}, ksp, nullptr, kbox};
       r.push_back(x);
     };
-    // the coefficient-field kernels exist for one large, one small and the
-    // smallest tile of each precision
+    // the coefficient-field and box kernels exist for one large, one small and
+    // the smallest tile of each precision. 32 x 32 leads the FP32 list: it
+    // recomputes a ring of 1.13 (64 x 16: 1.16) while two blocks still share a
+    // CU (64 x 32 holds a CU alone). 256^3 step, symmetric p: 94 us against
+    // 109 (64 x 16) and 97 (64 x 32 / 1024); batched 16 x 128^3 Adam: 283
+    // against 303 and 290 us.
+    add32(32, 32, 512, make_kernels<float, 32, 32, 512>());
     add32(64, 16, 512, make_kernels<float, 64, 16, 512>(), make_kernels<float, 64, 16, 512, true>(),
           fe::grad_sweep<float, 64, 16, 512, fe::kGrad, false, true>);
     add32(64, 32, 1024, make_kernels<float, 64, 32, 1024>());
-    add32(32, 32, 512, make_kernels<float, 32, 32, 512>());
     add32(64, 32, 768, make_kernels<float, 64, 32, 768>());
     add32(64, 16, 1024, make_kernels<float, 64, 16, 1024>());
     add32(64, 8, 512, make_kernels<float, 64, 8, 512>());
