@@ -47,6 +47,26 @@ def test_energy_and_gradient_match_oracle(dtype, sigma_k):
     assert rel_l2(g.cpu().double().numpy(), go) <= tol["grad"]
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_symmetric_p_energy_and_gradient_match_oracle(dtype):
+    """p = H^2 (symmetric in k1, k2: the box sweep takes the body without the S terms) on
+    the ragged noisy-ball box of the test above, sigma_k = 1."""
+    shape = (20, 24, 28)
+    h = 1.0 / 28
+    eps = 2.5 * h
+    rng = np.random.default_rng(6)
+    u0 = np.tanh((0.3 - np.sqrt(sum((c - 0.4) ** 2 for c in np.meshgrid(
+        *[(np.arange(k) + 0.5) * h for k in shape], indexing="ij")))) / (math.sqrt(2) * eps))
+    u0 = u0 + 0.05 * rng.standard_normal(shape)
+    ud = to_dev(u0, dtype)
+    flow = fe.FeL2Flow(shape, h, eps, WILLMORE, sigma_k=1.0, dtype=dtype)
+    E, g = flow.energy_grad(ud)
+    Eo, go = l2flow.energy_grad_replicate(oracle_input(ud), h, eps, WILLMORE, 1.0)
+    tol = TOL[dtype]
+    assert abs(E - Eo) <= tol["energy"] * abs(Eo), (E, Eo)
+    assert rel_l2(g.cpu().double().numpy(), go) <= tol["grad"]
+
+
 @pytest.mark.parametrize("shape,sigma_k", [((1, 9, 13), 0.0), ((7, 1, 5), 1.0), ((6, 5, 2), 1.0),
                                            ((2, 3, 2), 2.0), ((9, 6, 1), 2.0)])
 def test_thin_boxes_match_oracle(shape, sigma_k):
