@@ -51,6 +51,7 @@ struct Variant {
   Kernels<double> k64sp;
   SweepFn<float> k32box = nullptr;    // gradient with a box mask (padded, non-periodic fields)
   SweepFn<double> k64box = nullptr;
+  bool lead = false;   // a default candidate: chosen by the ring work its tiles cover a grid with
 };
 
 template <typename T, int TX, int TY, int NT, bool SP = false>
@@ -79,13 +80,20 @@ const std::vector<Variant>& variants() {
       Variant x{tx, ty, nt, 2, {}, k, {}, ksp, nullptr, kbox};
       r.push_back(x);
     };
-    // the coefficient-field and box kernels exist for one large, one small and
-    // the smallest tile of each precision. 32 x 32 leads the FP32 list: it
-    // recomputes a ring of 1.13 (64 x 16: 1.16) while two blocks still share a
-    // CU (64 x 32 holds a CU alone). 256^3 step, symmetric p: 94 us against
-    // 109 (64 x 16) and 97 (64 x 32 / 1024); batched 16 x 128^3 Adam: 283
-    // against 303 and 290 us.
+    // the coefficient-field and box kernels exist for a few large tiles, one
+    // small and the smallest tile of each precision (not for 50 x 20 with a
+    // coefficient field: 134 VGPRs, one block per CU). 32 x 32 and 50 x 20 lead
+    // the FP32 list: the same block (512 threads, three u loads and three ring
+    // voxels per thread, 48 KiB of LDS, two blocks per CU) over a tile whose
+    // ring is 1.13 or 1.14 of it. 32 x 32 covers power-of-two planes exactly,
+    // 50 x 20 planes of 100, 200 or 600 (where 32 x 32 computes 1.85x the
+    // plane at 100^2). 256^3 step, symmetric p: 94 us against 95 (64 x 16)
+    // and 97 (64 x 32 / 1024).
     add32(32, 32, 512, make_kernels<float, 32, 32, 512>());
+    r.back().lead = true;
+    add32(50, 20, 512, make_kernels<float, 50, 20, 512>(), {},
+          fe::grad_sweep<float, 50, 20, 512, fe::kGrad, false, true>);
+    r.back().lead = true;
     add32(64, 16, 512, make_kernels<float, 64, 16, 512>(), make_kernels<float, 64, 16, 512, true>(),
           fe::grad_sweep<float, 64, 16, 512, fe::kGrad, false, true>);
     add32(64, 32, 1024, make_kernels<float, 64, 32, 1024>());
@@ -101,6 +109,7 @@ const std::vector<Variant>& variants() {
           fe::grad_sweep<float, 8, 8, 64, fe::kGrad, false, true>);
     add64(32, 16, 512, make_kernels<double, 32, 16, 512>(), make_kernels<double, 32, 16, 512, true>(),
           fe::grad_sweep<double, 32, 16, 512, fe::kGrad, false, true>);
+    r.back().lead = true;
     add64(32, 8, 256, make_kernels<double, 32, 8, 256>());
     add64(16, 16, 256, make_kernels<double, 16, 16, 256>());
     add64(16, 8, 128, make_kernels<double, 16, 8, 128>(), make_kernels<double, 16, 8, 128, true>(),
@@ -126,6 +135,14 @@ template <>
 SweepFn<double> box_kernel_of<double>(const Variant& v) { return v.k64box; }
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Ring voxels one plane of the sweep evaluates when v's tiles cover an nx x ny
+// plane, ragged tiles included (their wrapped columns are evaluated too).
+double ring_work(const Variant& v, int nx, int ny) {
+  return (double)ceil_div(nx, v.tx) * ceil_div(ny, v.ty) * (v.tx + 2) * (v.ty + 2);
+}
+
+bool tile_fits(const Variant& v, int nx, int ny) { return v.tx <= std::max(nx, 8) && v.ty <= std::max(ny, 8); }
 
 }  // namespace
 
@@ -305,6 +322,20 @@ int block_slots(const fe_ctx* c, int variant) {
   return n;
 }
 
+// Time of a sweep whose busiest compute unit runs k = ceil(blocks / num_cu)
+// blocks of L planes, `slots` at a time, in units of one plane of a block in a
+// full CU: a full group of `slots` blocks costs 1 per plane, a CU left with
+// r < slots blocks (r / slots)^0.6 per plane (0.66 for one of two: alone it
+// hides less latency, yet finishes sooner). Fitted to the step sweep on 100^3
+// to 256^3 grids, one and 16 instances, two blocks per CU.
+double sweep_cost(long blocks, int num_cu, int slots, int L) {
+  const long k = (blocks + num_cu - 1) / num_cu;
+  const long rest = k % slots;
+  double t = (double)(k / slots) * L;
+  if (rest) t += L * std::pow((double)rest / slots, 0.6);
+  return t;
+}
+
 Geometry geometry(const fe_ctx* c, int variant, int lz_req) {
   const Variant& v = variants()[variant];
   Geometry g;
@@ -312,23 +343,23 @@ Geometry geometry(const fe_ctx* c, int variant, int lz_req) {
   g.nty = ceil_div(c->grid.ny, v.ty);
   int lz = lz_req;
   if (lz <= 0) {
+    // the equal z chunks whose sweep sweep_cost finishes first: longer chunks
+    // recompute fewer boundary planes, more of them fill more compute units,
+    // and a last round of blocks that fills only some CUs costs most of a
+    // round (256^3 in 32 x 32 tiles: 32 planes, 512 blocks; 200^3 in 50 x 20
+    // tiles: 17 planes, 480 blocks, 73 us against 102 us for 16 planes)
     const int nz = c->grid.nz;
-    const double cols = (double)g.ntx * g.nty * c->grid.batch;
-    const double slots = (double)c->num_cu * block_slots(c, variant);
-    if (cols * ceil_div(nz, 4) < slots) {
-      // too few columns to fill the resident block slots even with short
-      // chunks: one block per compute unit, with the chunks that gives (one
-      // block alone on a CU is slower per plane than two sharing it, but the
-      // extra boundary planes of chunks short enough for two cost more)
-      const int nzc = std::max(1, (int)(c->num_cu / cols));
-      lz = std::max(2, ceil_div(nz, nzc));
-    } else {
-      // the longest power-of-two chunk (fewest recomputed boundary planes)
-      // that still fills every resident block slot, at least 4 planes; then
-      // the same number of chunks made equal, so no chunk runs short
-      lz = 4;
-      while (2 * lz <= nz && cols * ceil_div(nz, 2 * lz) >= slots) lz *= 2;
-      lz = ceil_div(nz, ceil_div(nz, lz));
+    const long cols = (long)g.ntx * g.nty * c->grid.batch;
+    const int slots = block_slots(c, variant);
+    double best = 0.0;
+    for (int nzc = 1; nzc <= nz; ++nzc) {
+      const int l = ceil_div(nz, nzc);
+      if (nzc > 1 && l == ceil_div(nz, nzc - 1)) continue;   // the same chunks as nzc - 1
+      const double t = sweep_cost(cols * ceil_div(nz, l), c->num_cu, slots, l + 2);
+      if (lz <= 0 || t < best) {
+        best = t;
+        lz = l;
+      }
     }
   }
   lz = std::min(std::max(lz, 1), c->grid.nz);
@@ -348,34 +379,48 @@ bool has_box(int v, int dtype) {
   return dtype == FE_F32 ? x.k32box != nullptr : x.k64box != nullptr;
 }
 
-// The variant a sweep launches: the chosen one, unless a coefficient field is
-// in use and that variant has no coefficient-field kernels; then the first
-// one that has them and whose tile the grid fills.
+// The variant a sweep launches: the chosen one, unless a coefficient field or
+// a box mask is in use and that variant has no such kernels; then, of those
+// that have them and whose tile the grid fills, the one with the chosen
+// block size that evaluates the least ring (else the first).
 int sweep_variant(const fe_ctx* c) {
   auto ok = [&](int v) {
     return (!c->use_cfield || has_sp(v, c->grid.dtype)) && (!c->use_box || has_box(v, c->grid.dtype));
   };
   if (ok(c->variant)) return c->variant;
-  int last = c->variant;
+  const int nt = variants()[c->variant].nt;
+  int first = -1, best = -1, last = c->variant;
   for (int v = 0; v < (int)variants().size(); ++v) {
     if (!variant_ok(v, c->grid.dtype) || !ok(v)) continue;
-    const Variant& x = variants()[v];
-    if (x.tx <= std::max(c->grid.nx, 8) && x.ty <= std::max(c->grid.ny, 8)) return v;
     last = v;
+    const Variant& x = variants()[v];
+    if (!tile_fits(x, c->grid.nx, c->grid.ny)) continue;
+    if (first < 0) first = v;
+    if (x.nt == nt &&
+        (best < 0 || ring_work(x, c->grid.nx, c->grid.ny) < ring_work(variants()[best], c->grid.nx, c->grid.ny)))
+      best = v;
   }
-  return last;
+  return best >= 0 ? best : first >= 0 ? first : last;
 }
 
 int fields_in_use(const fe_ctx* c) { return (c->use_cfield ? 1 : 0) | (c->use_mfield ? 2 : 0); }
 
 int default_variant(const fe_grid& g) {
   const int dt = g.dtype;
-  // variants are listed best-first for large grids: take the first whose tile
-  // the grid fills
+  // of the leading variants whose tile the grid fills, the one that evaluates
+  // the least ring per plane (ties: the earlier)
+  int best = -1;
+  for (int v = 0; v < (int)variants().size(); ++v) {
+    const Variant& x = variants()[v];
+    if (!variant_ok(v, dt) || !x.lead || !tile_fits(x, g.nx, g.ny)) continue;
+    if (best < 0 || ring_work(x, g.nx, g.ny) < ring_work(variants()[best], g.nx, g.ny)) best = v;
+  }
+  if (best >= 0) return best;
+  // else, variants being listed largest tile first, the first whose tile the
+  // grid fills
   for (int v = 0; v < (int)variants().size(); ++v) {
     if (!variant_ok(v, dt)) continue;
-    const Variant& x = variants()[v];
-    if (x.tx <= std::max(g.nx, 8) && x.ty <= std::max(g.ny, 8)) return v;
+    if (tile_fits(variants()[v], g.nx, g.ny)) return v;
   }
   for (int v = (int)variants().size() - 1; v >= 0; --v)
     if (variant_ok(v, dt)) return v;

@@ -75,6 +75,68 @@ def test_ragged_grids_every_variant(dtype):
                 check_energy_grad(u, 0.1, 0.2, ALL_TERMS, dtype, variant=vi, z_chunk=zc)
 
 
+def _variant_index(tx, ty, nt, mask):
+    for vi, v in enumerate(fe.variants()):
+        if v[:3] == (tx, ty, nt) and v[3] & mask:
+            return vi
+    raise AssertionError(f"no variant {tx}x{ty}/{nt}")
+
+
+def test_default_tile_follows_the_grid():
+    """The default launch takes the leading tile whose cover of the plane evaluates the least
+    ring: 50 x 20 on planes of 100 and 200, 32 x 32 on power-of-two planes (FP32)."""
+    v3232 = _variant_index(32, 32, 512, 1)
+    v5020 = _variant_index(50, 20, 512, 1)
+    v3216 = _variant_index(32, 16, 512, 2)
+    cases = [((1, 100, 100, 100), torch.float32, v5020), ((16, 100, 100, 100), torch.float32, v5020),
+             ((1, 200, 200, 200), torch.float32, v5020), ((1, 100, 100, 600), torch.float32, v5020),
+             ((1, 256, 256, 256), torch.float32, v3232), ((16, 128, 128, 128), torch.float32, v3232),
+             ((1, 64, 64, 64), torch.float32, v3232), ((1, 100, 100, 100), torch.float64, v3216)]
+    for shape, dtype, want in cases:
+        ctx = fe.FeContext(shape, 0.01, 0.02, HELFRICH_SC, dtype=dtype)
+        got = ctx.get_launch()[0]
+        log(f"  {shape} {dtype}: default {fe.variants()[got][:3]}")
+        assert got == want, (shape, dtype, fe.variants()[got][:3])
+        ctx.close()
+
+
+def test_tile_50x20_spans_several_tiles():
+    """FP32 on a 120 x 47 x 9 grid in the 50 x 20 tile: three x tiles (the last 20 wide) and
+    three y tiles (the last 7 high). Energy and gradient against the oracle with both bodies
+    (every term; a p symmetric in k1, k2), z chunks of every length and of 4; one gradient step
+    against the oracle; an Adam step equal to the 32 x 32 tile's."""
+    vi = _variant_index(50, 20, 512, 1)
+    nz, ny, nx = 9, 47, 120
+    h = 1.0 / nx
+    u0 = np.random.default_rng(5020).uniform(-1, 1, size=(nz, ny, nx))
+    for a in (ALL_TERMS, HELFRICH_SC):
+        for zc in (0, 4):
+            log(f"case tile50x20 a={a} zc={zc}")
+            e, g = check_energy_grad(u0, h, 2 * h, a, torch.float32, variant=vi, z_chunk=zc)
+            log(f"  energy rel {e[0]:.2e}  grad rel L2 {g[0]:.2e}")
+    ctx = fe.FeContext((1, nz, ny, nx), h, 2 * h, HELFRICH_SC, dtype=torch.float32)
+    ctx.set_launch(vi, 0)
+    ud = to_dev(u0[None], torch.float32)
+    uo = oracle_input(ud)[0]
+    m = float(uo.mean())
+    ctx.step(ud, [m], 1e-3, 1)
+    uo1, _ = fo.descend(uo, h, 2 * h, HELFRICH_SC, m, 1e-3, 1)
+    err = rel_l2(ud[0].cpu().double().numpy() - uo, uo1 - uo)
+    log(f"  one step: update rel {err:.2e}")
+    assert err <= 1e-3
+    res = []
+    for v in (vi, _variant_index(32, 32, 512, 1)):
+        c2 = fe.FeContext((1, nz, ny, nx), h, 2 * h, ALL_TERMS, dtype=torch.float32)
+        c2.set_launch(v, 0)
+        u2 = to_dev(u0[None], torch.float32)
+        c2.step_adam(u2, [m], 2)
+        res.append(u2.cpu().double().numpy() - u0[None])
+        c2.close()
+    d = rel_l2(res[0], res[1])
+    log(f"  two Adam steps, 50x20 against 32x32: update rel {d:.2e}")
+    assert d <= 1e-5
+
+
 def test_batched_instances_with_own_parameters():
     """B = 6 instances of 24^3 with different eps, coefficients and fields in one launch."""
     n, B = 24, 6
