@@ -124,14 +124,18 @@ __device__ __forceinline__ T taps_dot(const BlurTaps<T>& k, const T* v, int step
 // space-dependent mass of Sec. 5.2) and block (0,0,0) advances the clock (when
 // given); without, it is in[]. r = 0 is a plain copy (or div). All loads of a thread are issued
 // before the first LDS write, so a block keeps many in flight.
+// ROWS: rows with nx + 2r <= 128 are staged whole (x0 = 0, one x tile, grid
+// (1, ceil(ny/kBlurRows), nz * batch)): a row of 100 then stages 116 samples
+// instead of two 64-wide tiles' 2 x (64 + 2r), and 100 of 128 lanes form outputs.
 constexpr int kBlurRows = 16;
+constexpr int kRowsMax = 128;   // ROWS: the longest staged row, nx + 2r
 
-template <typename T, bool DIV, int R = -1>
+template <typename T, bool DIV, int R = -1, bool ROWS = false>
 __global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __restrict__ out,
                                               const double* __restrict__ m0, const T* __restrict__ mfield,
                                               FieldDims d, T inv2h, BlurTaps<T> k, FlowClock* __restrict__ clk,
                                               double beta1, double beta2) {
-  constexpr int kW = 64 + 2 * kBlurMaxR;
+  constexpr int kW = ROWS ? kRowsMax : 64 + 2 * kBlurMaxR;
   constexpr int kPer = (kW + 63) / 64;          // segment elements per thread and row
   constexpr int kR = kBlurRows / 4;             // rows per thread
   __shared__ T s[kBlurRows][kW];
@@ -144,11 +148,11 @@ __global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __res
   }
   const Tile3 t = xcd_tile();
   const int z = t.z % d.nz, b = t.z / d.nz;
-  const int x0 = t.x * 64;
+  const int x0 = ROWS ? 0 : t.x * 64;
   const size_t plane = (size_t)d.nx * d.ny, vol = plane * d.nz;
   const T* base = in + (size_t)b * (DIV ? 3 : 1) * vol;
   const int r = R >= 0 ? R : k.r;
-  const int nseg = 64 + 2 * r;
+  const int nseg = (ROWS ? d.nx : 64) + 2 * r;
   // A wave's rows are uniform (threadIdx.y is the wave), so the row pointers
   // live in scalar registers and every load takes a 32-bit lane offset: the
   // segment's x positions and their periodic x neighbours, formed once.
@@ -208,14 +212,18 @@ __global__ __launch_bounds__(256) void blur_x(const T* __restrict__ in, T* __res
     }
   }
   __syncthreads();
-  const int x = x0 + threadIdx.x;
-  if (x >= d.nx) return;
 #pragma unroll
-  for (int i = 0; i < kR; ++i) {
-    const int y = t.y * kBlurRows + wy + 4 * i;
-    if (y >= d.ny) continue;
-    T* orow = out + (size_t)b * vol + (size_t)z * plane + (size_t)y * d.nx;
-    orow[x] = taps_dot<T, R>(k, &s[wy + 4 * i][threadIdx.x], 1);
+  for (int jo = 0; jo < (ROWS ? kPer : 1); ++jo) {
+    const int xo = threadIdx.x + 64 * jo;       // output position in the tile
+    const int x = x0 + xo;
+    if (x >= d.nx) break;
+#pragma unroll
+    for (int i = 0; i < kR; ++i) {
+      const int y = t.y * kBlurRows + wy + 4 * i;
+      if (y >= d.ny) continue;
+      T* orow = out + (size_t)b * vol + (size_t)z * plane + (size_t)y * d.nx;
+      orow[x] = taps_dot<T, R>(k, &s[wy + 4 * i][xo], 1);
+    }
   }
 }
 
@@ -284,24 +292,31 @@ __global__ __launch_bounds__(256) void blur_axis(const T* __restrict__ in, T* __
 // result equals blur_x followed by blur_axis<1> (each output is formed by the
 // same sums in the same order). Block (64, 8); grid (ceil(nx/64),
 // ceil(ny/kXYRows), nz * batch).
+// ROWS: rows with nx + 2R <= 128 are staged whole with their periodic halo
+// (grid (1, ceil(ny/kXYRows), nz * batch)); the x pass then deals out quads
+// 32 to a row, the y pass two columns per thread (x and x + 64). A row of 100
+// stages 116 samples instead of 2 x (64 + 2R) and takes 25 quads per row
+// where two 64-wide tiles take 32.
 constexpr int kXYRows = 32;
 
-template <typename T, int R>
+template <typename T, int R, bool ROWS = false>
 __global__ __launch_bounds__(512) void blur_xy(const T* __restrict__ in, T* __restrict__ out, FieldDims d,
                                                BlurTaps<T> k) {
   static_assert(R > 0 && 2 * R <= 64 && R % 2 == 0, "blur_xy needs a fixed even radius");
   constexpr int NT = 512;
-  constexpr int W = 64 + 2 * R, H = kXYRows + 2 * R;
   constexpr int OUT = 4;                        // outputs per thread and pass
+  // staged row width; ROWS: up to 128 staged, plus the 3 a ragged last quad reads past them
+  constexpr int W = ROWS ? kRowsMax + OUT : 64 + 2 * R, H = kXYRows + 2 * R;
+  constexpr int WM = ROWS ? kRowsMax : 64;      // x-blurred row width
   static_assert(kXYRows == OUT * (NT / 64), "one y window per thread");
   __shared__ T s_in[H][W];
-  __shared__ T s_mid[H][64];
+  __shared__ T s_mid[H][WM];
   const int tid = threadIdx.y * 64 + threadIdx.x;
   // Tiles in the hardware's order: this pass is bound by its LDS and VALU
   // work, not by its halo fetches (those hit MALL), and xcd_tile's placement
   // measured slower for it (16 x 100^3: 656 against 648 us per iteration).
   const int z = blockIdx.z % d.nz, b = blockIdx.z / d.nz;
-  const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kXYRows;
+  const int x0 = ROWS ? 0 : blockIdx.x * 64, y0 = blockIdx.y * kXYRows;
   const size_t plane = (size_t)d.nx * d.ny, vol = plane * d.nz;
   const T* src = in + (size_t)b * vol + (size_t)z * plane;
   // Stage the tile with its halo: wave w takes the rows w, w + 8, ... (their y
@@ -312,6 +327,7 @@ __global__ __launch_bounds__(512) void blur_xy(const T* __restrict__ in, T* __re
   const int wy = __builtin_amdgcn_readfirstlane(threadIdx.y);
   const int lane = threadIdx.x;
   const int xc0 = wrap_any(x0 - R + lane, d.nx), xc1 = wrap_any(x0 - R + 64 + lane, d.nx);
+  const bool second = ROWS ? 64 + lane < d.nx + 2 * R : lane < 2 * R;
   T v[RPW][2];
 #pragma unroll
   for (int i = 0; i < RPW; ++i) {
@@ -319,21 +335,24 @@ __global__ __launch_bounds__(512) void blur_xy(const T* __restrict__ in, T* __re
     if (rr >= H) continue;
     const T* row = src + (size_t)wrap_any(y0 - R + rr, d.ny) * d.nx;
     v[i][0] = row[xc0];
-    if (lane < 2 * R) v[i][1] = row[xc1];
+    if (second) v[i][1] = row[xc1];
   }
 #pragma unroll
   for (int i = 0; i < RPW; ++i) {
     const int rr = wy + (NT / 64) * i;
     if (rr >= H) continue;
     s_in[rr][lane] = v[i][0];
-    if (lane < 2 * R) s_in[rr][64 + lane] = v[i][1];
+    if (second) s_in[rr][64 + lane] = v[i][1];
   }
   __syncthreads();
-  // x blur of every staged row: thread -> (row, quad of four x-values)
+  // x blur of every staged row: thread -> (row, quad of four x-values); QPR
+  // quads per row (ROWS: the row's ceil(nx/4) of 32 slots)
+  constexpr int QPR = ROWS ? 32 : 16;
+  const int nquad = ROWS ? (d.nx + OUT - 1) / OUT : 16;
 #pragma unroll
-  for (int p = 0; p < (H * 16 + NT - 1) / NT; ++p) {
-    const int q = tid % 16, rr = tid / 16 + p * (NT / 16);
-    if (rr < H) {
+  for (int p = 0; p < (H * QPR + NT - 1) / NT; ++p) {
+    const int q = tid % QPR, rr = tid / QPR + p * (NT / QPR);
+    if (rr < H && q < nquad) {
       T w[OUT + 2 * R];
 #pragma unroll
       for (int i = 0; i < OUT + 2 * R; ++i) w[i] = s_in[rr][4 * q + i];
@@ -347,20 +366,24 @@ __global__ __launch_bounds__(512) void blur_xy(const T* __restrict__ in, T* __re
     }
   }
   __syncthreads();
-  // y blur from a register window of this thread's column
-  const int x = x0 + threadIdx.x;
-  if (x >= d.nx) return;
-  T col[OUT + 2 * R];
+  // y blur from a register window of this thread's column (ROWS: x and x + 64)
 #pragma unroll
-  for (int i = 0; i < OUT + 2 * R; ++i) col[i] = s_mid[threadIdx.y * OUT + i][threadIdx.x];
+  for (int jx = 0; jx < (ROWS ? 2 : 1); ++jx) {
+    const int xo = threadIdx.x + 64 * jx;
+    const int x = x0 + xo;
+    if (x >= d.nx) break;
+    T col[OUT + 2 * R];
 #pragma unroll
-  for (int o = 0; o < OUT; ++o) {
-    const int y = y0 + threadIdx.y * OUT + o;
-    if (y >= d.ny) break;
-    T acc = T(0);
+    for (int i = 0; i < OUT + 2 * R; ++i) col[i] = s_mid[threadIdx.y * OUT + i][xo];
 #pragma unroll
-    for (int j = 0; j <= 2 * R; ++j) acc += k.w[j] * col[o + j];
-    out[(size_t)b * vol + (size_t)z * plane + (size_t)y * d.nx + x] = acc;
+    for (int o = 0; o < OUT; ++o) {
+      const int y = y0 + threadIdx.y * OUT + o;
+      if (y >= d.ny) break;
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j <= 2 * R; ++j) acc += k.w[j] * col[o + j];
+      out[(size_t)b * vol + (size_t)z * plane + (size_t)y * d.nx + x] = acc;
+    }
   }
 }
 

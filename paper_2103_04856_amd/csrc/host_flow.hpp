@@ -37,13 +37,24 @@ bool flow_dims_ok(const fe_grid& g) {
 // flat runs of 256 voxels of a plane, one plane per grid z
 dim3 plane_grid(const fe::FieldDims& d) { return dim3(ceil_div(d.nx * d.ny, 256), 1, d.nz * d.batch); }
 
+// Whole rows staged per block (the ROWS forms) when a row and its halo fit
+// the 128 staged values.
+bool rows_fit(const fe::FieldDims& d, int r) { return d.nx + 2 * r <= fe::kRowsMax; }
+
 // The x pass (with the divergence when DIV), dispatched to the fixed-radius
-// instantiation when there is one.
+// instantiation when there is one, and to its ROWS form when the rows fit.
 template <typename T, bool DIV>
 void blur_x_pass(hipStream_t s, const fe::FieldDims& d, const fe::BlurTaps<T>& k, const T* in, T* out,
                  const double* m0, const T* mfield, T inv2h, fe::FlowClock* clk, double beta1, double beta2) {
   const dim3 g = x_grid(d), b(64, 4);
-  if (k.r == 4)
+  const dim3 gr(1, g.y, g.z);
+  if (k.r == 4 && rows_fit(d, 4))
+    hipLaunchKernelGGL((fe::blur_x<T, DIV, 4, true>), gr, b, 0, s, in, out, m0, mfield, d, inv2h, k, clk, beta1,
+                       beta2);
+  else if (k.r == 8 && rows_fit(d, 8))
+    hipLaunchKernelGGL((fe::blur_x<T, DIV, 8, true>), gr, b, 0, s, in, out, m0, mfield, d, inv2h, k, clk, beta1,
+                       beta2);
+  else if (k.r == 4)
     hipLaunchKernelGGL((fe::blur_x<T, DIV, 4>), g, b, 0, s, in, out, m0, mfield, d, inv2h, k, clk, beta1, beta2);
   else if (k.r == 8)
     hipLaunchKernelGGL((fe::blur_x<T, DIV, 8>), g, b, 0, s, in, out, m0, mfield, d, inv2h, k, clk, beta1, beta2);
@@ -58,8 +69,13 @@ dim3 xy_grid(const fe::FieldDims& d) { return dim3(ceil_div(d.nx, 64), ceil_div(
 template <typename T>
 void blur_xy_pass(hipStream_t s, const fe::FieldDims& d, const fe::BlurTaps<T>& k, const T* in, T* out) {
   const dim3 g = xy_grid(d), b(64, 8);
-  if (k.r == 4)
+  const dim3 gr(1, g.y, g.z);
+  if (k.r == 4 && rows_fit(d, 4))
+    hipLaunchKernelGGL((fe::blur_xy<T, 4, true>), gr, b, 0, s, in, out, d, k);
+  else if (k.r == 4)
     hipLaunchKernelGGL((fe::blur_xy<T, 4>), g, b, 0, s, in, out, d, k);
+  else if (rows_fit(d, 8))
+    hipLaunchKernelGGL((fe::blur_xy<T, 8, true>), gr, b, 0, s, in, out, d, k);
   else
     hipLaunchKernelGGL((fe::blur_xy<T, 8>), g, b, 0, s, in, out, d, k);
 }

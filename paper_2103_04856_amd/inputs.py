@@ -87,9 +87,11 @@ def random_instance_table(batch, seed):
 
 def white_noise_vector_field(n, seed, std, batch=None):
     """A0 ~ N(0, std^2) i.i.d. per voxel and component: the random initial vector field
-    of Algorithm 1. Shape [3, n, n, n] (components x, y, z) or [batch, 3, n, n, n]."""
+    of Algorithm 1. Shape [3, n, n, n] (components x, y, z) or [batch, 3, n, n, n]; n may
+    also be a grid shape (nz, ny, nx)."""
     rng = np.random.default_rng(seed)
-    shape = (3, n, n, n) if batch is None else (batch, 3, n, n, n)
+    grid = (n, n, n) if np.isscalar(n) else tuple(n)
+    shape = (3,) + grid if batch is None else (batch, 3) + grid
     return rng.normal(0.0, std, size=shape)
 
 

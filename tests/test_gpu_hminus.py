@@ -184,6 +184,30 @@ def test_rejects_bad_arguments():
     assert torch.count_nonzero(A).item() == 0
 
 
+@pytest.mark.parametrize("sigma_k", [1.0, 2.0])
+@pytest.mark.parametrize("shape", [(7, 19, 100), (5, 33, 130), (6, 11, 37)])
+def test_row_and_tile_blur_forms_match_oracle_fp64(sigma_k, shape):
+    """Non-cubic grids through both forms of the fixed-radius x and xy blurs (r = 4, 8):
+    rows of 100 and 37 staged whole with their periodic halo (one x tile per row, a
+    ragged last quad) and rows of 130 in 64-wide tiles (the last one ragged); ny no
+    multiple of the 16- or 32-row blocks. One iteration against the oracle."""
+    nz, ny, nx = shape
+    h = 1.0 / nx
+    ctx = fe.FeContext((1,) + shape, h, 2 * h, ASYM_C3, dtype=torch.float64)
+    Ad = to_dev(inputs.white_noise_vector_field(shape, 17, 0.4 * h)[None], torch.float64)
+    ud = torch.empty((1,) + shape, dtype=torch.float64, device="cuda")
+    Ao = oracle_input(Ad)[0]
+    m1 = np.zeros_like(Ao)
+    m2 = np.zeros_like(Ao)
+    log(f"case rows/tiles shape={shape} sigma_k={sigma_k}")
+    Eg = ctx.hminus_step(Ad, [-0.1], 1, sigma_k=sigma_k, u_out=ud)
+    Ao, m1, m2, Eo, _ = fo.hminus_adam_step(Ao, m1, m2, 1, h, 2 * h, ASYM_C3, -0.1, sigma_k)
+    assert abs(Eg[0].item() - Eo) <= 1e-10 * abs(Eo)
+    assert rel_l2(Ad.cpu().numpy()[0], Ao) <= 1e-11
+    uo = fo.gaussian_blur(fo.fd_divergence(Ao, h) - 0.1, sigma_k)
+    assert rel_l2(ud.cpu().numpy()[0], uo) <= 1e-11
+
+
 @pytest.mark.parametrize("sigma_k,n", [(4.0, 12), (0.25, 10), (3.0, 20), (1.5, 9)])
 def test_blur_radii_and_small_grids_match_oracle_fp64(sigma_k, n):
     """Blur widths off the fixed-radius kernels (r = 1, 6, 12) and the widest one (r = 16)
