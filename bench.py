@@ -382,7 +382,7 @@ def main():
                     help="also run one plain 64 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
     if not torch.cuda.is_available():
@@ -434,7 +434,7 @@ def main():
            "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": traffic}
     roof, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
     roof = dict(roof, kernel=kname, duration_us=step_us, ops_per_voxel=ops_voxel)
-    # the published FP32 vector peak counts packed two-wide FMAs; this build
+    # the published FP32 vector peak counts packed two-wide FMAs; the library
     # compiles with packed FP32 disabled, so its attainable ALU ceiling is half
     roof["unpacked_fp32_peak"] = FP32_VECTOR_PEAK_TFLOPS / 2
     roof["frac_of_unpacked_peak"] = tflops / (FP32_VECTOR_PEAK_TFLOPS / 2)

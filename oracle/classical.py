@@ -131,7 +131,7 @@ def curvature_histogram(u, h, eps, nbins, kmax, xi=XI):
 
 
 def diagnostic_stats(u, h, eps, a, xi=XI):
-    """Per-field summary used to judge a generated texture (Sec. 4.5, Experiment 4):
+    """Per-field summary used to assess a generated texture (Sec. 4.5, Experiment 4):
     (F_h, A_eps, normalised discrepancy, min u, max u). The paper deems a shape
     viable when the discrepancy is under 0.75, max u > 0.1 and min u < -0.1."""
     from .fe_oracle import energy
