@@ -120,14 +120,14 @@ def test_batched_equals_single_instances():
             assert Es[0].item() == Eb[b].item()
 
 
-@pytest.mark.parametrize("n,B", [(64, 16), (97, 7)])
+@pytest.mark.parametrize("n,B", [(64, 16), (97, 7), (100, 16)])
 def test_placement_does_not_change_results(n, B):
     """B instances of n^3 in one context, against each instance alone. Batched, every
     blur and Adam pass has 1024 workgroups or more, so they are renumbered across the
     XCDs (at 7 x 97^3 with a tail of workgroups that keep their numbers); alone, the y
-    and z blurs keep the hardware's order. Placement only moves tiles, so A and u agree
-    bit for bit (the energy's block partials may be summed over other z chunks, so G
-    agrees to rounding)."""
+    and z blurs keep the hardware's order; 16 x 100^3 is the batched flow of the
+    benchmark. Placement only moves tiles, so A and u agree bit for bit (the energy's
+    block partials may be summed over other z chunks, so G agrees to rounding)."""
     h = 1.0 / n
     sets = [ASYM_C3, WILLMORE_QUARTER, (0.5, 0.1, 1.5, -2.0, -3.0, 0.0)]
     eps = [(2.0 + 0.25 * (b % 3)) * h for b in range(B)]
