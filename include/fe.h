@@ -275,7 +275,10 @@ void fe_l2_destroy(fe_l2* flow);
  * fe_variant_info describes one (x and y interior tile, threads per block,
  * element size it supports). fe_set_launch picks a variant and a z-chunk
  * length (planes per block, >= 1; 0 = automatic). FE_EINVAL for a variant
- * that does not support the context's dtype.
+ * that does not support the context's dtype. A new context starts on the
+ * leading variant of its dtype whose tiles evaluate the fewest ring voxels on
+ * its x-y plane. Its automatic z chunks are the equal chunks whose blocks,
+ * dealt out over the compute units, finish first.
  */
 int fe_num_variants(void);
 int fe_variant_info(int variant, int* tile_x, int* tile_y, int* threads, int* dtype_mask);
