@@ -11,12 +11,16 @@ ASYM_C3 = (1.0, 0.0, 0.2, -4.0, -4.0, 0.0)            # 1 k1^2 + 0.2 k2^2 - 4 (k
 HELFRICH_SC = (1.0, 2.5, 1.0, -4.0, -4.0, 4.0)        # (k1 + k2 - 2)^2 + 0.5 k1 k2
 ALL_TERMS = (1.0, 0.3, 2.0, -3.0, 5.0, 0.7)           # every c_k nonzero
 
-# Tolerances against the FP64 oracle. FP32 values are the stated targets;
-# FP64 ones are far tighter than the stated 1e-5 / 1e-4, because only the
-# summation order differs.
+# Tolerances against the FP64 oracle. FP32 energy and gradient L2 values are
+# the stated targets; FP64 ones are far tighter than the stated 1e-5 / 1e-4,
+# because only the summation order differs. `voxel` bounds the worst single
+# voxel: max_i |g_i - g_oracle_i| <= voxel * max_i |g_oracle_i|, so that a few
+# wrong voxels (a tile corner, a ragged tail) cannot hide inside the L2 norm.
+# The FP32 value is the observed worst case on the test workloads with a
+# margin of about 10 (the umbilic voxels, where dS/dX = 1/(2S), dominate it).
 TOL = {
-    torch.float64: dict(energy=1e-10, grad=1e-9),
-    torch.float32: dict(energy=1e-4, grad=1e-3),
+    torch.float64: dict(energy=1e-10, grad=1e-9, voxel=1e-10),
+    torch.float32: dict(energy=1e-4, grad=1e-3, voxel=1e-3),
 }
 
 
@@ -35,6 +39,20 @@ def oracle_input(u_dev):
 
 def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def rel_max(a, b):
+    """max |a - b| / max |b|: the worst single voxel, relative to the field's scale."""
+    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+def check_field(got, ref, tol, what=""):
+    """Whole-field comparison: relative L2 and worst voxel. Returns (l2, worst)."""
+    l2, worst = rel_l2(got, ref), rel_max(got, ref)
+    assert l2 <= tol["grad"], (what, "rel L2", l2)
+    assert worst <= tol["voxel"], (what, "worst voxel", worst,
+                                   np.unravel_index(int(np.argmax(np.abs(got - ref))), np.shape(got)))
+    return l2, worst
 
 
 def check_energy_grad(u, h, eps, a, dtype, variant=None, z_chunk=0, tol=None):
@@ -63,9 +81,10 @@ def check_energy_grad(u, h, eps, a, dtype, variant=None, z_chunk=0, tol=None):
         scale = max(abs(Eo), fo.energy_abs(Un[b], h, eps_l[b], a_l[b]))
         e_errs.append(abs(E[b].item() - Eo) / scale)
         e_only = abs(E_only[b].item() - Eo) / scale
-        g_errs.append(rel_l2(gn[b], go))
         assert e_errs[-1] <= tol["energy"], (b, E[b].item(), Eo, e_errs[-1])
         assert e_only <= tol["energy"], (b, E_only[b].item(), Eo, e_only)
-        assert g_errs[-1] <= tol["grad"], (b, g_errs[-1])
+        l2, worst = check_field(gn[b], go, tol, f"instance {b}")
+        g_errs.append(l2)
+        log(f"    instance {b}: energy rel {e_errs[-1]:.2e} grad rel L2 {l2:.2e} worst voxel {worst:.2e}")
     ctx.close()
     return e_errs, g_errs

@@ -12,7 +12,7 @@ import torch
 from oracle import fe_oracle as fo
 from paper_2103_04856_amd import fe
 
-from gpu_helpers import TOL, log, oracle_input, rel_l2, to_dev
+from gpu_helpers import TOL, log, oracle_input, check_field, rel_l2, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -64,4 +64,4 @@ def test_random_configuration_matches_oracle(seed):
         assert abs(E[b].item() - Eo) <= tol["energy"] * scale, (b, E[b].item(), Eo)
         assert abs(E_only[b].item() - Eo) <= tol["energy"] * scale, (b, E_only[b].item(), Eo)
         if np.linalg.norm(go) > 0:
-            assert rel_l2(g[b].cpu().double().numpy(), go) <= tol["grad"], b
+            check_field(g[b].cpu().double().numpy(), go, tol, b)

@@ -8,7 +8,7 @@ import torch
 from oracle import fe_oracle as fo
 from paper_2103_04856_amd import fe, inputs
 
-from gpu_helpers import ASYM_C3, WILLMORE_QUARTER, log, oracle_input, rel_l2, to_dev
+from gpu_helpers import ALL_TERMS, ASYM_C3, WILLMORE_QUARTER, log, oracle_input, rel_l2, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -221,3 +221,113 @@ def test_autograd_descent_loop_keeps_mass():
         Es.append(E.item())
     assert abs(u.double().mean().item() - m) < 1e-6
     assert Es[-1] < Es[1]
+
+
+def _adam_reference(U0, h, eps, a, m, nsteps, vtol):
+    """The oracle's mass-projected Adam trajectory from U0 and the voxels whose update the
+    FP32 path cannot be expected to reproduce: those where the oracle's gradient at some
+    step is within the FP32 gradient's error of zero (vtol of its largest value), so that
+    its sign, which alone sets Adam's first move, is a rounding decision. A move there
+    changes the gradient up to two voxels away at the next step, so the set grows by two
+    voxels per later step (periodically)."""
+    from scipy.ndimage import maximum_filter
+    u, m1, m2 = U0.copy(), np.zeros_like(U0), np.zeros_like(U0)
+    undecided = np.zeros(U0.shape, dtype=bool)
+    for t in range(1, nsteps + 1):
+        if t > 1:
+            undecided = maximum_filter(undecided, size=5, mode="wrap")
+        _, go = fo.energy_grad(u, h, eps, a)
+        undecided |= np.abs(go) <= vtol * np.abs(go).max()
+        u, m1, m2, _ = fo.adam_projected_step(u, m1, m2, t, h, eps, a, m)
+    return u, undecided
+
+
+def _check_adam_update(d_got, d_ref, undecided, lr, what):
+    """Update against the oracle's: relative L2 over the field, the worst voxel where the
+    result is unique, and a valid move (at most nsteps lr plus the shift) elsewhere."""
+    l2 = rel_l2(d_got, d_ref)
+    scale = np.abs(d_ref).max()
+    dec = ~undecided
+    worst = float(np.abs(d_got - d_ref)[dec].max() / scale)
+    log(f"  {what}: update rel L2 {l2:.2e}, worst decided voxel {worst:.2e}, "
+        f"undecided voxels {int(undecided.sum())} of {undecided.size}")
+    assert l2 <= 1e-3, (what, l2)
+    assert worst <= 1e-3, (what, worst)
+    assert undecided.mean() <= 1e-3, (what, undecided.mean())
+    assert np.abs(d_got).max() <= 1.01 * scale + 10 * lr
+
+
+def test_fp32_adam_steps_match_oracle_128():
+    """The asymmetric 128^3 workload (u0 ~ U(-1,1) seed 1003, eps = 2h, a = (1, 0, 0.2, -4,
+    -4, 0), target mean -0.3): three FP32 mass-projected Adam steps (lr 1e-3) in the default
+    launch against the oracle's FP64 steps, at every voxel."""
+    n = 128
+    h = 1.0 / n
+    ud = to_dev(inputs.uniform_noise(n, 1003), torch.float32)
+    U0 = oracle_input(ud)
+    ctx = fe.FeContext((1, n, n, n), h, 2 * h, ASYM_C3, dtype=torch.float32)
+    ctx.step_adam(ud, [-0.3], 3)
+    uo, undecided = _adam_reference(U0, h, 2 * h, ASYM_C3, -0.3, 3, 1e-3)
+    _check_adam_update(ud.cpu().double().numpy() - U0, uo - U0, undecided, 1e-3, "128^3 3 Adam steps")
+    assert abs(ud.double().mean().item() + 0.3) <= 1e-6
+
+
+def test_fp32_adam_step_matches_oracle_batched_16x128():
+    """One FP32 Adam step of the batched workload (16 x 128^3, per-instance coefficients and
+    means, the launch the batched benchmark times) against the oracle, every instance."""
+    n, B = 128, 16
+    h = 1.0 / n
+    coeffs, means = inputs.random_instance_table(B, 4999)
+    ud = torch.stack([to_dev(inputs.uniform_noise(n, 4000 + b), torch.float32) for b in range(B)])
+    U0 = [oracle_input(ud[b]) for b in range(B)]
+    ctx = fe.FeContext(ud.shape, h, 2 * h, coeffs, dtype=torch.float32)
+    ctx.step_adam(ud, list(means), 1)
+    for b in range(B):
+        uo, undecided = _adam_reference(U0[b], h, 2 * h, coeffs[b], means[b], 1, 1e-3)
+        _check_adam_update(ud[b].cpu().double().numpy() - U0[b], uo - U0[b], undecided, 1e-3, f"instance {b}")
+
+
+@pytest.mark.parametrize("a", [ALL_TERMS, ASYM_C3], ids=["allterms", "asym"])
+def test_autograd_function_against_finite_differences_8cubed(a):
+    """FeEnergy in FP64 on an 8^3 grid (u ~ U(-1,1), eps = 2h): the gradient that backward
+    returns (the adjoint sweep) against central differences of the energy that forward
+    returns (the energy-only sweep), at every voxel with one Richardson step, and along a
+    random direction; and against the oracle's gradient."""
+    n = 8
+    h = 1.0 / n
+    u0 = inputs.uniform_noise(n, 808)
+    ctx = fe.FeContext((1, n, n, n), h, 2 * h, a, dtype=torch.float64)
+    u = to_dev(u0, torch.float64).requires_grad_(True)
+    fe.feps(u, ctx).sum().backward()
+    g = u.grad.detach().cpu().numpy()
+
+    def energy(x):
+        with torch.no_grad():
+            return fe.feps(x, ctx).sum().item()
+
+    base = to_dev(u0, torch.float64)
+    flat = base.view(-1)
+
+    def central(i, d):
+        flat[i] += d
+        ep = energy(base)
+        flat[i] -= 2 * d
+        em = energy(base)
+        flat[i] += d
+        return (ep - em) / (2 * d)
+
+    fd = np.array([(4.0 * central(i, 5e-7) - central(i, 1e-6)) / 3.0 for i in range(n ** 3)]).reshape(g.shape)
+    err = rel_l2(g, fd)
+    v = torch.from_numpy(np.random.default_rng(3).normal(size=u0.shape)).cuda()
+
+    def along(d):
+        return (energy(base + d * v) - energy(base - d * v)) / (2 * d)
+
+    dv = (4.0 * along(5e-7) - along(1e-6)) / 3.0
+    gv = float(np.sum(g * v.cpu().numpy()))
+    _, go = fo.energy_grad(u0, h, 2 * h, a)
+    log(f"  FeEnergy 8^3: FD rel L2 {err:.2e}, direction rel {abs(gv - dv) / abs(dv):.2e}, "
+        f"oracle rel L2 {rel_l2(g, go):.2e}")
+    assert err <= 1e-6
+    assert abs(gv - dv) <= 1e-7 * abs(dv)
+    assert rel_l2(g, go) <= 1e-9

@@ -227,6 +227,39 @@ def test_energy_is_linear_in_coefficients():
     assert abs(lhs - rhs) < 1e-12 * scale
 
 
+def test_energy_abs_sum_of_term_magnitudes():
+    """E_abs = h^3 sum_i sum_k |term_k| (the denominator of relative energy errors where
+    F ~ 0) against what fixes it without its own formula:
+    * where every term of the integrand is >= 0 it equals F: p = (k1 + k2)^2 / 4 (only
+      c2 (Tr M)^2), c5 alone (rho S, a10 = -a01), a00 alone (eps |grad u|^2), and
+      a20 = a02 alone (c1 ||M||^2);
+    * a11 alone gives c1 = -c2 < 0, so E_abs flips the ||M||^2 term: it equals F of
+      (1, 1, 1, 0, 0, 0), which has c1 = c2 > 0;
+    * E_abs >= |F|, strictly where a term changes sign over the grid (Tr M for c4),
+      so no term is dropped and none is summed with its sign;
+    * it is a sum over terms: E_abs(a) = sum_k E_abs(a_k) for a split of a into vectors
+      a_k that each select one term of eq. (Feps), and E_abs(s a) = |s| E_abs(a)."""
+    u = _rand_field(10, 21)
+    h, eps = 1 / 10, 0.2
+    for a in (WILLMORE_QUARTER, (0, 0, 0, 1.0, -1.0, 0), (0, 0, 0, 0, 0, 2.0), (1.0, 0, 1.0, 0, 0, 0)):
+        assert fo.energy_abs(u, h, eps, a) == pytest.approx(fo.energy(u, h, eps, a), rel=1e-13)
+    assert fo.energy_abs(u, h, eps, (0, 1.0, 0, 0, 0, 0)) == pytest.approx(
+        fo.energy(u, h, eps, (1.0, 1.0, 1.0, 0, 0, 0)), rel=1e-13)
+    c4 = (0, 0, 0, 1.0, 1.0, 0)
+    c3 = (1.0, 0, -1.0, 0, 0, 0)
+    for a in (c4, c3):
+        assert fo.energy_abs(u, h, eps, a) > 1.05 * abs(fo.energy(u, h, eps, a))
+    # one vector per term of eq. (Feps): c1 .. c6 (c2 alone needs a20 = a02 = a11 / 2)
+    units = [np.array(v, dtype=np.float64) for v in
+             ((1, 0, 1, 0, 0, 0), (0.5, 1, 0.5, 0, 0, 0), (1, 0, -1, 0, 0, 0), (0, 0, 0, 1, 1, 0),
+              (0, 0, 0, 1, -1, 0), (0, 0, 0, 0, 0, 1))]
+    w = np.array([0.7, -1.3, 2.1, -0.4, 0.9, 3.0])
+    a = sum(wk * uk for wk, uk in zip(w, units))
+    parts = sum(abs(wk) * fo.energy_abs(u, h, eps, uk) for wk, uk in zip(w, units))
+    assert fo.energy_abs(u, h, eps, a) == pytest.approx(parts, rel=1e-12)
+    assert fo.energy_abs(u, h, eps, -2.5 * a) == pytest.approx(2.5 * parts, rel=1e-12)
+
+
 def test_tanh_profile_diffuse_curvatures_are_exact_on_level_sets():
     """Sec. 3.1: on a tanh profile the diffuse curvatures are those of the level sets.
     Ball of radius R: H = 2/|x - c| and K = 1/|x - c|^2 in the interface band, up to
