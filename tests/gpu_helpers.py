@@ -13,14 +13,18 @@ ALL_TERMS = (1.0, 0.3, 2.0, -3.0, 5.0, 0.7)           # every c_k nonzero
 
 # Tolerances against the FP64 oracle. FP32 energy and gradient L2 values are
 # the stated targets; FP64 ones are far tighter than the stated 1e-5 / 1e-4,
-# because only the summation order differs. `voxel` bounds the worst single
-# voxel: max_i |g_i - g_oracle_i| <= voxel * max_i |g_oracle_i|, so that a few
-# wrong voxels (a tile corner, a ragged tail) cannot hide inside the L2 norm.
-# The FP32 value is the observed worst case on the test workloads with a
-# margin of about 10 (the umbilic voxels, where dS/dX = 1/(2S), dominate it).
+# because only the summation order differs. `voxel` bounds every single voxel:
+# |g_i - go_i| <= voxel * (|go_i| + rms(go)), i.e. a relative error where the
+# oracle's value is at least the field's rms and an absolute one (against the
+# rms) where it is smaller, so that a few wrong voxels (a tile corner, a ragged
+# tail) cannot hide inside the L2 norm, nor ordinary voxels behind the few
+# large gradients of umbilic voxels (dS/dX = 1/(2S)) that set the field's max.
+# The voxel bounds are the worst case observed over every test workload (FP64
+# 5e-11, FP32 2.6e-4, at umbilic voxels of the asymmetric batched 128^3
+# instances) with a margin of about 10.
 TOL = {
-    torch.float64: dict(energy=1e-10, grad=1e-9, voxel=1e-10),
-    torch.float32: dict(energy=1e-4, grad=1e-3, voxel=1e-3),
+    torch.float64: dict(energy=1e-10, grad=1e-9, voxel=5e-10),
+    torch.float32: dict(energy=1e-4, grad=1e-3, voxel=2e-3),
 }
 
 
@@ -41,17 +45,31 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def rms(b):
+    return float(np.sqrt(np.mean(np.square(b))))
+
+
+def voxel_errors(a, b):
+    """|a_i - b_i| / (|b_i| + rms(b)) at every voxel (see TOL)."""
+    return np.abs(a - b) / (np.abs(b) + max(rms(b), 1e-300))
+
+
 def rel_max(a, b):
-    """max |a - b| / max |b|: the worst single voxel, relative to the field's scale."""
+    """max |a - b| / max |b|: the worst single voxel against the field's largest value."""
     return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
 
 
 def check_field(got, ref, tol, what=""):
-    """Whole-field comparison: relative L2 and worst voxel. Returns (l2, worst)."""
-    l2, worst = rel_l2(got, ref), rel_max(got, ref)
+    """Whole-field comparison: relative L2 and the worst voxel (see TOL). Returns (l2, worst)."""
+    l2 = rel_l2(got, ref)
+    ve = voxel_errors(got, ref)
+    worst = float(ve.max())
+    where = np.unravel_index(int(np.argmax(ve)), np.shape(got))
+    log(f"      {what}: rel L2 {l2:.2e}, worst voxel {worst:.2e} at {tuple(int(i) for i in where)} "
+        f"(|go| {abs(float(ref[where])):.2e}, rms {rms(ref):.2e}, max {float(np.abs(ref).max()):.2e}; "
+        f"against max {rel_max(got, ref):.2e})")
     assert l2 <= tol["grad"], (what, "rel L2", l2)
-    assert worst <= tol["voxel"], (what, "worst voxel", worst,
-                                   np.unravel_index(int(np.argmax(np.abs(got - ref))), np.shape(got)))
+    assert worst <= tol["voxel"], (what, "worst voxel", worst, where)
     return l2, worst
 
 

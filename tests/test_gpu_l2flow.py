@@ -19,16 +19,36 @@ WILLMORE = (1.0, 2.0, 1.0, 0.0, 0.0, 0.0)
 SIGMA = closed_forms.SIGMA
 
 
+def _blur_rounding_sensitivity(u, h, eps, a, sigma_k):
+    """How far the oracle's own gradient moves when the blurred field k * u, which an FP32
+    path stores in FP32, is rounded to FP32 and everything else stays FP64: (relative L2,
+    worst voxel in the metric of check_field). Oracle functions only."""
+    from oracle import fe_oracle as fo
+    from gpu_helpers import voxel_errors
+    _, g = l2flow.energy_grad_replicate(u, h, eps, a, sigma_k)
+    ub = l2flow.blur_replicate(u, sigma_k).astype(np.float32).astype(np.float64)
+    ue = l2flow.pad_replicate(ub, 1)
+    ubar, gamma, theta, _ = fo.adjoint_fields(ue, h, eps, a)
+    box = np.zeros(ue.shape, dtype=bool)
+    box[1:-1, 1:-1, 1:-1] = True
+    g_ext = h ** 3 * fo.transpose_stencils(np.where(box, ubar, 0.0), [np.where(box, x, 0.0) for x in gamma],
+                                           [np.where(box, x, 0.0) for x in theta], h)
+    gr = l2flow.blur_replicate_adjoint(l2flow.pad_replicate_adjoint(g_ext, 1), sigma_k)
+    return rel_l2(gr, g), float(voxel_errors(gr, g).max())
+
+
 @pytest.mark.parametrize("dtype,sigma_k", [(torch.float64, 0.0), (torch.float64, 0.5), (torch.float64, 1.0),
-                                           (torch.float64, 2.0), (torch.float32, 0.0), (torch.float32, 1.0),
-                                           (torch.float32, 2.0)])
+                                           (torch.float64, 2.0), (torch.float32, 0.0), (torch.float32, 0.5),
+                                           (torch.float32, 1.0), (torch.float32, 2.0)])
 def test_energy_and_gradient_match_oracle(dtype, sigma_k):
     """A ragged 20 x 24 x 28 box of noise around a ball, every term of p. The blur
     widths cover every pad width the kernels special-case (1, 4, 8) and a general
-    one (2). FP32 leaves out sigma_k = 0.5: a blur that weak keeps the noise, and
-    F_h is then so sensitive to the FP32 rounding of the blurred field that the
-    gradient moves by 4e-3 relative (the FP64 path on the same code agrees with
-    the oracle to 1e-11, and FP32 without blur to 1e-5)."""
+    one (2). With a blur in FP32 the energy is evaluated on a stored FP32 blurred
+    field; a weak blur keeps the noise, and near its umbilic voxels (dS/dX = 1/(2S))
+    F_h is so sensitive to that rounding that the oracle's own gradient moves by up to
+    2e-2 per voxel (sigma_k = 0.5) when only that field is rounded. FP32 gradients are
+    therefore held to 10 times that sensitivity where it exceeds the usual bounds (the
+    FP64 path agrees with the oracle to 1e-11, and FP32 without blur to 1e-5)."""
     shape = (20, 24, 28)
     h = 1.0 / 28
     eps = 2.5 * h
@@ -41,7 +61,12 @@ def test_energy_and_gradient_match_oracle(dtype, sigma_k):
     E, g = flow.energy_grad(ud)
     uo = oracle_input(ud)
     Eo, go = l2flow.energy_grad_replicate(uo, h, eps, ALL_TERMS, sigma_k)
-    tol = TOL[dtype]
+    tol = dict(TOL[dtype])
+    if dtype == torch.float32 and sigma_k > 0:
+        s_l2, s_vox = _blur_rounding_sensitivity(uo, h, eps, ALL_TERMS, sigma_k)
+        log(f"  oracle sensitivity to the FP32 blurred field: rel L2 {s_l2:.2e}, worst voxel {s_vox:.2e}")
+        tol["grad"] = max(tol["grad"], 10 * s_l2)
+        tol["voxel"] = max(tol["voxel"], 10 * s_vox)
     scale = abs(Eo) + abs(l2flow.energy_replicate(uo, h, eps, (1, 0, 1, 0, 0, 0), sigma_k))
     assert abs(E - Eo) <= tol["energy"] * max(abs(Eo), scale), (E, Eo)
     check_field(g.cpu().double().numpy(), go, tol)
@@ -88,13 +113,10 @@ def test_thin_boxes_match_oracle(shape, sigma_k):
 
 @pytest.mark.parametrize("history,max_iter,nsteps", [(3, 5, 4), (14, 12, 2)])
 def test_lbfgs_steps_match_torch_lbfgs_on_the_oracle(history, max_iter, nsteps):
-    """FP64, 16^3 noisy ball, blur sigma_k = 1, p = H^2: steps of inner iterations
-    against torch.optim.LBFGS (lr 1) driving the oracle's energy and gradient; the
-    history wraps in both cases, and history 14 takes two passes of both the Gram
-    and the direction kernels (28 history vectors, 29 direction terms). eps = 2.5h
-    keeps the trajectory free of the wild steps that L-BFGS without line search can
-    take (at eps = 2h one iterate reaches F ~ 1e24); after such a step the two
-    implementations' rounding differences, though both correct, grow without bound."""
+    """FP64, 16^3 noisy ball, eps = 2.5h, blur sigma_k = 1, p = H^2: steps of inner
+    iterations against torch.optim.LBFGS (lr 1) driving the oracle's energy and gradient;
+    the history wraps in both cases, and history 14 takes two passes of both the Gram
+    and the direction kernels (28 history vectors, 29 direction terms)."""
     n = 16
     h = 1.0 / n
     eps = 2.5 * h
@@ -110,6 +132,35 @@ def test_lbfgs_steps_match_torch_lbfgs_on_the_oracle(history, max_iter, nsteps):
     np.testing.assert_allclose(Eg, Eo, rtol=1e-9)
     assert rel_l2(ug, uo) <= 1e-8
     log(f"  energies {Eg}")
+
+
+def test_lbfgs_matches_torch_lbfgs_up_to_the_wild_iterate():
+    """The same problem at eps = 2h, history 3, one iteration per step, so that every
+    evaluation's energy is returned (the same 20 iterates as 4 steps of 5 iterations).
+    Without line search the run passes an iterate with F ~ 7e24. Up to it every energy
+    equals torch.optim.LBFGS's on the oracle (rtol 1e-9), and at it to 1e-7 (there |u|
+    reaches ~1e4 and the density, of degree 6 in u through W', magnifies the rounding of
+    the step that led there). The direction
+    taken from it is so ill-conditioned that exact arithmetic on the same vectors lands
+    16% away from torch's next energy (tests/test_lbfgs_recursion.py), so later
+    iterates are checked for what stays unique: finite energies and a descent overall."""
+    n = 16
+    h = 1.0 / n
+    eps = 2.0 * h
+    u0 = inputs.noisy_sphere(n, 0.3, eps, 0.02, 8)
+    ud = to_dev(u0, torch.float64)
+    flow = fe.FeL2Flow((n, n, n), h, eps, WILLMORE, sigma_k=1.0, dtype=torch.float64)
+    flow.set_lbfgs(lr=1.0, history=3, max_iter=1)
+    flow.load(ud)
+    Eg = np.array(flow.step(20))
+    _, Eo = l2flow.lbfgs_flow(oracle_input(ud), h, eps, WILLMORE, 1.0, 20, lr=1.0, history=3, max_iter=1)
+    Eo = np.array(Eo)
+    wild = int(np.argmax(Eo > 1e20))
+    log(f"  wild iterate {wild}: F {Eo[wild]:.3e}; energies {Eg}")
+    assert Eo[wild] > 1e20 and wild > 0
+    np.testing.assert_allclose(Eg[:wild], Eo[:wild], rtol=1e-9)
+    np.testing.assert_allclose(Eg[wild], Eo[wild], rtol=1e-7)
+    assert np.isfinite(Eg).all() and Eg[-1] < 0.2 * Eg[0]
 
 
 def test_flow_is_stationary_on_a_sphere_fp32():

@@ -280,12 +280,12 @@ def test_full_size_step_in_the_bench_configuration():
     mass = [float(u0.double().mean().item())]
     u1 = u0.clone()
     ctx.step(u1, mass, tau, 1)
-    U0 = oracle_input(u0)[0]
+    U0 = oracle_input(u0)
     _, _, go = slab_oracle(U0, h, 1.5 * h, HELFRICH_SC)
     v = U0 - tau * go
     d_ref = (v + (mass[0] - v.mean())) - U0
     del v, go
-    d_got = u1[0].cpu().double().numpy() - U0
+    d_got = u1.cpu().double().numpy() - U0
     l2, worst = check_field(d_got, d_ref, TOL[torch.float32], "step update")
     log(f"  one step: update rel L2 {l2:.2e} worst voxel {worst:.2e}")
     assert abs(u1.double().mean().item() - mass[0]) <= 1e-6

@@ -8,7 +8,7 @@ import torch
 from oracle import fe_oracle as fo
 from paper_2103_04856_amd import fe, inputs
 
-from gpu_helpers import ALL_TERMS, ASYM_C3, WILLMORE_QUARTER, log, oracle_input, rel_l2, to_dev
+from gpu_helpers import ALL_TERMS, ASYM_C3, TOL, WILLMORE_QUARTER, log, oracle_input, rel_l2, to_dev, voxel_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -226,10 +226,10 @@ def test_autograd_descent_loop_keeps_mass():
 def _adam_reference(U0, h, eps, a, m, nsteps, vtol):
     """The oracle's mass-projected Adam trajectory from U0 and the voxels whose update the
     FP32 path cannot be expected to reproduce: those where the oracle's gradient at some
-    step is within the FP32 gradient's error of zero (vtol of its largest value), so that
-    its sign, which alone sets Adam's first move, is a rounding decision. A move there
-    changes the gradient up to two voxels away at the next step, so the set grows by two
-    voxels per later step (periodically)."""
+    step is within the FP32 gradient's per-voxel error bound of zero (|go| <= vtol (|go| +
+    rms go)), so that its sign, which alone sets Adam's first move, is a rounding decision.
+    A move there changes the gradient up to two voxels away at the next step, so the set
+    grows by two voxels per later step (periodically)."""
     from scipy.ndimage import maximum_filter
     u, m1, m2 = U0.copy(), np.zeros_like(U0), np.zeros_like(U0)
     undecided = np.zeros(U0.shape, dtype=bool)
@@ -237,24 +237,26 @@ def _adam_reference(U0, h, eps, a, m, nsteps, vtol):
         if t > 1:
             undecided = maximum_filter(undecided, size=5, mode="wrap")
         _, go = fo.energy_grad(u, h, eps, a)
-        undecided |= np.abs(go) <= vtol * np.abs(go).max()
+        undecided |= np.abs(go) <= vtol * (np.abs(go) + np.sqrt(np.mean(go * go)))
         u, m1, m2, _ = fo.adam_projected_step(u, m1, m2, t, h, eps, a, m)
     return u, undecided
 
 
 def _check_adam_update(d_got, d_ref, undecided, lr, what):
-    """Update against the oracle's: relative L2 over the field, the worst voxel where the
-    result is unique, and a valid move (at most nsteps lr plus the shift) elsewhere."""
+    """Update against the oracle's: relative L2 over the field; every voxel within the
+    per-voxel bound except where a sign decision could reach (undecided), which must be
+    rare; and every move a valid Adam move (at most about lr per step plus the shift)."""
     l2 = rel_l2(d_got, d_ref)
-    scale = np.abs(d_ref).max()
-    dec = ~undecided
-    worst = float(np.abs(d_got - d_ref)[dec].max() / scale)
-    log(f"  {what}: update rel L2 {l2:.2e}, worst decided voxel {worst:.2e}, "
-        f"undecided voxels {int(undecided.sum())} of {undecided.size}")
+    ve = voxel_errors(d_got, d_ref)
+    tol = TOL[torch.float32]["voxel"]
+    bad = ve > tol
+    worst = float(ve[~undecided].max()) if (~undecided).any() else 0.0
+    log(f"  {what}: update rel L2 {l2:.2e}, worst voxel {float(ve.max()):.2e}, voxels beyond {tol:g}: "
+        f"{int(bad.sum())}, worst outside the {int(undecided.sum())} undecided voxels {worst:.2e}")
     assert l2 <= 1e-3, (what, l2)
-    assert worst <= 1e-3, (what, worst)
-    assert undecided.mean() <= 1e-3, (what, undecided.mean())
-    assert np.abs(d_got).max() <= 1.01 * scale + 10 * lr
+    assert not (bad & ~undecided).any(), (what, worst)
+    assert bad.mean() <= 1e-3, (what, int(bad.sum()))
+    assert np.abs(d_got).max() <= 1.01 * np.abs(d_ref).max() + 10 * lr
 
 
 def test_fp32_adam_steps_match_oracle_128():
@@ -267,7 +269,7 @@ def test_fp32_adam_steps_match_oracle_128():
     U0 = oracle_input(ud)
     ctx = fe.FeContext((1, n, n, n), h, 2 * h, ASYM_C3, dtype=torch.float32)
     ctx.step_adam(ud, [-0.3], 3)
-    uo, undecided = _adam_reference(U0, h, 2 * h, ASYM_C3, -0.3, 3, 1e-3)
+    uo, undecided = _adam_reference(U0, h, 2 * h, ASYM_C3, -0.3, 3, TOL[torch.float32]["voxel"])
     _check_adam_update(ud.cpu().double().numpy() - U0, uo - U0, undecided, 1e-3, "128^3 3 Adam steps")
     assert abs(ud.double().mean().item() + 0.3) <= 1e-6
 
@@ -283,7 +285,7 @@ def test_fp32_adam_step_matches_oracle_batched_16x128():
     ctx = fe.FeContext(ud.shape, h, 2 * h, coeffs, dtype=torch.float32)
     ctx.step_adam(ud, list(means), 1)
     for b in range(B):
-        uo, undecided = _adam_reference(U0[b], h, 2 * h, coeffs[b], means[b], 1, 1e-3)
+        uo, undecided = _adam_reference(U0[b], h, 2 * h, coeffs[b], means[b], 1, TOL[torch.float32]["voxel"])
         _check_adam_update(ud[b].cpu().double().numpy() - U0[b], uo - U0[b], undecided, 1e-3, f"instance {b}")
 
 
