@@ -104,6 +104,30 @@ int fe_energy_grad(fe_ctx* ctx, const void* u, void* g, double* energy);
 int fe_energy_grad_async(fe_ctx* ctx, const void* u, void* g, double* energy_dev);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): fe_energy_grad_async
+ * without a context. It allocates nothing and calls nothing that allocates;
+ * its per-instance table and block partials live in one static 1 MiB device
+ * array that each device holds until the process ends.
+ *   grid, eps, p_coeffs  as in fe_create (host memory, read during the call);
+ *                        batch <= 16.
+ *   u           device field [batch][nz][ny][nx] on the current device, read only.
+ *   g           device field, written with dF_h/du (must not overlap u), or NULL.
+ *   energy_dev  device array of `batch` doubles receiving F_h(u_b), or NULL
+ *               (not both NULL).
+ *   stream      hipStream_t the work is ordered on (NULL: default stream).
+ * Nothing synchronises; the launch shape is the one a fresh context would
+ * choose. FE_EINVAL for a batch above 16, invalid parameters, or a grid whose
+ * sweep needs more block partials than the array holds (65280; 256^3 needs 512).
+ * Every call on a device shares that device's array (the last call's contents
+ * stay there; every value a call reads it has written first in stream order),
+ * so calls that overlap on one device - on two streams, or from two host
+ * threads - race and must be serialised by the caller.
+ */
+int fe_energy_grad_noalloc(const fe_grid* grid, const double* eps, const double* p_coeffs, const void* u,
+                           void* g, double* energy_dev, void* stream);
+
+/*
  * nsteps mass-preserving descent steps, in place on u (Sec. 4.1 keeps the mean
  * of u fixed along the flow):
  *   u <- v + (mass[b] - mean(v)),  v = u - tau dF_h/du,

@@ -1,7 +1,8 @@
 // The library's one translation unit: the kernels (fe_*.hpp) and the host side
 // of the C ABI declared in include/fe.h, split by topic into host_core.hpp
 // (context, constants, sweeps, step loops, autotuner), host_flow.hpp
-// (Algorithm 1), host_diag.hpp (diagnostics) and host_l2.hpp (Algorithm 2).
+// (Algorithm 1), host_diag.hpp (diagnostics), host_l2.hpp (Algorithm 2) and
+// host_noalloc.hpp (the allocation-free energy + gradient entry point).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,3 +25,4 @@
 #include "host_flow.hpp"
 #include "host_diag.hpp"
 #include "host_l2.hpp"
+#include "host_noalloc.hpp"

@@ -240,33 +240,38 @@ int check_params(int batch, const double* eps, const double* a) {
 
 // Per-instance constants: c1..c6 of eq. (Feps) folded with the unit scales of
 // the raw-difference formulation (s = eps/h^2, 1/(2h), h^3, eps/(4h^2)).
+// One instance's constants: spacing h, width e, coefficients a[6], orientation
+// term mu (0: off) along theta[3].
+template <typename T>
+fe::InstParams<T> inst_params(double h, double e, const double* a, double mu, const double* theta) {
+  const double h3 = h * h * h;
+  const double a20 = a[0], a11 = a[1], a02 = a[2], a10 = a[3], a01 = a[4], a00 = a[5];
+  const double c1 = (a20 + a02 - a11) / (2.0 * e), c2 = a11 / (2.0 * e), c3 = (a20 - a02) / (2.0 * e);
+  const double c4 = (a10 + a01) / 2.0, c5 = (a10 - a01) / 2.0, c6 = a00;
+  const double sc = e / (h * h);
+  fe::InstParams<T> p;
+  p.lam_d = 1.0 / (e * sc);
+  p.lam = T(p.lam_d);
+  p.C1 = T(h3 * c1 * sc * sc);
+  p.C2 = T(h3 * c2 * sc * sc);
+  p.C3 = T(h3 * c3 * sc * sc);
+  p.C4 = T(h3 * c4 * sc / (2.0 * h));
+  p.C5 = T(h3 * c5 * sc / (2.0 * h));
+  p.C6 = T(h3 * c6 * e / (4.0 * h * h));
+  p.xi = T(kXi / (sc * sc));
+  p.inv_xi = T(sc * sc / kXi);
+  p.Co = T(h3 * e * mu / (4.0 * h * h));
+  p.thx = T(theta[0]);
+  p.thy = T(theta[1]);
+  p.thz = T(theta[2]);
+  return p;
+}
+
 template <typename T>
 void fill_params(const fe_ctx* c, std::vector<fe::InstParams<T>>& out) {
-  const double h = c->grid.h, h3 = h * h * h;
   out.resize(c->grid.batch);
-  for (int b = 0; b < c->grid.batch; ++b) {
-    const double e = c->eps[b];
-    const double* a = &c->coeffs[6 * b];
-    const double a20 = a[0], a11 = a[1], a02 = a[2], a10 = a[3], a01 = a[4], a00 = a[5];
-    const double c1 = (a20 + a02 - a11) / (2.0 * e), c2 = a11 / (2.0 * e), c3 = (a20 - a02) / (2.0 * e);
-    const double c4 = (a10 + a01) / 2.0, c5 = (a10 - a01) / 2.0, c6 = a00;
-    const double sc = e / (h * h);
-    fe::InstParams<T>& p = out[b];
-    p.lam_d = 1.0 / (e * sc);
-    p.lam = T(p.lam_d);
-    p.C1 = T(h3 * c1 * sc * sc);
-    p.C2 = T(h3 * c2 * sc * sc);
-    p.C3 = T(h3 * c3 * sc * sc);
-    p.C4 = T(h3 * c4 * sc / (2.0 * h));
-    p.C5 = T(h3 * c5 * sc / (2.0 * h));
-    p.C6 = T(h3 * c6 * e / (4.0 * h * h));
-    p.xi = T(kXi / (sc * sc));
-    p.inv_xi = T(sc * sc / kXi);
-    p.Co = T(h3 * e * c->mu[b] / (4.0 * h * h));
-    p.thx = T(c->theta[3 * b]);
-    p.thy = T(c->theta[3 * b + 1]);
-    p.thz = T(c->theta[3 * b + 2]);
-  }
+  for (int b = 0; b < c->grid.batch; ++b)
+    out[b] = inst_params<T>(c->grid.h, c->eps[b], &c->coeffs[6 * b], c->mu[b], &c->theta[3 * b]);
 }
 
 template <typename T>
@@ -314,9 +319,9 @@ struct Geometry {
 };
 
 // Blocks of the step sweep of `variant` that one compute unit holds at once.
-int block_slots(const fe_ctx* c, int variant) {
+int block_slots(int dtype, int variant) {
   const Variant& v = variants()[variant];
-  const void* fn = c->grid.dtype == FE_F32 ? (const void*)v.k32.step : (const void*)v.k64.step;
+  const void* fn = dtype == FE_F32 ? (const void*)v.k32.step : (const void*)v.k64.step;
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, v.nt, 0) != hipSuccess || n < 1) n = 1;
   return n;
@@ -336,11 +341,11 @@ double sweep_cost(long blocks, int num_cu, int slots, int L) {
   return t;
 }
 
-Geometry geometry(const fe_ctx* c, int variant, int lz_req) {
+Geometry geometry_of(const fe_grid& grid, int num_cu, int variant, int lz_req) {
   const Variant& v = variants()[variant];
   Geometry g;
-  g.ntx = ceil_div(c->grid.nx, v.tx);
-  g.nty = ceil_div(c->grid.ny, v.ty);
+  g.ntx = ceil_div(grid.nx, v.tx);
+  g.nty = ceil_div(grid.ny, v.ty);
   int lz = lz_req;
   if (lz <= 0) {
     // the equal z chunks whose sweep sweep_cost finishes first: longer chunks
@@ -348,26 +353,28 @@ Geometry geometry(const fe_ctx* c, int variant, int lz_req) {
     // and a last round of blocks that fills only some CUs costs most of a
     // round (256^3 in 32 x 32 tiles: 32 planes, 512 blocks; 200^3 in 50 x 20
     // tiles: 17 planes, 480 blocks, 73 us against 102 us for 16 planes)
-    const int nz = c->grid.nz;
-    const long cols = (long)g.ntx * g.nty * c->grid.batch;
-    const int slots = block_slots(c, variant);
+    const int nz = grid.nz;
+    const long cols = (long)g.ntx * g.nty * grid.batch;
+    const int slots = block_slots(grid.dtype, variant);
     double best = 0.0;
     for (int nzc = 1; nzc <= nz; ++nzc) {
       const int l = ceil_div(nz, nzc);
       if (nzc > 1 && l == ceil_div(nz, nzc - 1)) continue;   // the same chunks as nzc - 1
-      const double t = sweep_cost(cols * ceil_div(nz, l), c->num_cu, slots, l + 2);
+      const double t = sweep_cost(cols * ceil_div(nz, l), num_cu, slots, l + 2);
       if (lz <= 0 || t < best) {
         best = t;
         lz = l;
       }
     }
   }
-  lz = std::min(std::max(lz, 1), c->grid.nz);
+  lz = std::min(std::max(lz, 1), grid.nz);
   g.lz = lz;
-  g.nzc = ceil_div(c->grid.nz, lz);
+  g.nzc = ceil_div(grid.nz, lz);
   g.per_inst = g.ntx * g.nty * g.nzc;
   return g;
 }
+
+Geometry geometry(const fe_ctx* c, int variant, int lz_req) { return geometry_of(c->grid, c->num_cu, variant, lz_req); }
 
 bool has_sp(int v, int dtype) {
   const Variant& x = variants()[v];

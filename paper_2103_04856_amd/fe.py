@@ -69,6 +69,7 @@ SIGNATURES = {
     "fe_l2_step": (ctypes.c_int, [_P, ctypes.c_int, _DP]),
     "fe_l2_set_stream": (ctypes.c_int, [_P, _P]),
     "fe_l2_destroy": (None, [_P]),
+    "fe_energy_grad_noalloc": (ctypes.c_int, [ctypes.POINTER(FeGrid), _DP, _DP, _P, _P, _P, _P]),
     "fe_num_variants": (ctypes.c_int, []),
     "fe_variant_info": (ctypes.c_int, [ctypes.c_int, _IP, _IP, _IP, _IP]),
     "fe_set_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
@@ -362,6 +363,37 @@ class FeContext:
                                  ctypes.byref(best)))
         v, z = self.get_launch()
         return v, z, best.value
+
+
+NOALLOC_MAX_BATCH = 16
+
+
+def energy_grad_noalloc(u, h, eps, coeffs, g=None, energy_out=None, with_grad=True):
+    """fe_energy_grad_noalloc: energy (and gradient) of u [B, nz, ny, nx] without a context
+    and without any device allocation by the library (its workspace is a static device
+    array; calls that overlap on one device race). g and energy_out, if given, receive the
+    results (else torch allocates them here). Stream-ordered on the current torch stream,
+    no synchronisation. Returns (energies float64 [B] on the device, g or None)."""
+    if not isinstance(u, torch.Tensor) or u.device.type != "cuda" or not u.is_contiguous() \
+            or u.dtype not in (torch.float32, torch.float64):
+        raise ValueError("u must be a contiguous float32/float64 device tensor")
+    shape = tuple(u.shape) if u.dim() == 4 else (1, *u.shape)
+    B, nz, ny, nx = shape
+    eps_l, coeff_l = FeContext._param_lists(eps, coeffs, B)
+    if with_grad and g is None:
+        g = torch.empty_like(u)
+    if g is not None and (g.shape != u.shape or g.dtype != u.dtype or not g.is_contiguous()
+                          or g.device != u.device):
+        raise ValueError("g must match u")
+    if energy_out is None:
+        energy_out = torch.empty(B, dtype=torch.float64, device=u.device)
+    grid = FeGrid(nx, ny, nz, B, float(h), FE_F32 if u.dtype == torch.float32 else FE_F64)
+    with torch.cuda.device(u.device):
+        _check(lib().fe_energy_grad_noalloc(ctypes.byref(grid), _dbl(eps_l), _dbl(coeff_l), _P(u.data_ptr()),
+                                            _P(g.data_ptr()) if g is not None else _P(0),
+                                            _P(energy_out.data_ptr()),
+                                            _P(torch.cuda.current_stream(u.device).cuda_stream)))
+    return energy_out, g
 
 
 class FeL2Flow:

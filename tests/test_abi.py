@@ -116,3 +116,18 @@ def test_l2_create_rejects_before_device_work(L, grid, sigma_k, msg):
     rc = L.fe_l2_create(ctypes.byref(fe.FeGrid(**grid)), 0.25, fe._dbl([1, 2, 1, 0, 0, 0]), sigma_k, None,
                         ctypes.byref(out))
     assert rc == fe.FE_EINVAL and not out.value and msg in L.fe_last_error().decode()
+
+
+@pytest.mark.parametrize("grid,msg", [
+    (dict(GOOD, batch=17), "16"),
+    (dict(GOOD, nx=8192, ny=8192, nz=1), "partials"),   # 256 x 256 tile columns
+    (dict(GOOD, nx=0), "grid sizes"),
+])
+def test_noalloc_rejects_before_device_work(L, grid, msg):
+    """The allocation-free entry point checks its limits (batch <= 16, the block partials
+    its static array holds) on the host, before it looks up the array or launches."""
+    B = grid["batch"]
+    rc = L.fe_energy_grad_noalloc(ctypes.byref(fe.FeGrid(**grid)), fe._dbl([0.25] * B),
+                                  fe._dbl([1, 2, 1, 0, 0, 0] * B), ctypes.c_void_p(8), ctypes.c_void_p(16),
+                                  None, None)
+    assert rc == fe.FE_EINVAL and msg in L.fe_last_error().decode()
