@@ -26,6 +26,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "fe_voxel.hpp"
 
 namespace fe {
@@ -553,6 +555,125 @@ __global__ __launch_bounds__(NT) void energy_sweep(SweepArgs<T> a) {
   }
 
   write_partials<NT>(a, bt.logical, acc_f, acc_m, sred);
+}
+
+// Energy only, one x column per lane: a block owns a 64 x (V NWV) tile of
+// columns and a chunk of lz planes of one instance; wave w owns rows
+// [w V, w V + V) of the tile and lane l the column x0 + l. Per plane the u
+// plane (prefetched into registers one plane earlier) is staged in LDS with a
+// periodic halo of 1, and after the plane's one barrier every thread copies the
+// 3 x (V + 2) window around its V voxels into registers. The windows of three
+// consecutive planes hold all 19 stencil samples of the V voxels, so each
+// staged value is read from LDS once per thread that needs it (6 reads per
+// voxel at V = 2 instead of 19), and the three window roles rotate through an
+// unrolled loop instead of moving registers. Two LDS slots suffice: a plane's
+// slot is rewritten two planes later, after every thread has passed the
+// barrier that follows its last read. Partial [0] is the block's energy.
+template <typename T, int V, int NWV>
+__global__ __launch_bounds__(64 * NWV) void energy_sweep_cols(SweepArgs<T> a) {
+  constexpr int TX = 64, TY = V * NWV, NT = 64 * NWV;
+  constexpr int UX = TX + 2, UY = TY + 2;
+  constexpr int NU = (UX * UY + NT - 1) / NT;
+  constexpr int WR = V + 2;
+
+  __shared__ T su[2][UY * UX];
+  __shared__ double sred[NWV][2];
+
+  const int tid = threadIdx.x;
+  const int lane = tid % kWave, wv = tid / kWave;
+  const BlockTile bt = block_tile<T, TX, TY>(a);
+  const int x0 = bt.x0, y0 = bt.y0, k0 = bt.k0, kend = bt.kend;
+  const size_t plane = (size_t)a.nx * a.ny;
+  const T* srcb = a.src + (size_t)bt.inst * a.nz * plane;
+  const InstParams<T> prm = a.prm[bt.inst];
+
+  int uoff[NU];
+#pragma unroll
+  for (int j = 0; j < NU; ++j) {
+    const int e = tid + j * NT;
+    const int ex = e % UX, ey = e / UX;
+    uoff[j] = (e < UX * UY) ? wrap_index(y0 - 1 + ey, a.ny) * a.nx + wrap_index(x0 - 1 + ex, a.nx) : 0;
+  }
+  T pre[NU];
+  auto fetch = [&](int p) {
+    const T* sp = srcb + (size_t)wrap_index(p, a.nz) * plane;
+#pragma unroll
+    for (int j = 0; j < NU; ++j)
+      if (tid + j * NT < UX * UY) pre[j] = sp[uoff[j]];
+  };
+  auto stage = [&](int slot) {
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      const int e = tid + j * NT;
+      if (e < UX * UY) su[slot][e] = pre[j];
+    }
+  };
+  // window row r of this thread is tile row wv V + r - 1; column c is x0 + lane + c - 1
+  auto read_window = [&](int slot, T (&w)[WR][3]) {
+    const T* b = su[slot] + (wv * V) * UX + lane;
+#pragma unroll
+    for (int r = 0; r < WR; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w[r][c] = b[r * UX + c];
+  };
+  const bool xin = x0 + lane < a.nx;
+  double acc_f = 0.0;
+  T w0[WR][3], w1[WR][3], w2[WR][3];
+  // prologue: planes k0 - 1 and k0 into the windows, plane k0 + 1 in flight
+  fetch(k0 - 1);
+  stage(0);
+  fetch(k0);
+  __syncthreads();
+  read_window(0, w0);
+  stage(1);
+  fetch(k0 + 1);
+  __syncthreads();
+  read_window(1, w1);
+  // the body without S~ terms where the instance has none (one uniform branch)
+  auto run = [&](auto nos_tag) {
+    constexpr bool NOS = decltype(nos_tag)::value;
+    auto compute = [&](const T (&m)[WR][3], const T (&c)[WR][3], const T (&pl)[WR][3]) {
+      T fs = T(0);
+#pragma unroll
+      for (int r = 0; r < V; ++r) {
+        auto st = [&]() {
+          Stencil19<T> s;
+          s.c = c[r + 1][1];
+          s.xm = c[r + 1][0]; s.xp = c[r + 1][2]; s.ym = c[r][1]; s.yp = c[r + 2][1];
+          s.zm = m[r + 1][1]; s.zp = pl[r + 1][1];
+          s.xpyp = c[r + 2][2]; s.xpym = c[r][2]; s.xmyp = c[r + 2][0]; s.xmym = c[r][0];
+          s.xpzp = pl[r + 1][2]; s.xpzm = m[r + 1][2]; s.xmzp = pl[r + 1][0]; s.xmzm = m[r + 1][0];
+          s.ypzp = pl[r + 2][1]; s.ypzm = m[r + 2][1]; s.ymzp = pl[r][1]; s.ymzm = m[r][1];
+          return s;
+        };
+        const T f = voxel_density_body<NOS>(st(), st, prm, a.k);
+        if (xin && y0 + wv * V + r < a.ny) fs += f;
+      }
+      acc_f += double(fs);
+    };
+    // plane p: stage p + 1 (into the slot of p - 1), prefetch p + 2, barrier,
+    // window of p + 1, then the V voxels of plane p
+    auto plane_step = [&](int p, const T (&m)[WR][3], const T (&c)[WR][3], T (&pl)[WR][3]) {
+      const int slot = (p - k0 + 2) & 1;
+      stage(slot);
+      if (p + 2 <= kend) fetch(p + 2);
+      __syncthreads();
+      read_window(slot, pl);
+      compute(m, c, pl);
+    };
+    for (int p = k0; p < kend; p += 3) {
+      plane_step(p, w0, w1, w2);
+      if (p + 1 >= kend) break;
+      plane_step(p + 1, w1, w2, w0);
+      if (p + 2 >= kend) break;
+      plane_step(p + 2, w2, w0, w1);
+    }
+  };
+  if (has_s_terms(prm))
+    run(std::false_type{});
+  else
+    run(std::true_type{});
+  write_partials<NT>(a, bt.logical, acc_f, 0.0, sred);
 }
 
 // Per-instance results of a sweep from its block partials, one wave per

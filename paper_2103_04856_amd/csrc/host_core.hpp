@@ -509,8 +509,93 @@ int finish_sums(fe_ctx* c, hipStream_t s, const double* partials, double* energy
   return FE_OK;
 }
 
+// The energy-only sweep (fe::energy_sweep_cols): one x column per lane, 64-wide
+// tiles of 8 waves, 2 rows per thread in FP32 (64 x 16 tiles, 110 VGPRs), 1 in
+// FP64 (64 x 8, 120 VGPRs): two blocks per CU. 256^3 FP32, measured against 3
+// and 4 rows per thread, 4 and 16 waves per block and chunks of 8 to 64
+// planes: 31.5 us (symmetric p) and 47 us (full body) at 32-plane chunks, the
+// makespan model's choice, within 2% of the fastest of those shapes.
+constexpr int kEnergyWaves = 8;
+int energy_rows(int dtype) { return dtype == FE_F32 ? 2 : 1; }
+
+const void* energy_cols_kernel(int dtype) {
+  return dtype == FE_F32 ? (const void*)fe::energy_sweep_cols<float, 2, kEnergyWaves>
+                         : (const void*)fe::energy_sweep_cols<double, 1, kEnergyWaves>;
+}
+
+// Launch geometry of the energy-only sweep: tiles as above, z chunks by the
+// makespan model of the gradient sweep (a chunk of lz planes costs about lz + 1,
+// its two halo planes being loads only).
+Geometry energy_geometry(const fe_grid& grid, int num_cu) {
+  Geometry g;
+  g.ntx = ceil_div(grid.nx, 64);
+  g.nty = ceil_div(grid.ny, energy_rows(grid.dtype) * kEnergyWaves);
+  int slots = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&slots, energy_cols_kernel(grid.dtype), 64 * kEnergyWaves, 0) !=
+          hipSuccess || slots < 1)
+    slots = 1;
+  const long cols = (long)g.ntx * g.nty * grid.batch;
+  double best = 0.0;
+  int lz = 0;
+  for (int nzc = 1; nzc <= grid.nz; ++nzc) {
+    const int l = ceil_div(grid.nz, nzc);
+    if (nzc > 1 && l == ceil_div(grid.nz, nzc - 1)) continue;
+    const double t = sweep_cost(cols * ceil_div(grid.nz, l), num_cu, slots, l + 1);
+    if (lz <= 0 || t < best) {
+      best = t;
+      lz = l;
+    }
+  }
+  g.lz = lz;
+  g.nzc = ceil_div(grid.nz, lz);
+  g.per_inst = g.ntx * g.nty * g.nzc;
+  return g;
+}
+
+// One energy-only sweep of u: block partials into `partials`; returns its geometry.
+template <typename T>
+int launch_energy_cols(const fe_grid& grid, const Geometry& geo, const void* u, const void* prm, double* partials,
+                       hipStream_t s) {
+  fe::SweepArgs<T> a{};
+  a.src = static_cast<const T*>(u);
+  a.prm = static_cast<const fe::InstParams<T>*>(prm);
+  a.partials = partials;
+  a.inv_nvox = 1.0 / ((double)grid.nx * grid.ny * grid.nz);
+  a.k = grid_consts<T>(grid.h);
+  a.nx = grid.nx;
+  a.ny = grid.ny;
+  a.nz = grid.nz;
+  a.ntx = geo.ntx;
+  a.nty = geo.nty;
+  a.nzc = geo.nzc;
+  a.lz = geo.lz;
+  a.batch = grid.batch;
+  const dim3 blocks((unsigned)(geo.per_inst * grid.batch)), threads(64 * kEnergyWaves);
+  constexpr int V = std::is_same<T, float>::value ? 2 : 1;
+  hipLaunchKernelGGL((fe::energy_sweep_cols<T, V, kEnergyWaves>), blocks, threads, 0, s, a);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+int launch_energy_cols_any(const fe_grid& grid, const Geometry& geo, const void* u, const void* prm,
+                           double* partials, hipStream_t s) {
+  return grid.dtype == FE_F32 ? launch_energy_cols<float>(grid, geo, u, prm, partials, s)
+                              : launch_energy_cols<double>(grid, geo, u, prm, partials, s);
+}
+
 // A gradient (or energy-only, kind -1) sweep and its energies into energy_dev.
 int sweep_energy(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, double* energy_dev) {
+  if (kind < 0 && !c->use_cfield && !c->use_box) {
+    const Geometry geo = energy_geometry(c->grid, c->num_cu);
+    if ((size_t)geo.per_inst > c->max_blocks) return set_error(FE_EINVAL, "internal: partials workspace too small");
+    int rc = launch_energy_cols_any(c->grid, geo, src, c->d_prm, partials_buf(c, 0), s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(fe::sweep_finish, dim3(c->grid.batch), dim3(64), 0, s, (const double*)partials_buf(c, 0),
+                       geo.per_inst, energy_dev, (const double*)c->d_mass,
+                       1.0 / ((double)c->grid.nx * c->grid.ny * c->grid.nz), (double*)nullptr);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+  }
   const StepRule none{fe::kGrad, 0.0, 0.0, 0.0, 0.0};
   int rc = sweep(c, s, kind, src, dst, nullptr, partials_buf(c, 0), none);
   return rc ? rc : finish_sums(c, s, partials_buf(c, 0), energy_dev, nullptr);
@@ -689,6 +774,8 @@ int fe_create(const fe_grid* grid, const double* eps, const double* p_coeffs, vo
     const Variant& x = variants()[v];
     mb = std::max(mb, (size_t)ceil_div(grid->nx, x.tx) * ceil_div(grid->ny, x.ty) * grid->nz);
   }
+  mb = std::max(mb, (size_t)ceil_div(grid->nx, 64) * ceil_div(grid->ny, energy_rows(grid->dtype) * kEnergyWaves) *
+                        grid->nz);
   c->max_blocks = mb;
   const size_t prm_bytes = grid->dtype == FE_F32 ? sizeof(fe::InstParams<float>) : sizeof(fe::InstParams<double>);
   if (hipMalloc(&c->d_prm, prm_bytes * grid->batch) != hipSuccess ||

@@ -67,7 +67,7 @@ template <typename T>
 int noalloc_sweep(const fe_grid& grid, const double* eps, const double* a, const void* u, void* g,
                   double* energy_dev, hipStream_t stream, const ScratchSlot& slot) {
   const int vi = default_variant(grid);
-  const Geometry geo = geometry_of(grid, slot.num_cu, vi, 0);
+  const Geometry geo = g ? geometry_of(grid, slot.num_cu, vi, 0) : energy_geometry(grid, slot.num_cu);
   const size_t nblocks = (size_t)geo.per_inst * grid.batch;
   if (nblocks > kScratchPartials)
     return set_error(FE_EINVAL, "grid needs %zu block partials; the static scratch holds %zu", nblocks,
@@ -99,8 +99,13 @@ int noalloc_sweep(const fe_grid& grid, const double* eps, const double* a, const
   sa.nzc = geo.nzc;
   sa.lz = geo.lz;
   sa.batch = grid.batch;
-  hipLaunchKernelGGL(g ? k.grad : k.energy, dim3((unsigned)nblocks), dim3((unsigned)v.nt), 0, stream, sa);
-  FE_HIP(hipGetLastError());
+  if (g) {
+    hipLaunchKernelGGL(k.grad, dim3((unsigned)nblocks), dim3((unsigned)v.nt), 0, stream, sa);
+    FE_HIP(hipGetLastError());
+  } else {
+    const int rc = launch_energy_cols<T>(grid, geo, u, prm, partials, stream);
+    if (rc) return rc;
+  }
   if (energy_dev) {
     hipLaunchKernelGGL(fe::sweep_finish, dim3(grid.batch), dim3(64), 0, stream, (const double*)partials,
                        geo.per_inst, energy_dev, (const double*)nullptr, sa.inv_nvox, (double*)nullptr);
@@ -127,7 +132,9 @@ int fe_energy_grad_noalloc(const fe_grid* grid, const double* eps, const double*
   {
     // a bound that needs no device: at least one z chunk per tile column
     const Variant& v = variants()[default_variant(*grid)];
-    const size_t cols = (size_t)ceil_div(grid->nx, v.tx) * ceil_div(grid->ny, v.ty) * grid->batch;
+    const size_t cols = g ? (size_t)ceil_div(grid->nx, v.tx) * ceil_div(grid->ny, v.ty) * grid->batch
+                          : (size_t)ceil_div(grid->nx, 64) *
+                                ceil_div(grid->ny, energy_rows(grid->dtype) * kEnergyWaves) * grid->batch;
     if (cols > kScratchPartials)
       return set_error(FE_EINVAL, "grid needs at least %zu block partials; the static scratch holds %zu", cols,
                        kScratchPartials);
