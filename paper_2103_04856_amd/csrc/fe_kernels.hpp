@@ -76,6 +76,9 @@ __device__ __forceinline__ int xcd_logical_block(int linear, int total) {
   return (linear % kXcd) * (total / kXcd) + linear / kXcd;
 }
 
+// Which per-voxel bodies a sweep kernel holds (see grad_sweep).
+enum SweepBody { kBodyAny = 0, kBodyNoS = 1, kBodyFull = 2 };
+
 // What the fused sweep writes.
 enum SweepMode {
   kGrad = 0,      // dst = dF_h/du (h^3 included); partial[1] = sum of src
@@ -224,13 +227,19 @@ __device__ __forceinline__ BlockTile block_tile(const SweepArgs<T>& a) {
 // read after the second barrier: three rotating u slots and two barriers per
 // plane suffice.
 //
+// BODY: which per-voxel body the kernel holds. kBodyAny picks it per instance
+// (a batch that mixes p symmetric in k1, k2 with others); kBodyNoS and
+// kBodyFull hold one body only, for batches whose instances all take it: a
+// single body needs fewer registers (FP32 32 x 32 tiles: step without S~ terms
+// 81 VGPRs against 116 with both bodies; Adam 96 and 123 against 130, where
+// both bodies leave one block per CU).
 // SP: the coefficients C1..C6 come per voxel from a.cfield (loaded for every
 // ring voxel of a plane right after the plane is staged, so their latency
 // overlaps the barrier) instead of from the instance's parameters.
 // BOX: only voxels inside [box_lo, box_hi) carry a density; the others (the
 // padding of a non-periodic field) have zero adjoints, and the gradient is
 // written at every voxel, padding included, for the caller to fold back.
-template <typename T, int TX, int TY, int NT, int MODE, bool SP = false, bool BOX = false>
+template <typename T, int TX, int TY, int NT, int MODE, bool SP = false, bool BOX = false, int BODY = kBodyAny>
 __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   constexpr int UX = TX + 4, UY = TY + 4;      // u window: interior + halo 2
   constexpr int RX = TX + 2, RY = TY + 2;      // adjoint ring: interior + 1
@@ -385,20 +394,27 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
       const T* pc = su[sc] + c;
       const T* pm = su[sm] + c;
       const T* pp = su[sp] + c;
-      // the body without S~ terms only where the instance has none and the
-      // registers allow it: the Adam sweep, already near the register limit of
-      // two blocks per CU, keeps the one full body
-      const T f = voxel_density_adjoint<SP || MODE == kStepAdam>(
-          load_stencil<T, UX>(pc, pm, pp), [&]() { return load_stencil<T, UX>(pc, pm, pp); }, pv, a.k, ad);
-      sx[GX][v] = ad.gx; sx[GY][v] = ad.gy;
+      // with both bodies, the one without S~ terms where the instance has none,
+      // so an instance takes the same arithmetic in every batch it is part of
+      // (a coefficient field varies per voxel: always the full body)
+      auto st = [&]() { return load_stencil<T, UX>(pc, pm, pp); };
+      T f;
+      if constexpr (BODY == kBodyNoS)
+        f = voxel_density_adjoint_body<true>(st(), st, pv, a.k, ad);
+      else if constexpr (BODY == kBodyFull)
+        f = voxel_density_adjoint_body<false>(st(), st, pv, a.k, ad);
+      else
+        f = voxel_density_adjoint<SP>(st(), st, pv, a.k, ad);
+      sx[GX][v] = ad.hgx; sx[GY][v] = ad.hgy;
       sx[BXX][v] = ad.nbxx; sx[BYY][v] = ad.nbyy;
-      sx[BXY][v] = ad.nbxy; sx[BXZ][v] = ad.nbxz; sx[BYZ][v] = ad.nbyz;
+      sx[BXY][v] = ad.dbxy; sx[BXZ][v] = ad.dbxz; sx[BYZ][v] = ad.dbyz;
       return f;
     };
     // Interior and border voxels are dealt out from one index space, so the
     // per-thread counts differ by at most one (the border goes to the threads
     // whose interior share is shorter).
     T own_ub[NO], own_gz[NO], own_bxx[NO], own_byy[NO], own_bzz[NO], own_u[NO];
+    T fpl = T(0);                              // this thread's energy of plane p (one FP64 add per plane)
 #pragma unroll
     for (int j = 0; j < NW; ++j) {
       const int item = tid + j * NT;
@@ -415,21 +431,25 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
           own_bxx[j] = ad.nbxx;
           own_byy[j] = ad.nbyy;
           own_bzz[j] = ad.nbzz;
-          if (out_plane && x0 + ix < a.nx && y0 + iy < a.ny) acc_f += double(f);
+          if (out_plane && x0 + ix < a.nx && y0 + iy < a.ny) fpl += f;
         }
       }
     }
+    acc_f += double(fpl);
     __syncthreads();
 
     // ---- transposed stencils on the interior ----
-    // The b adjoints are held negated (nb = -df/db), which flips their signs here.
+    // The b adjoints are held negated (nb = -df/db), which flips their signs
+    // here; GX, GY hold half the a_x, a_y derivatives and BXY, BXZ, BYZ twice
+    // the (negated) b_ab ones, hence the factors 2 and 1/2.
+    T mpl = T(0);                              // this thread's sum of the field written for plane p - 1
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
       const int w = tid + j * NT;
       if (w < TX * TY) {
         const int ix = w % TX, iy = w / TX;
         const int v = (iy + 1) * RX + ix + 1;
-        const T d = (sx[BXZ][v + 1] - sx[BXZ][v - 1]) + (sx[BYZ][v + RX] - sx[BYZ][v - RX]);
+        const T d = T(0.5) * ((sx[BXZ][v + 1] - sx[BXZ][v - 1]) + (sx[BYZ][v + RX] - sx[BYZ][v - RX]));
         const T bzz = own_bzz[j], gz = own_gz[j];
         const T upn = bzz + gz + d;    // minus what plane p adds to output plane p-1
         const T lo = gz + d - bzz;     // what plane p adds to output plane p+1
@@ -442,7 +462,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
             if (MODE == kStepGD) {
               const T un = uc - a.tau * g;
               dstb[idx] = un;
-              acc_m += double(un);
+              mpl += un;
             } else if (MODE == kStepAdam) {
               const T mo = a.beta1 * m1c[j] + (T(1) - a.beta1) * g;
               const T vo = a.beta2 * m2c[j] + (T(1) - a.beta2) * g * g;
@@ -450,23 +470,25 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
               a.m2[inst_off + idx] = vo;
               const T un = uc - a.tau * (mo * bc1) * rcp_t(sqrt_t(vo * bc2) + a.adam_eps);
               dstb[idx] = un;
-              acc_m += double(un);
+              mpl += un;
             } else {
               dstb[idx] = g;
-              acc_m += double(uc);
+              mpl += uc;
             }
           }
         }
         const T cin = (own_ub[j] + T(2) * ((bzz + own_bxx[j]) + own_byy[j]))
-                      - ((sx[GX][v + 1] - sx[GX][v - 1]) + (sx[GY][v + RX] - sx[GY][v - RX]))
+                      - T(2) * ((sx[GX][v + 1] - sx[GX][v - 1]) + (sx[GY][v + RX] - sx[GY][v - RX]))
                       - ((sx[BXX][v + 1] + sx[BXX][v - 1]) + (sx[BYY][v + RX] + sx[BYY][v - RX]))
-                      - ((sx[BXY][v + RX + 1] - sx[BXY][v - RX + 1]) - (sx[BXY][v + RX - 1] - sx[BXY][v - RX - 1]));
+                      - T(0.5) * ((sx[BXY][v + RX + 1] - sx[BXY][v - RX + 1]) -
+                                  (sx[BXY][v + RX - 1] - sx[BXY][v - RX - 1]));
         l_pp[j] = l_prev[j];
         l_prev[j] = lo;
         c_prev[j] = cin;
         u_prev[j] = own_u[j];
       }
     }
+    acc_m += double(mpl);
     // plane p+2 goes where p-1 was: its last reader has passed the second barrier
     const int t = sm;
     sm = sc;

@@ -108,13 +108,16 @@ struct Forward {
 
 // Adjoint of one voxel: derivatives of f~ with respect to the raw stencil
 // values, which the transposed stencils spread to the neighbours. The b
-// entries are returned negated (nb = -df~/db), which the gather absorbs.
+// entries are returned negated (nb = -df~/db), which the gather absorbs, and
+// the in-plane ones in the scale that needs no multiply here (powers of two,
+// exact; the gather applies them once per output voxel instead).
 template <typename T>
 struct VoxelAdjoint {
   T ub;                 // df~/du(i) through W'
-  T gx, gy, gz;         // df~/da_a
+  T hgx, hgy;           // df~/da_x / 2, df~/da_y / 2
+  T gz;                 // df~/da_z
   T nbxx, nbyy, nbzz;   // -df~/db_aa
-  T nbxy, nbxz, nbyz;   // -df~/db_ab
+  T dbxy, dbxz, dbyz;   // -2 df~/db_ab
 };
 
 // The chain up to X~ in FP64 (see the header comment).
@@ -313,7 +316,7 @@ __device__ __forceinline__ T voxel_density_adjoint_body(const Stencil19<T>& s, R
                                                         VoxelAdjoint<T>& a) {
   const Forward<T> fw = forward_chain<NOS>(s, reload, p, k);
   const T tr = fw.tr;
-  T f, rhob, trb0, bxx, byy, bzz, cq;
+  T f, rhob, trb0, bxx, byy, bzz, cqh;
   const T rs = fw.rs;
   const T rho = fw.R * rs;                         // 2h rho
   const T c1x2 = p.C1 + p.C1;
@@ -325,7 +328,7 @@ __device__ __forceinline__ T voxel_density_adjoint_body(const Stencil19<T>& s, R
     bxx = c1x2 * fw.mxx + trb0;
     byy = c1x2 * fw.myy + trb0;
     bzz = c1x2 * fw.mzz + trb0;
-    cq = p.C1;
+    cqh = T(0.5) * p.C1;
   } else {
     T P, sig;
     softplus_xi(fw.X, p, P, sig);
@@ -346,38 +349,38 @@ __device__ __forceinline__ T voxel_density_adjoint_body(const Stencil19<T>& s, R
     bxx = c1x2 * fw.mxx + trb0 + kap2 * fw.dxx;
     byy = c1x2 * fw.myy + trb0 + kap2 * fw.dyy;
     bzz = c1x2 * fw.mzz + trb0 + kap2 * fw.dzz;
-    cq = p.C1 + kap2;
+    cqh = T(0.5) * p.C1 + kap;
   }
-  // q_ab = 4 df/do_ab = (C1 + 2 kap) o_ab
-  const T qxy = cq * fw.oxy, qxz = cq * fw.oxz, qyz = cq * fw.oyz;
+  // qh_ab = 2 df/do_ab = (C1/2 + kap) o_ab = -2 df/db_ab
+  const T qxy = cqh * fw.oxy, qxz = cqh * fw.oxz, qyz = cqh * fw.oyz;
   // m_aa = sw a_a^2 - b_aa,  o_ab = 4 sw a_a a_b - b_ab
   a.nbxx = bxx;
   a.nbyy = byy;
   a.nbzz = bzz;
-  a.nbxy = T(0.25) * qxy;
-  a.nbxz = T(0.25) * qxz;
-  a.nbyz = T(0.25) * qyz;
+  a.dbxy = qxy;
+  a.dbxz = qxz;
+  a.dbyz = qyz;
 
   const T ax = fw.ax, ay = fw.ay, az = fw.az, sw = fw.sw;
   const T swb = bxx * (ax * ax) + byy * (ay * ay) + bzz * (az * az) +
-                (qxy * (ax * ay) + qxz * (ax * az) + qyz * (ay * az));      // df/dsw
+                T(2) * (qxy * (ax * ay) + qxz * (ax * az) + qyz * (ay * az));   // df/dsw
   // sw = lam W'(u) / R, R = Q + reg, rho~ = sqrt(R)
   const T Qb = p.C6 + T(0.5) * rhob * rs - swb * sw * fw.Rinv;            // df/dQ
   const T c = fw.c;
   a.ub = swb * (p.lam * (T(3) * c * c - T(1))) * fw.Rinv;
-  const T Qb2 = Qb + Qb;
-  const T bxx2 = bxx + bxx, byy2 = byy + byy, bzz2 = bzz + bzz;
-  a.gx = sw * (bxx2 * ax + qxy * ay + qxz * az) + Qb2 * ax;
-  a.gy = sw * (byy2 * ay + qxy * ax + qyz * az) + Qb2 * ay;
-  a.gz = sw * (bzz2 * az + qxz * ax + qyz * ay) + Qb2 * az;
+  // df/da_a / 2 = sw (b_aa a_a + sum_b qh_ab a_b) + Qb a_a
+  a.hgx = sw * (bxx * ax + qxy * ay + qxz * az) + Qb * ax;
+  a.hgy = sw * (byy * ay + qxy * ax + qyz * az) + Qb * ay;
+  T hgz = sw * (bzz * az + qxz * ax + qyz * ay) + Qb * az;
   if (p.Co != T(0)) {                              // orientation term and its derivative in a
     const T ta = p.thx * ax + p.thy * ay + p.thz * az;
-    f += p.Co * ta * ta;
-    const T t2 = T(2) * p.Co * ta;
-    a.gx += t2 * p.thx;
-    a.gy += t2 * p.thy;
-    a.gz += t2 * p.thz;
+    const T tco = p.Co * ta;
+    f += tco * ta;
+    a.hgx += tco * p.thx;
+    a.hgy += tco * p.thy;
+    hgz += tco * p.thz;
   }
+  a.gz = hgz + hgz;
   return f;
 }
 

@@ -34,11 +34,14 @@ constexpr int kGraphPairs = 8;  // descent steps per captured graph: 2 x kGraphP
 template <typename T>
 using SweepFn = void (*)(fe::SweepArgs<T>);
 
+// The sweep kernels of one launch shape: [fe::SweepBody] for the gradient, the
+// plain step and the Adam step (the single-body ones only for the leading
+// shapes; nullptr where not built).
 template <typename T>
 struct Kernels {
-  SweepFn<T> grad = nullptr;
-  SweepFn<T> step = nullptr;
-  SweepFn<T> adam = nullptr;
+  SweepFn<T> grad[3] = {nullptr, nullptr, nullptr};
+  SweepFn<T> step[3] = {nullptr, nullptr, nullptr};
+  SweepFn<T> adam[3] = {nullptr, nullptr, nullptr};
   SweepFn<T> energy = nullptr;
 };
 
@@ -54,14 +57,30 @@ struct Variant {
   bool lead = false;   // a default candidate: chosen by the ring work its tiles cover a grid with
 };
 
-template <typename T, int TX, int TY, int NT, bool SP = false>
+template <typename T, int TX, int TY, int NT, bool SP = false, bool BODIES = false>
 Kernels<T> make_kernels() {
   Kernels<T> k;
-  k.grad = fe::grad_sweep<T, TX, TY, NT, fe::kGrad, SP>;
-  k.step = fe::grad_sweep<T, TX, TY, NT, fe::kStepGD, SP>;
-  k.adam = fe::grad_sweep<T, TX, TY, NT, fe::kStepAdam, SP>;
+  k.grad[fe::kBodyAny] = fe::grad_sweep<T, TX, TY, NT, fe::kGrad, SP>;
+  k.step[fe::kBodyAny] = fe::grad_sweep<T, TX, TY, NT, fe::kStepGD, SP>;
+  k.adam[fe::kBodyAny] = fe::grad_sweep<T, TX, TY, NT, fe::kStepAdam, SP>;
+  if constexpr (BODIES && !SP) {
+    k.grad[fe::kBodyNoS] = fe::grad_sweep<T, TX, TY, NT, fe::kGrad, false, false, fe::kBodyNoS>;
+    k.step[fe::kBodyNoS] = fe::grad_sweep<T, TX, TY, NT, fe::kStepGD, false, false, fe::kBodyNoS>;
+    k.adam[fe::kBodyNoS] = fe::grad_sweep<T, TX, TY, NT, fe::kStepAdam, false, false, fe::kBodyNoS>;
+    k.grad[fe::kBodyFull] = fe::grad_sweep<T, TX, TY, NT, fe::kGrad, false, false, fe::kBodyFull>;
+    k.step[fe::kBodyFull] = fe::grad_sweep<T, TX, TY, NT, fe::kStepGD, false, false, fe::kBodyFull>;
+    k.adam[fe::kBodyFull] = fe::grad_sweep<T, TX, TY, NT, fe::kStepAdam, false, false, fe::kBodyFull>;
+  }
   k.energy = fe::energy_sweep<T, TX, TY, NT, SP>;
   return k;
+}
+
+// The kernel of `kind` (a fe::SweepMode) for a batch whose instances all take
+// `body`, or the per-instance one where no single-body kernel is built.
+template <typename T>
+SweepFn<T> sweep_kernel(const Kernels<T>& k, int kind, int body) {
+  const SweepFn<T>* f = kind == fe::kGrad ? k.grad : kind == fe::kStepGD ? k.step : k.adam;
+  return f[body] ? f[body] : f[fe::kBodyAny];
 }
 
 // Static LDS of grad_sweep is (4 (TX+4)(TY+4) + 7 (TX+2)(TY+2)) sizeof(T) plus
@@ -89,9 +108,9 @@ const std::vector<Variant>& variants() {
     // 50 x 20 planes of 100, 200 or 600 (where 32 x 32 computes 1.85x the
     // plane at 100^2). 256^3 step, symmetric p: 94 us against 95 (64 x 16)
     // and 97 (64 x 32 / 1024).
-    add32(32, 32, 512, make_kernels<float, 32, 32, 512>());
+    add32(32, 32, 512, make_kernels<float, 32, 32, 512, false, true>());
     r.back().lead = true;
-    add32(50, 20, 512, make_kernels<float, 50, 20, 512>(), {},
+    add32(50, 20, 512, make_kernels<float, 50, 20, 512, false, true>(), {},
           fe::grad_sweep<float, 50, 20, 512, fe::kGrad, false, true>);
     r.back().lead = true;
     add32(64, 16, 512, make_kernels<float, 64, 16, 512>(), make_kernels<float, 64, 16, 512, true>(),
@@ -107,7 +126,7 @@ const std::vector<Variant>& variants() {
     add32(16, 8, 128, make_kernels<float, 16, 8, 128>());
     add32(8, 8, 64, make_kernels<float, 8, 8, 64>(), make_kernels<float, 8, 8, 64, true>(),
           fe::grad_sweep<float, 8, 8, 64, fe::kGrad, false, true>);
-    add64(32, 16, 512, make_kernels<double, 32, 16, 512>(), make_kernels<double, 32, 16, 512, true>(),
+    add64(32, 16, 512, make_kernels<double, 32, 16, 512, false, true>(), make_kernels<double, 32, 16, 512, true>(),
           fe::grad_sweep<double, 32, 16, 512, fe::kGrad, false, true>);
     r.back().lead = true;
     add64(32, 8, 256, make_kernels<double, 32, 8, 256>());
@@ -165,10 +184,11 @@ struct GraphKey {
   int variant;
   int lz;
   int fields;                   // bit 0: coefficient field in use, bit 1: mass field in use
+  int body;                     // the per-voxel body the sweeps hold (fe::SweepBody)
   bool operator<(const GraphKey& o) const {
-    return std::tie(u, mode, tau, beta1, beta2, adam_eps, sigma, pairs, variant, lz, fields) <
+    return std::tie(u, mode, tau, beta1, beta2, adam_eps, sigma, pairs, variant, lz, fields, body) <
            std::tie(o.u, o.mode, o.tau, o.beta1, o.beta2, o.adam_eps, o.sigma, o.pairs, o.variant, o.lz,
-                    o.fields);
+                    o.fields, o.body);
   }
 };
 constexpr int kFlowMode = 100;
@@ -205,6 +225,7 @@ struct fe_ctx {
   size_t max_blocks = 0;              // per instance, over all variants and z chunks
   int variant = -1;
   int lz = 0;                         // 0 = automatic
+  int body = 0;                       // fe::SweepBody every instance takes (kBodyAny: they differ)
   int num_cu = 256;                   // compute units of the device
   std::map<GraphKey, hipGraphExec_t> graphs;
 };
@@ -282,14 +303,25 @@ fe::GridConsts<T> grid_consts(double h) {
   return k;
 }
 
+// The body every instance of `p` takes (fe::has_s_terms on the typed constants,
+// as the kernels decide it), or kBodyAny if they differ.
+template <typename T>
+int batch_body(const fe::InstParams<T>* p, int batch) {
+  int nos = 0;
+  for (int b = 0; b < batch; ++b) nos += (p[b].C3 == T(0) && p[b].C5 == T(0)) ? 1 : 0;
+  return nos == batch ? fe::kBodyNoS : nos == 0 ? fe::kBodyFull : fe::kBodyAny;
+}
+
 int upload_params(fe_ctx* c) {
   if (c->grid.dtype == FE_F32) {
     std::vector<fe::InstParams<float>> p;
     fill_params(c, p);
+    c->body = batch_body(p.data(), c->grid.batch);
     FE_HIP(hipMemcpyAsync(c->d_prm, p.data(), p.size() * sizeof(p[0]), hipMemcpyHostToDevice, c->stream));
   } else {
     std::vector<fe::InstParams<double>> p;
     fill_params(c, p);
+    c->body = batch_body(p.data(), c->grid.batch);
     FE_HIP(hipMemcpyAsync(c->d_prm, p.data(), p.size() * sizeof(p[0]), hipMemcpyHostToDevice, c->stream));
   }
   // the host vectors die here: make sure the copies have consumed them
@@ -321,7 +353,7 @@ struct Geometry {
 // Blocks of the step sweep of `variant` that one compute unit holds at once.
 int block_slots(int dtype, int variant) {
   const Variant& v = variants()[variant];
-  const void* fn = dtype == FE_F32 ? (const void*)v.k32.step : (const void*)v.k64.step;
+  const void* fn = dtype == FE_F32 ? (const void*)v.k32.step[fe::kBodyAny] : (const void*)v.k64.step[fe::kBodyAny];
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, v.nt, 0) != hipSuccess || n < 1) n = 1;
   return n;
@@ -378,7 +410,7 @@ Geometry geometry(const fe_ctx* c, int variant, int lz_req) { return geometry_of
 
 bool has_sp(int v, int dtype) {
   const Variant& x = variants()[v];
-  return dtype == FE_F32 ? x.k32sp.grad != nullptr : x.k64sp.grad != nullptr;
+  return dtype == FE_F32 ? x.k32sp.grad[fe::kBodyAny] != nullptr : x.k64sp.grad[fe::kBodyAny] != nullptr;
 }
 
 bool has_box(int v, int dtype) {
@@ -477,9 +509,7 @@ int launch_sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst,
   a.batch = c->grid.batch;
   const dim3 grid((unsigned)(geo.per_inst * c->grid.batch));
   const dim3 block((unsigned)v.nt);
-  SweepFn<T> fn = kind < 0 ? k.energy
-                 : kind == fe::kGrad ? k.grad
-                 : kind == fe::kStepGD ? k.step : k.adam;
+  SweepFn<T> fn = kind < 0 ? k.energy : sweep_kernel<T>(k, kind, c->use_cfield ? (int)fe::kBodyAny : c->body);
   if (c->use_box) {
     if (kind != fe::kGrad || c->use_cfield) return set_error(FE_EINVAL, "internal: box sweeps are gradient-only");
     fn = box_kernel_of<T>(v);
@@ -679,8 +709,8 @@ int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int 
   if (gpairs > 0) {
     if ((rc = tick(c->stream, pending))) return rc;
     pending = 0;
-    GraphKey key{u,      rule.mode,           rule.tau, rule.beta1,     rule.beta2, rule.adam_eps, 0.0,
-                 gpairs, sweep_variant(c), c->lz,    fields_in_use(c)};
+    GraphKey key{u,      rule.mode,           rule.tau, rule.beta1,       rule.beta2, rule.adam_eps, 0.0,
+                 gpairs, sweep_variant(c), c->lz,    fields_in_use(c), c->body};
     auto it = c->graphs.find(key);
     hipGraphExec_t exec = nullptr;
     if (it == c->graphs.end()) {

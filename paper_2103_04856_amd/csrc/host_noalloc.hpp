@@ -100,7 +100,8 @@ int noalloc_sweep(const fe_grid& grid, const double* eps, const double* a, const
   sa.lz = geo.lz;
   sa.batch = grid.batch;
   if (g) {
-    hipLaunchKernelGGL(k.grad, dim3((unsigned)nblocks), dim3((unsigned)v.nt), 0, stream, sa);
+    hipLaunchKernelGGL(sweep_kernel<T>(k, fe::kGrad, batch_body(pack.p, grid.batch)), dim3((unsigned)nblocks),
+                       dim3((unsigned)v.nt), 0, stream, sa);
     FE_HIP(hipGetLastError());
   } else {
     const int rc = launch_energy_cols<T>(grid, geo, u, prm, partials, stream);

@@ -8,7 +8,8 @@ import torch
 from oracle import fe_oracle as fo
 from paper_2103_04856_amd import fe, inputs
 
-from gpu_helpers import ALL_TERMS, ASYM_C3, TOL, WILLMORE_QUARTER, log, oracle_input, rel_l2, to_dev, voxel_errors
+from gpu_helpers import (ALL_TERMS, ASYM_C3, HELFRICH_SC, TOL, WILLMORE_QUARTER, log, oracle_input, rel_l2, to_dev,
+                         voxel_errors)
 
 pytestmark = pytest.mark.gpu
 
@@ -333,3 +334,23 @@ def test_autograd_function_against_finite_differences_8cubed(a):
     assert err <= 1e-6
     assert abs(gv - dv) <= 1e-7 * abs(dv)
     assert rel_l2(g, go) <= 1e-9
+
+
+def test_adam_in_a_mixed_batch_equals_each_instance_alone():
+    """A batch that mixes a p symmetric in k1, k2 (no S~ terms) with an asymmetric one runs
+    the sweep that picks the body per instance; alone, each runs a single-body sweep. Both
+    take the same arithmetic: three Adam steps give the same bits (FP32 and FP64)."""
+    n = 20
+    h = 1.0 / n
+    coeffs = [HELFRICH_SC, ASYM_C3]
+    U = np.stack([inputs.uniform_noise(n, 310 + b) for b in range(2)])
+    for dtype in (torch.float32, torch.float64):
+        ctx = fe.FeContext(U.shape, h, 2 * h, coeffs, dtype=dtype)
+        ub = to_dev(U, dtype)
+        ctx.step_adam(ub, [0.0, -0.2], 3)
+        for b in range(2):
+            c1 = fe.FeContext((1, n, n, n), h, 2 * h, coeffs[b], dtype=dtype)
+            c1.set_launch(*ctx.get_launch())
+            u1 = to_dev(U[b:b + 1], dtype)
+            c1.step_adam(u1, [[0.0, -0.2][b]], 3)
+            assert torch.equal(u1[0], ub[b]), (dtype, b)
