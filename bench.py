@@ -7,16 +7,25 @@ hot path). K steps run as one fe_step call, i.e. as replays of a captured HIP
 graph, with the field resident in HBM. Before the K timed steps come the W
 warmup steps and then CLOCK_SETTLE_S seconds more of the same steps, untimed,
 in which the GPU reaches its steady clocks (it raises them over the first tens
-of milliseconds of load); every other timed loop settles the same way.
+of milliseconds of load); every other timed loop settles the same way. Each
+workload is also timed as repeated samples (calls of 1 + 2 x 16 graph-replayed
+steps, or repeated launches), reported as median and min-max.
 
 Workload (value): a single 256^3 periodic grid, FP32, u0 ~ U(-1,1) (seed 1005),
 eps = 1.5h, p = (k1 + k2 - 2)^2 + 0.5 k1 k2, target mean 0, tau = 1e-3.
-Also reported: the batched form (16 independent 128^3 textures with their own
-coefficients and target means, eps = 2h, mass-projected Adam with lr 1e-3,
-one launch per step)
-against 16 sequential single-instance calls, the energy+gradient sweep
-without the update, and Algorithm 1 (the H^-1 flow on a vector field with
-the Gaussian blur and Adam) at the paper's 100^3 simulation size.
+Also reported, per workload of the method's five configurations:
+  * 16 independent 128^3 textures with their own coefficients and target
+    means, eps = 2h, mass-projected Adam with lr 1e-3, one launch per step,
+    with its own roofline, against 16 sequential single-instance calls;
+  * the energy+gradient sweep without the update and the energy-only sweep
+    (the autograd forward), each with its roofline;
+  * 32^3 FP64 (200 steps), 64^3 FP32 and FP64 (noisy ball), 128^3 FP32
+    (asymmetric p: Adam steps and autograd-driven steps);
+  * Algorithm 1 (the H^-1 flow on a vector field with the Gaussian blur and
+    Adam) at the paper's 100^3 simulation size, the coefficient-field
+    workloads and Algorithm 2 (Willmore flow, Clifford torus);
+  * the FP64 NumPy oracle on the host: one core on the 256^3 field, and all
+    cores (a process pool over the 16 instances) on the batched workload.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu] [--gpus 1]
 """
@@ -57,9 +66,25 @@ FLOPS_S_TERMS = 45
 def flops_per_voxel(a):
     """Algorithmic operations per voxel update for p coefficients a = (a20, a11, a02, a10, a01, a00)."""
     return FLOPS_PER_VOXEL - (FLOPS_S_TERMS if a[0] == a[2] and a[3] == a[4] else 0)
-# Algorithmic HBM bytes per voxel and step, FP32: read u, write the new u.
+# The forward alone (the energy-only sweep): stencils, M with its invariants
+# and the density, 97 operations, of which 18 are the S~ terms.
+FLOPS_FORWARD, FLOPS_FORWARD_S_TERMS = 97, 18
+# Adam on one voxel: both moments (5), the bias-corrected update (7), replacing
+# the plain step's 3.
+FLOPS_ADAM_EXTRA = 12 - 3
+
+
+def forward_flops_per_voxel(a):
+    return FLOPS_FORWARD - (FLOPS_FORWARD_S_TERMS if a[0] == a[2] and a[3] == a[4] else 0)
+
+
+# Algorithmic HBM bytes per voxel, FP32: a step reads u and writes the new u;
+# energy + gradient reads u and writes g; the energy alone reads u; an Adam
+# step also reads and writes both moments.
 BYTES_PER_VOXEL_STEP = 8
-BYTES_PER_VOXEL_GRAD = 8       # read u, write g
+BYTES_PER_VOXEL_GRAD = 8
+BYTES_PER_VOXEL_ENERGY = 4
+BYTES_PER_VOXEL_ADAM = 24
 # The batched workload states no step rule. Its coefficients have a20 != a02,
 # where the plain gradient step diverges near umbilic voxels at any useful step
 # size, so it runs the paper's optimiser: mass-projected Adam, lr 1e-3.
@@ -115,6 +140,32 @@ def settle(fn, min_s=CLOCK_SETTLE_S):
         torch.cuda.synchronize()
 
 
+def samples(fn, reps):
+    """fn() timed reps times, each between its own pair of HIP events on the current
+    stream; returns the list of ms."""
+    s = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record(s)
+        fn()
+        e1.record(s)
+    torch.cuda.synchronize()
+    return [e0.elapsed_time(e1) for e0, e1 in ev]
+
+
+def spread(ms, per=1.0):
+    """Median and min-max of timed samples, each covering `per` units, in us per unit."""
+    us = sorted(1e3 * m / per for m in ms)
+    return {"median_us": us[len(us) // 2] if len(us) % 2 else 0.5 * (us[len(us) // 2 - 1] + us[len(us) // 2]),
+            "min_us": us[0], "max_us": us[-1], "samples": len(us)}
+
+
+# A sample of a step loop: the first step launched directly, then two replays of
+# the captured 16-step graph.
+SAMPLE_STEPS = 33
+
+
 def time_region(fn, reps=1):
     """Run fn() reps times between HIP events on the current stream; returns ms per rep."""
     s = torch.cuda.current_stream()
@@ -134,22 +185,25 @@ def bench_single(n, steps, warmup, tune):
     u = torch.from_numpy(inputs.uniform_noise(n, 1005)).float().cuda()
     ctx = fe.FeContext(u.shape, h, 1.5 * h, HELFRICH_SC, dtype=torch.float32)
     if tune:
-        g = torch.empty_like(u)
-        v, z, us = ctx.autotune(u, g, iters=5)
+        v, z, us, _ = ctx.autotune(u, kind="step", iters=5)
         log(f"autotune 256: variant {v} {fe.variants()[v][:3]} z_chunk {z}: {us:.1f} us")
-        del g
     mass = [float(u.double().mean().item())]
     # warm-up also captures the step graph that the timed call replays
-    ctx.step(u, mass, 1e-3, max(warmup, 16))
-    settle(lambda: ctx.step(u, mass, 1e-3, 16))
+    ctx.step(u, mass, 1e-3, max(warmup, 17))
+    settle(lambda: ctx.step(u, mass, 1e-3, SAMPLE_STEPS))
     ms = time_region(lambda: ctx.step(u, mass, 1e-3, steps))
-    # the energy+gradient sweep alone (no update, no projection)
+    step_spread = spread(samples(lambda: ctx.step(u, mass, 1e-3, SAMPLE_STEPS), 10), SAMPLE_STEPS)
+    out = {"ms_step": ms / steps, "step_spread": step_spread}
+    # the energy+gradient sweep alone (no update, no projection), and the energy alone
     g = torch.empty_like(u)
     E = torch.empty(1, dtype=torch.float64, device=u.device)
-    for _ in range(3):
-        ctx.energy_grad_async(u, g, E)
-    settle(lambda: ctx.energy_grad_async(u, g, E))
-    ms_grad = time_region(lambda: ctx.energy_grad_async(u, g, E), reps=steps)
+    for with_grad, key in ((True, "grad"), (False, "energy")):
+        def one():
+            ctx.energy_grad_async(u, g if with_grad else None, E, with_grad=with_grad)
+        for _ in range(3):
+            one()
+        settle(one)
+        out[key] = spread(samples(one, max(steps, 30)))
     # the diagnostics sweep: curvature fields, a 64 x 64 histogram and the summary
     curv = torch.empty((1, 4) + u.shape, dtype=u.dtype, device=u.device)
     hist = torch.empty((1, 64, 64), dtype=torch.float64, device=u.device)
@@ -159,24 +213,35 @@ def bench_single(n, steps, warmup, tune):
 
     diag()
     settle(diag)
-    ms_diag = time_region(diag, reps=max(steps // 10, 5))
+    out["diag"] = spread(samples(diag, 10))
     del curv, hist
-    return ctx, u, ms / steps, ms_grad, ms_diag
+    return ctx, u, out
 
 
-def bench_batched(n, B, steps, warmup, tune):
+def bench_batched(n, B, warmup, tune):
+    """The batched workload as calls of SAMPLE_STEPS mass-projected Adam steps (whole graph
+    replays); the same 16 textures as 16 single-instance contexts called one after the other."""
     h = 1.0 / n
     coeffs, means = inputs.random_instance_table(B, 4999)
     U = torch.stack([torch.from_numpy(inputs.uniform_noise(n, 4000 + b)).float() for b in range(B)]).cuda()
     ctx = fe.FeContext(U.shape, h, 2 * h, coeffs, dtype=torch.float32)
     if tune:
-        g = torch.empty_like(U)
-        v, z, us = ctx.autotune(U, g, iters=5)
+        v, z, us, _ = ctx.autotune(U, kind="adam", iters=5)
         log(f"autotune batched: variant {v} {fe.variants()[v][:3]} z_chunk {z}: {us:.1f} us")
-        del g
-    ctx.step_adam(U, list(means), max(warmup, 16), lr=ADAM_LR)
-    settle(lambda: ctx.step_adam(U, list(means), 16, lr=ADAM_LR))
-    ms_b = time_region(lambda: ctx.step_adam(U, list(means), steps, lr=ADAM_LR)) / steps
+    ctx.step_adam(U, list(means), max(warmup, 17), lr=ADAM_LR)
+    settle(lambda: ctx.step_adam(U, list(means), SAMPLE_STEPS, lr=ADAM_LR))
+    b_spread = spread(samples(lambda: ctx.step_adam(U, list(means), SAMPLE_STEPS, lr=ADAM_LR), 6), SAMPLE_STEPS)
+    # the energy+gradient sweep of the batch alone
+    g = torch.empty_like(U)
+    E = torch.empty(B, dtype=torch.float64, device=U.device)
+
+    def sweep():
+        ctx.energy_grad_async(U, g, E)
+
+    sweep()
+    settle(sweep)
+    grad_spread = spread(samples(sweep, 20))
+    del g
     # the same 16 textures, one single-instance context each, called one after the other,
     # each with the launch shape that is best for a single 128^3 grid
     singles = []
@@ -184,25 +249,91 @@ def bench_batched(n, B, steps, warmup, tune):
     for b in range(B):
         c1 = fe.FeContext((1, n, n, n), h, 2 * h, coeffs[b], dtype=torch.float32)
         if single_launch is None and tune:
-            g1 = torch.empty_like(U[0:1])
-            v1, z1, us1 = c1.autotune(U[0:1], g1, iters=5)
+            v1, z1, us1, _ = c1.autotune(U[0:1].contiguous(), kind="adam", iters=5)
             log(f"autotune single 128: variant {v1} {fe.variants()[v1][:3]} z_chunk {z1}: {us1:.1f} us")
             single_launch = (v1, z1)
-            del g1
         if single_launch is not None:
             c1.set_launch(*single_launch)
         singles.append(c1)
     views = [U[b:b + 1] for b in range(B)]
     for b in range(B):
-        singles[b].step_adam(views[b], [means[b]], 16, lr=ADAM_LR)
+        singles[b].step_adam(views[b], [means[b]], 17, lr=ADAM_LR)
 
     def run_singles():
         for b in range(B):
-            singles[b].step_adam(views[b], [means[b]], steps, lr=ADAM_LR)
+            singles[b].step_adam(views[b], [means[b]], SAMPLE_STEPS, lr=ADAM_LR)
 
-    settle(lambda: singles[0].step_adam(views[0], [means[0]], 16, lr=ADAM_LR))
-    ms_s = time_region(run_singles) / steps
-    return ms_b, ms_s
+    settle(lambda: singles[0].step_adam(views[0], [means[0]], SAMPLE_STEPS, lr=ADAM_LR))
+    s_spread = spread(samples(run_singles, 3), SAMPLE_STEPS)
+    return b_spread, grad_spread, s_spread, ctx.get_launch()
+
+
+def bench_configs(args):
+    """The method's smaller configurations: 32^3 FP64 (energy+gradient; 200 steps), 64^3
+    noisy ball FP32 and FP64 (energy+gradient), 128^3 FP32 asymmetric p (energy+gradient,
+    Adam steps, autograd-driven steps). Rates from timed samples (median)."""
+    out = {}
+    # 32^3 FP64, Willmore p, u0 ~ U(-1,1) seed 1001, eps = 2h, mean 0, tau = 1e-3
+    n = 32
+    h = 1.0 / n
+    u = torch.from_numpy(inputs.uniform_noise(n, 1001)).double().cuda()
+    ctx = fe.FeContext(u.shape, h, 2 * h, (0.25, 0.5, 0.25, 0, 0, 0), dtype=torch.float64)
+    g = torch.empty_like(u)
+    E = torch.empty(1, dtype=torch.float64, device=u.device)
+    settle(lambda: ctx.energy_grad_async(u, g, E), 0.05)
+    sw = spread(samples(lambda: ctx.energy_grad_async(u, g, E), 50))
+    u1 = u.clone()
+    ctx.step(u1, [0.0], 1e-3, 17)
+    u1 = u.clone()
+    t200 = samples(lambda: ctx.step(u1, [0.0], 1e-3, 200), 1)[0]
+    out["32cubed_fp64"] = {"energy_grad": sw, "voxels_per_s": n ** 3 / (sw["median_us"] * 1e-6),
+                           "steps_200_ms": t200, "steps_per_s": 200 / (t200 * 1e-3),
+                           "config": "32^3 FP64, u0~U(-1,1) seed 1001, eps=2h, p=(k1+k2)^2/4, mean 0, tau=1e-3"}
+    # 64^3 noisy ball, eps = 1.5h, Willmore p, FP32 and FP64
+    n = 64
+    h = 1.0 / n
+    u0 = inputs.noisy_sphere(n, 0.3, 1.5 * h, 0.01, 1002)
+    for dt, key in ((torch.float32, "64cubed_fp32"), (torch.float64, "64cubed_fp64")):
+        u = torch.from_numpy(u0).to(dt).cuda()
+        ctx = fe.FeContext(u.shape, h, 1.5 * h, (0.25, 0.5, 0.25, 0, 0, 0), dtype=dt)
+        g = torch.empty_like(u)
+        settle(lambda: ctx.energy_grad_async(u, g, E), 0.05)
+        sw = spread(samples(lambda: ctx.energy_grad_async(u, g, E), 50))
+        out[key] = {"energy_grad": sw, "voxels_per_s": n ** 3 / (sw["median_us"] * 1e-6),
+                    "config": "64^3 tanh ball R=0.3 + N(0,0.01^2) seed 1002, eps=1.5h, p=(k1+k2)^2/4"}
+    # 128^3 FP32, asymmetric p, mean -0.3
+    n = 128
+    h = 1.0 / n
+    a3 = (1.0, 0.0, 0.2, -4.0, -4.0, 0.0)
+    u = torch.from_numpy(inputs.uniform_noise(n, 1003)).float().cuda()
+    ctx = fe.FeContext(u.shape, h, 2 * h, a3, dtype=torch.float32)
+    g = torch.empty_like(u)
+    settle(lambda: ctx.energy_grad_async(u, g, E), 0.05)
+    sw = spread(samples(lambda: ctx.energy_grad_async(u, g, E), 50))
+    u1 = u.clone()
+    ctx.step_adam(u1, [-0.3], 17)
+    settle(lambda: ctx.step_adam(u1, [-0.3], SAMPLE_STEPS), 0.05)
+    sa = spread(samples(lambda: ctx.step_adam(u1, [-0.3], SAMPLE_STEPS), 5), SAMPLE_STEPS)
+    # autograd-driven steps: E = FeEnergy(u) (energy-only sweep), backward (the adjoint
+    # sweep), then the step and the mass projection in torch
+    x = u.clone()
+
+    def autograd_step():
+        nonlocal x
+        y = x.detach().requires_grad_(True)
+        fe.feps(y, ctx).sum().backward()
+        with torch.no_grad():
+            v = y - 1e-3 * y.grad
+            x = v + (-0.3 - v.mean())
+
+    for _ in range(5):
+        autograd_step()
+    st = spread(samples(autograd_step, 30))
+    out["128cubed_fp32"] = {"energy_grad": sw, "voxels_per_s": n ** 3 / (sw["median_us"] * 1e-6),
+                            "adam_step": sa, "adam_steps_per_s": 1e6 / sa["median_us"],
+                            "autograd_step": st, "autograd_steps_per_s": 1e6 / st["median_us"],
+                            "config": "128^3 FP32, u0~U(-1,1) seed 1003, eps=2h, a=(1,0,0.2,-4,-4,0), mean -0.3"}
+    return out
 
 
 # Algorithm 1 at the paper's simulation size (Sec. 5): 100^3 pixels with dx = 0.01,
@@ -308,6 +439,24 @@ def bench_clifford_torus(steps=24):
     return dt, E / sigma / (8 * math.pi ** 2), ratio, steps * 20
 
 
+def host_cpu():
+    """(CPU model, logical CPUs visible to this process)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        ncpu = os.cpu_count() or 1
+    return model, ncpu
+
+
 def cpu_baseline(n=256, budget_s=10.0, max_evals=3):
     """The FP64 NumPy oracle on a bounded sample of the same workload: whole 256^3
     energy + gradient evaluations, repeated until about budget_s seconds (at most
@@ -320,8 +469,38 @@ def cpu_baseline(n=256, budget_s=10.0, max_evals=3):
         fo.energy_grad(u, h, 1.5 * h, HELFRICH_SC)
         evals += 1
     dt = time.perf_counter() - t0
+    model, ncpu = host_cpu()
     return dict(value=evals * u.size / dt, unit="voxel energy+gradient evals/s", cores=1, kind="oracle",
-                sample=f"{evals} FP64 energy+gradient evaluation(s) of the full 256^3 field ({dt:.1f} s)")
+                sample=f"{evals} FP64 energy+gradient evaluation(s) of the full 256^3 field ({dt:.1f} s)",
+                cpu_model=model, nproc=ncpu)
+
+
+def _oracle_instance(b):
+    """One instance of the batched workload through the oracle (a pool worker)."""
+    from oracle import fe_oracle as fo
+    n = 128
+    h = 1.0 / n
+    coeffs, _ = inputs.random_instance_table(16, 4999)
+    u = inputs.uniform_noise(n, 4000 + b)
+    fo.energy_grad(u, h, 2 * h, coeffs[b])
+    return u.size
+
+
+def cpu_baseline_batched(B=16):
+    """The oracle on the batched workload with every host core: one FP64 energy+gradient
+    evaluation of each of the 16 instances, a process pool of min(16, CPUs) workers."""
+    import multiprocessing as mp
+    model, ncpu = host_cpu()
+    workers = max(1, min(B, ncpu))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_instance, range(min(workers, B)))     # start the workers, import numpy
+        t0 = time.perf_counter()
+        vox = sum(pool.map(_oracle_instance, range(B)))
+        dt = time.perf_counter() - t0
+    return dict(value=vox / dt, unit="voxel energy+gradient evals/s", cores=workers, kind="oracle",
+                sample=f"one FP64 energy+gradient evaluation of each of the 16 instances of 128^3 ({dt:.1f} s)",
+                cpu_model=model, nproc=ncpu)
 
 
 def other_workloads(args, extra, n, vox):
@@ -376,6 +555,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--main-only", action="store_true",
                     help="only the 256^3 workload (step, sweep, diagnostics): for counter runs")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the 256^3 step and the batched workload: for counter runs")
     ap.add_argument("--tune", action="store_true",
                     help="run the launch-shape autotuner first (default: the library's default shape)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -385,6 +566,12 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    # the all-cores oracle baseline starts its worker processes before this process
+    # touches the GPU (a process that has initialised the GPU starts no programs)
+    pool_baseline = None
+    if not args.no_cpu and not args.main_only and not args.batched_only and not args.no_batched:
+        log("CPU oracle baseline (all cores, the 16 x 128^3 batch) ...")
+        pool_baseline = cpu_baseline_batched()
     if not torch.cuda.is_available():
         print("no ROCm device visible", file=sys.stderr)
         sys.exit(1)
@@ -401,43 +588,53 @@ def main():
     n = 256
     vox = n ** 3
     log(f"device {torch.cuda.get_device_name(0)}; 256^3 FP32 step loop ...")
-    ctx, u, ms_step, ms_grad, ms_diag = bench_single(n, args.steps, args.warmup, args.tune)
+    ctx, u, single = bench_single(n, args.steps, args.warmup, args.tune)
+    ms_step = single["ms_step"]
     variant, zc = ctx.get_launch()
-    log(f"  {ms_step * 1e3:.1f} us/step, energy+grad sweep {ms_grad * 1e3:.1f} us, diagnostics {ms_diag * 1e3:.1f} us")
+    log(f"  {ms_step * 1e3:.1f} us/step (samples: median {single['step_spread']['median_us']:.1f}, "
+        f"{single['step_spread']['min_us']:.1f}-{single['step_spread']['max_us']:.1f}), "
+        f"energy+grad sweep {single['grad']['median_us']:.1f} us, energy sweep {single['energy']['median_us']:.1f} us, "
+        f"diagnostics {single['diag']['median_us']:.1f} us")
     value = vox / (ms_step * 1e-3)
 
     extra = {}
     if not args.no_batched and not args.main_only:
         log("16 x 128^3 batched vs 16 single-instance calls ...")
-        ms_b, ms_s = bench_batched(128, 16, max(args.steps // 2, 10), args.warmup, args.tune)
+        b_spread, bg_spread, s_spread, (bvar, bzc) = bench_batched(128, 16, args.warmup, args.tune)
         vb = 16 * 128 ** 3
+        bv = fe.variants()[bvar]
+        bk = f"grad_sweep<float,{bv[0]},{bv[1]},{bv[2]},2,false,false,2>"
+        broof, bother = roofline(FLOPS_PER_VOXEL + FLOPS_ADAM_EXTRA, BYTES_PER_VOXEL_ADAM, vb,
+                                 b_spread["median_us"], bk, measured_traffic(bk, bzc))
+        groof, _ = roofline(FLOPS_PER_VOXEL, BYTES_PER_VOXEL_GRAD, vb, bg_spread["median_us"],
+                            f"grad_sweep<float,{bv[0]},{bv[1]},{bv[2]},0,false,false,2>", None)
         extra["batched_16x128"] = {
-            "value": vb / (ms_b * 1e-3), "ms_per_step": ms_b,
-            "sequential_singles_value": vb / (ms_s * 1e-3), "sequential_singles_ms_per_step": ms_s,
-            "unit": "voxel energy+gradient evals/s", "step_rule": "mass-projected Adam, lr 1e-3"}
-        log(f"  batched {ms_b * 1e3:.1f} us/step, singles {ms_s * 1e3:.1f} us/step")
+            "value": vb / (b_spread["median_us"] * 1e-6), "us_per_step": b_spread,
+            "unit": "voxel energy+gradient evals/s", "step_rule": "mass-projected Adam, lr 1e-3",
+            "launch_variant": list(bv[:3]), "z_chunk": bzc,
+            "roofline": broof, "roofline_other": bother,
+            "energy_grad_sweep": {"value": vb / (bg_spread["median_us"] * 1e-6), "us": bg_spread, "roofline": groof},
+            "sequential_singles_value": vb / (s_spread["median_us"] * 1e-6), "sequential_singles_us_per_step": s_spread,
+            "batched_over_singles": s_spread["median_us"] / b_spread["median_us"],
+            "batched_over_256cubed_per_voxel": (vb / b_spread["median_us"]) / (vox / (ms_step * 1e3))}
+        log(f"  batched {b_spread['median_us']:.1f} us/step ({b_spread['min_us']:.1f}-{b_spread['max_us']:.1f}), "
+            f"its sweep {bg_spread['median_us']:.1f} us, singles {s_spread['median_us']:.1f} us/step")
 
-    if not args.main_only:
+    if not args.main_only and not args.batched_only:
+        log("smaller configurations (32^3 FP64, 64^3 FP32/FP64, 128^3 FP32) ...")
+        extra["configs"] = bench_configs(args)
+        for k, v in extra["configs"].items():
+            log(f"  {k}: energy+grad {v['energy_grad']['median_us']:.1f} us ({v['voxels_per_s']:.3g} voxel/s)")
         other_workloads(args, extra, n, vox)
 
-    step_us = ms_step * 1e3
-    bytes_step = BYTES_PER_VOXEL_STEP * vox
-    hbm_gbs = bytes_step / (step_us * 1e-6) / 1e9
-    ops_voxel = flops_per_voxel(HELFRICH_SC)
-    tflops = ops_voxel * vox / (step_us * 1e-6) / 1e12
     vinfo = fe.variants()[variant]
-    kname = f"grad_sweep<float,{vinfo[0]},{vinfo[1]},{vinfo[2]},1>"
-    traffic = measured_traffic(kname, zc)
-    alu = {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-           "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic}
-    hbm = {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": traffic}
-    roof, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
-    roof = dict(roof, kernel=kname, duration_us=step_us, ops_per_voxel=ops_voxel)
-    # the published FP32 vector peak counts packed two-wide FMAs; the library
-    # compiles with packed FP32 disabled, so its attainable ALU ceiling is half
-    roof["unpacked_fp32_peak"] = FP32_VECTOR_PEAK_TFLOPS / 2
-    roof["frac_of_unpacked_peak"] = tflops / (FP32_VECTOR_PEAK_TFLOPS / 2)
+    kname = f"grad_sweep<float,{vinfo[0]},{vinfo[1]},{vinfo[2]},1,false,false,1>"
+    roof, other = roofline(flops_per_voxel(HELFRICH_SC), BYTES_PER_VOXEL_STEP, vox, ms_step * 1e3, kname,
+                           measured_traffic(kname, zc))
+    eroof, eother = roofline(forward_flops_per_voxel(HELFRICH_SC), BYTES_PER_VOXEL_ENERGY, vox,
+                             single["energy"]["median_us"], "energy_sweep_cols<float,2,8>", None)
+    groof, _ = roofline(flops_per_voxel(HELFRICH_SC), BYTES_PER_VOXEL_GRAD, vox, single["grad"]["median_us"],
+                        f"grad_sweep<float,{vinfo[0]},{vinfo[1]},{vinfo[2]},0,false,false,1>", None)
 
     out = {
         "metric": "voxel energy+gradient evals/sec at 256^3 FP32 and batched 16x128^3; % HBM peak",
@@ -459,18 +656,43 @@ def main():
                    "z_chunk": zc},
         "roofline": roof,
         "roofline_other": other,
-        "energy_grad_sweep": {"value": vox / (ms_grad * 1e-3), "us": ms_grad * 1e3,
-                              "hbm_frac": BYTES_PER_VOXEL_GRAD * vox / (ms_grad * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "us_per_step_samples": single["step_spread"],
         "steps_per_s": 1e3 / ms_step,
-        "diagnostics_sweep": {"us": ms_diag * 1e3, "voxels_per_s": vox / (ms_diag * 1e-3),
+        "energy_grad_sweep": {"value": vox / (single["grad"]["median_us"] * 1e-6), "us": single["grad"],
+                              "roofline": groof},
+        "energy_sweep": {"value": vox / (single["energy"]["median_us"] * 1e-6), "us": single["energy"],
+                         "unit": "voxel energy evals/s", "roofline": eroof, "roofline_other": eother},
+        "diagnostics_sweep": {"us": single["diag"], "voxels_per_s": vox / (single["diag"]["median_us"] * 1e-6),
                               "outputs": "H, K, kappa1, kappa2 fields, 64x64 curvature histogram, "
                                          "F_h, A_eps, discrepancy, min/max u"},
     }
     out.update(extra)
     if not args.no_cpu:
-        log("CPU oracle baseline ...")
+        log("CPU oracle baseline (one core, 256^3) ...")
         out["cpu_baseline"] = cpu_baseline()
+    if pool_baseline is not None:
+        out["cpu_baseline_batched"] = pool_baseline
     print(json.dumps(out), flush=True)
+
+
+def roofline(ops_per_voxel, bytes_per_voxel, voxels, us, kernel, traffic):
+    """(the binding roof, the other) for a kernel doing `voxels` voxels in `us`: its
+    algorithmic operations against the FP32 vector peak and its algorithmic bytes
+    against HBM; the larger fraction is the bound."""
+    tflops = ops_per_voxel * voxels / (us * 1e-6) / 1e12
+    gbs = bytes_per_voxel * voxels / (us * 1e-6) / 1e9
+    alu = {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic}
+    hbm = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": gbs / HBM_PEAK_GBS, "traffic": traffic}
+    roof, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
+    roof = dict(roof, kernel=kernel, duration_us=us, ops_per_voxel=ops_per_voxel, bytes_per_voxel=bytes_per_voxel)
+    # the published FP32 vector peak counts packed two-wide FMAs; the library
+    # compiles with packed FP32 disabled, so its attainable ALU ceiling is half
+    if roof["bound"] == "alu":
+        roof["unpacked_fp32_peak"] = FP32_VECTOR_PEAK_TFLOPS / 2
+        roof["frac_of_unpacked_peak"] = tflops / (FP32_VECTOR_PEAK_TFLOPS / 2)
+    return roof, other
 
 
 if __name__ == "__main__":

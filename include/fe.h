@@ -309,14 +309,40 @@ int fe_variant_info(int variant, int* tile_x, int* tile_y, int* threads, int* dt
 int fe_set_launch(fe_ctx* ctx, int variant, int z_chunk);
 int fe_get_launch(const fe_ctx* ctx, int* variant, int* z_chunk);
 
+/* What fe_autotune times: the sweep that fe_energy_grad, fe_step or fe_step_adam runs. */
+enum fe_tune_kind { FE_TUNE_GRAD = 0, FE_TUNE_STEP = 1, FE_TUNE_ADAM = 2 };
+
 /*
- * Time every variant that supports the context's dtype (and a few z-chunk
- * lengths) on fe_energy_grad_async(u, g) with `iters` launches each, pick the
- * fastest, and keep it in the context. u and g as in fe_energy_grad; g is
- * overwritten. best_us (host, may be NULL) receives the best time per call
- * in microseconds. Synchronises the stream.
+ * Pick the launch shape (variant and z-chunk length) for the sweep that `kind`
+ * names, and keep it in the context. The choice depends on the grid, batch,
+ * dtype, kind, on whether the instances' p are symmetric in k1, k2 (which
+ * per-voxel body the sweep holds), on a coefficient field or box mask, and on
+ * the device architecture; a choice made earlier in this process for the same
+ * key, or loaded by fe_tune_cache_load, is taken without timing (*cached = 1).
+ * Otherwise the workload first runs 50 ms untimed (the clocks settle), then
+ * every variant that supports the dtype is timed at a few z-chunk lengths,
+ * `iters` launches each, and the fastest is kept and cached.
+ *   u        device field, read only.
+ *   work     device field of u's size, distinct from u, overwritten (the step
+ *            kinds run on a copy of u there and in the context's step buffer).
+ *   kind     FE_TUNE_GRAD, FE_TUNE_STEP or FE_TUNE_ADAM (not for a box mask).
+ *   iters    launches per candidate, >= 1.
+ *   best_us  host, may be NULL: time per launch of the choice, in microseconds.
+ *   cached   host, may be NULL: 1 if the choice came from the cache, else 0.
+ * FE_TUNE_ADAM times on temporary moments: the context's Adam state is kept.
+ * Synchronises the stream. FE_EINVAL on bad arguments.
  */
-int fe_autotune(fe_ctx* ctx, const void* u, void* g, int iters, double* best_us);
+int fe_autotune(fe_ctx* ctx, const void* u, void* work, int kind, int iters, double* best_us, int* cached);
+
+/*
+ * The autotuner's cache, shared by every context of the process: save it to a
+ * text file (one "key variant z_chunk us" line per entry), merge a saved file
+ * into it (FE_EINVAL, and nothing merged, if a line is malformed or names a
+ * variant this library does not have), or empty it.
+ */
+int fe_tune_cache_save(const char* path);
+int fe_tune_cache_load(const char* path);
+void fe_tune_cache_clear(void);
 
 /* Release the context and everything it allocated. NULL is a no-op. */
 void fe_destroy(fe_ctx* ctx);

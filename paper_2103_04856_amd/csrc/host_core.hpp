@@ -760,6 +760,47 @@ int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int 
   return copy_energy_out(c, energy);
 }
 
+// Launch shapes chosen by fe_autotune, kept for the process (and saved to or
+// loaded from a text file on request), keyed by what the choice depends on.
+struct TuneEntry {
+  int variant = 0, lz = 0;
+  double us = 0.0;
+};
+std::map<std::string, TuneEntry> g_tune_cache;
+std::mutex g_tune_mu;
+
+// "<nx>x<ny>x<nz>x<batch>:<f32|f64>:<grad|step|adam>:<body>:<field|box|->:<device arch>"
+// (the key holds no spaces).
+int tune_key(const fe_ctx* c, int kind, std::string& key) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess)
+    return set_error(FE_EHIP, "hipGetDeviceProperties failed");
+  std::string arch = prop.gcnArchName;
+  for (char& ch : arch)
+    if (ch == ' ') ch = '_';
+  static const char* kinds[] = {"grad", "step", "adam"};
+  static const char* bodies[] = {"any", "nos", "full"};
+  char buf[320];
+  std::snprintf(buf, sizeof(buf), "%dx%dx%dx%d:%s:%s:%s:%s:%s", c->grid.nx, c->grid.ny, c->grid.nz, c->grid.batch,
+                c->grid.dtype == FE_F32 ? "f32" : "f64", kinds[kind], bodies[c->body],
+                c->use_box ? "box" : c->use_cfield ? "field" : "-", arch.c_str());
+  key = buf;
+  return FE_OK;
+}
+
+bool tune_lookup(const std::string& key, TuneEntry& out) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune_cache.find(key);
+  if (it == g_tune_cache.end()) return false;
+  out = it->second;
+  return true;
+}
+
+void tune_store(const std::string& key, const TuneEntry& e) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune_cache[key] = e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1017,23 +1058,99 @@ int fe_get_launch(const fe_ctx* c, int* variant, int* z_chunk) {
   return FE_OK;
 }
 
-int fe_autotune(fe_ctx* c, const void* u, void* g, int iters, double* best_us) {
+int fe_autotune(fe_ctx* c, const void* u, void* work, int kind, int iters, double* best_us, int* cached) {
   g_last_error.clear();
   if (!c) return set_error(FE_EINVAL, "ctx is NULL");
-  if (!u || !g || u == g) return set_error(FE_EINVAL, "u and g must be distinct device fields");
+  if (!u || !work || u == work) return set_error(FE_EINVAL, "u and work must be distinct device fields");
   if (iters < 1) return set_error(FE_EINVAL, "iters must be >= 1");
+  if (kind != FE_TUNE_GRAD && kind != FE_TUNE_STEP && kind != FE_TUNE_ADAM)
+    return set_error(FE_EINVAL, "kind must be FE_TUNE_GRAD, FE_TUNE_STEP or FE_TUNE_ADAM");
+  if (kind != FE_TUNE_GRAD && c->use_box) return set_error(FE_EINVAL, "a box-masked context has no step sweeps");
   DeviceGuard dg(c->device);
+  if (cached) *cached = 0;
+  std::string key;
+  int rc = tune_key(c, kind, key);
+  if (rc) return rc;
+  TuneEntry hit;
+  if (tune_lookup(key, hit)) {
+    c->variant = hit.variant;
+    c->lz = hit.lz;
+    if (best_us) *best_us = hit.us;
+    if (cached) *cached = 1;
+    return FE_OK;
+  }
   const int keep_v = c->variant, keep_lz = c->lz;
-  hipEvent_t e0, e1;
-  FE_HIP(hipEventCreate(&e0));
-  FE_HIP(hipEventCreate(&e1));
+  // the field the sweeps run on: u itself for the gradient sweep (read only);
+  // for steps, a copy in `work` that ping-pongs with the context's buffer
+  const size_t bytes = field_elems(c->grid) * elem_size(c->grid);
+  void* tmp_m1 = nullptr;
+  void* tmp_m2 = nullptr;
+  int* tmp_t = nullptr;
+  void* keep_m1 = c->d_m1;
+  void* keep_m2 = c->d_m2;
+  int* keep_t = c->d_adam_t;
+  auto restore = [&]() {
+    c->d_m1 = keep_m1;
+    c->d_m2 = keep_m2;
+    c->d_adam_t = keep_t;
+    (void)hipStreamSynchronize(c->stream);
+    for (void* p : {tmp_m1, tmp_m2, (void*)tmp_t})
+      if (p) (void)hipFree(p);
+  };
+  if (kind != FE_TUNE_GRAD) {
+    if (!c->d_pingpong && hipMalloc(&c->d_pingpong, bytes) != hipSuccess) {
+      c->d_pingpong = nullptr;
+      return set_error(FE_ENOMEM, "ping-pong field allocation failed");
+    }
+    FE_HIP(hipMemcpyAsync(work, u, bytes, hipMemcpyDeviceToDevice, c->stream));
+  }
+  if (kind == FE_TUNE_ADAM) {
+    // temporary moments: the context's optimiser state is left as it is
+    if (hipMalloc(&tmp_m1, bytes) != hipSuccess || hipMalloc(&tmp_m2, bytes) != hipSuccess ||
+        hipMalloc((void**)&tmp_t, sizeof(int)) != hipSuccess) {
+      restore();
+      return set_error(FE_ENOMEM, "temporary Adam moment allocation failed");
+    }
+    c->d_m1 = tmp_m1;
+    c->d_m2 = tmp_m2;
+    c->d_adam_t = tmp_t;
+    if ((rc = adam_reset_launch(c))) {
+      restore();
+      return rc;
+    }
+  }
+  const StepRule rule{kind == FE_TUNE_ADAM ? fe::kStepAdam : fe::kStepGD, 1e-3, 0.9, 0.999, 1e-8};
+  int flip = 0;
+  auto launch = [&]() -> int {
+    if (kind == FE_TUNE_GRAD) return fe_energy_grad_async(c, u, work, nullptr);
+    // one step on the copy (no mass shift: the same kernel, without the first
+    // wave's sum of its predecessor's partials)
+    void* src = flip ? c->d_pingpong : work;
+    void* dst = flip ? work : c->d_pingpong;
+    flip ^= 1;
+    return sweep(c, c->stream, rule.mode, src, dst, nullptr, partials_buf(c, 0), rule, 0);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    restore();
+    return set_error(FE_EHIP, "hipEventCreate failed");
+  }
+  // settle the clocks: 50 ms of the workload in the current launch shape
+  {
+    const auto t0 = std::chrono::steady_clock::now();
+    while (rc == FE_OK && std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(50)) {
+      for (int i = 0; i < 4 && rc == FE_OK; ++i) rc = launch();
+      if (hipStreamSynchronize(c->stream) != hipSuccess) rc = set_error(FE_EHIP, "hipStreamSynchronize failed");
+    }
+  }
   double best = 1e300;
   int best_v = keep_v, best_lz = keep_lz;
-  int rc = FE_OK;
   for (int v = 0; v < (int)variants().size() && rc == FE_OK; ++v) {
     if (!variant_ok(v, c->grid.dtype)) continue;
     const Variant& x = variants()[v];
     if (x.tx > 2 * c->grid.nx || x.ty > 2 * c->grid.ny) continue;
+    if ((c->use_cfield && !has_sp(v, c->grid.dtype)) || (c->use_box && !has_box(v, c->grid.dtype))) continue;
     // z chunks: powers of two from 4, the equal-chunk length with as many
     // chunks as each, and the automatic choice
     std::vector<int> lzs;
@@ -1048,10 +1165,10 @@ int fe_autotune(fe_ctx* c, const void* u, void* g, int iters, double* best_us) {
     for (int lz : lzs) {
       c->variant = v;
       c->lz = lz;
-      rc = fe_energy_grad_async(c, u, g, nullptr);   // warm-up
+      rc = launch();   // warm-up
       if (rc) break;
       if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = set_error(FE_EHIP, "hipEventRecord failed"); break; }
-      for (int i = 0; i < iters && rc == FE_OK; ++i) rc = fe_energy_grad_async(c, u, g, nullptr);
+      for (int i = 0; i < iters && rc == FE_OK; ++i) rc = launch();
       if (rc) break;
       if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
         rc = set_error(FE_EHIP, "event timing failed");
@@ -1069,11 +1186,58 @@ int fe_autotune(fe_ctx* c, const void* u, void* g, int iters, double* best_us) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  c->variant = best_v;
-  c->lz = best_lz;
+  restore();
+  c->variant = rc ? keep_v : best_v;
+  c->lz = rc ? keep_lz : best_lz;
   if (rc) return rc;
+  tune_store(key, TuneEntry{best_v, best_lz, best});
   if (best_us) *best_us = best;
   return FE_OK;
+}
+
+int fe_tune_cache_save(const char* path) {
+  g_last_error.clear();
+  if (!path) return set_error(FE_EINVAL, "path is NULL");
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return set_error(FE_EINVAL, "cannot open %s for writing", path);
+  for (const auto& kv : g_tune_cache)
+    std::fprintf(f, "%s %d %d %.6f\n", kv.first.c_str(), kv.second.variant, kv.second.lz, kv.second.us);
+  const bool ok = std::fclose(f) == 0;
+  return ok ? FE_OK : set_error(FE_EINVAL, "writing %s failed", path);
+}
+
+int fe_tune_cache_load(const char* path) {
+  g_last_error.clear();
+  if (!path) return set_error(FE_EINVAL, "path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return set_error(FE_EINVAL, "cannot open %s", path);
+  std::map<std::string, TuneEntry> got;
+  char line[512];
+  int lineno = 0;
+  int rc = FE_OK;
+  while (std::fgets(line, sizeof(line), f)) {
+    ++lineno;
+    char key[400];
+    TuneEntry e;
+    if (line[0] == '\n' || line[0] == '#') continue;
+    if (std::sscanf(line, "%399s %d %d %lf", key, &e.variant, &e.lz, &e.us) != 4 || e.variant < 0 ||
+        e.variant >= (int)variants().size() || e.lz < 0) {
+      rc = set_error(FE_EINVAL, "%s:%d: not a tuning record", path, lineno);
+      break;
+    }
+    got[key] = e;
+  }
+  std::fclose(f);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  for (const auto& kv : got) g_tune_cache[kv.first] = kv.second;
+  return FE_OK;
+}
+
+void fe_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune_cache.clear();
 }
 
 void fe_destroy(fe_ctx* c) {

@@ -74,7 +74,10 @@ SIGNATURES = {
     "fe_variant_info": (ctypes.c_int, [ctypes.c_int, _IP, _IP, _IP, _IP]),
     "fe_set_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
     "fe_get_launch": (ctypes.c_int, [_P, _IP, _IP]),
-    "fe_autotune": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _DP]),
+    "fe_autotune": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _DP, _IP]),
+    "fe_tune_cache_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "fe_tune_cache_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "fe_tune_cache_clear": (None, []),
     "fe_destroy": (None, [_P]),
     "fe_last_error": (ctypes.c_char_p, []),
 }
@@ -354,15 +357,34 @@ class FeContext:
         _check(lib().fe_get_launch(self._h, ctypes.byref(v), ctypes.byref(z)))
         return v.value, z.value
 
-    def autotune(self, u, g=None, iters=10):
-        """Time every launch variant on u and keep the fastest; returns (variant, z_chunk, us)."""
-        g = torch.empty_like(u) if g is None else g
+    TUNE_KINDS = {"grad": 0, "step": 1, "adam": 2}
+
+    def autotune(self, u, work=None, kind="grad", iters=10):
+        """Pick the launch shape for the sweep of `kind` ("grad": fe_energy_grad, "step":
+        fe_step, "adam": fe_step_adam) and keep it; returns (variant, z_chunk, us, cached).
+        u is not modified; work (u's shape, overwritten) is allocated here if not given."""
+        work = torch.empty_like(u) if work is None else work
         best = ctypes.c_double()
+        cached = ctypes.c_int()
         self._sync_stream()
-        _check(lib().fe_autotune(self._h, self._field(u, "u"), self._field(g, "g"), int(iters),
-                                 ctypes.byref(best)))
+        _check(lib().fe_autotune(self._h, self._field(u, "u"), self._field(work, "work"), self.TUNE_KINDS[kind],
+                                 int(iters), ctypes.byref(best), ctypes.byref(cached)))
         v, z = self.get_launch()
-        return v, z, best.value
+        return v, z, best.value, bool(cached.value)
+
+
+def tune_cache_save(path):
+    """Save the autotuner's choices of this process to a text file."""
+    _check(lib().fe_tune_cache_save(os.fsencode(path)))
+
+
+def tune_cache_load(path):
+    """Merge a saved file of autotuner choices into this process's cache."""
+    _check(lib().fe_tune_cache_load(os.fsencode(path)))
+
+
+def tune_cache_clear():
+    lib().fe_tune_cache_clear()
 
 
 NOALLOC_MAX_BATCH = 16

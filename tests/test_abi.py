@@ -131,3 +131,22 @@ def test_noalloc_rejects_before_device_work(L, grid, msg):
                                   fe._dbl([1, 2, 1, 0, 0, 0] * B), ctypes.c_void_p(8), ctypes.c_void_p(16),
                                   None, None)
     assert rc == fe.FE_EINVAL and msg in L.fe_last_error().decode()
+
+
+def test_tune_cache_file_round_trip(L, tmp_path):
+    """The autotuner's cache file: a saved record loads back unchanged; a malformed line or
+    an unknown variant is rejected and nothing is merged (host only, no device work)."""
+    L.fe_tune_cache_clear()
+    good = tmp_path / "good.txt"
+    good.write_text("64x64x64x1:f32:step:nos:-:gfx950 0 32 12.500000\n")
+    assert L.fe_tune_cache_load(str(good).encode()) == fe.FE_OK
+    out = tmp_path / "out.txt"
+    assert L.fe_tune_cache_save(str(out).encode()) == fe.FE_OK
+    assert out.read_text() == good.read_text()
+    for bad in ("not a record\n", f"k 0 1 2.0\nk2 {L.fe_num_variants()} 4 1.0\n", "k -1 4 1.0\n"):
+        p = tmp_path / "bad.txt"
+        p.write_text(bad)
+        assert L.fe_tune_cache_load(str(p).encode()) == fe.FE_EINVAL
+    L.fe_tune_cache_clear()
+    assert L.fe_tune_cache_save(str(out).encode()) == fe.FE_OK and out.read_text() == ""
+    assert L.fe_tune_cache_load(str(tmp_path / "missing.txt").encode()) == fe.FE_EINVAL

@@ -45,9 +45,10 @@ def test_autotune_keeps_its_choice_and_the_results():
     u = to_dev(inputs.uniform_noise(n, 9), torch.float32)
     ctx = fe.FeContext((1, n, n, n), 1 / n, 2 / n, ALL_TERMS, dtype=torch.float32)
     E0, g0 = ctx.energy_grad(u)
-    v, z, us = ctx.autotune(u, iters=2)
+    fe.tune_cache_clear()
+    v, z, us, cached = ctx.autotune(u, iters=2)
     log(f"  autotune 48^3: variant {fe.variants()[v][:3]} z chunk {z}: {us:.1f} us")
-    assert us > 0 and ctx.get_launch() == (v, z)
+    assert us > 0 and not cached and ctx.get_launch() == (v, z)
     E1, g1 = ctx.energy_grad(u)
     d = (torch.linalg.vector_norm((g1 - g0).double()) / torch.linalg.vector_norm(g0.double())).item()
     assert d <= 2e-6
@@ -55,3 +56,53 @@ def test_autotune_keeps_its_choice_and_the_results():
     # and it is reproducible at that launch
     E2, g2 = ctx.energy_grad(u)
     assert torch.equal(g2, g1) and E2[0].item() == E1[0].item()
+
+
+def test_autotune_cache_is_used_and_persists(tmp_path):
+    """A second context with the same grid, batch, dtype, body and kind takes the cached
+    choice without timing; another kind is timed anew; a saved cache, loaded after the
+    cache was emptied, serves the choice again; u is never modified."""
+    n = 40
+    u = to_dev(inputs.uniform_noise(n, 12), torch.float32)
+    u_before = u.clone()
+    fe.tune_cache_clear()
+    c1 = fe.FeContext((1, n, n, n), 1 / n, 2 / n, ALL_TERMS, dtype=torch.float32)
+    v1, z1, us1, cached1 = c1.autotune(u, kind="step", iters=2)
+    assert not cached1 and torch.equal(u, u_before)
+    c2 = fe.FeContext((1, n, n, n), 1 / n, 2 / n, ALL_TERMS, dtype=torch.float32)
+    v2, z2, us2, cached2 = c2.autotune(u, kind="step", iters=2)
+    assert cached2 and (v2, z2, us2) == (v1, z1, us1) and c2.get_launch() == (v1, z1)
+    _, _, _, cached3 = c2.autotune(u, kind="grad", iters=2)
+    assert not cached3
+    path = str(tmp_path / "tune.txt")
+    fe.tune_cache_save(path)
+    fe.tune_cache_clear()
+    c3 = fe.FeContext((1, n, n, n), 1 / n, 2 / n, ALL_TERMS, dtype=torch.float32)
+    fe.tune_cache_load(path)
+    v3, z3, _, cached4 = c3.autotune(u, kind="step", iters=2)
+    assert cached4 and (v3, z3) == (v1, z1)
+    # a p symmetric in k1, k2 runs another kernel: another key
+    c4 = fe.FeContext((1, n, n, n), 1 / n, 2 / n, (1.0, 2.5, 1.0, -4.0, -4.0, 4.0), dtype=torch.float32)
+    _, _, _, cached5 = c4.autotune(u, kind="step", iters=2)
+    assert not cached5
+    assert torch.equal(u, u_before)
+    log(f"  cache file:\n{open(path).read()}")
+
+
+def test_autotune_for_adam_keeps_the_optimiser_state():
+    """Tuning the Adam sweep between steps does not disturb the context's moments or step
+    number: 3 steps, tuning, 2 steps equal 5 steps in one call of a fresh context."""
+    n = 24
+    u0 = inputs.uniform_noise(n, 13)
+    fe.tune_cache_clear()
+    ca = fe.FeContext((1, n, n, n), 1 / n, 2 / n, ALL_TERMS, dtype=torch.float32)
+    cb = fe.FeContext((1, n, n, n), 1 / n, 2 / n, ALL_TERMS, dtype=torch.float32)
+    ua, ub = to_dev(u0, torch.float32), to_dev(u0, torch.float32)
+    ca.step_adam(ua, [0.1], 3)
+    keep = ca.get_launch()
+    ca.autotune(ua, kind="adam", iters=2)
+    ca.set_launch(*keep)
+    ca.step_adam(ua, [0.1], 2)
+    cb.set_launch(*keep)
+    cb.step_adam(ub, [0.1], 5)
+    assert torch.equal(ua, ub)
