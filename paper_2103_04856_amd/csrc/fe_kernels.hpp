@@ -223,9 +223,9 @@ __device__ __forceinline__ BlockTile block_tile(const SweepArgs<T>& a) {
 // their centre-only adjoints (du, da_z, db_aa) stay in registers and only the
 // seven values the neighbours read go through LDS; the one-voxel border of
 // the ring is shared out afterwards. The gather takes u at its output voxels
-// from registers (read while that plane was the centre plane), so no u slot is
-// read after the second barrier: three rotating u slots and two barriers per
-// plane suffice.
+// from registers (read from the slot of plane p-1 before the second barrier),
+// so no u slot is read after the second barrier: three rotating u slots and
+// two barriers per plane suffice.
 //
 // BODY: which per-voxel body the kernel holds. kBodyAny picks it per instance
 // (a batch that mixes p symmetric in k1, k2 with others); kBodyNoS and
@@ -319,10 +319,10 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
 
   double acc_f = 0.0, acc_m = 0.0;
   T c_prev[NO], l_prev[NO], l_pp[NO];
-  T u_prev[NO];                                // u at this thread's output voxels of plane p-1
+  T u_out[NO];                                 // u at this thread's output voxels of plane p-1
   T m1c[NO], m2c[NO], m1n[NO], m2n[NO];        // Adam moments: current and next output plane
 #pragma unroll
-  for (int j = 0; j < NO; ++j) c_prev[j] = l_prev[j] = l_pp[j] = u_prev[j] = m1n[j] = m2n[j] = T(0);
+  for (int j = 0; j < NO; ++j) c_prev[j] = l_prev[j] = l_pp[j] = u_out[j] = m1n[j] = m2n[j] = T(0);
 
   // plane q lives in slot (q - k0 + 2) mod 3; the three slots rotate
   fetch(k0 - 2);
@@ -413,7 +413,9 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
     // Interior and border voxels are dealt out from one index space, so the
     // per-thread counts differ by at most one (the border goes to the threads
     // whose interior share is shorter).
-    T own_ub[NO], own_gz[NO], own_bxx[NO], own_byy[NO], own_bzz[NO], own_u[NO];
+    // the centre-only adjoint terms of this thread's output voxels: ub + 2 (b_zz +
+    // b_xx + b_yy), a_z and b_zz (the last two also reach the planes above and below)
+    T own_c0[NO], own_gz[NO], own_bzz[NO];
     T fpl = T(0);                              // this thread's energy of plane p (one FP64 add per plane)
 #pragma unroll
     for (int j = 0; j < NW; ++j) {
@@ -425,12 +427,12 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
         VoxelAdjoint<T> ad;
         const T f = eval(v, ad, SP ? with_coeffs(prm, cv[j]) : prm);
         if (j < NO && inner) {
-          own_u[j] = su[sc][(iy + 2) * UX + ix + 2];
-          own_ub[j] = ad.ub;
+          own_c0[j] = ad.ub + T(2) * ((ad.nbzz + ad.nbxx) + ad.nbyy);
           own_gz[j] = ad.gz;
-          own_bxx[j] = ad.nbxx;
-          own_byy[j] = ad.nbyy;
           own_bzz[j] = ad.nbzz;
+          // u of output plane p-1 at this voxel, read before the second barrier
+          // (its slot takes plane p+2 in the next iteration)
+          u_out[j] = su[sm][(iy + 2) * UX + ix + 2];
           if (out_plane && x0 + ix < a.nx && y0 + iy < a.ny) fpl += f;
         }
       }
@@ -458,7 +460,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
           if (gx < a.nx && gy < a.ny) {
             const T g = (c_prev[j] - upn) + l_pp[j];
             const size_t idx = (size_t)(p - 1) * plane + (size_t)gy * a.nx + gx;
-            const T uc = u_prev[j];
+            const T uc = u_out[j];
             if (MODE == kStepGD) {
               const T un = uc - a.tau * g;
               dstb[idx] = un;
@@ -477,7 +479,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
             }
           }
         }
-        const T cin = (own_ub[j] + T(2) * ((bzz + own_bxx[j]) + own_byy[j]))
+        const T cin = own_c0[j]
                       - T(2) * ((sx[GX][v + 1] - sx[GX][v - 1]) + (sx[GY][v + RX] - sx[GY][v - RX]))
                       - ((sx[BXX][v + 1] + sx[BXX][v - 1]) + (sx[BYY][v + RX] + sx[BYY][v - RX]))
                       - T(0.5) * ((sx[BXY][v + RX + 1] - sx[BXY][v - RX + 1]) -
@@ -485,7 +487,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
         l_pp[j] = l_prev[j];
         l_prev[j] = lo;
         c_prev[j] = cin;
-        u_prev[j] = own_u[j];
+
       }
     }
     acc_m += double(mpl);

@@ -12,8 +12,8 @@ import torch
 from oracle import fe_oracle as fo
 from paper_2103_04856_amd import fe, inputs
 
-from gpu_helpers import (ALL_TERMS, ASYM_C3, HELFRICH_SC, TOL, WILLMORE_QUARTER, check_energy_grad, check_field,
-                         log, oracle_input, rel_l2, to_dev)
+from gpu_helpers import (ALL_TERMS, ASYM_C3, HELFRICH_SC, ROUNDING, TOL, WILLMORE_QUARTER, assert_same_to_rounding,
+                         check_energy_grad, check_field, log, oracle_input, rel_l2, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -170,7 +170,8 @@ def test_symmetric_and_asymmetric_instances_in_one_launch():
     """p symmetric in k1, k2 (c3 = c5 = 0: Helfrich, Willmore) takes the body without the
     S terms; the others the full body; the choice is per instance. A launch that mixes
     them, with one p having c5 only (a20 = a02, a10 != a01), matches the oracle and gives
-    each instance the bits of its own single-instance launch."""
+    each instance its single-instance result (to rounding: alone, an instance runs a
+    single-body kernel, which may contract multiply-adds differently)."""
     n, B = 28, 4
     h = 1.0 / n
     coeffs = [HELFRICH_SC, ASYM_C3, WILLMORE_QUARTER, (1.0, 0.5, 1.0, -2.0, -1.0, 0.0)]
@@ -186,7 +187,8 @@ def test_symmetric_and_asymmetric_instances_in_one_launch():
             c1 = fe.FeContext((1, n, n, n), h, eps[b], coeffs[b], dtype=dtype)
             c1.set_launch(*ctx.get_launch())
             Eb, gb = c1.energy_grad(ud[b:b + 1].contiguous())
-            assert Eb[0].item() == E[b].item() and torch.equal(gb[0], g[b]), (dtype, b)
+            assert_same_to_rounding(gb[0], g[b], dtype, (dtype, b))
+            assert abs(Eb[0].item() - E[b].item()) <= ROUNDING[dtype] * abs(E[b].item()), (dtype, b)
 
 
 def test_repeated_calls_are_bitwise_deterministic():
