@@ -118,10 +118,12 @@ def measured_traffic(kernel, z_chunk):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sources_sha256_prefix") != kernel_hash() or t.get("kernel") != kernel \
-            or t.get("z_chunk") != z_chunk:
+    if t.get("kernel_sources_sha256_prefix") != kernel_hash():
         return None
-    return t.get("traffic_bytes")
+    for r in t.get("records", []):
+        if r.get("kernel") == kernel and r.get("z_chunk") == z_chunk:
+            return r.get("traffic_bytes")
+    return None
 
 
 # After its warmup steps, every timed loop first runs the same work untimed for
@@ -606,8 +608,9 @@ def main():
         bk = f"grad_sweep<float,{bv[0]},{bv[1]},{bv[2]},2,false,false,2>"
         broof, bother = roofline(FLOPS_PER_VOXEL + FLOPS_ADAM_EXTRA, BYTES_PER_VOXEL_ADAM, vb,
                                  b_spread["median_us"], bk, measured_traffic(bk, bzc))
-        groof, _ = roofline(FLOPS_PER_VOXEL, BYTES_PER_VOXEL_GRAD, vb, bg_spread["median_us"],
-                            f"grad_sweep<float,{bv[0]},{bv[1]},{bv[2]},0,false,false,2>", None)
+        gk = f"grad_sweep<float,{bv[0]},{bv[1]},{bv[2]},0,false,false,2>"
+        groof, _ = roofline(FLOPS_PER_VOXEL, BYTES_PER_VOXEL_GRAD, vb, bg_spread["median_us"], gk,
+                            measured_traffic(gk, bzc))
         extra["batched_16x128"] = {
             "value": vb / (b_spread["median_us"] * 1e-6), "us_per_step": b_spread,
             "unit": "voxel energy+gradient evals/s", "step_rule": "mass-projected Adam, lr 1e-3",
@@ -631,10 +634,12 @@ def main():
     kname = f"grad_sweep<float,{vinfo[0]},{vinfo[1]},{vinfo[2]},1,false,false,1>"
     roof, other = roofline(flops_per_voxel(HELFRICH_SC), BYTES_PER_VOXEL_STEP, vox, ms_step * 1e3, kname,
                            measured_traffic(kname, zc))
+    ek = "energy_sweep_cols<float,2,8>"
     eroof, eother = roofline(forward_flops_per_voxel(HELFRICH_SC), BYTES_PER_VOXEL_ENERGY, vox,
-                             single["energy"]["median_us"], "energy_sweep_cols<float,2,8>", None)
-    groof, _ = roofline(flops_per_voxel(HELFRICH_SC), BYTES_PER_VOXEL_GRAD, vox, single["grad"]["median_us"],
-                        f"grad_sweep<float,{vinfo[0]},{vinfo[1]},{vinfo[2]},0,false,false,1>", None)
+                             single["energy"]["median_us"], ek, measured_traffic(ek, None))
+    gk = f"grad_sweep<float,{vinfo[0]},{vinfo[1]},{vinfo[2]},0,false,false,1>"
+    groof, _ = roofline(flops_per_voxel(HELFRICH_SC), BYTES_PER_VOXEL_GRAD, vox, single["grad"]["median_us"], gk,
+                        measured_traffic(gk, zc))
 
     out = {
         "metric": "voxel energy+gradient evals/sec at 256^3 FP32 and batched 16x128^3; % HBM peak",
