@@ -270,6 +270,16 @@ def bench_batched(n, B, warmup, tune):
     return b_spread, grad_spread, s_spread, ctx.get_launch()
 
 
+def step_samples(ctx, u, mass, reps=5):
+    """Graph-replayed mass-projected steps (tau = 1e-3) on a copy of u: reps samples
+    of SAMPLE_STEPS steps after 17 untimed ones, in us per step. At these sizes the
+    stream-ordered energy+gradient call is bound by the host's launch rate; the step
+    loop shows what the device sustains."""
+    u1 = u.clone()
+    ctx.step(u1, mass, 1e-3, 17)
+    return spread(samples(lambda: ctx.step(u1, mass, 1e-3, SAMPLE_STEPS), reps), SAMPLE_STEPS)
+
+
 def bench_configs(args):
     """The method's smaller configurations: 32^3 FP64 (energy+gradient; 200 steps), 64^3
     noisy ball FP32 and FP64 (energy+gradient), 128^3 FP32 asymmetric p (energy+gradient,
@@ -288,8 +298,10 @@ def bench_configs(args):
     ctx.step(u1, [0.0], 1e-3, 17)
     u1 = u.clone()
     t200 = samples(lambda: ctx.step(u1, [0.0], 1e-3, 200), 1)[0]
+    ss = step_samples(ctx, u, [0.0])
     out["32cubed_fp64"] = {"energy_grad": sw, "voxels_per_s": n ** 3 / (sw["median_us"] * 1e-6),
                            "steps_200_ms": t200, "steps_per_s": 200 / (t200 * 1e-3),
+                           "step": ss, "step_voxels_per_s": n ** 3 / (ss["median_us"] * 1e-6),
                            "config": "32^3 FP64, u0~U(-1,1) seed 1001, eps=2h, p=(k1+k2)^2/4, mean 0, tau=1e-3"}
     # 64^3 noisy ball, eps = 1.5h, Willmore p, FP32 and FP64
     n = 64
@@ -301,8 +313,12 @@ def bench_configs(args):
         g = torch.empty_like(u)
         settle(lambda: ctx.energy_grad_async(u, g, E), 0.05)
         sw = spread(samples(lambda: ctx.energy_grad_async(u, g, E), 50))
+        ss = step_samples(ctx, u, [u.double().mean().item()])
         out[key] = {"energy_grad": sw, "voxels_per_s": n ** 3 / (sw["median_us"] * 1e-6),
-                    "config": "64^3 tanh ball R=0.3 + N(0,0.01^2) seed 1002, eps=1.5h, p=(k1+k2)^2/4"}
+                    "step": ss, "step_voxels_per_s": n ** 3 / (ss["median_us"] * 1e-6),
+                    "steps_per_s": 1e6 / ss["median_us"],
+                    "config": "64^3 tanh ball R=0.3 + N(0,0.01^2) seed 1002, eps=1.5h, p=(k1+k2)^2/4, "
+                              "mass-projected step tau=1e-3 at the initial mean"}
     # 128^3 FP32, asymmetric p, mean -0.3
     n = 128
     h = 1.0 / n
@@ -475,6 +491,27 @@ def cpu_baseline(n=256, budget_s=10.0, max_evals=3):
     return dict(value=evals * u.size / dt, unit="voxel energy+gradient evals/s", cores=1, kind="oracle",
                 sample=f"{evals} FP64 energy+gradient evaluation(s) of the full 256^3 field ({dt:.1f} s)",
                 cpu_model=model, nproc=ncpu)
+
+
+def cpu_baseline_configs(budget_s=1.0):
+    """The oracle (one core) on the smaller configurations' inputs: FP64 energy + gradient
+    evaluations repeated for about budget_s seconds each (at least one)."""
+    from oracle import fe_oracle as fo
+    willmore_q = (0.25, 0.5, 0.25, 0.0, 0.0, 0.0)
+    cases = {
+        "32cubed": (inputs.uniform_noise(32, 1001), 32, 2.0, willmore_q),
+        "64cubed": (inputs.noisy_sphere(64, 0.3, 1.5 / 64, 0.01, 1002), 64, 1.5, willmore_q),
+        "128cubed": (inputs.uniform_noise(128, 1003), 128, 2.0, (1.0, 0.0, 0.2, -4.0, -4.0, 0.0)),
+    }
+    out = {}
+    for key, (u, n, eps_h, a) in cases.items():
+        evals, t0 = 0, time.perf_counter()
+        while evals == 0 or (time.perf_counter() - t0 < budget_s and evals < 100):
+            fo.energy_grad(u, 1.0 / n, eps_h / n, a)
+            evals += 1
+        dt = time.perf_counter() - t0
+        out[key] = {"value": evals * u.size / dt, "evals": evals, "seconds": dt}
+    return out
 
 
 def _oracle_instance(b):
@@ -675,6 +712,8 @@ def main():
     if not args.no_cpu:
         log("CPU oracle baseline (one core, 256^3) ...")
         out["cpu_baseline"] = cpu_baseline()
+        if not args.main_only and not args.batched_only:
+            out["cpu_baseline"]["per_config"] = cpu_baseline_configs()
     if pool_baseline is not None:
         out["cpu_baseline_batched"] = pool_baseline
     print(json.dumps(out), flush=True)
