@@ -19,8 +19,10 @@ Also reported, per workload of the method's five configurations:
     with its own roofline, against 16 sequential single-instance calls;
   * the energy+gradient sweep without the update and the energy-only sweep
     (the autograd forward), each with its roofline;
+  * the 256^3 field with a general p (S terms on): its sweep and Adam steps;
   * 32^3 FP64 (200 steps), 64^3 FP32 and FP64 (noisy ball), 128^3 FP32
-    (asymmetric p: Adam steps and autograd-driven steps);
+    (asymmetric p: Adam steps and autograd-driven steps, eager and captured
+    in a CUDA graph);
   * Algorithm 1 (the H^-1 flow on a vector field with the Gaussian blur and
     Adam) at the paper's 100^3 simulation size, the coefficient-field
     workloads and Algorithm 2 (Willmore flow, Clifford torus);
@@ -220,6 +222,36 @@ def bench_single(n, steps, warmup, tune):
     return ctx, u, out
 
 
+# A general p, with the S terms (a20 != a02): the 128^3 configuration's coefficients.
+GENERAL_P = (1.0, 0.0, 0.2, -4.0, -4.0, 0.0)
+
+
+def bench_general(n, steps):
+    """The 256^3 field of the step workload with the general p: the energy+gradient sweep
+    and mass-projected Adam steps (the plain step diverges near umbilic voxels for such p),
+    both with the full per-voxel body."""
+    h = 1.0 / n
+    u = torch.from_numpy(inputs.uniform_noise(n, 1005)).float().cuda()
+    ctx = fe.FeContext(u.shape, h, 1.5 * h, GENERAL_P, dtype=torch.float32)
+    g = torch.empty_like(u)
+    E = torch.empty(1, dtype=torch.float64, device=u.device)
+
+    def one():
+        ctx.energy_grad_async(u, g, E)
+
+    for _ in range(3):
+        one()
+    settle(one)
+    sw = spread(samples(one, max(steps, 30)))
+    mass = [float(u.double().mean().item())]
+    ctx.step_adam(u, mass, 17)
+    settle(lambda: ctx.step_adam(u, mass, SAMPLE_STEPS))
+    sa = spread(samples(lambda: ctx.step_adam(u, mass, SAMPLE_STEPS), 5), SAMPLE_STEPS)
+    v, zc = ctx.get_launch()
+    ctx.close()
+    return sw, sa, v, zc
+
+
 def bench_batched(n, B, warmup, tune):
     """The batched workload as calls of SAMPLE_STEPS mass-projected Adam steps (whole graph
     replays); the same 16 textures as 16 single-instance contexts called one after the other."""
@@ -268,6 +300,31 @@ def bench_batched(n, B, warmup, tune):
     settle(lambda: singles[0].step_adam(views[0], [means[0]], SAMPLE_STEPS, lr=ADAM_LR))
     s_spread = spread(samples(run_singles, 3), SAMPLE_STEPS)
     return b_spread, grad_spread, s_spread, ctx.get_launch()
+
+
+def capture_graph(fn, warm=3):
+    """fn captured in a CUDA graph after `warm` eager calls on a side stream (the
+    capture records the library's kernels, which take the current stream)."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(warm):
+            fn()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fn()
+    return graph
+
+
+def replay_samples(graph, reps=5):
+    """Samples of SAMPLE_STEPS replays of a captured graph, in us per replay."""
+    def run():
+        for _ in range(SAMPLE_STEPS):
+            graph.replay()
+    run()
+    settle(run, 0.05)
+    return spread(samples(run, reps), SAMPLE_STEPS)
 
 
 def step_samples(ctx, u, mass, reps=5):
@@ -332,24 +389,43 @@ def bench_configs(args):
     ctx.step_adam(u1, [-0.3], 17)
     settle(lambda: ctx.step_adam(u1, [-0.3], SAMPLE_STEPS), 0.05)
     sa = spread(samples(lambda: ctx.step_adam(u1, [-0.3], SAMPLE_STEPS), 5), SAMPLE_STEPS)
-    # autograd-driven steps: E = FeEnergy(u) (energy-only sweep), backward (the adjoint
-    # sweep), then the step and the mass projection in torch
-    x = u.clone()
+    # autograd-driven steps, the paper's loop: E = FeEnergy(y) (energy-only sweep), backward
+    # (the adjoint sweep), torch.optim.Adam on y (fused and capturable: one kernel, its step
+    # count on the device), then the mass projection in torch; eager, and captured in a CUDA graph
+    # (whose replays skip the host work of the autograd engine, about 90 us per backward
+    # pass here); also the forward and backward alone, captured
+    def autograd_adam(x0):
+        y = x0.clone().requires_grad_(True)
+        opt = torch.optim.Adam([y], lr=ADAM_LR, fused=True, capturable=True)
 
-    def autograd_step():
-        nonlocal x
-        y = x.detach().requires_grad_(True)
-        fe.feps(y, ctx).sum().backward()
-        with torch.no_grad():
-            v = y - 1e-3 * y.grad
-            x = v + (-0.3 - v.mean())
+        def step():
+            opt.zero_grad(set_to_none=True)
+            fe.feps(y, ctx).sum().backward()
+            opt.step()
+            with torch.no_grad():
+                y.add_(-0.3 - y.mean())
+        return step
 
+    autograd_step = autograd_adam(u)
     for _ in range(5):
         autograd_step()
     st = spread(samples(autograd_step, 30))
+    g_st = capture_graph(autograd_adam(u))
+    sgs = replay_samples(g_st)
+    y = u.clone().requires_grad_(True)
+    g_fb = capture_graph(lambda: torch.autograd.grad(fe.feps(y, ctx).sum(), y))
+    sfb = replay_samples(g_fb)
+    del g_fb, g_st
+    log(f"  128^3 autograd Adam step: eager {st['median_us']:.1f} us, graph-captured {sgs['median_us']:.1f} us "
+        f"(forward + backward {sfb['median_us']:.1f} us; fused Adam step {sa['median_us']:.1f} us)")
     out["128cubed_fp32"] = {"energy_grad": sw, "voxels_per_s": n ** 3 / (sw["median_us"] * 1e-6),
                             "adam_step": sa, "adam_steps_per_s": 1e6 / sa["median_us"],
                             "autograd_step": st, "autograd_steps_per_s": 1e6 / st["median_us"],
+                            "autograd_step_rule": "FeEnergy forward + backward, torch.optim.Adam lr 1e-3 "
+                                                  "(fused, capturable), mass projection in torch",
+                            "autograd_forward_backward_graphed": sfb,
+                            "autograd_step_graphed": sgs, "autograd_graphed_steps_per_s": 1e6 / sgs["median_us"],
+                            "autograd_forward_backward_graphed_over_adam_step": sfb["median_us"] / sa["median_us"],
                             "config": "128^3 FP32, u0~U(-1,1) seed 1003, eps=2h, a=(1,0,0.2,-4,-4,0), mean -0.3"}
     return out
 
@@ -637,6 +713,22 @@ def main():
     value = vox / (ms_step * 1e-3)
 
     extra = {}
+    if not args.batched_only:
+        log("256^3 with a general p (S terms): energy+gradient sweep and Adam steps ...")
+        gsw, gsa, gv, gzc = bench_general(n, args.steps)
+        gvi = fe.variants()[gv]
+        ak = f"grad_sweep<float,{gvi[0]},{gvi[1]},{gvi[2]},2,false,false,2>"
+        gk = f"grad_sweep<float,{gvi[0]},{gvi[1]},{gvi[2]},0,false,false,2>"
+        aroof, _ = roofline(FLOPS_PER_VOXEL + FLOPS_ADAM_EXTRA, BYTES_PER_VOXEL_ADAM, vox, gsa["median_us"], ak,
+                            measured_traffic(ak, gzc))
+        sroof, _ = roofline(FLOPS_PER_VOXEL, BYTES_PER_VOXEL_GRAD, vox, gsw["median_us"], gk,
+                            measured_traffic(gk, gzc))
+        extra["general_p_256"] = {
+            "p": list(GENERAL_P), "eps": "1.5h", "z_chunk": gzc,
+            "energy_grad_sweep": {"value": vox / (gsw["median_us"] * 1e-6), "us": gsw, "roofline": sroof},
+            "adam_step": {"value": vox / (gsa["median_us"] * 1e-6), "us": gsa, "roofline": aroof},
+            "unit": "voxel energy+gradient evals/s"}
+        log(f"  sweep {gsw['median_us']:.1f} us, Adam step {gsa['median_us']:.1f} us")
     if not args.no_batched and not args.main_only:
         log("16 x 128^3 batched vs 16 single-instance calls ...")
         b_spread, bg_spread, s_spread, (bvar, bzc) = bench_batched(128, 16, args.warmup, args.tune)

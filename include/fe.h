@@ -104,6 +104,20 @@ int fe_energy_grad(fe_ctx* ctx, const void* u, void* g, double* energy);
 int fe_energy_grad_async(fe_ctx* ctx, const void* u, void* g, double* energy_dev);
 
 /*
+ * The gradient alone, scaled per instance: g_b = s_b dF_h/du_b, the backward of
+ * an energy whose incoming derivative is s (the chain rule through eq. (Feps)).
+ * The density is linear in its coefficients, so the sweep runs with every
+ * coefficient of instance b multiplied by s_b (with a coefficient field, the
+ * gradient is scaled after the sweep). No energy is formed; stream-ordered,
+ * nothing synchronises, nothing is allocated.
+ *   u       device field [batch][nz][ny][nx], read only.
+ *   g       device field, written; must not overlap u.
+ *   gscale  device array of `batch` doubles (s), read in stream order.
+ * Equal to s_b times fe_energy_grad's g up to rounding, not bitwise.
+ */
+int fe_grad_scaled_async(fe_ctx* ctx, const void* u, void* g, const double* gscale);
+
+/*
  * For callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): fe_energy_grad_async
  * without a context. It allocates nothing and calls nothing that allocates;

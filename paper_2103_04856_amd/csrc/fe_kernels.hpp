@@ -731,6 +731,37 @@ __global__ __launch_bounds__(256) void add_shift(const T* src, T* dst, const dou
   }
 }
 
+// The per-instance table with every coefficient of the density of instance b
+// (C1..C6 and the orientation term's Co) multiplied by s[b]: the density is
+// linear in them, so a gradient sweep with this table gives s_b dF_h/du_b.
+// One wave; the geometric constants are copied unchanged.
+template <typename T>
+__global__ __launch_bounds__(64) void scale_params(const InstParams<T>* __restrict__ src,
+                                                   InstParams<T>* __restrict__ dst, const double* __restrict__ s,
+                                                   int batch) {
+  for (int b = threadIdx.x; b < batch; b += blockDim.x) {
+    InstParams<T> q = src[b];
+    const double f = s[b];
+    q.C1 = T(double(q.C1) * f);
+    q.C2 = T(double(q.C2) * f);
+    q.C3 = T(double(q.C3) * f);
+    q.C4 = T(double(q.C4) * f);
+    q.C5 = T(double(q.C5) * f);
+    q.C6 = T(double(q.C6) * f);
+    q.Co = T(double(q.Co) * f);
+    dst[b] = q;
+  }
+}
+
+// g[b][i] *= s[b] (grid: x over the instance's voxels, y over instances).
+template <typename T>
+__global__ __launch_bounds__(256) void scale_per_instance(T* g, size_t per_inst, const double* __restrict__ s) {
+  const T f = T(s[blockIdx.y]);
+  T* gb = g + (size_t)blockIdx.y * per_inst;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < per_inst; i += (size_t)gridDim.x * blockDim.x)
+    gb[i] *= f;
+}
+
 // Scaled coefficient field from a(x) = (a20, a11, a02, a10, a01, a00)(x)
 // ([batch][6][vol] in, [batch][6][vol] out), the per-voxel form of the
 // per-instance C1..C6 (see fe_voxel.hpp): with kq = h^3 s^2 / (2 eps),

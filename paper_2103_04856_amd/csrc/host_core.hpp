@@ -201,6 +201,8 @@ struct fe_ctx {
   std::vector<double> eps, coeffs;    // host copies [batch], [batch][6]
   std::vector<double> mu, theta;      // orientation term [batch], [batch][3] (mu = 0: off)
   void* d_prm = nullptr;              // InstParams<T>[batch]
+  void* d_prm_scaled = nullptr;       // InstParams<T>[batch] with the coefficients scaled (fe_grad_scaled_async)
+  const void* prm_active = nullptr;   // the table sweeps read while set (else d_prm)
   double* d_partials = nullptr;       // [2][batch][max_blocks][2]: block partials of two sweeps (steps alternate)
   double* d_energy = nullptr;         // [batch]
   double* d_mass = nullptr;           // [batch]
@@ -484,7 +486,7 @@ int launch_sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst,
   fe::SweepArgs<T> a;
   a.src = static_cast<const T*>(src);
   a.dst = static_cast<T*>(dst);
-  a.prm = static_cast<const fe::InstParams<T>*>(c->d_prm);
+  a.prm = static_cast<const fe::InstParams<T>*>(c->prm_active ? c->prm_active : c->d_prm);
   a.prev_partials = prev_partials;
   a.partials = partials;
   a.mass = c->d_mass;
@@ -850,6 +852,7 @@ int fe_create(const fe_grid* grid, const double* eps, const double* p_coeffs, vo
   c->max_blocks = mb;
   const size_t prm_bytes = grid->dtype == FE_F32 ? sizeof(fe::InstParams<float>) : sizeof(fe::InstParams<double>);
   if (hipMalloc(&c->d_prm, prm_bytes * grid->batch) != hipSuccess ||
+      hipMalloc(&c->d_prm_scaled, prm_bytes * grid->batch) != hipSuccess ||
       hipMalloc((void**)&c->d_partials, sizeof(double) * 4 * mb * grid->batch) != hipSuccess ||
       hipMalloc((void**)&c->d_energy, sizeof(double) * grid->batch) != hipSuccess ||
       hipMalloc((void**)&c->d_mass, sizeof(double) * grid->batch) != hipSuccess ||
@@ -968,6 +971,42 @@ int fe_energy_grad_async(fe_ctx* c, const void* u, void* g, double* energy_dev) 
   if (g == u) return set_error(FE_EINVAL, "g must not alias u");
   DeviceGuard dg(c->device);
   return sweep_energy(c, c->stream, g ? fe::kGrad : -1, u, g, energy_dev ? energy_dev : c->d_energy);
+}
+
+int fe_grad_scaled_async(fe_ctx* c, const void* u, void* g, const double* gscale) {
+  g_last_error.clear();
+  if (!c) return set_error(FE_EINVAL, "ctx is NULL");
+  if (!u || !g || !gscale) return set_error(FE_EINVAL, "u, g and gscale must not be NULL");
+  if (g == u) return set_error(FE_EINVAL, "g must not alias u");
+  DeviceGuard dg(c->device);
+  const StepRule none{fe::kGrad, 0.0, 0.0, 0.0, 0.0};
+  const bool f32 = c->grid.dtype == FE_F32;
+  if (c->use_cfield) {
+    // the coefficients vary per voxel: the plain sweep, then g_b *= s_b
+    int rc = sweep(c, c->stream, fe::kGrad, u, g, nullptr, partials_buf(c, 0), none);
+    if (rc) return rc;
+    const size_t per = (size_t)c->grid.nx * c->grid.ny * c->grid.nz;
+    const dim3 blocks((unsigned)std::min<size_t>((per + 255) / 256, 4096), (unsigned)c->grid.batch);
+    if (f32)
+      hipLaunchKernelGGL(fe::scale_per_instance<float>, blocks, dim3(256), 0, c->stream, (float*)g, per, gscale);
+    else
+      hipLaunchKernelGGL(fe::scale_per_instance<double>, blocks, dim3(256), 0, c->stream, (double*)g, per, gscale);
+    FE_HIP(hipGetLastError());
+    return FE_OK;
+  }
+  if (f32)
+    hipLaunchKernelGGL(fe::scale_params<float>, dim3(1), dim3(64), 0, c->stream,
+                       (const fe::InstParams<float>*)c->d_prm, (fe::InstParams<float>*)c->d_prm_scaled, gscale,
+                       c->grid.batch);
+  else
+    hipLaunchKernelGGL(fe::scale_params<double>, dim3(1), dim3(64), 0, c->stream,
+                       (const fe::InstParams<double>*)c->d_prm, (fe::InstParams<double>*)c->d_prm_scaled, gscale,
+                       c->grid.batch);
+  FE_HIP(hipGetLastError());
+  c->prm_active = c->d_prm_scaled;
+  const int rc = sweep(c, c->stream, fe::kGrad, u, g, nullptr, partials_buf(c, 0), none);
+  c->prm_active = nullptr;
+  return rc;
 }
 
 int fe_energy(fe_ctx* c, const void* u, double* energy) {
@@ -1245,6 +1284,7 @@ void fe_destroy(fe_ctx* c) {
   DeviceGuard dg(c->device);
   drop_graphs(c);
   if (c->d_prm) (void)hipFree(c->d_prm);
+  if (c->d_prm_scaled) (void)hipFree(c->d_prm_scaled);
   if (c->d_partials) (void)hipFree(c->d_partials);
   if (c->d_energy) (void)hipFree(c->d_energy);
   if (c->d_mass) (void)hipFree(c->d_mass);

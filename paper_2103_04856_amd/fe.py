@@ -48,6 +48,7 @@ SIGNATURES = {
     "fe_energy": (ctypes.c_int, [_P, _P, _DP]),
     "fe_energy_grad": (ctypes.c_int, [_P, _P, _P, _DP]),
     "fe_energy_grad_async": (ctypes.c_int, [_P, _P, _P, _P]),
+    "fe_grad_scaled_async": (ctypes.c_int, [_P, _P, _P, _P]),
     "fe_step": (ctypes.c_int, [_P, _P, _DP, ctypes.c_double, ctypes.c_int, _DP]),
     "fe_step_adam": (ctypes.c_int, [_P, _P, _DP, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_int, _DP]),
@@ -258,6 +259,17 @@ class FeContext:
                                           self._field(g, "g") if with_grad else _P(0),
                                           _P(energy_out.data_ptr())))
         return energy_out, g
+
+    def grad_scaled_async(self, u, scale, g=None):
+        """Stream-ordered, no sync: g_b = scale_b dF_h/du_b, scale a float64 device tensor [B]."""
+        if g is None:
+            g = torch.empty_like(u)
+        if not isinstance(scale, torch.Tensor) or scale.device.type != "cuda" or scale.dtype != torch.float64 \
+                or scale.numel() != self.shape[0] or not scale.is_contiguous():
+            raise ValueError(f"scale must be a contiguous float64 device tensor of {self.shape[0]} values")
+        self._sync_stream()
+        _check(lib().fe_grad_scaled_async(self._h, self._field(u, "u"), self._field(g, "g"), _P(scale.data_ptr())))
+        return g
 
     def step(self, u, mass, tau, nsteps):
         """nsteps mass-projected descent steps in place on u; returns F_h before the last step."""
@@ -494,7 +506,8 @@ class FeL2Flow:
 
 class FeEnergy(torch.autograd.Function):
     """E = F_h(u) per instance (float64 [B]); backward recomputes the Hessian and
-    applies the hand-written adjoint kernel: dL/du = sum_b dL/dE_b dF_h/du_b."""
+    applies the hand-written adjoint kernel with the incoming dL/dE_b folded into
+    instance b's coefficients: dL/du_b = dL/dE_b dF_h/du_b, in one sweep."""
 
     @staticmethod
     def forward(ctx, u, fe):
@@ -506,13 +519,8 @@ class FeEnergy(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gE):
         (u,) = ctx.saved_tensors
-        _, g = ctx.fe.energy_grad_async(u.contiguous())
-        scale = gE.to(u.dtype)
-        if u.dim() == 4:
-            scale = scale.view(-1, 1, 1, 1)
-        else:
-            scale = scale.reshape(())
-        return g * scale, None
+        scale = gE.to(torch.float64).reshape(-1).contiguous()
+        return ctx.fe.grad_scaled_async(u.contiguous(), scale), None
 
 
 def feps(u, fe):

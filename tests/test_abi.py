@@ -96,6 +96,7 @@ def test_create_rejects_null_pointers(L):
 
 def test_calls_on_null_context_fail_cleanly(L):
     assert L.fe_energy_grad(None, None, None, None) == fe.FE_EINVAL
+    assert L.fe_grad_scaled_async(None, None, None, None) == fe.FE_EINVAL
     assert L.fe_step(None, None, None, 1e-3, 1, None) == fe.FE_EINVAL
     assert L.fe_set_launch(None, 0, 0) == fe.FE_EINVAL
     assert L.fe_hminus_step(None, None, None, 2.0, 1e-3, 0.9, 0.999, 1e-8, 1, None, None) == fe.FE_EINVAL

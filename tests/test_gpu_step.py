@@ -199,7 +199,8 @@ def test_autograd_function_matches_kernel_gradient():
         E = fe.feps(u, ctx)
         (3.0 * E.sum()).backward()
         _, g = ctx.energy_grad(u.detach())
-        assert torch.allclose(u.grad, 3.0 * g, rtol=1e-6 if dtype == torch.float32 else 1e-14)
+        # the backward folds the incoming 3.0 into the coefficients: equal to rounding
+        assert_same_to_rounding(u.grad, 3.0 * g, dtype, "backward")
         Eo, go = fo.energy_grad(oracle_input(u), h, 2 * h, ASYM_C3)
         assert rel_l2(u.grad.cpu().double().numpy() / 3.0, go) <= (1e-3 if dtype == torch.float32 else 1e-9)
 
@@ -222,6 +223,94 @@ def test_autograd_descent_loop_keeps_mass():
         Es.append(E.item())
     assert abs(u.double().mean().item() - m) < 1e-6
     assert Es[-1] < Es[1]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_grad_scaled_equals_scaled_gradient(dtype):
+    """fe_grad_scaled_async against s_b times fe_energy_grad's gradient, to rounding:
+    three instances (asymmetric p with the orientation term, symmetric p, every term),
+    scales (2.5, -0.75, 0); then the same with a coefficient field (scaled after the
+    sweep); the context's own parameters stay unchanged."""
+    n = 24
+    h = 1.0 / n
+    U = np.stack([inputs.uniform_noise(n, s) for s in (3, 4, 5)])
+    ud = to_dev(U, dtype)
+    ctx = fe.FeContext(ud.shape, h, [2 * h, 1.5 * h, 2 * h], [ASYM_C3, HELFRICH_SC, ALL_TERMS], dtype=dtype)
+    ctx.set_orientation([30.0, 0.0, 5.0], [(0.0, 0.6, 0.8)] * 3)
+    scale = torch.tensor([2.5, -0.75, 0.0], dtype=torch.float64, device="cuda")
+    E0, g0 = ctx.energy_grad(ud)
+    gs = ctx.grad_scaled_async(ud, scale)
+    torch.cuda.synchronize()
+    for b in range(3):
+        ref = g0[b] * scale[b].item()
+        if scale[b].item() == 0.0:
+            assert torch.count_nonzero(gs[b]).item() == 0
+        else:
+            assert_same_to_rounding(gs[b], ref, dtype, f"instance {b}")
+    E1, g1 = ctx.energy_grad(ud)
+    assert torch.equal(E0, E1) and torch.equal(g0, g1)
+    a_field = torch.empty((3, 6) + ud.shape[1:], dtype=dtype, device="cuda")
+    for b, a in enumerate([ASYM_C3, HELFRICH_SC, ALL_TERMS]):
+        for k in range(6):
+            a_field[b, k] = a[k] * (1.0 + 0.1 * torch.rand(ud.shape[1:], device="cuda", dtype=dtype))
+    ctx.set_coeff_field(a_field)
+    _, gf = ctx.energy_grad(ud)
+    gsf = ctx.grad_scaled_async(ud, scale)
+    torch.cuda.synchronize()
+    for b in range(2):
+        assert_same_to_rounding(gsf[b], gf[b] * scale[b].item(), dtype, f"field instance {b}")
+    assert torch.count_nonzero(gsf[2]).item() == 0
+
+
+def _autograd_adam(ctx, x0, m, lr):
+    """The paper's optimisation loop through autograd: y a leaf tensor, E = FeEnergy(y),
+    backward by the adjoint kernel, torch.optim.Adam (fused and capturable: one kernel,
+    its step count and bias corrections on the device), then y <- y + (m - mean y). Returns (y, one step)."""
+    y = x0.clone().requires_grad_(True)
+    opt = torch.optim.Adam([y], lr=lr, fused=True, capturable=True)
+
+    def step():
+        opt.zero_grad(set_to_none=True)
+        fe.feps(y, ctx).sum().backward()
+        opt.step()
+        with torch.no_grad():
+            y.add_(m - y.mean())
+    return y, step
+
+
+@pytest.mark.parametrize("n,dtype", [(20, torch.float64), (128, torch.float32)])
+def test_graph_captured_autograd_step_equals_eager(n, dtype):
+    """The autograd-driven Adam step (energy-only sweep forward, adjoint sweep backward,
+    torch Adam, mass projection) captured in a CUDA graph after three eager steps: four
+    replays, each followed by eager work on the same context and a synchronisation, each
+    equal bit for bit to the same step run eagerly from the same state."""
+    h = 1.0 / n
+    ctx = fe.FeContext((1, n, n, n), h, 2 * h, ASYM_C3, dtype=dtype)
+    x0 = to_dev(inputs.uniform_noise(n, 1003), dtype)
+    yg, step_g = _autograd_adam(ctx, x0, -0.3, 1e-3)
+    ye, step_e = _autograd_adam(ctx, x0, -0.3, 1e-3)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            step_g()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step_g()
+    for _ in range(3):
+        step_e()
+    assert torch.equal(yg, ye)
+    other = to_dev(inputs.uniform_noise(n, 77), dtype)
+    for r in range(4):
+        graph.replay()
+        step_e()
+        torch.cuda.synchronize()
+        assert torch.isfinite(yg).all() and torch.equal(yg, ye), f"replay {r}"
+        ctx.energy_grad(other)                     # eager work on the same context between replays
+        torch.cuda.synchronize()
+    assert abs(yg.double().mean().item() + 0.3) < (1e-12 if dtype == torch.float64 else 1e-6)
+    assert not torch.equal(yg, x0)
 
 
 def _adam_reference(U0, h, eps, a, m, nsteps, vtol):
