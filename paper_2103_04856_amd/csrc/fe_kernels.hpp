@@ -720,14 +720,48 @@ __global__ __launch_bounds__(64) void adam_tick(int* t, int n) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *t += n;
 }
 
-// dst[b][i] = src[b][i] + shift[b] (src may equal dst).
+// dst[b][i] = src[b][i] + shift[b] (src may equal dst). Grid: x over the
+// instance's voxels, y over instances. VEC: 16-byte groups (the host checks
+// alignment and that an instance is a whole number of groups), each thread
+// issuing its four loads before its four stores.
 template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static __device__ __forceinline__ float4 add(float4 v, float s) { return make_float4(v.x + s, v.y + s, v.z + s, v.w + s); }
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static __device__ __forceinline__ double2 add(double2 v, double s) { return make_double2(v.x + s, v.y + s); }
+};
+
+template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void add_shift(const T* src, T* dst, const double* __restrict__ shift,
-                                                 size_t per_inst, int batch) {
-  const size_t n = per_inst * (size_t)batch;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const int b = (int)(i / per_inst);
-    dst[i] = src[i] + T(shift[b]);
+                                                 size_t per_inst) {
+  const T s = T(shift[blockIdx.y]);
+  const T* sb = src + (size_t)blockIdx.y * per_inst;
+  T* db = dst + (size_t)blockIdx.y * per_inst;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if constexpr (VEC) {
+    using V = typename Vec16<T>::type;
+    constexpr int U = 4;
+    const size_t ng = per_inst / (16 / sizeof(T));
+    const V* sv = reinterpret_cast<const V*>(sb);
+    V* dv = reinterpret_cast<V*>(db);
+    for (size_t i = i0; i < ng; i += U * stride) {
+      V r[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k)
+        if (i + k * stride < ng) r[k] = sv[i + k * stride];
+#pragma unroll
+      for (int k = 0; k < U; ++k)
+        if (i + k * stride < ng) dv[i + k * stride] = Vec16<T>::add(r[k], s);
+    }
+  } else {
+    for (size_t i = i0; i < per_inst; i += stride) db[i] = sb[i] + s;
   }
 }
 

@@ -647,6 +647,32 @@ void drop_graphs(fe_ctx* c) {
   c->graphs.clear();
 }
 
+// u = last + shift per instance (last may be u): 16-byte accesses when both
+// fields are 16-byte aligned and an instance is a whole number of groups.
+int launch_add_shift(fe_ctx* c, const void* last, void* u, const double* shift) {
+  const size_t per_inst = (size_t)c->grid.nx * c->grid.ny * c->grid.nz;
+  const size_t w = 16 / elem_size(c->grid);
+  const bool vec = per_inst % w == 0 && (uintptr_t)last % 16 == 0 && (uintptr_t)u % 16 == 0;
+  const size_t work = vec ? (per_inst / w + 3) / 4 : per_inst;     // per thread: 4 groups, or 1 voxel
+  const dim3 blocks((unsigned)std::max<size_t>(1, std::min<size_t>((work + 255) / 256, 4096)),
+                    (unsigned)c->grid.batch);
+  const bool f32 = c->grid.dtype == FE_F32;
+  if (f32 && vec)
+    hipLaunchKernelGGL((fe::add_shift<float, true>), blocks, dim3(256), 0, c->stream, (const float*)last, (float*)u,
+                       shift, per_inst);
+  else if (f32)
+    hipLaunchKernelGGL((fe::add_shift<float, false>), blocks, dim3(256), 0, c->stream, (const float*)last,
+                       (float*)u, shift, per_inst);
+  else if (vec)
+    hipLaunchKernelGGL((fe::add_shift<double, true>), blocks, dim3(256), 0, c->stream, (const double*)last,
+                       (double*)u, shift, per_inst);
+  else
+    hipLaunchKernelGGL((fe::add_shift<double, false>), blocks, dim3(256), 0, c->stream, (const double*)last,
+                       (double*)u, shift, per_inst);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
 int adam_tick_launch(fe_ctx* c, hipStream_t s, int n) {
   hipLaunchKernelGGL(fe::adam_tick, dim3(1), dim3(64), 0, s, c->d_adam_t, n);
   FE_HIP(hipGetLastError());
@@ -750,15 +776,7 @@ int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int 
   // the energy of the last step's input and the shift of its output
   double* shift = c->d_shift;
   if ((rc = finish_sums(c, c->stream, last_p, c->d_energy, shift))) return rc;
-  const size_t per_inst = (size_t)c->grid.nx * c->grid.ny * c->grid.nz;
-  const int nblk = (int)std::min<size_t>((field_elems(c->grid) + 255) / 256, 65536);
-  if (c->grid.dtype == FE_F32)
-    hipLaunchKernelGGL(fe::add_shift<float>, dim3(nblk), dim3(256), 0, c->stream, (const float*)last, (float*)u,
-                       shift, per_inst, B);
-  else
-    hipLaunchKernelGGL(fe::add_shift<double>, dim3(nblk), dim3(256), 0, c->stream, (const double*)last,
-                       (double*)u, shift, per_inst, B);
-  FE_HIP(hipGetLastError());
+  if ((rc = launch_add_shift(c, last, u, shift))) return rc;
   return copy_energy_out(c, energy);
 }
 
