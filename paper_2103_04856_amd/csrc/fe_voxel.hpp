@@ -170,6 +170,48 @@ __device__ __forceinline__ Forward<T> forward_fp64(const Stencil19<T>& s, const 
   return o;
 }
 
+// The FP32 chain's re-evaluation where X~ is ill-conditioned: the differences,
+// the matrix entries and the invariants again in FP64 from the same samples,
+// overwriting only what the cancellation in X~ spoils (m, o, 2m - T~, T~, N~,
+// X~). |a|^2, R, 1/R, 1/sqrt(R) and the a themselves carry no cancellation
+// (sums of squares; a single difference of two samples is off by at most one
+// FP32 rounding), so the FP32 values stand; lam W'(u) / R is formed in FP64
+// here because the m_aa subtract it times a_a^2 from b_aa.
+__device__ __forceinline__ void redo_fp64(const Stencil19<float>& s, const InstParams<float>& p,
+                                          const GridConsts<float>& k, Forward<float>& o) {
+  const double c = s.c;
+  const double ax = double(s.xp) - double(s.xm);
+  const double ay = double(s.yp) - double(s.ym);
+  const double az = double(s.zp) - double(s.zm);
+  const double c2u = c + c;
+  const double bxx = double(s.xp) + double(s.xm) - c2u;
+  const double byy = double(s.yp) + double(s.ym) - c2u;
+  const double bzz = double(s.zp) + double(s.zm) - c2u;
+  const double bxy = (double(s.xpyp) - double(s.xpym)) - (double(s.xmyp) - double(s.xmym));
+  const double bxz = (double(s.xpzp) - double(s.xpzm)) - (double(s.xmzp) - double(s.xmzm));
+  const double byz = (double(s.ypzp) - double(s.ypzm)) - (double(s.ymzp) - double(s.ymzm));
+  const double axx = ax * ax, ayy = ay * ay, azz = az * az;
+  const double R = (axx + ayy + azz) + k.reg_d;
+  const double sw = p.lam_d * c * (c * c - 1.0) * rcp_f64(R);
+  const double sw4 = 4.0 * sw;
+  const double mxx = sw * axx - bxx;
+  const double myy = sw * ayy - byy;
+  const double mzz = sw * azz - bzz;
+  const double oxy = sw4 * (ax * ay) - bxy;
+  const double oxz = sw4 * (ax * az) - bxz;
+  const double oyz = sw4 * (ay * az) - byz;
+  const double tr = mxx + myy + mzz;
+  const double n2 = (mxx * mxx + myy * myy + mzz * mzz) + 0.125 * (oxy * oxy + oxz * oxz + oyz * oyz);
+  o.mxx = float(mxx); o.myy = float(myy); o.mzz = float(mzz);
+  o.oxy = float(oxy); o.oxz = float(oxz); o.oyz = float(oyz);
+  o.dxx = float(2.0 * mxx - tr);
+  o.dyy = float(2.0 * myy - tr);
+  o.dzz = float(2.0 * mzz - tr);
+  o.tr = float(tr);
+  o.n2 = float(n2);
+  o.X = float(2.0 * n2 - tr * tr);
+}
+
 // Whether the density has the S~ terms: C3 (a20 - a02) and C5 (a10 - a01)
 // vanish for every p symmetric in kappa1 and kappa2 (Willmore, Helfrich), and
 // then S~, its softplus and dS~/dX~ meet only zero coefficients: f~ and its
@@ -249,7 +291,7 @@ __device__ __forceinline__ Forward<float> forward_chain(const Stencil19<float>& 
                                                         const GridConsts<float>& k) {
   bool redo;
   Forward<float> o = forward_fp32<NOS>(s, p, k, redo);
-  if (redo) o = forward_fp64(reload(), p, k);
+  if (redo) redo_fp64(reload(), p, k, o);
   return o;
 }
 
