@@ -34,6 +34,16 @@ namespace fe {
 
 constexpr int kWave = 64;
 
+// A lane's byte offset into a plane, made opaque to the optimiser where a loop
+// over planes uses it: the access then stays a block-uniform plane address
+// (scalar registers, advanced by the scalar unit) plus this 32-bit offset,
+// instead of a 64-bit per-lane pointer advanced with vector arithmetic every
+// plane. The empty statement emits no instruction.
+__device__ __forceinline__ unsigned lane_offset(unsigned o) {
+  __asm__("" : "+v"(o));
+  return o;
+}
+
 __device__ __forceinline__ int wrap_index(int v, int n) {
   int r = v % n;
   return r < 0 ? r + n : r;
@@ -271,21 +281,35 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
     bc2 = T(1.0 / (1.0 - ::pow(double(a.beta2), double(t))));
   }
 
-  // In-plane offsets of the u window, computed once (periodic wrap in x, y).
-  int uoff[NU];
+  // In-plane byte offsets of the u window (periodic wrap in x, y) and of this
+  // thread's output voxels, computed once. A plane is under 4 GiB (checked on the
+  // host), so every load and store is a block-uniform plane address plus a 32-bit
+  // lane offset, with no 64-bit address arithmetic per access.
+  unsigned uoff[NU];
 #pragma unroll
   for (int j = 0; j < NU; ++j) {
     const int e = tid + j * NT;
     const int ex = e % UX, ey = e / UX;
-    uoff[j] = (e < UX * UY) ? wrap_index(y0 - 2 + ey, a.ny) * a.nx + wrap_index(x0 - 2 + ex, a.nx) : 0;
+    uoff[j] = (e < UX * UY)
+                  ? (unsigned)(wrap_index(y0 - 2 + ey, a.ny) * a.nx + wrap_index(x0 - 2 + ex, a.nx)) * sizeof(T)
+                  : 0u;
+  }
+  unsigned ooff[NO];
+  bool oin[NO];                                // an output voxel inside the grid
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    const int w = tid + j * NT;
+    const int gx = x0 + w % TX, gy = y0 + w / TX;
+    oin[j] = w < TX * TY && gx < a.nx && gy < a.ny;
+    ooff[j] = oin[j] ? (unsigned)(gy * a.nx + gx) * sizeof(T) : 0u;
   }
   T pre[NU];
   T shift = T(0);                              // steps: the uniform shift of src, set below
   auto fetch = [&](int p) {
-    const T* sp = srcb + (size_t)wrap_index(p, a.nz) * plane;
+    const char* sp = reinterpret_cast<const char*>(srcb + (size_t)wrap_index(p, a.nz) * plane);
 #pragma unroll
     for (int j = 0; j < NU; ++j)
-      if (tid + j * NT < UX * UY) pre[j] = sp[uoff[j]];
+      if (tid + j * NT < UX * UY) pre[j] = *reinterpret_cast<const T*>(sp + lane_offset(uoff[j]));
   };
   auto stage = [&](int slot) {
 #pragma unroll
@@ -356,14 +380,14 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
         m2c[j] = m2n[j];
       }
       if (it + 1 < nit && p >= k0) {
+        const size_t po = inst_off + (size_t)p * plane;
+        const char* m1p = reinterpret_cast<const char*>(a.m1 + po);
+        const char* m2p = reinterpret_cast<const char*>(a.m2 + po);
 #pragma unroll
         for (int j = 0; j < NO; ++j) {
-          const int w = tid + j * NT;
-          const int gx = x0 + w % TX, gy = y0 + w / TX;
-          const size_t gi = inst_off + (size_t)p * plane + (size_t)gy * a.nx + gx;
-          const bool ok = w < TX * TY && gx < a.nx && gy < a.ny;
-          m1n[j] = ok ? a.m1[gi] : T(0);
-          m2n[j] = ok ? a.m2[gi] : T(0);
+          const unsigned o = lane_offset(ooff[j]);
+          m1n[j] = oin[j] ? *reinterpret_cast<const T*>(m1p + o) : T(0);
+          m2n[j] = oin[j] ? *reinterpret_cast<const T*>(m2p + o) : T(0);
         }
       }
     }
@@ -445,6 +469,8 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
     // here; GX, GY hold half the a_x, a_y derivatives and BXY, BXZ, BYZ twice
     // the (negated) b_ab ones, hence the factors 2 and 1/2.
     T mpl = T(0);                              // this thread's sum of the field written for plane p - 1
+    const size_t po = (size_t)(it >= 2 ? p - 1 : 0) * plane;   // output plane p - 1 (written from it = 2)
+    char* dpl = reinterpret_cast<char*>(dstb + po);
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
       const int w = tid + j * NT;
@@ -455,28 +481,26 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
         const T bzz = own_bzz[j], gz = own_gz[j];
         const T upn = bzz + gz + d;    // minus what plane p adds to output plane p-1
         const T lo = gz + d - bzz;     // what plane p adds to output plane p+1
-        if (it >= 2) {
-          const int gx = x0 + ix, gy = y0 + iy;
-          if (gx < a.nx && gy < a.ny) {
-            const T g = (c_prev[j] - upn) + l_pp[j];
-            const size_t idx = (size_t)(p - 1) * plane + (size_t)gy * a.nx + gx;
-            const T uc = u_out[j];
-            if (MODE == kStepGD) {
-              const T un = uc - a.tau * g;
-              dstb[idx] = un;
-              mpl += un;
-            } else if (MODE == kStepAdam) {
-              const T mo = a.beta1 * m1c[j] + (T(1) - a.beta1) * g;
-              const T vo = a.beta2 * m2c[j] + (T(1) - a.beta2) * g * g;
-              a.m1[inst_off + idx] = mo;
-              a.m2[inst_off + idx] = vo;
-              const T un = uc - a.tau * (mo * bc1) * rcp_t(sqrt_t(vo * bc2) + a.adam_eps);
-              dstb[idx] = un;
-              mpl += un;
-            } else {
-              dstb[idx] = g;
-              mpl += uc;
-            }
+        if (it >= 2 && oin[j]) {
+          const T g = (c_prev[j] - upn) + l_pp[j];
+          const unsigned o = lane_offset(ooff[j]);
+          T* dp = reinterpret_cast<T*>(dpl + o);
+          const T uc = u_out[j];
+          if (MODE == kStepGD) {
+            const T un = uc - a.tau * g;
+            *dp = un;
+            mpl += un;
+          } else if (MODE == kStepAdam) {
+            const T mo = a.beta1 * m1c[j] + (T(1) - a.beta1) * g;
+            const T vo = a.beta2 * m2c[j] + (T(1) - a.beta2) * g * g;
+            *reinterpret_cast<T*>(reinterpret_cast<char*>(a.m1 + inst_off + po) + o) = mo;
+            *reinterpret_cast<T*>(reinterpret_cast<char*>(a.m2 + inst_off + po) + o) = vo;
+            const T un = uc - a.tau * (mo * bc1) * rcp_t(sqrt_t(vo * bc2) + a.adam_eps);
+            *dp = un;
+            mpl += un;
+          } else {
+            *dp = g;
+            mpl += uc;
           }
         }
         const T cin = own_c0[j]

@@ -245,8 +245,9 @@ int check_grid(const fe_grid* g) {
   if (!(g->h > 0.0) || !std::isfinite(g->h)) return set_error(FE_EINVAL, "h must be finite and > 0");
   if (g->dtype != FE_F32 && g->dtype != FE_F64) return set_error(FE_EINVAL, "dtype must be FE_F32 or FE_F64");
   const double n = (double)g->nx * g->ny * g->nz;
-  if (n * g->batch > 4.0e9 || (double)g->nx * g->ny > 2.0e9)
-    return set_error(FE_EINVAL, "grid too large for 32-bit plane indexing");
+  const double plane_bytes = (double)g->nx * g->ny * (g->dtype == FE_F64 ? 8.0 : 4.0);
+  if (n * g->batch > 4.0e9 || plane_bytes >= 4294967296.0)
+    return set_error(FE_EINVAL, "grid too large for 32-bit plane indexing (planes must be under 4 GiB)");
   return FE_OK;
 }
 

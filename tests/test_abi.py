@@ -74,6 +74,13 @@ def test_create_rejects_bad_grid(L, field, value, msg):
     assert rc == fe.FE_EINVAL and not out.value and msg in err
 
 
+@pytest.mark.parametrize("nx,ny,dtype", [(40000, 30000, 0), (30000, 20000, 1)])
+def test_create_rejects_planes_of_4_gib(L, nx, ny, dtype):
+    rc, out, err = _create(L, fe.FeGrid(nx=nx, ny=ny, nz=1, batch=1, h=0.125, dtype=dtype), [0.25],
+                           [1, 2, 1, 0, 0, 0])
+    assert rc == fe.FE_EINVAL and not out.value and "too large" in err
+
+
 @pytest.mark.parametrize("eps,coeffs,msg", [
     ([0.0], [1, 2, 1, 0, 0, 0], "eps[0]"),
     ([-1.0], [1, 2, 1, 0, 0, 0], "eps[0]"),

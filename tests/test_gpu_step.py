@@ -69,6 +69,27 @@ def test_mass_is_exact_every_step():
             assert abs(s - (-0.3) * n ** 3) <= tol * u.double().abs().sum().item(), (dtype, k, s)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_steps_on_an_odd_sized_batch(dtype):
+    """Two instances of 13 x 11 x 7 (1001 voxels: the final shift takes its scalar path,
+    no 16-byte groups) with their own masses: three steps against the oracle, each
+    instance's mean exact."""
+    shape = (7, 11, 13)
+    h = 1.0 / 13
+    U = np.stack([inputs.uniform_noise(16, s)[:7, :11, :13] for s in (41, 42)])
+    ud = to_dev(U, dtype)
+    masses = [-0.2, 0.15]
+    ctx = fe.FeContext(ud.shape, h, [2 * h, 2 * h], [WILLMORE_QUARTER, HELFRICH_SC], dtype=dtype)
+    Uo = oracle_input(ud)
+    ctx.step(ud, masses, 1e-3, 3)
+    for b in range(2):
+        uo, _ = fo.descend(Uo[b], h, 2 * h, [WILLMORE_QUARTER, HELFRICH_SC][b], masses[b], 1e-3, 3)
+        err = rel_l2(ud[b].cpu().double().numpy(), uo)
+        assert err <= (1e-11 if dtype == torch.float64 else 1e-5), (b, err)
+        mean = ud[b].double().mean().item()
+        assert abs(mean - masses[b]) <= (1e-13 if dtype == torch.float64 else 1e-6), (b, mean)
+
+
 def test_energy_decreases_after_first_step():
     """Config-1 flow (32^3 FP64, tau = 1e-3): monotone decrease after step 1 and the
     energy after 200 steps within 1% of the oracle run."""
