@@ -635,19 +635,22 @@ __global__ __launch_bounds__(64 * NWV) void energy_sweep_cols(SweepArgs<T> a) {
   const T* srcb = a.src + (size_t)bt.inst * a.nz * plane;
   const InstParams<T> prm = a.prm[bt.inst];
 
-  int uoff[NU];
+  // byte offsets within a plane (under 4 GiB), as in grad_sweep
+  unsigned uoff[NU];
 #pragma unroll
   for (int j = 0; j < NU; ++j) {
     const int e = tid + j * NT;
     const int ex = e % UX, ey = e / UX;
-    uoff[j] = (e < UX * UY) ? wrap_index(y0 - 1 + ey, a.ny) * a.nx + wrap_index(x0 - 1 + ex, a.nx) : 0;
+    uoff[j] = (e < UX * UY)
+                  ? (unsigned)(wrap_index(y0 - 1 + ey, a.ny) * a.nx + wrap_index(x0 - 1 + ex, a.nx)) * sizeof(T)
+                  : 0u;
   }
   T pre[NU];
   auto fetch = [&](int p) {
-    const T* sp = srcb + (size_t)wrap_index(p, a.nz) * plane;
+    const char* sp = reinterpret_cast<const char*>(srcb + (size_t)wrap_index(p, a.nz) * plane);
 #pragma unroll
     for (int j = 0; j < NU; ++j)
-      if (tid + j * NT < UX * UY) pre[j] = sp[uoff[j]];
+      if (tid + j * NT < UX * UY) pre[j] = *reinterpret_cast<const T*>(sp + lane_offset(uoff[j]));
   };
   auto stage = [&](int slot) {
 #pragma unroll
