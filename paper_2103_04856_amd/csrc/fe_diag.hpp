@@ -55,7 +55,7 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
   constexpr int UX = TX + 2, UY = TY + 2;
   constexpr int NU = (UX * UY + NT - 1) / NT;
   constexpr int NO = (TX * TY + NT - 1) / NT;
-  __shared__ T su[3][UY * UX];
+  __shared__ T su[4][UY * UX];                 // four plane slots: one barrier per plane
   __shared__ double shist[kDiagMaxBins * kDiagMaxBins];
   __shared__ double sred[NT / kWave][kDiagStats];
 
@@ -70,19 +70,36 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
   const int nb2 = d.hist ? d.nbins * d.nbins : 0;
   for (int i = tid; i < nb2; i += NT) shist[i] = 0.0;
 
-  int uoff[NU];
+  // byte offsets within a plane (under 4 GiB): the u window, and this thread's
+  // output voxels for the curvature fields
+  unsigned uoff[NU];
 #pragma unroll
   for (int j = 0; j < NU; ++j) {
     const int e = tid + j * NT;
     const int ex = e % UX, ey = e / UX;
-    uoff[j] = (e < UX * UY) ? wrap_index(y0 - 1 + ey, a.ny) * a.nx + wrap_index(x0 - 1 + ex, a.nx) : 0;
+    uoff[j] = (e < UX * UY)
+                  ? (unsigned)(wrap_index(y0 - 1 + ey, a.ny) * a.nx + wrap_index(x0 - 1 + ex, a.nx)) * sizeof(T)
+                  : 0u;
   }
-  auto load_plane = [&](int p, int slot) {
-    const T* sp = srcb + (size_t)wrap_index(p, a.nz) * plane;
+  unsigned ooff[NO];
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    const int w = tid + j * NT;
+    ooff[j] = (unsigned)((y0 + w / TX) * a.nx + x0 + w % TX) * sizeof(T);
+  }
+  // the next plane is loaded into registers while the current one is computed
+  T pre[NU];
+  auto fetch = [&](int p) {
+    const char* sp = reinterpret_cast<const char*>(srcb + (size_t)wrap_index(p, a.nz) * plane);
+#pragma unroll
+    for (int j = 0; j < NU; ++j)
+      if (tid + j * NT < UX * UY) pre[j] = *reinterpret_cast<const T*>(sp + lane_offset(uoff[j]));
+  };
+  auto stage = [&](int slot) {
 #pragma unroll
     for (int j = 0; j < NU; ++j) {
       const int e = tid + j * NT;
-      if (e < UX * UY) su[slot][e] = sp[uoff[j]];
+      if (e < UX * UY) su[slot][e] = pre[j];
     }
   };
 
@@ -93,12 +110,18 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
   // runs are summed in a register and reach LDS with one atomic
   int run_bin = -1;
   double run_w = 0.0;
-  load_plane(k0 - 1, 0);
-  load_plane(k0, 1);
+  fetch(k0 - 1);
+  stage(0);
+  fetch(k0);
+  stage(1);
+  fetch(k0 + 1);
   for (int it = 0; it < kend - k0; ++it) {
     const int p = k0 + it;
-    const int sm = it % 3, sc = (it + 1) % 3, sp = (it + 2) % 3;
-    load_plane(p + 1, sp);
+    // planes p - 1, p, p + 1 in slots it, it + 1, it + 2 (mod 4): the slot staged
+    // here was last read two planes ago, before the previous plane's barrier
+    const int sm = it & 3, sc = (it + 1) & 3, sp = (it + 2) & 3;
+    stage(sp);                                 // plane p + 1
+    if (it + 1 < kend - k0) fetch(p + 2);      // in flight during this plane's compute
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
@@ -127,11 +150,13 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
         const T sq = fw.X > T(0) ? sqrt_t(fw.X) : T(0);
         const T k1 = (fw.tr + sq) * rs, k2 = (fw.tr - sq) * rs;
         if (d.curv) {
-          const size_t o = (size_t)bt.inst * 4 * vol + gi;
-          d.curv[o] = T(2) * fw.tr * rs;
-          d.curv[o + vol] = T(2) * (fw.tr * fw.tr - fw.n2) * (d.inv_h2 * rcp_t(fw.R));
-          d.curv[o + 2 * vol] = k1;
-          d.curv[o + 3 * vol] = k2;
+          char* cb = reinterpret_cast<char*>(d.curv + (size_t)bt.inst * 4 * vol + (size_t)p * plane);
+          const unsigned o = lane_offset(ooff[j]);
+          const size_t fb = vol * sizeof(T);     // bytes per field
+          *reinterpret_cast<T*>(cb + o) = T(2) * fw.tr * rs;
+          *reinterpret_cast<T*>(cb + fb + o) = T(2) * (fw.tr * fw.tr - fw.n2) * (d.inv_h2 * rcp_t(fw.R));
+          *reinterpret_cast<T*>(cb + 2 * fb + o) = k1;
+          *reinterpret_cast<T*>(cb + 3 * fb + o) = k2;
         }
         if (d.hist) {
           const double wgt = di.cw * double(fw.Q);
@@ -148,7 +173,6 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
         }
       }
     }
-    __syncthreads();
   }
   if (run_bin >= 0) unsafeAtomicAdd(&shist[run_bin], run_w);
 
