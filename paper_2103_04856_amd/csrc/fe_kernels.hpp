@@ -328,7 +328,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   // SP: in-plane offsets of this thread's ring voxels and their coefficients
   const size_t vol = plane * a.nz;
   const T* cfb = SP ? a.cfield + (size_t)bt.inst * 6 * vol : nullptr;
-  int coff[SP ? NW : 1];
+  unsigned coff[SP ? NW : 1];                  // byte offsets within a plane
   VoxelCoeffs<T> cv[SP ? NW : 1];
   if (SP) {
 #pragma unroll
@@ -337,7 +337,8 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
       int v = 0;
       if (item < NI) v = (item / TX + 1) * RX + item % TX + 1;
       else if (item < NI + NB) v = border_pos(item - NI);
-      coff[j] = wrap_index(y0 - 1 + v / RX, a.ny) * a.nx + wrap_index(x0 - 1 + v % RX, a.nx);
+      coff[j] = (unsigned)(wrap_index(y0 - 1 + v / RX, a.ny) * a.nx + wrap_index(x0 - 1 + v % RX, a.nx)) *
+                sizeof(T);
     }
   }
 
@@ -395,7 +396,14 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
       const size_t zoff = (size_t)wrap_index(p, a.nz) * plane;
 #pragma unroll
       for (int j = 0; j < NW; ++j)
-        if (tid + j * NT < NI + NB) cv[j] = load_coeffs(cfb, vol, zoff + coff[j]);
+        if (tid + j * NT < NI + NB) {
+          // the six coefficient fields of plane p: uniform addresses, one lane offset
+          const char* cp = reinterpret_cast<const char*>(cfb + zoff);
+          const unsigned o = lane_offset(coff[j]);
+#pragma unroll
+          for (int k = 0; k < 6; ++k)
+            cv[j].c[k] = *reinterpret_cast<const T*>(cp + (size_t)k * vol * sizeof(T) + o);
+        }
     }
     __syncthreads();
 
