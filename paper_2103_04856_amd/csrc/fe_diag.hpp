@@ -89,12 +89,13 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
   }
   // the next plane is loaded into registers while the current one is computed
   T pre[NU];
-  auto fetch = [&](int p) {
-    const char* sp = reinterpret_cast<const char*>(srcb + (size_t)wrap_index(p, a.nz) * plane);
+  auto fetch_wrapped = [&](int pw) {          // pw: a plane index already in [0, nz)
+    const char* sp = reinterpret_cast<const char*>(srcb + (size_t)pw * plane);
 #pragma unroll
     for (int j = 0; j < NU; ++j)
       if (tid + j * NT < UX * UY) pre[j] = *reinterpret_cast<const T*>(sp + lane_offset(uoff[j]));
   };
+  auto fetch = [&](int p) { fetch_wrapped(wrap_index(p, a.nz)); };
   auto stage = [&](int slot) {
 #pragma unroll
     for (int j = 0; j < NU; ++j) {
@@ -115,13 +116,15 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
   fetch(k0);
   stage(1);
   fetch(k0 + 1);
+  int pf = wrap_index(k0 + 2, a.nz);           // plane p + 2, wrapped (advanced by one per plane)
   for (int it = 0; it < kend - k0; ++it) {
     const int p = k0 + it;
     // planes p - 1, p, p + 1 in slots it, it + 1, it + 2 (mod 4): the slot staged
     // here was last read two planes ago, before the previous plane's barrier
     const int sm = it & 3, sc = (it + 1) & 3, sp = (it + 2) & 3;
     stage(sp);                                 // plane p + 1
-    if (it + 1 < kend - k0) fetch(p + 2);      // in flight during this plane's compute
+    if (it + 1 < kend - k0) fetch_wrapped(pf); // plane p + 2, in flight during this plane's compute
+    pf = pf + 1 == a.nz ? 0 : pf + 1;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < NO; ++j) {

@@ -305,12 +305,13 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   }
   T pre[NU];
   T shift = T(0);                              // steps: the uniform shift of src, set below
-  auto fetch = [&](int p) {
-    const char* sp = reinterpret_cast<const char*>(srcb + (size_t)wrap_index(p, a.nz) * plane);
+  auto fetch_wrapped = [&](int pw) {          // pw: a plane index already in [0, nz)
+    const char* sp = reinterpret_cast<const char*>(srcb + (size_t)pw * plane);
 #pragma unroll
     for (int j = 0; j < NU; ++j)
       if (tid + j * NT < UX * UY) pre[j] = *reinterpret_cast<const T*>(sp + lane_offset(uoff[j]));
   };
+  auto fetch = [&](int p) { fetch_wrapped(wrap_index(p, a.nz)); };
   auto stage = [&](int slot) {
 #pragma unroll
     for (int j = 0; j < NU; ++j) {
@@ -367,10 +368,12 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
 
   const int nit = (kend - k0) + 2;             // forward planes k0-1 .. kend
   int sm = 0, sc = 1, sp = 2;                  // slots of p-1, p, p+1
+  int pf = wrap_index(k0 + 1, a.nz);           // plane p + 2, wrapped (advanced by one per plane)
   for (int it = 0; it < nit; ++it) {
     const int p = k0 - 1 + it;
     stage(sp);
-    if (it + 1 < nit) fetch(p + 2);            // in flight during this plane's compute
+    if (it + 1 < nit) fetch_wrapped(pf);       // plane p + 2, in flight during this plane's compute
+    pf = pf + 1 == a.nz ? 0 : pf + 1;
     // Adam moments of output plane p (written in the next iteration), loaded a
     // whole plane ahead: the wait for them then leaves this plane's stores in
     // flight (loads and stores share one in-order counter)
@@ -654,12 +657,13 @@ __global__ __launch_bounds__(64 * NWV) void energy_sweep_cols(SweepArgs<T> a) {
                   : 0u;
   }
   T pre[NU];
-  auto fetch = [&](int p) {
-    const char* sp = reinterpret_cast<const char*>(srcb + (size_t)wrap_index(p, a.nz) * plane);
+  auto fetch_wrapped = [&](int pw) {          // pw: a plane index already in [0, nz)
+    const char* sp = reinterpret_cast<const char*>(srcb + (size_t)pw * plane);
 #pragma unroll
     for (int j = 0; j < NU; ++j)
       if (tid + j * NT < UX * UY) pre[j] = *reinterpret_cast<const T*>(sp + lane_offset(uoff[j]));
   };
+  auto fetch = [&](int p) { fetch_wrapped(wrap_index(p, a.nz)); };
   auto stage = [&](int slot) {
 #pragma unroll
     for (int j = 0; j < NU; ++j) {
@@ -712,10 +716,12 @@ __global__ __launch_bounds__(64 * NWV) void energy_sweep_cols(SweepArgs<T> a) {
     };
     // plane p: stage p + 1 (into the slot of p - 1), prefetch p + 2, barrier,
     // window of p + 1, then the V voxels of plane p
+    int pf = wrap_index(k0 + 2, a.nz);         // plane p + 2, wrapped (advanced by one per plane)
     auto plane_step = [&](int p, const T (&m)[WR][3], const T (&c)[WR][3], T (&pl)[WR][3]) {
       const int slot = (p - k0 + 2) & 1;
       stage(slot);
-      if (p + 2 <= kend) fetch(p + 2);
+      if (p + 2 <= kend) fetch_wrapped(pf);
+      pf = pf + 1 == a.nz ? 0 : pf + 1;
       __syncthreads();
       read_window(slot, pl);
       compute(m, c, pl);
