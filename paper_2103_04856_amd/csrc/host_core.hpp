@@ -543,8 +543,8 @@ int finish_sums(fe_ctx* c, hipStream_t s, const double* partials, double* energy
 }
 
 // The energy-only sweep (fe::energy_sweep_cols): one x column per lane, 64-wide
-// tiles of 8 waves, 2 rows per thread in FP32 (64 x 16 tiles, 110 VGPRs), 1 in
-// FP64 (64 x 8, 120 VGPRs): two blocks per CU. 256^3 FP32, measured against 3
+// tiles of 8 waves, 2 rows per thread in FP32 (64 x 16 tiles, 106 VGPRs), 1 in
+// FP64 (64 x 8, 119 VGPRs): two blocks per CU. 256^3 FP32, measured against 3
 // and 4 rows per thread, 4 and 16 waves per block and chunks of 8 to 64
 // planes: 31.5 us (symmetric p) and 47 us (full body) at 32-plane chunks, the
 // makespan model's choice, within 2% of the fastest of those shapes.
