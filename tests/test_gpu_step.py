@@ -334,6 +334,39 @@ def test_graph_captured_autograd_step_equals_eager(n, dtype):
     assert not torch.equal(yg, x0)
 
 
+def test_config_128cubed_2000_autograd_adam_steps():
+    """The 128^3 asymmetric-p workload driven through autograd for 2000 steps (the step
+    captured in a CUDA graph and replayed): the field stays finite, keeps its mean -0.3
+    and its energy falls."""
+    n = 128
+    h = 1.0 / n
+    ctx = fe.FeContext((1, n, n, n), h, 2 * h, ASYM_C3, dtype=torch.float32)
+    x0 = to_dev(inputs.uniform_noise(n, 1003), torch.float32)
+    E0 = ctx.energy(x0)[0].item()
+    y, step = _autograd_adam(ctx, x0, -0.3, 1e-3)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            step()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    Es = []
+    for k in range(1997):
+        graph.replay()
+        if (k + 1) % 499 == 0:
+            torch.cuda.synchronize()
+            Es.append(ctx.energy(y.detach())[0].item())
+    torch.cuda.synchronize()
+    E1 = ctx.energy(y.detach())[0].item()
+    log(f"  2000 autograd Adam steps: F_h {E0:.6g} -> {E1:.6g} (every 499: {Es})")
+    assert torch.isfinite(y).all()
+    assert abs(y.double().mean().item() + 0.3) < 1e-5
+    assert np.isfinite(Es).all() and E1 < 0.5 * E0
+
+
 def _adam_reference(U0, h, eps, a, m, nsteps, vtol):
     """The oracle's mass-projected Adam trajectory from U0 and the voxels whose update the
     FP32 path cannot be expected to reproduce: those where the oracle's gradient at some
