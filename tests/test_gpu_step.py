@@ -367,6 +367,24 @@ def test_config_128cubed_2000_autograd_adam_steps():
     assert np.isfinite(Es).all() and E1 < 0.5 * E0
 
 
+def test_config_256cubed_1000_steps():
+    """The 256^3 benchmark workload for 1000 mass-projected steps (tau = 1e-3, graph
+    replays): energies finite and falling from call to call, the mean kept to FP32
+    rounding."""
+    n = 256
+    h = 1.0 / n
+    u = to_dev(inputs.uniform_noise(n, 1005), torch.float32)
+    m = float(u.double().mean().item())
+    ctx = fe.FeContext((1, n, n, n), h, 1.5 * h, HELFRICH_SC, dtype=torch.float32)
+    Es = [ctx.energy(u)[0].item()]
+    for _ in range(4):
+        Es.append(ctx.step(u, [m], 1e-3, 250)[0].item())
+    Es.append(ctx.energy(u)[0].item())
+    log(f"  1000 steps at 256^3: F_h {Es}")
+    assert np.isfinite(Es).all() and all(b < a for a, b in zip(Es, Es[1:]))
+    assert abs(u.double().mean().item() - m) < 1e-6
+
+
 def _adam_reference(U0, h, eps, a, m, nsteps, vtol):
     """The oracle's mass-projected Adam trajectory from U0 and the voxels whose update the
     FP32 path cannot be expected to reproduce: those where the oracle's gradient at some
