@@ -68,8 +68,8 @@ typedef struct fe_ctx fe_ctx;   /* opaque: parameters, reduction workspace, step
  *   out      receives the new context.
  * Allocates only small device workspaces (O(batch x blocks) doubles); the
  * ping-pong buffer of fe_step is allocated on its first call.
- * Limits: a plane (nx * ny samples) under 4 GiB, the kernels addressing it
- * with 32-bit byte offsets; at most 4e9 samples in all.
+ * Limits: a plane (nx * ny samples) of at most 4 GiB - 64 KiB, the kernels
+ * addressing it with 32-bit byte offsets; at most 4e9 samples in all.
  * Returns FE_EINVAL, FE_ENOMEM or FE_EHIP on failure (*out is then NULL).
  */
 int fe_create(const fe_grid* grid, const double* eps, const double* p_coeffs,

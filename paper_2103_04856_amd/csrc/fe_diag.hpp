@@ -41,6 +41,27 @@ struct DiagArgs {
   T inv_h, inv_h2;
 };
 
+// A raw buffer over `bytes` bytes from `base` (stride 0; the third-dword format
+// of a 32-bit raw buffer on gfx9-family chips). The hardware drops a store whose
+// offset is at or past `bytes`, so a store that must not land can still be
+// issued, at kDropOffset: the memory operations issued are then the same on
+// every path. Planes are at most 4 GiB - 64 KiB (checked on the host), so
+// kDropOffset is never in range.
+constexpr unsigned kDropOffset = 0xFFFFFFF0u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ void store_or_drop(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+}
+
+__device__ __forceinline__ void store_or_drop(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+}
+
 template <typename T>
 __device__ __forceinline__ int diag_bin(T k, T kmax, T scale, int nbins) {
   const T kc = k < -kmax ? -kmax : (k > kmax ? kmax : k);
@@ -55,6 +76,7 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
   constexpr int UX = TX + 2, UY = TY + 2;
   constexpr int NU = (UX * UY + NT - 1) / NT;
   constexpr int NO = (TX * TY + NT - 1) / NT;
+  static_assert(NO == 1, "the curvatures held for one plane are one voxel per thread");
   __shared__ T su[4][UY * UX];                 // four plane slots: one barrier per plane
   __shared__ double shist[kDiagMaxBins * kDiagMaxBins];
   __shared__ double sred[NT / kWave][kDiagStats];
@@ -70,7 +92,7 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
   const int nb2 = d.hist ? d.nbins * d.nbins : 0;
   for (int i = tid; i < nb2; i += NT) shist[i] = 0.0;
 
-  // byte offsets within a plane (under 4 GiB): the u window, and this thread's
+  // byte offsets within a plane (at most 4 GiB - 64 KiB): the u window, and this thread's
   // output voxels for the curvature fields
   unsigned uoff[NU];
 #pragma unroll
@@ -111,6 +133,22 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
   // runs are summed in a register and reach LDS with one atomic
   int run_bin = -1;
   double run_w = 0.0;
+  // The curvatures of plane p are stored at the top of the next plane's
+  // iteration, before the wait for the plane fetched ahead: loads and stores
+  // share one in-order counter, so stores issued after that fetch (at the end of
+  // the iteration) would make the wait cover them too. Every iteration issues
+  // the four stores (the first to an empty buffer), so the wait is the same on
+  // entry and round the loop.
+  T held[4] = {T(0), T(0), T(0), T(0)};        // H, K, kappa1, kappa2 of plane p - 1
+  unsigned held_off = kDropOffset;
+  const unsigned fbytes = d.curv ? (unsigned)(plane * sizeof(T)) : 0u;
+  const size_t fstep = d.curv ? vol : 0;       // elements from one curvature field to the next
+  auto store_held = [&](int q, bool any) {     // plane q's held curvatures (none unless any)
+    const T* cb = d.curv ? d.curv + (size_t)bt.inst * 4 * vol + (size_t)q * plane : a.src;
+    const unsigned nb = any ? fbytes : 0u;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) store_or_drop(held[f], plane_rsrc(cb + f * fstep, nb), held_off);
+  };
   fetch(k0 - 1);
   stage(0);
   fetch(k0);
@@ -122,6 +160,7 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
     // planes p - 1, p, p + 1 in slots it, it + 1, it + 2 (mod 4): the slot staged
     // here was last read two planes ago, before the previous plane's barrier
     const int sm = it & 3, sc = (it + 1) & 3, sp = (it + 2) & 3;
+    store_held(it > 0 ? p - 1 : p, it > 0);   // plane p - 1
     stage(sp);                                 // plane p + 1
     if (it + 1 < kend - k0) fetch_wrapped(pf); // plane p + 2, in flight during this plane's compute
     pf = pf + 1 == a.nz ? 0 : pf + 1;
@@ -129,54 +168,56 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
       const int w = tid + j * NT;
-      if (w >= TX * TY) continue;
       const int ix = w % TX, iy = w / TX;
-      if (x0 + ix >= a.nx || y0 + iy >= a.ny) continue;
-      const int c = (iy + 1) * UX + ix + 1;
-      const T* pc = su[sc] + c;
-      const T* pm = su[sm] + c;
-      const T* pp = su[sp] + c;
-      const Forward<T> fw = forward_chain(load_stencil<T, UX>(pc, pm, pp),
-                                          [&]() { return load_stencil<T, UX>(pc, pm, pp); }, prm, a.k);
-      const size_t gi = (size_t)p * plane + (size_t)(y0 + iy) * a.nx + (x0 + ix);
-      acc_f += double(density_of(
-          fw, a.cfield ? with_coeffs(prm, load_coeffs(a.cfield + (size_t)bt.inst * 6 * vol, vol, gi)) : prm));
-      const T grad_part = T(di.ca) * fw.Q;
-      const T w2 = T(1) - fw.c * fw.c;
-      const T well_part = T(di.cb) * w2 * w2;
-      acc_area += double(grad_part + well_part);
-      acc_disc += double(grad_part > well_part ? grad_part - well_part : well_part - grad_part);
-      umin = fw.c < umin ? fw.c : umin;
-      umax = fw.c > umax ? fw.c : umax;
-      if (d.curv || d.hist) {
-        const T rs = fw.rs * d.inv_h;                    // 1 / (h sqrt R)
-        const T sq = fw.X > T(0) ? sqrt_t(fw.X) : T(0);
-        const T k1 = (fw.tr + sq) * rs, k2 = (fw.tr - sq) * rs;
-        if (d.curv) {
-          char* cb = reinterpret_cast<char*>(d.curv + (size_t)bt.inst * 4 * vol + (size_t)p * plane);
-          const unsigned o = lane_offset(ooff[j]);
-          const size_t fb = vol * sizeof(T);     // bytes per field
-          *reinterpret_cast<T*>(cb + o) = T(2) * fw.tr * rs;
-          *reinterpret_cast<T*>(cb + fb + o) = T(2) * (fw.tr * fw.tr - fw.n2) * (d.inv_h2 * rcp_t(fw.R));
-          *reinterpret_cast<T*>(cb + 2 * fb + o) = k1;
-          *reinterpret_cast<T*>(cb + 3 * fb + o) = k2;
-        }
-        if (d.hist) {
-          const double wgt = di.cw * double(fw.Q);
-          if (wgt != 0.0) {
-            const int bin = diag_bin(k1, d.kmax, d.bin_scale, d.nbins) * d.nbins +
-                            diag_bin(k2, d.kmax, d.bin_scale, d.nbins);
-            if (bin != run_bin) {
-              if (run_bin >= 0) unsafeAtomicAdd(&shist[run_bin], run_w);
-              run_bin = bin;
-              run_w = 0.0;
+      const bool valid = w < TX * TY && x0 + ix < a.nx && y0 + iy < a.ny;
+      T cH = T(0), cK = T(0), k1 = T(0), k2 = T(0);
+      if (valid) {
+        const int c = (iy + 1) * UX + ix + 1;
+        const T* pc = su[sc] + c;
+        const T* pm = su[sm] + c;
+        const T* pp = su[sp] + c;
+        const Forward<T> fw = forward_chain(load_stencil<T, UX>(pc, pm, pp),
+                                            [&]() { return load_stencil<T, UX>(pc, pm, pp); }, prm, a.k);
+        const size_t gi = (size_t)p * plane + (size_t)(y0 + iy) * a.nx + (x0 + ix);
+        acc_f += double(density_of(
+            fw, a.cfield ? with_coeffs(prm, load_coeffs(a.cfield + (size_t)bt.inst * 6 * vol, vol, gi)) : prm));
+        const T grad_part = T(di.ca) * fw.Q;
+        const T w2 = T(1) - fw.c * fw.c;
+        const T well_part = T(di.cb) * w2 * w2;
+        acc_area += double(grad_part + well_part);
+        acc_disc += double(grad_part > well_part ? grad_part - well_part : well_part - grad_part);
+        umin = fw.c < umin ? fw.c : umin;
+        umax = fw.c > umax ? fw.c : umax;
+        if (d.curv || d.hist) {
+          const T rs = fw.rs * d.inv_h;                    // 1 / (h sqrt R)
+          const T sq = fw.X > T(0) ? sqrt_t(fw.X) : T(0);
+          k1 = (fw.tr + sq) * rs;
+          k2 = (fw.tr - sq) * rs;
+          cH = T(2) * fw.tr * rs;
+          cK = T(2) * (fw.tr * fw.tr - fw.n2) * (d.inv_h2 * rcp_t(fw.R));
+          if (d.hist) {
+            const double wgt = di.cw * double(fw.Q);
+            if (wgt != 0.0) {
+              const int bin = diag_bin(k1, d.kmax, d.bin_scale, d.nbins) * d.nbins +
+                              diag_bin(k2, d.kmax, d.bin_scale, d.nbins);
+              if (bin != run_bin) {
+                if (run_bin >= 0) unsafeAtomicAdd(&shist[run_bin], run_w);
+                run_bin = bin;
+                run_w = 0.0;
+              }
+              run_w += wgt;
             }
-            run_w += wgt;
           }
         }
       }
+      held[0] = cH;
+      held[1] = cK;
+      held[2] = k1;
+      held[3] = k2;
+      held_off = valid ? ooff[j] : kDropOffset;
     }
   }
+  if (kend > k0) store_held(kend - 1, true);
   if (run_bin >= 0) unsafeAtomicAdd(&shist[run_bin], run_w);
 
   // block reduction of the five statistics

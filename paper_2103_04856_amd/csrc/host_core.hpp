@@ -246,8 +246,8 @@ int check_grid(const fe_grid* g) {
   if (g->dtype != FE_F32 && g->dtype != FE_F64) return set_error(FE_EINVAL, "dtype must be FE_F32 or FE_F64");
   const double n = (double)g->nx * g->ny * g->nz;
   const double plane_bytes = (double)g->nx * g->ny * (g->dtype == FE_F64 ? 8.0 : 4.0);
-  if (n * g->batch > 4.0e9 || plane_bytes >= 4294967296.0)
-    return set_error(FE_EINVAL, "grid too large for 32-bit plane indexing (planes must be under 4 GiB)");
+  if (n * g->batch > 4.0e9 || plane_bytes > 4294901760.0)
+    return set_error(FE_EINVAL, "grid too large for 32-bit plane indexing (planes must be at most 4 GiB - 64 KiB)");
   return FE_OK;
 }
 
@@ -374,6 +374,24 @@ double sweep_cost(long blocks, int num_cu, int slots, int L) {
   double t = (double)(k / slots) * L;
   if (rest) t += L * std::pow((double)rest / slots, 0.6);
   return t;
+}
+
+// The z chunk length of a halo-1 sweep (the energy-only and diagnostics sweeps)
+// over `cols` tile columns that sweep_cost finishes first, a chunk of l planes
+// costing about l + 1 (its two halo planes are loads only).
+int halo1_chunk(long cols, int nz, int num_cu, int slots) {
+  double best = 0.0;
+  int lz = 0;
+  for (int nzc = 1; nzc <= nz; ++nzc) {
+    const int l = ceil_div(nz, nzc);
+    if (nzc > 1 && l == ceil_div(nz, nzc - 1)) continue;
+    const double t = sweep_cost(cols * ceil_div(nz, l), num_cu, slots, l + 1);
+    if (lz <= 0 || t < best) {
+      best = t;
+      lz = l;
+    }
+  }
+  return lz;
 }
 
 Geometry geometry_of(const fe_grid& grid, int num_cu, int variant, int lz_req) {
@@ -567,20 +585,8 @@ Geometry energy_geometry(const fe_grid& grid, int num_cu) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&slots, energy_cols_kernel(grid.dtype), 64 * kEnergyWaves, 0) !=
           hipSuccess || slots < 1)
     slots = 1;
-  const long cols = (long)g.ntx * g.nty * grid.batch;
-  double best = 0.0;
-  int lz = 0;
-  for (int nzc = 1; nzc <= grid.nz; ++nzc) {
-    const int l = ceil_div(grid.nz, nzc);
-    if (nzc > 1 && l == ceil_div(grid.nz, nzc - 1)) continue;
-    const double t = sweep_cost(cols * ceil_div(grid.nz, l), num_cu, slots, l + 1);
-    if (lz <= 0 || t < best) {
-      best = t;
-      lz = l;
-    }
-  }
-  g.lz = lz;
-  g.nzc = ceil_div(grid.nz, lz);
+  g.lz = halo1_chunk((long)g.ntx * g.nty * grid.batch, grid.nz, num_cu, slots);
+  g.nzc = ceil_div(grid.nz, g.lz);
   g.per_inst = g.ntx * g.nty * g.nzc;
   return g;
 }

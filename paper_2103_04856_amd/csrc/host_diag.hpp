@@ -4,18 +4,22 @@
 
 namespace {
 
-// The diagnostics sweep: one tile shape for both precisions, z chunks of up to 32.
-constexpr int kDiagTX = 64, kDiagTY = 8, kDiagNT = 512, kDiagLZ = 32;
+// The diagnostics sweep: one tile shape for both precisions.
+constexpr int kDiagTX = 64, kDiagTY = 8, kDiagNT = 512;
 
 template <typename T>
 int diagnostics(fe_ctx* c, const void* u, void* curv, double* hist, int nbins, double kmax, double* stats) {
   const int B = c->grid.batch;
   const int ntx = ceil_div(c->grid.nx, kDiagTX), nty = ceil_div(c->grid.ny, kDiagTY);
-  // the longest z chunk (fewest recomputed halo planes) that still gives every
-  // compute unit two blocks
-  int lz = kDiagLZ;
-  while (lz > 4 && (double)ntx * nty * ceil_div(c->grid.nz, lz) * B < 2.0 * c->num_cu) lz /= 2;
-  lz = std::min(lz, c->grid.nz);
+  // z chunks by the makespan model: at 256^3 in FP32, 43-plane chunks give 768
+  // blocks, one round of three per CU, where 32-plane chunks gave 1024 blocks and
+  // a last round a third full
+  int slots = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&slots, (const void*)fe::diag_sweep<T, kDiagTX, kDiagTY, kDiagNT>,
+                                                   kDiagNT, 0) != hipSuccess ||
+      slots < 1)
+    slots = 1;
+  const int lz = halo1_chunk((long)ntx * nty * B, c->grid.nz, c->num_cu, slots);
   const int nzc = ceil_div(c->grid.nz, lz);
   const size_t per_inst = (size_t)ntx * nty * nzc;
   // layout of d_diag: DiagInst[B] | stats[B][5] | partials[B][per_inst][5]
