@@ -97,6 +97,26 @@ def test_batched_noise_matches_oracle_and_single_instances(dtype):
         assert torch.equal(s1[0], stats[b]) and torch.equal(k1[0], curv[b])
 
 
+@pytest.mark.parametrize("shape,dtype", [((1, 9, 70), torch.float64), ((5, 1, 3), torch.float64),
+                                         ((2, 3, 130), torch.float32), ((202, 64, 64), torch.float32)])
+def test_thin_ragged_and_chunked_grids_match_oracle(shape, dtype):
+    """Single planes and rows, x tiles ragged against 64, and a tall grid split into
+    short z chunks (4 planes on 256 compute units) with a shorter last one: the
+    curvature fields written by every plane of every chunk (the first and last
+    included) and the other outputs against the oracle."""
+    nz, ny, nx = shape
+    h = 1.0 / max(shape)
+    eps = 2 * h
+    U = np.random.default_rng(sum(shape)).uniform(-1, 1, size=shape)
+    ud = to_dev(U, dtype)[None].contiguous()
+    ctx = fe.FeContext((1, nz, ny, nx), h, eps, ASYM_C3, dtype=dtype)
+    stats, curv, hist = ctx.diagnostics(ud, curvatures=True, nbins=16, kmax=50.0)
+    u = oracle_input(ud)[0]
+    errs = _check_instance(u, h, eps, ASYM_C3, stats[0].numpy(), curv[0].cpu().double().numpy(),
+                           hist[0].cpu().numpy(), 16, 50.0, dtype)
+    log(f"  {shape} {dtype}: curvature weighted rel L2 {max(errs):.1e}")
+
+
 def test_deterministic_and_optional_outputs():
     n = 32
     h = 1.0 / n
