@@ -29,6 +29,7 @@ def test_orientation_energy_and_gradient(dtype):
     ctx.set_orientation(mus, [THETA, THETA])
     E, g = ctx.energy_grad(Ud)
     E_only = ctx.energy(Ud)
+    stats, _, _ = ctx.diagnostics(Ud)          # its F_h carries the term too
     Uo = oracle_input(Ud)
     tol = TOL[dtype]
     for b in range(2):
@@ -37,6 +38,7 @@ def test_orientation_energy_and_gradient(dtype):
         scale = max(abs(Eo), fo.energy_abs(Uo[b], h, eps[b], coeffs[b], orient=orient))
         assert abs(E[b].item() - Eo) <= tol["energy"] * scale
         assert abs(E_only[b].item() - Eo) <= tol["energy"] * scale
+        assert abs(stats[b, 0].item() - Eo) <= tol["energy"] * scale
         check_field(g[b].cpu().double().numpy(), go, tol, f"instance {b}")
     # the term changes the result of the second instance only
     ctx.set_orientation([0.0, 0.0], [THETA, THETA])
