@@ -155,11 +155,13 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
   stage(1);
   fetch(k0 + 1);
   int pf = wrap_index(k0 + 2, a.nz);           // plane p + 2, wrapped (advanced by one per plane)
+  start_priority();
   for (int it = 0; it < kend - k0; ++it) {
     const int p = k0 + it;
     // planes p - 1, p, p + 1 in slots it, it + 1, it + 2 (mod 4): the slot staged
     // here was last read two planes ago, before the previous plane's barrier
     const int sm = it & 3, sc = (it + 1) & 3, sp = (it + 2) & 3;
+    progress_priority(it, kend - k0);
     store_held(it > 0 ? p - 1 : p, it > 0);   // plane p - 1
     stage(sp);                                 // plane p + 1
     if (it + 1 < kend - k0) fetch_wrapped(pf); // plane p + 2, in flight during this plane's compute

@@ -44,6 +44,25 @@ __device__ __forceinline__ unsigned lane_offset(unsigned o) {
   return o;
 }
 
+// Issue priority of a sweep's waves at plane `it` of the n planes of its z
+// chunk. The blocks of a sweep share compute units (two or three each) and
+// start together, and a compute unit issues the older block's waves first: left
+// alone, the first block finished long before the others, which then ran with
+// the unit half idle (256^3 step: 142 k against 186 k shader cycles per block).
+// The priority falls as a block advances (3 from the start, 2 from half way, 1
+// from three quarters, 0 for the last tenth), so a block that lags takes the
+// issue slots until it has caught up. The first level is set before the loop
+// (start_priority), so that the loop keeps a single body: a branch on the first
+// iteration made the compiler peel it, and the copies contracted some products
+// into FMAs differently, which broke the bitwise agreement between launch shapes.
+__device__ __forceinline__ void start_priority() { __builtin_amdgcn_s_setprio(3); }
+
+__device__ __forceinline__ void progress_priority(int it, int n) {
+  if (it == n / 2) __builtin_amdgcn_s_setprio(2);
+  if (it == (3 * n) / 4) __builtin_amdgcn_s_setprio(1);
+  if (it == (9 * n) / 10) __builtin_amdgcn_s_setprio(0);
+}
+
 __device__ __forceinline__ int wrap_index(int v, int n) {
   int r = v % n;
   return r < 0 ? r + n : r;
@@ -369,8 +388,10 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   const int nit = (kend - k0) + 2;             // forward planes k0-1 .. kend
   int sm = 0, sc = 1, sp = 2;                  // slots of p-1, p, p+1
   int pf = wrap_index(k0 + 1, a.nz);           // plane p + 2, wrapped (advanced by one per plane)
+  start_priority();
   for (int it = 0; it < nit; ++it) {
     const int p = k0 - 1 + it;
+    progress_priority(it, nit);
     stage(sp);
     if (it + 1 < nit) fetch_wrapped(pf);       // plane p + 2, in flight during this plane's compute
     pf = pf + 1 == a.nz ? 0 : pf + 1;
@@ -718,6 +739,7 @@ __global__ __launch_bounds__(64 * NWV) void energy_sweep_cols(SweepArgs<T> a) {
     // window of p + 1, then the V voxels of plane p
     int pf = wrap_index(k0 + 2, a.nz);         // plane p + 2, wrapped (advanced by one per plane)
     auto plane_step = [&](int p, const T (&m)[WR][3], const T (&c)[WR][3], T (&pl)[WR][3]) {
+      progress_priority(p - k0, kend - k0);
       const int slot = (p - k0 + 2) & 1;
       stage(slot);
       if (p + 2 <= kend) fetch_wrapped(pf);
@@ -726,6 +748,7 @@ __global__ __launch_bounds__(64 * NWV) void energy_sweep_cols(SweepArgs<T> a) {
       read_window(slot, pl);
       compute(m, c, pl);
     };
+    start_priority();
     for (int p = k0; p < kend; p += 3) {
       plane_step(p, w0, w1, w2);
       if (p + 1 >= kend) break;
