@@ -189,10 +189,13 @@ int fe_adam_reset(fe_ctx* ctx);
  * instance).
  *   a_field  device [batch][6][nz][ny][nx] in the context's precision, the six
  *            coefficients in the order (a20, a11, a02, a10, a01, a00); the
- *            library keeps its own scaled copy (six fields, allocated on first
- *            use). NULL returns to the per-instance coefficients.
+ *            library keeps its own scaled copy (one record of six values per
+ *            voxel, allocated on first use). NULL returns to the per-instance
+ *            coefficients.
  * fe_set_params drops an installed field (its scaling depends on eps); set it
- * again afterwards. Synchronises the stream.
+ * again afterwards. Synchronises the stream. FE_EINVAL when nx * ny * 6
+ * samples exceed 4 GiB - 64 KiB (the sweeps address a plane of records with
+ * 32-bit offsets).
  */
 int fe_set_coeff_field(fe_ctx* ctx, const void* a_field);
 

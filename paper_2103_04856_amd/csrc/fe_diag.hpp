@@ -182,7 +182,7 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
                                             [&]() { return load_stencil<T, UX>(pc, pm, pp); }, prm, a.k);
         const size_t gi = (size_t)p * plane + (size_t)(y0 + iy) * a.nx + (x0 + ix);
         acc_f += double(density_of(
-            fw, a.cfield ? with_coeffs(prm, load_coeffs(a.cfield + (size_t)bt.inst * 6 * vol, vol, gi)) : prm));
+            fw, a.cfield ? with_coeffs(prm, coeff_records(a.cfield)[(size_t)bt.inst * vol + gi]) : prm));
         const T grad_part = T(di.ca) * fw.Q;
         const T w2 = T(1) - fw.c * fw.c;
         const T well_part = T(di.cb) * w2 * w2;

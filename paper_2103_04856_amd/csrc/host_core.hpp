@@ -218,7 +218,7 @@ struct fe_ctx {
   fe::FlowClock* d_flow_clk = nullptr; // H^-1 flow: Adam step number and bias corrections (device)
   double* d_diag = nullptr;           // diagnostics: per-instance constants, stats, block partials
   size_t diag_bytes = 0;
-  void* d_cfield = nullptr;           // scaled coefficient field [batch][6][nz][ny][nx] (Sec. 5.2)
+  void* d_cfield = nullptr;           // scaled coefficient field, [batch][nz][ny][nx] records of six (Sec. 5.2)
   bool use_cfield = false;
   void* d_mfield = nullptr;           // mass field m(x) [batch][nz][ny][nx] of the flow (Sec. 5.2)
   bool use_mfield = false;
@@ -923,6 +923,9 @@ int fe_set_coeff_field(fe_ctx* c, const void* a_field) {
     c->use_cfield = false;
     return FE_OK;
   }
+  // the sweeps address a plane of six-value records with 32-bit byte offsets
+  if ((double)c->grid.nx * c->grid.ny * 6.0 * (double)elem_size(c->grid) > 4294901760.0)
+    return set_error(FE_EINVAL, "coefficient field too large: nx * ny * 6 samples must be at most 4 GiB - 64 KiB");
   DeviceGuard dg(c->device);
   const size_t n = field_elems(c->grid);
   if (!c->d_cfield && hipMalloc(&c->d_cfield, 6 * n * elem_size(c->grid)) != hipSuccess) {
