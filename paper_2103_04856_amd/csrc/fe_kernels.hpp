@@ -145,8 +145,8 @@ struct SweepArgs {
 // The six scaled coefficients of one voxel from the coefficient field (Sec. 5.2:
 // a(x) acts at the voxel where the density is evaluated). The context keeps the
 // field as one record per voxel, so a voxel's six values are one contiguous
-// 24-byte (FP64: 48-byte) access: three 8-byte (16-byte) loads instead of six
-// loads from six planes far apart.
+// 24-byte (FP64: 48-byte) record, read with two or three wide loads instead of
+// six loads from six planes a field apart.
 template <typename T>
 struct alignas(2 * sizeof(T)) VoxelCoeffs {
   T c[6];
