@@ -508,8 +508,9 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
         const int v = (iy + 1) * RX + ix + 1;
         const T d = T(0.5) * ((sx[BXZ][v + 1] - sx[BXZ][v - 1]) + (sx[BYZ][v + RX] - sx[BYZ][v - RX]));
         const T bzz = own_bzz[j], gz = own_gz[j];
-        const T upn = bzz + gz + d;    // minus what plane p adds to output plane p-1
-        const T lo = gz + d - bzz;     // what plane p adds to output plane p+1
+        const T gd = gz + d;
+        const T upn = gd + bzz;        // minus what plane p adds to output plane p-1
+        const T lo = gd - bzz;         // what plane p adds to output plane p+1
         if (it >= 2 && oin[j]) {
           const T g = (c_prev[j] - upn) + l_pp[j];
           const unsigned o = lane_offset(ooff[j]);

@@ -358,15 +358,19 @@ __device__ __forceinline__ T voxel_density_adjoint_body(const Stencil19<T>& s, R
                                                         VoxelAdjoint<T>& a) {
   const Forward<T> fw = forward_chain<NOS>(s, reload, p, k);
   const T tr = fw.tr;
-  T f, rhob, trb0, bxx, byy, bzz, cqh;
+  T f, hrhob, trb0, bxx, byy, bzz, cqh;
   const T rs = fw.rs;
   const T rho = fw.R * rs;                         // 2h rho
   const T c1x2 = p.C1 + p.C1;
+  // f~ = C1 N~ + T~ g1 + C5 rho~ S~ + C6 Q with g1 = C2 T~ + C3 S~ + C4 rho~, so
+  // df/dT~ = g1 + C2 T~ (the product C2 T~ serves both)
+  const T ctr = p.C2 * tr;
   if constexpr (NOS) {
-    f = p.C1 * fw.n2 + tr * (p.C2 * tr + p.C4 * rho) + p.C6 * fw.Q;
+    const T g1 = ctr + p.C4 * rho;
+    f = p.C1 * fw.n2 + tr * g1 + p.C6 * fw.Q;
     // ---- reverse sweep ----
-    rhob = p.C4 * tr;                              // df/drho~
-    trb0 = T(2) * p.C2 * tr + p.C4 * rho;
+    hrhob = (T(0.5) * p.C4) * tr;                  // df/drho~ / 2
+    trb0 = g1 + ctr;
     bxx = c1x2 * fw.mxx + trb0;
     byy = c1x2 * fw.myy + trb0;
     bzz = c1x2 * fw.mzz + trb0;
@@ -377,17 +381,19 @@ __device__ __forceinline__ T voxel_density_adjoint_body(const Stencil19<T>& s, R
     const T rsP = P > T(0) ? rsqrt_t(P) : T(0);
     const T S = P * rsP;
 
-    f = p.C1 * fw.n2 + tr * (p.C2 * tr + p.C3 * S + p.C4 * rho) + p.C5 * rho * S + p.C6 * fw.Q;
+    const T g1 = (ctr + p.C3 * S) + p.C4 * rho;
+    const T c5r = p.C5 * rho;
+    f = p.C1 * fw.n2 + tr * g1 + c5r * S + p.C6 * fw.Q;
 
     // ---- reverse sweep ----
-    const T Sb = p.C3 * tr + p.C5 * rho;           // df/dS~
-    rhob = p.C4 * tr + p.C5 * S;                   // df/drho~
+    const T Sb = p.C3 * tr + c5r;                  // df/dS~
+    hrhob = (T(0.5) * p.C4) * tr + (T(0.5) * p.C5) * S;   // df/drho~ / 2
     const T kap = Sb * sig * (T(0.5) * rsP);       // df/dX~  (dS~/dX~ = sig / (2S~); 0 where S~ = 0)
     const T kap2 = kap + kap;
     // df/dm_aa = 2 C1 m_aa + df/dT~ + 2 kap (2 m_aa - T~): the X~ part is
     // written with the difference formed in the forward chain, so no two
     // kap-sized terms cancel.
-    trb0 = T(2) * p.C2 * tr + p.C3 * S + p.C4 * rho;
+    trb0 = g1 + ctr;
     bxx = c1x2 * fw.mxx + trb0 + kap2 * fw.dxx;
     byy = c1x2 * fw.myy + trb0 + kap2 * fw.dyy;
     bzz = c1x2 * fw.mzz + trb0 + kap2 * fw.dzz;
@@ -404,16 +410,22 @@ __device__ __forceinline__ T voxel_density_adjoint_body(const Stencil19<T>& s, R
   a.dbyz = qyz;
 
   const T ax = fw.ax, ay = fw.ay, az = fw.az, sw = fw.sw;
-  const T swb = bxx * (ax * ax) + byy * (ay * ay) + bzz * (az * az) +
-                T(2) * (qxy * (ax * ay) + qxz * (ax * az) + qyz * (ay * az));   // df/dsw
+  // D_a = b_aa a_a + sum_b qh_ab a_b. Since m_aa and o_ab depend on sw through
+  // sw a_a^2 and 4 sw a_a a_b, df/dsw = sum_a a_a D_a, and the part of
+  // df/da_a / 2 that goes through m and o is sw D_a.
+  const T Dx = bxx * ax + qxy * ay + qxz * az;
+  const T Dy = byy * ay + qxy * ax + qyz * az;
+  const T Dz = bzz * az + qxz * ax + qyz * ay;
+  const T swb = ax * Dx + ay * Dy + az * Dz;                              // df/dsw
   // sw = lam W'(u) / R, R = Q + reg, rho~ = sqrt(R)
-  const T Qb = p.C6 + T(0.5) * rhob * rs - swb * sw * fw.Rinv;            // df/dQ
+  const T swbR = swb * fw.Rinv;
+  const T Qb = p.C6 + hrhob * rs - swbR * sw;                             // df/dQ
   const T c = fw.c;
-  a.ub = swb * (p.lam * (T(3) * c * c - T(1))) * fw.Rinv;
-  // df/da_a / 2 = sw (b_aa a_a + sum_b qh_ab a_b) + Qb a_a
-  a.hgx = sw * (bxx * ax + qxy * ay + qxz * az) + Qb * ax;
-  a.hgy = sw * (byy * ay + qxy * ax + qyz * az) + Qb * ay;
-  T hgz = sw * (bzz * az + qxz * ax + qyz * ay) + Qb * az;
+  a.ub = swbR * (p.lam * (T(3) * c * c - T(1)));
+  // df/da_a / 2 = sw D_a + Qb a_a
+  a.hgx = sw * Dx + Qb * ax;
+  a.hgy = sw * Dy + Qb * ay;
+  T hgz = sw * Dz + Qb * az;
   if (p.Co != T(0)) {                              // orientation term and its derivative in a
     const T ta = p.thx * ax + p.thy * ay + p.thz * az;
     const T tco = p.Co * ta;
