@@ -175,9 +175,10 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
       T cH = T(0), cK = T(0), k1 = T(0), k2 = T(0);
       if (valid) {
         const int c = (iy + 1) * UX + ix + 1;
-        const T* pc = su[sc] + c;
-        const T* pm = su[sm] + c;
-        const T* pp = su[sp] + c;
+        const unsigned lo = stencil_base<T, UX>(c);
+        const char* pc = reinterpret_cast<const char*>(su[sc]) + lo;
+        const char* pm = reinterpret_cast<const char*>(su[sm]) + lo;
+        const char* pp = reinterpret_cast<const char*>(su[sp]) + lo;
         const Forward<T> fw = forward_chain(load_stencil<T, UX>(pc, pm, pp),
                                             [&]() { return load_stencil<T, UX>(pc, pm, pp); }, prm, a.k);
         const size_t gi = (size_t)p * plane + (size_t)(y0 + iy) * a.nx + (x0 + ix);

@@ -207,16 +207,46 @@ __device__ __forceinline__ void instance_sums(const double* __restrict__ partial
   sm = m;
 }
 
-// The 19 stencil samples around the LDS position pc (plane p), pm (p-1), pp (p+1).
+// The 19 stencil samples of a voxel from the LDS planes p (bc), p-1 (bm) and
+// p+1 (bp) of a window UX values wide. Each pointer is the byte address of
+// the sample at (x-1, y-1) in its plane, so every sample sits at a
+// non-negative constant offset of at most 2 UX + 2 values from it, which the
+// LDS read instructions (paired reads included) take as their immediate:
+// three address additions per voxel, one per plane.
 template <typename T, int UX>
-__device__ __forceinline__ Stencil19<T> load_stencil(const T* pc, const T* pm, const T* pp) {
+__device__ __forceinline__ Stencil19<T> load_stencil(const char* bc, const char* bm, const char* bp) {
+  auto at = [](const char* b, int i) { return *reinterpret_cast<const T*>(b + i * (int)sizeof(T)); };
+  constexpr int C = UX + 1;                    // the centre
   Stencil19<T> s;
-  s.c = pc[0];
-  s.xm = pc[-1]; s.xp = pc[1]; s.ym = pc[-UX]; s.yp = pc[UX]; s.zm = pm[0]; s.zp = pp[0];
-  s.xpyp = pc[UX + 1]; s.xpym = pc[1 - UX]; s.xmyp = pc[UX - 1]; s.xmym = pc[-UX - 1];
-  s.xpzp = pp[1]; s.xpzm = pm[1]; s.xmzp = pp[-1]; s.xmzm = pm[-1];
-  s.ypzp = pp[UX]; s.ypzm = pm[UX]; s.ymzp = pp[-UX]; s.ymzm = pm[-UX];
+  s.c = at(bc, C);
+  s.xm = at(bc, C - 1); s.xp = at(bc, C + 1); s.ym = at(bc, C - UX); s.yp = at(bc, C + UX);
+  s.zm = at(bm, C); s.zp = at(bp, C);
+  s.xpyp = at(bc, C + UX + 1); s.xpym = at(bc, C + 1 - UX); s.xmyp = at(bc, C + UX - 1); s.xmym = at(bc, 0);
+  s.xpzp = at(bp, C + 1); s.xpzm = at(bm, C + 1); s.xmzp = at(bp, C - 1); s.xmzm = at(bm, C - 1);
+  s.ypzp = at(bp, C + UX); s.ypzm = at(bm, C + UX); s.ymzp = at(bp, C - UX); s.ymzm = at(bm, C - UX);
   return s;
+}
+
+// Byte offset in an LDS window plane of the sample at (x-1, y-1) of the voxel
+// whose centre is value index c, kept opaque so that the compiler addresses
+// the stencil from it rather than from the centre (negative offsets, which the
+// LDS instructions do not take, would cost extra additions).
+template <typename T, int UX>
+__device__ __forceinline__ unsigned stencil_base(int c) {
+  return lane_offset((unsigned)(c - UX - 1) * (unsigned)sizeof(T));
+}
+
+// An LDS address held in a register the compiler may not re-form: reads through
+// it take their distance from it as the instruction's immediate offset, so a
+// base formed once before a loop costs no address addition inside it.
+template <typename T>
+using lds_cptr = __attribute__((address_space(3))) const T*;
+
+template <typename T>
+__device__ __forceinline__ lds_cptr<T> opaque_lds(const T* p) {
+  lds_cptr<T> q = (lds_cptr<T>)p;
+  __asm__("" : "+v"(q));
+  return q;
 }
 
 // Block -> (instance, tile x, tile y, z chunk).
@@ -345,6 +375,19 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
     const int k = b - 2 * RX;
     return (1 + (k >> 1)) * RX + ((k & 1) ? RX - 1 : 0);
   };
+  // ring position of this thread's ring item j (interior first, then the border)
+  auto ring_pos = [&](int j) {
+    const int item = tid + j * NT;
+    return item < NI ? (item / TX + 1) * RX + item % TX + 1 : border_pos(item - NI);
+  };
+  // LDS byte offset of each ring item's stencil base (its (x-1, y-1) sample) in a
+  // u window plane, the same in every plane
+  unsigned slo[NW];
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    const int v = ring_pos(j);
+    slo[j] = stencil_base<T, UX>((v / RX + 1) * UX + v % RX + 1);
+  }
   // SP: in-plane offsets of this thread's ring voxels and their coefficients
   const size_t vol = plane * a.nz;
   const VoxelCoeffs<T>* cfb = SP ? coeff_records(a.cfield) + (size_t)bt.inst * vol : nullptr;
@@ -363,6 +406,27 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   }
 
   double acc_f = 0.0, acc_m = 0.0;
+  // The gather reads seven fields around each output voxel, 4.6 KB apart in LDS
+  // (beyond the reach of a paired read's immediates), so every field needs an
+  // address of its own: with FP32 these are formed once here instead of at
+  // every plane (14 registers, which the FP32 kernels without a coefficient
+  // field have to spare at two blocks per compute unit).
+  constexpr bool kGatherBases = sizeof(T) == 4 && !SP;
+  lds_cptr<T> gbase[kGatherBases ? NO : 1][NFIELD];
+  if constexpr (kGatherBases) {
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      const int w = tid + j * NT;
+      const int v = w < NI ? (w / TX + 1) * RX + w % TX + 1 : RX + 1;
+#pragma unroll
+      for (int f = 0; f < NFIELD; ++f) gbase[j][f] = opaque_lds(&sx[f][v - RX - 1]);
+    }
+  }
+  // field f of the ring at index v + d, for this thread's output voxel j at v
+  auto sxat = [&](int j, int v, int f, int d) -> T {
+    if constexpr (kGatherBases) return gbase[j][f][d + RX + 1];
+    else return sx[f][v + d];
+  };
   T c_prev[NO], l_prev[NO], l_pp[NO];
   T u_out[NO];                                 // u at this thread's output voxels of plane p-1
   T m1c[NO], m2c[NO], m1n[NO], m2n[NO];        // Adam moments: current and next output plane
@@ -432,8 +496,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
     const bool out_plane = (p >= k0) && (p < kend);
     const int pz = BOX ? wrap_index(p, a.nz) : 0;
     const bool zin = !BOX || (pz >= a.box_lo[2] && pz < a.box_hi[2]);
-    auto eval = [&](int v, VoxelAdjoint<T>& ad, const InstParams<T>& pv) {
-      const int c = (v / RX + 1) * UX + v % RX + 1;
+    auto eval = [&](int v, unsigned lo, VoxelAdjoint<T>& ad, const InstParams<T>& pv) {
       if (BOX) {
         const int gx = wrap_index(x0 - 1 + v % RX, a.nx), gy = wrap_index(y0 - 1 + v / RX, a.ny);
         if (!zin || gx < a.box_lo[0] || gx >= a.box_hi[0] || gy < a.box_lo[1] || gy >= a.box_hi[1]) {
@@ -444,9 +507,9 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
           return T(0);
         }
       }
-      const T* pc = su[sc] + c;
-      const T* pm = su[sm] + c;
-      const T* pp = su[sp] + c;
+      const char* pc = reinterpret_cast<const char*>(su[sc]) + lo;
+      const char* pm = reinterpret_cast<const char*>(su[sm]) + lo;
+      const char* pp = reinterpret_cast<const char*>(su[sp]) + lo;
       // with both bodies, the one without S~ terms where the instance has none,
       // so an instance takes the same arithmetic in every batch it is part of
       // (a coefficient field varies per voxel: always the full body)
@@ -476,16 +539,17 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
       if (item < NI + NB) {
         const bool inner = item < NI;
         const int ix = item % TX, iy = item / TX;
-        const int v = inner ? (iy + 1) * RX + ix + 1 : border_pos(item - NI);
         VoxelAdjoint<T> ad;
-        const T f = eval(v, ad, SP ? with_coeffs(prm, cv[j]) : prm);
+        const T f = eval(ring_pos(j), slo[j], ad, SP ? with_coeffs(prm, cv[j]) : prm);
         if (j < NO && inner) {
           own_c0[j] = ad.ub + T(2) * ((ad.nbzz + ad.nbxx) + ad.nbyy);
           own_gz[j] = ad.gz;
           own_bzz[j] = ad.nbzz;
-          // u of output plane p-1 at this voxel, read before the second barrier
-          // (its slot takes plane p+2 in the next iteration)
-          u_out[j] = su[sm][(iy + 2) * UX + ix + 2];
+          // u of output plane p-1 at this voxel (the stencil's centre in plane
+          // p-1), read before the second barrier (its slot takes plane p+2 in
+          // the next iteration)
+          u_out[j] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(su[sm]) + slo[j] +
+                                                 (UX + 1) * sizeof(T));
           if (out_plane && x0 + ix < a.nx && y0 + iy < a.ny) fpl += f;
         }
       }
@@ -506,7 +570,8 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
       if (w < TX * TY) {
         const int ix = w % TX, iy = w / TX;
         const int v = (iy + 1) * RX + ix + 1;
-        const T d = T(0.5) * ((sx[BXZ][v + 1] - sx[BXZ][v - 1]) + (sx[BYZ][v + RX] - sx[BYZ][v - RX]));
+        const T d = T(0.5) * ((sxat(j, v, BXZ, 1) - sxat(j, v, BXZ, -1)) +
+                              (sxat(j, v, BYZ, RX) - sxat(j, v, BYZ, -RX)));
         const T bzz = own_bzz[j], gz = own_gz[j];
         const T gd = gz + d;
         const T upn = gd + bzz;        // minus what plane p adds to output plane p-1
@@ -534,10 +599,12 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
           }
         }
         const T cin = own_c0[j]
-                      - T(2) * ((sx[GX][v + 1] - sx[GX][v - 1]) + (sx[GY][v + RX] - sx[GY][v - RX]))
-                      - ((sx[BXX][v + 1] + sx[BXX][v - 1]) + (sx[BYY][v + RX] + sx[BYY][v - RX]))
-                      - T(0.5) * ((sx[BXY][v + RX + 1] - sx[BXY][v - RX + 1]) -
-                                  (sx[BXY][v + RX - 1] - sx[BXY][v - RX - 1]));
+                      - T(2) * ((sxat(j, v, GX, 1) - sxat(j, v, GX, -1)) +
+                                (sxat(j, v, GY, RX) - sxat(j, v, GY, -RX)))
+                      - ((sxat(j, v, BXX, 1) + sxat(j, v, BXX, -1)) +
+                         (sxat(j, v, BYY, RX) + sxat(j, v, BYY, -RX)))
+                      - T(0.5) * ((sxat(j, v, BXY, RX + 1) - sxat(j, v, BXY, -RX + 1)) -
+                                  (sxat(j, v, BXY, RX - 1) - sxat(j, v, BXY, -RX - 1)));
         l_pp[j] = l_prev[j];
         l_prev[j] = lo;
         c_prev[j] = cin;
@@ -618,15 +685,16 @@ __global__ __launch_bounds__(NT) void energy_sweep(SweepArgs<T> a) {
       if (w >= TX * TY) continue;
       const int ix = w % TX, iy = w / TX;
       const int c = (iy + 1) * UX + ix + 1;
-      const T* pc = su[sc] + c;
-      const T* pm = su[sm] + c;
-      const T* pp = su[sp] + c;
-      const T f = voxel_density<SP>(load_stencil<T, UX>(pc, pm, pp),
-                                    [&]() { return load_stencil<T, UX>(pc, pm, pp); },
+      const unsigned lo = stencil_base<T, UX>(c);
+      const char* pc = reinterpret_cast<const char*>(su[sc]) + lo;
+      const char* pm = reinterpret_cast<const char*>(su[sm]) + lo;
+      const char* pp = reinterpret_cast<const char*>(su[sp]) + lo;
+      const Stencil19<T> st = load_stencil<T, UX>(pc, pm, pp);
+      const T f = voxel_density<SP>(st, [&]() { return load_stencil<T, UX>(pc, pm, pp); },
                                     SP ? with_coeffs(prm, cv[j]) : prm, a.k);
       if (x0 + ix < a.nx && y0 + iy < a.ny) {
         acc_f += double(f);
-        acc_m += double(pc[0]);
+        acc_m += double(st.c);
       }
     }
     __syncthreads();
