@@ -41,27 +41,6 @@ struct DiagArgs {
   T inv_h, inv_h2;
 };
 
-// A raw buffer over `bytes` bytes from `base` (stride 0; the third-dword format
-// of a 32-bit raw buffer on gfx9-family chips). The hardware drops a store whose
-// offset is at or past `bytes`, so a store that must not land can still be
-// issued, at kDropOffset: the memory operations issued are then the same on
-// every path. Planes are at most 4 GiB - 64 KiB (checked on the host), so
-// kDropOffset is never in range.
-constexpr unsigned kDropOffset = 0xFFFFFFF0u;
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, unsigned bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
-}
-
-__device__ __forceinline__ void store_or_drop(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
-}
-
-__device__ __forceinline__ void store_or_drop(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-  typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
-}
-
 template <typename T>
 __device__ __forceinline__ int diag_bin(T k, T kmax, T scale, int nbins) {
   const T kc = k < -kmax ? -kmax : (k > kmax ? kmax : k);
@@ -112,10 +91,10 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
   // the next plane is loaded into registers while the current one is computed
   T pre[NU];
   auto fetch_wrapped = [&](int pw) {          // pw: a plane index already in [0, nz)
-    const char* sp = reinterpret_cast<const char*>(srcb + (size_t)pw * plane);
+    const auto r = plane_rsrc(srcb + (size_t)pw * plane, (unsigned)(plane * sizeof(T)));
 #pragma unroll
     for (int j = 0; j < NU; ++j)
-      if (tid + j * NT < UX * UY) pre[j] = *reinterpret_cast<const T*>(sp + lane_offset(uoff[j]));
+      if (tid + j * NT < UX * UY) pre[j] = buffer_load(r, uoff[j], T());
   };
   auto fetch = [&](int p) { fetch_wrapped(wrap_index(p, a.nz)); };
   auto stage = [&](int slot) {
@@ -147,7 +126,7 @@ __global__ __launch_bounds__(NT) void diag_sweep(SweepArgs<T> a, DiagArgs<T> d) 
     const T* cb = d.curv ? d.curv + (size_t)bt.inst * 4 * vol + (size_t)q * plane : a.src;
     const unsigned nb = any ? fbytes : 0u;
 #pragma unroll
-    for (int f = 0; f < 4; ++f) store_or_drop(held[f], plane_rsrc(cb + f * fstep, nb), held_off);
+    for (int f = 0; f < 4; ++f) buffer_store(held[f], plane_rsrc(cb + f * fstep, nb), held_off);
   };
   fetch(k0 - 1);
   stage(0);

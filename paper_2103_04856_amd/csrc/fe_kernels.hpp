@@ -44,6 +44,39 @@ __device__ __forceinline__ unsigned lane_offset(unsigned o) {
   return o;
 }
 
+// A raw buffer over `bytes` bytes from `base` (stride 0; the third-dword format
+// of a 32-bit raw buffer on gfx9-family chips). The hardware drops a store whose
+// offset is at or past `bytes`, so a store that must not land can still be
+// issued, at kDropOffset: the memory operations issued are then the same on
+// every path. Planes are at most 4 GiB - 64 KiB (checked on the host), so
+// kDropOffset is never in range.
+constexpr unsigned kDropOffset = 0xFFFFFFF0u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ void buffer_store(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+}
+
+__device__ __forceinline__ void buffer_store(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+}
+
+// Loads and stores through such a buffer take the 32-bit lane offset as an
+// operand of the instruction, so the compiler neither widens it to a 64-bit
+// lane address nor needs it kept opaque, and the plane address stays in
+// scalar registers.
+__device__ __forceinline__ float buffer_load(__amdgpu_buffer_rsrc_t r, unsigned off, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+
+__device__ __forceinline__ double buffer_load(__amdgpu_buffer_rsrc_t r, unsigned off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
 // Issue priority of a sweep's waves at plane `it` of the n planes of its z
 // chunk. The blocks of a sweep share compute units (two or three each) and
 // start together, and a compute unit issues the older block's waves first: left
@@ -354,11 +387,12 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   }
   T pre[NU];
   T shift = T(0);                              // steps: the uniform shift of src, set below
+  const unsigned pbytes = (unsigned)(plane * sizeof(T));
   auto fetch_wrapped = [&](int pw) {          // pw: a plane index already in [0, nz)
-    const char* sp = reinterpret_cast<const char*>(srcb + (size_t)pw * plane);
+    const auto r = plane_rsrc(srcb + (size_t)pw * plane, pbytes);
 #pragma unroll
     for (int j = 0; j < NU; ++j)
-      if (tid + j * NT < UX * UY) pre[j] = *reinterpret_cast<const T*>(sp + lane_offset(uoff[j]));
+      if (tid + j * NT < UX * UY) pre[j] = buffer_load(r, uoff[j], T());
   };
   auto fetch = [&](int p) { fetch_wrapped(wrap_index(p, a.nz)); };
   auto stage = [&](int slot) {
@@ -470,13 +504,11 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
       }
       if (it + 1 < nit && p >= k0) {
         const size_t po = inst_off + (size_t)p * plane;
-        const char* m1p = reinterpret_cast<const char*>(a.m1 + po);
-        const char* m2p = reinterpret_cast<const char*>(a.m2 + po);
+        const auto r1 = plane_rsrc(a.m1 + po, pbytes), r2 = plane_rsrc(a.m2 + po, pbytes);
 #pragma unroll
         for (int j = 0; j < NO; ++j) {
-          const unsigned o = lane_offset(ooff[j]);
-          m1n[j] = oin[j] ? *reinterpret_cast<const T*>(m1p + o) : T(0);
-          m2n[j] = oin[j] ? *reinterpret_cast<const T*>(m2p + o) : T(0);
+          m1n[j] = oin[j] ? buffer_load(r1, ooff[j], T()) : T(0);
+          m2n[j] = oin[j] ? buffer_load(r2, ooff[j], T()) : T(0);
         }
       }
     }
@@ -563,7 +595,9 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
     // the (negated) b_ab ones, hence the factors 2 and 1/2.
     T mpl = T(0);                              // this thread's sum of the field written for plane p - 1
     const size_t po = (size_t)(it >= 2 ? p - 1 : 0) * plane;   // output plane p - 1 (written from it = 2)
-    char* dpl = reinterpret_cast<char*>(dstb + po);
+    const auto rd = plane_rsrc(dstb + po, pbytes);
+    const auto rm1 = plane_rsrc(MODE == kStepAdam ? a.m1 + inst_off + po : dstb, pbytes);
+    const auto rm2 = plane_rsrc(MODE == kStepAdam ? a.m2 + inst_off + po : dstb, pbytes);
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
       const int w = tid + j * NT;
@@ -578,23 +612,22 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
         const T lo = gd - bzz;         // what plane p adds to output plane p+1
         if (it >= 2 && oin[j]) {
           const T g = (c_prev[j] - upn) + l_pp[j];
-          const unsigned o = lane_offset(ooff[j]);
-          T* dp = reinterpret_cast<T*>(dpl + o);
+          const unsigned o = ooff[j];
           const T uc = u_out[j];
           if (MODE == kStepGD) {
             const T un = uc - a.tau * g;
-            *dp = un;
+            buffer_store(un, rd, o);
             mpl += un;
           } else if (MODE == kStepAdam) {
             const T mo = a.beta1 * m1c[j] + (T(1) - a.beta1) * g;
             const T vo = a.beta2 * m2c[j] + (T(1) - a.beta2) * g * g;
-            *reinterpret_cast<T*>(reinterpret_cast<char*>(a.m1 + inst_off + po) + o) = mo;
-            *reinterpret_cast<T*>(reinterpret_cast<char*>(a.m2 + inst_off + po) + o) = vo;
+            buffer_store(mo, rm1, o);
+            buffer_store(vo, rm2, o);
             const T un = uc - a.tau * (mo * bc1) * rcp_t(sqrt_t(vo * bc2) + a.adam_eps);
-            *dp = un;
+            buffer_store(un, rd, o);
             mpl += un;
           } else {
-            *dp = g;
+            buffer_store(g, rd, o);
             mpl += uc;
           }
         }
@@ -745,10 +778,10 @@ __global__ __launch_bounds__(64 * NWV) void energy_sweep_cols(SweepArgs<T> a) {
   }
   T pre[NU];
   auto fetch_wrapped = [&](int pw) {          // pw: a plane index already in [0, nz)
-    const char* sp = reinterpret_cast<const char*>(srcb + (size_t)pw * plane);
+    const auto r = plane_rsrc(srcb + (size_t)pw * plane, (unsigned)(plane * sizeof(T)));
 #pragma unroll
     for (int j = 0; j < NU; ++j)
-      if (tid + j * NT < UX * UY) pre[j] = *reinterpret_cast<const T*>(sp + lane_offset(uoff[j]));
+      if (tid + j * NT < UX * UY) pre[j] = buffer_load(r, uoff[j], T());
   };
   auto fetch = [&](int p) { fetch_wrapped(wrap_index(p, a.nz)); };
   auto stage = [&](int slot) {
