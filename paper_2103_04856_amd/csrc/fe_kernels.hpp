@@ -275,6 +275,13 @@ __device__ __forceinline__ unsigned stencil_base(int c) {
 template <typename T>
 using lds_cptr = __attribute__((address_space(3))) const T*;
 
+// Two adjoint values that the gather reads at the same neighbours, kept
+// together so that one LDS instruction moves both.
+template <typename T>
+struct alignas(2 * sizeof(T)) FieldPair {
+  T a, b;
+};
+
 template <typename T>
 __device__ __forceinline__ lds_cptr<T> opaque_lds(const T* p) {
   lds_cptr<T> q = (lds_cptr<T>)p;
@@ -340,11 +347,30 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   constexpr int NO = (NI + NT - 1) / NT;       // interior voxels per thread
   constexpr int NB = 2 * RX + 2 * TY;          // border voxels of the ring
   constexpr int NW = (NI + NB + NT - 1) / NT;  // ring voxels per thread (interior first)
-  enum { GX = 0, GY, BXX, BYY, BXY, BXZ, BYZ, NFIELD };
+  // The gather reads a_x's and b_xx's adjoints at the same two neighbours
+  // (x +- 1), and a_y's and b_yy's at y +- 1: without a coefficient field each
+  // such pair is one 8-byte record (XP, YP: two field rows of sx seen as
+  // RY * RX records), written with one instruction and read with one paired
+  // instruction per neighbour pair; with one (whose kernels have no registers
+  // to spare for the wider reads) the four are rows of their own, in the same
+  // storage. BXY, BXZ and BYZ are single fields.
+  enum { XP = 0, YP = 2, BXY = 4, BXZ, BYZ, NFIELD };
+  constexpr bool kPairs = !SP;
   constexpr bool STEP = MODE != kGrad;
 
   __shared__ T su[3][UY * UX];
-  __shared__ T sx[NFIELD][RY * RX];
+  __shared__ alignas(4 * sizeof(T)) T sx[NFIELD][RY * RX];
+  FieldPair<T>* const xrec = reinterpret_cast<FieldPair<T>*>(&sx[XP][0]);   // (a_x / 2, b_xx) adjoints
+  FieldPair<T>* const yrec = reinterpret_cast<FieldPair<T>*>(&sx[YP][0]);   // (a_y / 2, b_yy) adjoints
+  auto put_xy = [&](int v, T gx, T bxx, T gy, T byy) {
+    if constexpr (kPairs) {
+      xrec[v] = FieldPair<T>{gx, bxx};
+      yrec[v] = FieldPair<T>{gy, byy};
+    } else {
+      sx[XP][v] = gx; sx[XP + 1][v] = bxx;
+      sx[YP][v] = gy; sx[YP + 1][v] = byy;
+    }
+  };
   __shared__ double sred[NT / kWave][2];
 
   const int tid = threadIdx.x;
@@ -446,20 +472,35 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
   // every plane (14 registers, which the FP32 kernels without a coefficient
   // field have to spare at two blocks per compute unit).
   constexpr bool kGatherBases = sizeof(T) == 4 && !SP;
-  lds_cptr<T> gbase[kGatherBases ? NO : 1][NFIELD];
+  constexpr int NSINGLE = NFIELD - BXY;
+  lds_cptr<T> gbase[kGatherBases ? NO : 1][NSINGLE];
+  lds_cptr<FieldPair<T>> gxr[kGatherBases ? NO : 1], gyr[kGatherBases ? NO : 1];
   if constexpr (kGatherBases) {
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
       const int w = tid + j * NT;
       const int v = w < NI ? (w / TX + 1) * RX + w % TX + 1 : RX + 1;
 #pragma unroll
-      for (int f = 0; f < NFIELD; ++f) gbase[j][f] = opaque_lds(&sx[f][v - RX - 1]);
+      for (int f = 0; f < NSINGLE; ++f) gbase[j][f] = opaque_lds(&sx[BXY + f][v - RX - 1]);
+      gxr[j] = opaque_lds(&xrec[v - RX - 1]);
+      gyr[j] = opaque_lds(&yrec[v - RX - 1]);
     }
   }
-  // field f of the ring at index v + d, for this thread's output voxel j at v
+  // single field f (BXY, BXZ or BYZ) of the ring at index v + d, and the x and
+  // y records there, for this thread's output voxel j at v
   auto sxat = [&](int j, int v, int f, int d) -> T {
-    if constexpr (kGatherBases) return gbase[j][f][d + RX + 1];
+    if constexpr (kGatherBases) return gbase[j][f - BXY][d + RX + 1];
     else return sx[f][v + d];
+  };
+  auto xat = [&](int j, int v, int d) -> FieldPair<T> {
+    if constexpr (kGatherBases) return FieldPair<T>{gxr[j][d + RX + 1].a, gxr[j][d + RX + 1].b};
+    else if constexpr (kPairs) return xrec[v + d];
+    else return FieldPair<T>{sx[XP][v + d], sx[XP + 1][v + d]};
+  };
+  auto yat = [&](int j, int v, int d) -> FieldPair<T> {
+    if constexpr (kGatherBases) return FieldPair<T>{gyr[j][d + RX + 1].a, gyr[j][d + RX + 1].b};
+    else if constexpr (kPairs) return yrec[v + d];
+    else return FieldPair<T>{sx[YP][v + d], sx[YP + 1][v + d]};
   };
   T c_prev[NO], l_prev[NO], l_pp[NO];
   T u_out[NO];                                 // u at this thread's output voxels of plane p-1
@@ -533,8 +574,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
         const int gx = wrap_index(x0 - 1 + v % RX, a.nx), gy = wrap_index(y0 - 1 + v / RX, a.ny);
         if (!zin || gx < a.box_lo[0] || gx >= a.box_hi[0] || gy < a.box_lo[1] || gy >= a.box_hi[1]) {
           ad = VoxelAdjoint<T>{};
-          sx[GX][v] = T(0); sx[GY][v] = T(0);
-          sx[BXX][v] = T(0); sx[BYY][v] = T(0);
+          put_xy(v, T(0), T(0), T(0), T(0));
           sx[BXY][v] = T(0); sx[BXZ][v] = T(0); sx[BYZ][v] = T(0);
           return T(0);
         }
@@ -553,8 +593,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
         f = voxel_density_adjoint_body<false>(st(), st, pv, a.k, ad);
       else
         f = voxel_density_adjoint<SP>(st(), st, pv, a.k, ad);
-      sx[GX][v] = ad.hgx; sx[GY][v] = ad.hgy;
-      sx[BXX][v] = ad.nbxx; sx[BYY][v] = ad.nbyy;
+      put_xy(v, ad.hgx, ad.nbxx, ad.hgy, ad.nbyy);
       sx[BXY][v] = ad.dbxy; sx[BXZ][v] = ad.dbxz; sx[BYZ][v] = ad.dbyz;
       return f;
     };
@@ -591,7 +630,7 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
 
     // ---- transposed stencils on the interior ----
     // The b adjoints are held negated (nb = -df/db), which flips their signs
-    // here; GX, GY hold half the a_x, a_y derivatives and BXY, BXZ, BYZ twice
+    // here; the records' first values hold half the a_x, a_y derivatives and BXY, BXZ, BYZ twice
     // the (negated) b_ab ones, hence the factors 2 and 1/2.
     T mpl = T(0);                              // this thread's sum of the field written for plane p - 1
     const size_t po = (size_t)(it >= 2 ? p - 1 : 0) * plane;   // output plane p - 1 (written from it = 2)
@@ -631,11 +670,11 @@ __global__ __launch_bounds__(NT) void grad_sweep(SweepArgs<T> a) {
             mpl += uc;
           }
         }
+        const FieldPair<T> xp1 = xat(j, v, 1), xm1 = xat(j, v, -1);
+        const FieldPair<T> yp1 = yat(j, v, RX), ym1 = yat(j, v, -RX);
         const T cin = own_c0[j]
-                      - T(2) * ((sxat(j, v, GX, 1) - sxat(j, v, GX, -1)) +
-                                (sxat(j, v, GY, RX) - sxat(j, v, GY, -RX)))
-                      - ((sxat(j, v, BXX, 1) + sxat(j, v, BXX, -1)) +
-                         (sxat(j, v, BYY, RX) + sxat(j, v, BYY, -RX)))
+                      - T(2) * ((xp1.a - xm1.a) + (yp1.a - ym1.a))
+                      - ((xp1.b + xm1.b) + (yp1.b + ym1.b))
                       - T(0.5) * ((sxat(j, v, BXY, RX + 1) - sxat(j, v, BXY, -RX + 1)) -
                                   (sxat(j, v, BXY, RX - 1) - sxat(j, v, BXY, -RX - 1)));
         l_pp[j] = l_prev[j];
