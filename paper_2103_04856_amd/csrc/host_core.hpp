@@ -353,7 +353,9 @@ struct Geometry {
   int ntx, nty, nzc, lz, per_inst;
 };
 
-// Blocks of the step sweep of `variant` that one compute unit holds at once.
+// Blocks of the step sweep of `variant` that one compute unit holds at once,
+// for the body that serves any batch (the allocation-free entry point, which
+// has no context).
 int block_slots(int dtype, int variant) {
   const Variant& v = variants()[variant];
   const void* fn = dtype == FE_F32 ? (const void*)v.k32.step[fe::kBodyAny] : (const void*)v.k64.step[fe::kBodyAny];
@@ -394,7 +396,9 @@ int halo1_chunk(long cols, int nz, int num_cu, int slots) {
   return lz;
 }
 
-Geometry geometry_of(const fe_grid& grid, int num_cu, int variant, int lz_req) {
+// `slots`: blocks of the launched kernel that one compute unit holds at once
+// (used when lz_req is 0, automatic).
+Geometry geometry_of(const fe_grid& grid, int num_cu, int variant, int lz_req, int slots) {
   const Variant& v = variants()[variant];
   Geometry g;
   g.ntx = ceil_div(grid.nx, v.tx);
@@ -408,7 +412,6 @@ Geometry geometry_of(const fe_grid& grid, int num_cu, int variant, int lz_req) {
     // tiles: 17 planes, 480 blocks, 73 us against 102 us for 16 planes)
     const int nz = grid.nz;
     const long cols = (long)g.ntx * g.nty * grid.batch;
-    const int slots = block_slots(grid.dtype, variant);
     double best = 0.0;
     for (int nzc = 1; nzc <= nz; ++nzc) {
       const int l = ceil_div(nz, nzc);
@@ -427,7 +430,31 @@ Geometry geometry_of(const fe_grid& grid, int num_cu, int variant, int lz_req) {
   return g;
 }
 
-Geometry geometry(const fe_ctx* c, int variant, int lz_req) { return geometry_of(c->grid, c->num_cu, variant, lz_req); }
+// The kernel launch_sweep runs for `kind` (-1: energy only, else a
+// fe::SweepMode) with `variant` on this context.
+template <typename T>
+SweepFn<T> sweep_fn(const fe_ctx* c, const Variant& v, int kind) {
+  if (c->use_box) return box_kernel_of<T>(v);
+  const Kernels<T>& k = kernels_of<T>(v, c->use_cfield);
+  return kind < 0 ? k.energy : sweep_kernel<T>(k, kind, c->use_cfield ? (int)fe::kBodyAny : c->body);
+}
+
+// Blocks of that kernel one compute unit holds at once: its registers and LDS
+// decide it (the symmetric step body at 32 x 32 takes three, the bodies with the
+// S terms two), and the automatic z chunks follow it.
+int launch_slots(const fe_ctx* c, int variant, int kind) {
+  const Variant& v = variants()[variant];
+  const void* fn = c->grid.dtype == FE_F32 ? (const void*)sweep_fn<float>(c, v, kind)
+                                           : (const void*)sweep_fn<double>(c, v, kind);
+  int n = 0;
+  if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, v.nt, 0) != hipSuccess || n < 1) n = 1;
+  return n;
+}
+
+// Launch geometry of a sweep of `kind` with `variant` on this context.
+Geometry geometry(const fe_ctx* c, int variant, int lz_req, int kind) {
+  return geometry_of(c->grid, c->num_cu, variant, lz_req, lz_req > 0 ? 1 : launch_slots(c, variant, kind));
+}
 
 bool has_sp(int v, int dtype) {
   const Variant& x = variants()[v];
@@ -498,10 +525,9 @@ template <typename T>
 int launch_sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, const double* prev_partials,
                  double* partials, const StepRule& rule, int t_add) {
   const int vi = sweep_variant(c);
-  const Geometry geo = geometry(c, vi, c->lz);
+  const Geometry geo = geometry(c, vi, c->lz, kind);
   if ((size_t)geo.per_inst > c->max_blocks) return set_error(FE_EINVAL, "internal: partials workspace too small");
   const Variant& v = variants()[vi];
-  const Kernels<T>& k = kernels_of<T>(v, c->use_cfield);
   fe::SweepArgs<T> a;
   a.src = static_cast<const T*>(src);
   a.dst = static_cast<T*>(dst);
@@ -530,10 +556,10 @@ int launch_sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst,
   a.batch = c->grid.batch;
   const dim3 grid((unsigned)(geo.per_inst * c->grid.batch));
   const dim3 block((unsigned)v.nt);
-  SweepFn<T> fn = kind < 0 ? k.energy : sweep_kernel<T>(k, kind, c->use_cfield ? (int)fe::kBodyAny : c->body);
+  if (c->use_box && (kind != fe::kGrad || c->use_cfield))
+    return set_error(FE_EINVAL, "internal: box sweeps are gradient-only");
+  const SweepFn<T> fn = sweep_fn<T>(c, v, kind);
   if (c->use_box) {
-    if (kind != fe::kGrad || c->use_cfield) return set_error(FE_EINVAL, "internal: box sweeps are gradient-only");
-    fn = box_kernel_of<T>(v);
     for (int i = 0; i < 3; ++i) {
       a.box_lo[i] = c->box_lo[i];
       a.box_hi[i] = c->box_hi[i];
@@ -550,10 +576,11 @@ int sweep(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst, const 
                                  : launch_sweep<double>(c, s, kind, src, dst, prev_partials, partials, rule, t_add);
 }
 
-// Per-instance totals of the sweep that wrote `partials` (same launch shape):
-// energy_dev[b] and, when shift is given, shift[b] = mass[b] - mean of its field.
-int finish_sums(fe_ctx* c, hipStream_t s, const double* partials, double* energy_dev, double* shift) {
-  const Geometry geo = geometry(c, sweep_variant(c), c->lz);
+// Per-instance totals of the sweep of `kind` that wrote `partials` (same launch
+// shape): energy_dev[b] and, when shift is given, shift[b] = mass[b] - mean of
+// its field.
+int finish_sums(fe_ctx* c, hipStream_t s, const double* partials, double* energy_dev, double* shift, int kind) {
+  const Geometry geo = geometry(c, sweep_variant(c), c->lz, kind);
   hipLaunchKernelGGL(fe::sweep_finish, dim3(c->grid.batch), dim3(64), 0, s, partials, geo.per_inst, energy_dev,
                      (const double*)c->d_mass, 1.0 / ((double)c->grid.nx * c->grid.ny * c->grid.nz), shift);
   FE_HIP(hipGetLastError());
@@ -637,7 +664,7 @@ int sweep_energy(fe_ctx* c, hipStream_t s, int kind, const void* src, void* dst,
   }
   const StepRule none{fe::kGrad, 0.0, 0.0, 0.0, 0.0};
   int rc = sweep(c, s, kind, src, dst, nullptr, partials_buf(c, 0), none);
-  return rc ? rc : finish_sums(c, s, partials_buf(c, 0), energy_dev, nullptr);
+  return rc ? rc : finish_sums(c, s, partials_buf(c, 0), energy_dev, nullptr, kind);
 }
 
 int copy_energy_out(fe_ctx* c, double* energy) {
@@ -782,7 +809,7 @@ int run_steps(fe_ctx* c, void* u, const double* mass, const StepRule& rule, int 
   if ((rc = tick(c->stream, pending))) return rc;
   // the energy of the last step's input and the shift of its output
   double* shift = c->d_shift;
-  if ((rc = finish_sums(c, c->stream, last_p, c->d_energy, shift))) return rc;
+  if ((rc = finish_sums(c, c->stream, last_p, c->d_energy, shift, rule.mode))) return rc;
   if ((rc = launch_add_shift(c, last, u, shift))) return rc;
   return copy_energy_out(c, energy);
 }
@@ -1121,7 +1148,7 @@ int fe_set_launch(fe_ctx* c, int variant, int z_chunk) {
 int fe_get_launch(const fe_ctx* c, int* variant, int* z_chunk) {
   if (!c) return set_error(FE_EINVAL, "ctx is NULL");
   if (variant) *variant = c->variant;
-  if (z_chunk) *z_chunk = geometry(c, c->variant, c->lz).lz;
+  if (z_chunk) *z_chunk = geometry(c, c->variant, c->lz, fe::kStepGD).lz;
   return FE_OK;
 }
 
@@ -1226,7 +1253,7 @@ int fe_autotune(fe_ctx* c, const void* u, void* work, int kind, int iters, doubl
       lzs.push_back(p);
       lzs.push_back(ceil_div(nz, ceil_div(nz, p)));
     }
-    lzs.push_back(geometry(c, v, 0).lz);
+    lzs.push_back(geometry(c, v, 0, kind == FE_TUNE_GRAD ? (int)fe::kGrad : rule.mode).lz);
     std::sort(lzs.begin(), lzs.end());
     lzs.erase(std::unique(lzs.begin(), lzs.end()), lzs.end());
     for (int lz : lzs) {

@@ -253,7 +253,7 @@ int fe_hminus_step(fe_ctx* c, void* A, const double* m0, double sigma_k, double 
     if (energy) for (int b = 0; b < c->grid.batch; ++b) energy[b] = 0.0;
     return FE_OK;
   }
-  int rc = finish_sums(c, c->stream, partials_buf(c, 0), c->d_energy, nullptr);   // the last iteration's G
+  int rc = finish_sums(c, c->stream, partials_buf(c, 0), c->d_energy, nullptr, fe::kGrad);   // the last iteration's G
   if (rc) return rc;
   return copy_energy_out(c, energy);
 }

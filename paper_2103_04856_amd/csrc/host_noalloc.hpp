@@ -67,7 +67,8 @@ template <typename T>
 int noalloc_sweep(const fe_grid& grid, const double* eps, const double* a, const void* u, void* g,
                   double* energy_dev, hipStream_t stream, const ScratchSlot& slot) {
   const int vi = default_variant(grid);
-  const Geometry geo = g ? geometry_of(grid, slot.num_cu, vi, 0) : energy_geometry(grid, slot.num_cu);
+  const Geometry geo =
+      g ? geometry_of(grid, slot.num_cu, vi, 0, block_slots(grid.dtype, vi)) : energy_geometry(grid, slot.num_cu);
   const size_t nblocks = (size_t)geo.per_inst * grid.batch;
   if (nblocks > kScratchPartials)
     return set_error(FE_EINVAL, "grid needs %zu block partials; the static scratch holds %zu", nblocks,
