@@ -13,7 +13,7 @@ sys.path.insert(0, ROOT)
 
 import bench  # noqa: E402
 
-VOXELS = {32: 256 ** 3, 64: 16 * 128 ** 3, None: 256 ** 3}
+VOXELS = {22: 256 ** 3, 32: 256 ** 3, 64: 16 * 128 ** 3, None: 256 ** 3}
 ALGO_BYTES = {1: bench.BYTES_PER_VOXEL_STEP, 0: bench.BYTES_PER_VOXEL_GRAD, 2: bench.BYTES_PER_VOXEL_ADAM}
 
 
