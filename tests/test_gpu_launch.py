@@ -10,7 +10,7 @@ import torch
 
 from paper_2103_04856_amd import fe, inputs
 
-from gpu_helpers import ALL_TERMS, log, to_dev
+from gpu_helpers import ALL_TERMS, ASYM_C3, HELFRICH_SC, log, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -106,3 +106,26 @@ def test_autotune_for_adam_keeps_the_optimiser_state():
     cb.set_launch(*keep)
     cb.step_adam(ub, [0.1], 5)
     assert torch.equal(ua, ub)
+
+
+def test_automatic_z_chunks_follow_the_occupancy_of_the_kernel_that_runs():
+    """The automatic z chunks come from the blocks per compute unit of the kernel the
+    call launches: at 256^3 in 32 x 32 tiles the symmetric step (the body without the
+    S terms, 75 VGPRs) fits three blocks per CU and takes 22-plane chunks (768 blocks,
+    one round), a p with the S terms two blocks and 32-plane chunks (512 blocks). The
+    two launch shapes give the same gradient to rounding."""
+    n = 256
+    h = 1.0 / n
+    u = to_dev(inputs.uniform_noise(n, 1005), torch.float32)
+    v32 = [i for i, v in enumerate(fe.variants()) if v[:3] == (32, 32, 512)][0]
+    sym = fe.FeContext(u.shape, h, 1.5 * h, HELFRICH_SC, dtype=torch.float32)
+    asym = fe.FeContext(u.shape, h, 1.5 * h, ASYM_C3, dtype=torch.float32)
+    log("case 256^3 automatic z chunks")
+    assert sym.get_launch() == (v32, 22)
+    assert asym.get_launch() == (v32, 32)
+    E22, g22 = sym.energy_grad(u)
+    sym.set_launch(v32, 32)
+    E32, g32 = sym.energy_grad(u)
+    d = (torch.linalg.vector_norm((g22 - g32).double()) / torch.linalg.vector_norm(g32.double())).item()
+    assert d <= 2e-6, d
+    assert abs(E22[0].item() - E32[0].item()) <= 1e-6 * abs(E32[0].item())
