@@ -353,17 +353,6 @@ struct Geometry {
   int ntx, nty, nzc, lz, per_inst;
 };
 
-// Blocks of the step sweep of `variant` that one compute unit holds at once,
-// for the body that serves any batch (the allocation-free entry point, which
-// has no context).
-int block_slots(int dtype, int variant) {
-  const Variant& v = variants()[variant];
-  const void* fn = dtype == FE_F32 ? (const void*)v.k32.step[fe::kBodyAny] : (const void*)v.k64.step[fe::kBodyAny];
-  int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, v.nt, 0) != hipSuccess || n < 1) n = 1;
-  return n;
-}
-
 // Time of a sweep whose busiest compute unit runs k = ceil(blocks / num_cu)
 // blocks of L planes, `slots` at a time, in units of one plane of a block in a
 // full CU: a full group of `slots` blocks costs 1 per plane, a CU left with

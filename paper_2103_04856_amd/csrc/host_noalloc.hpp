@@ -67,22 +67,26 @@ template <typename T>
 int noalloc_sweep(const fe_grid& grid, const double* eps, const double* a, const void* u, void* g,
                   double* energy_dev, hipStream_t stream, const ScratchSlot& slot) {
   const int vi = default_variant(grid);
-  const Geometry geo =
-      g ? geometry_of(grid, slot.num_cu, vi, 0, block_slots(grid.dtype, vi)) : energy_geometry(grid, slot.num_cu);
+  ParamPack<T> pack{};
+  const double theta0[3] = {0.0, 0.0, 0.0};
+  for (int b = 0; b < grid.batch; ++b) pack.p[b] = inst_params<T>(grid.h, eps[b], a + 6 * b, 0.0, theta0);
+  const Variant& v = variants()[vi];
+  const Kernels<T>& k = kernels_of<T>(v, false);
+  const SweepFn<T> fn = sweep_kernel<T>(k, fe::kGrad, batch_body(pack.p, grid.batch));
+  // z chunks from the blocks per compute unit of the kernel launched, as in a context
+  int slots = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&slots, (const void*)fn, v.nt, 0) != hipSuccess || slots < 1)
+    slots = 1;
+  const Geometry geo = g ? geometry_of(grid, slot.num_cu, vi, 0, slots) : energy_geometry(grid, slot.num_cu);
   const size_t nblocks = (size_t)geo.per_inst * grid.batch;
   if (nblocks > kScratchPartials)
     return set_error(FE_EINVAL, "grid needs %zu block partials; the static scratch holds %zu", nblocks,
                      kScratchPartials);
-  ParamPack<T> pack{};
-  const double theta0[3] = {0.0, 0.0, 0.0};
-  for (int b = 0; b < grid.batch; ++b) pack.p[b] = inst_params<T>(grid.h, eps[b], a + 6 * b, 0.0, theta0);
   auto* prm = reinterpret_cast<fe::InstParams<T>*>(slot.ptr);
   double* partials = reinterpret_cast<double*>(static_cast<char*>(slot.ptr) + kScratchPrmBytes);
   hipLaunchKernelGGL(store_params<T>, dim3(1), dim3(64), 0, stream, pack, grid.batch, prm);
   FE_HIP(hipGetLastError());
 
-  const Variant& v = variants()[vi];
-  const Kernels<T>& k = kernels_of<T>(v, false);
   fe::SweepArgs<T> sa{};
   sa.src = static_cast<const T*>(u);
   sa.dst = static_cast<T*>(g);
@@ -101,8 +105,7 @@ int noalloc_sweep(const fe_grid& grid, const double* eps, const double* a, const
   sa.lz = geo.lz;
   sa.batch = grid.batch;
   if (g) {
-    hipLaunchKernelGGL(sweep_kernel<T>(k, fe::kGrad, batch_body(pack.p, grid.batch)), dim3((unsigned)nblocks),
-                       dim3((unsigned)v.nt), 0, stream, sa);
+    hipLaunchKernelGGL(fn, dim3((unsigned)nblocks), dim3((unsigned)v.nt), 0, stream, sa);
     FE_HIP(hipGetLastError());
   } else {
     const int rc = launch_energy_cols<T>(grid, geo, u, prm, partials, stream);
